@@ -1,0 +1,132 @@
+/*
+ * join.h -- C ABI of libjoin, a single-GPU (MI355X, gfx950) relational join library.
+ *
+ * The operations follow "GPU-based Efficient Join Algorithms on Hadoop" (Wang, Li, Wang, Li):
+ *   - the equi join and theta join problem statements (Section 2.3): two relations, a join
+ *     condition on one attribute of each, and the output is the set of matching tuple pairs;
+ *   - the column layout handed to the GPU (Section 3.2.2): one buffer per attribute, all in the
+ *     same tuple order, and a match of record m of one table with record n of the other yields
+ *     the pair of positions (m, n);
+ *   - the GPU entry points of Algorithm 1 (Join_GPU(T', S', NB_T, NB_S)) and Algorithm 3
+ *     (GPU_theta_join(S, T)), which receive both tables and their sizes;
+ *   - the result-size problem of Section 3.3.3: the paper preallocates a bound (NB_T * NB_S,
+ *     Section 3.3.1, or its estimate R_size); this library instead counts the result exactly,
+ *     scans the per-work-unit counts on the device and writes each pair at its exact offset, so
+ *     the caller allocates the output once at its exact size.
+ *
+ * Naming: the paper's table T (the smaller, hashed table, Section 2.3 and Section 3.3.2) is R
+ * here; its S is S.  A predicate always reads  R.col  op  S.col.
+ *
+ * Conventions for every call below
+ *   - Pointers inside join_rel_t, the workspace and the output are DEVICE pointers on the
+ *     current HIP device.  join_rel_t / join_pred_t structs themselves and `count` are HOST
+ *     pointers.  The caller owns every buffer; the library never allocates device memory and
+ *     keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All device work is
+ *     enqueued on it in order.  The only host synchronisation is the 8-byte read of the exact
+ *     count in join_count, join_hash and join_theta.
+ *   - Counts and offsets are uint64.  Output is int32 pairs, interleaved (rid_R, rid_S), i.e. a
+ *     row-major [count][2] int32 array.  The order of pairs is unspecified; the multiset is
+ *     exact (bag semantics: duplicate keys produce every matching pair).
+ *   - Status codes are returned; nothing throws or aborts across the ABI.  After a non-zero
+ *     status, join_last_error() describes it (thread-local).
+ */
+#ifndef JOIN_H
+#define JOIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define JOIN_OK 0
+#define JOIN_E_INVAL 1       /* bad argument: NULL with n > 0, n < 0, bad op, w < 0, ...       */
+#define JOIN_E_CAPACITY 2    /* output capacity below the exact count; nothing was written     */
+#define JOIN_E_WORKSPACE 3   /* workspace NULL or smaller than join_workspace_bytes()          */
+#define JOIN_E_HIP 4         /* a HIP runtime call failed; text in join_last_error()           */
+#define JOIN_E_UNSUPPORTED 5 /* a size beyond the supported range (n > 2^31 - 1)               */
+
+/* ---- join kinds -------------------------------------------------------------------------- */
+#define JOIN_KIND_HASH 1  /* equi join R.key = S.key (Section 3.3.2, hash join)                */
+#define JOIN_KIND_THETA 2 /* theta join, nested-loop evaluation (Sections 3.3.1 and 4.2)       */
+
+/* ---- predicate operators (Section 2.3: =, <, >, <=, >=; Figure "greenc": not-equal) -------- */
+typedef enum {
+    JOIN_OP_NONE = 0, /* no condition on this column (only valid for op_c)                    */
+    JOIN_OP_EQ = 1,   /* R.x == S.x                                                          */
+    JOIN_OP_NE = 2,   /* R.x != S.x                                                          */
+    JOIN_OP_LT = 3,   /* R.x <  S.x   (signed int32)                                         */
+    JOIN_OP_LE = 4,   /* R.x <= S.x                                                          */
+    JOIN_OP_GT = 5,   /* R.x >  S.x                                                          */
+    JOIN_OP_GE = 6,   /* R.x >= S.x                                                          */
+    JOIN_OP_BAND = 7  /* |R.a - S.a| <= w, exact integer arithmetic; only valid for op_a      */
+} join_op_t;
+
+/* One relation in column layout (Section 3.2.2).  Device pointers.
+ *   key  : the equi-join key, or theta column a.  Required when n > 0.
+ *   key2 : theta column c; required when the predicate's op_c != JOIN_OP_NONE, else ignored.
+ *   rid  : opaque int32 payload written to the output; NULL means "row position" (0..n-1).
+ *   n    : number of rows, 0 <= n <= 2^31 - 1. */
+typedef struct {
+    const int32_t* key;
+    const int32_t* key2;
+    const int32_t* rid;
+    int64_t n;
+} join_rel_t;
+
+/* Theta predicate: op_a(R.key, S.key) AND op_c(R.key2, S.key2).
+ *   op_a : JOIN_OP_EQ .. JOIN_OP_BAND
+ *   w    : band half-width for JOIN_OP_BAND, 0 <= w <= 2^31 - 1 (ignored otherwise)
+ *   op_c : JOIN_OP_NONE .. JOIN_OP_GE (BAND is rejected on c) */
+typedef struct {
+    int32_t op_a;
+    int32_t w;
+    int32_t op_c;
+} join_pred_t;
+
+/* Workspace size in bytes needed by join_count / join_materialize / join_hash / join_theta for
+ * this kind and these sizes.  Depends only on (kind, nR, nS, pred) and the library's tuning
+ * environment (JOIN_HASH_BITS, ...), so the same value serves a count and its later
+ * materialize.  Returns 0 for invalid arguments (kind unknown, n < 0). */
+size_t join_workspace_bytes(int kind, int64_t nR, int64_t nS, const join_pred_t* pred);
+
+/* Exact result size (Section 3.3.3, done exactly).  Runs the count pass and the device scan of
+ * per-work-unit counts, leaves the plan, partitioned data and offsets in `ws`, and writes the
+ * exact number of output pairs to *count (host).  `pred` may be NULL for JOIN_KIND_HASH.
+ * Between join_count and join_materialize the caller must not change R, S or ws.
+ * Errors: JOIN_E_INVAL, JOIN_E_WORKSPACE, JOIN_E_UNSUPPORTED, JOIN_E_HIP. */
+int join_count(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
+               void* ws, size_t ws_bytes, void* stream, uint64_t* count);
+
+/* Write pass: writes every pair at the offset the preceding join_count computed in `ws`
+ * (same kind, R, S, pred and ws).  `pairs` holds `capacity` pairs (2*capacity int32).  If the
+ * exact count exceeds `capacity`, nothing is written and JOIN_E_CAPACITY is returned when the
+ * library can tell on the host (the count of the last join_count on this thread for this ws);
+ * in every case the device never writes past `capacity`.  Asynchronous: no host sync. */
+int join_materialize(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
+                     void* ws, size_t ws_bytes, int32_t* pairs, uint64_t capacity, void* stream);
+
+/* One-shot equi join (Algorithm 1's Join_GPU, hash join of Section 3.3.2): count, scan, and
+ * if capacity >= *count write.  snprintf semantics: *count is always set on success of the
+ * count; if capacity < *count nothing is written, JOIN_E_CAPACITY is returned and ws stays
+ * valid for a later join_materialize without recounting. */
+int join_hash(const join_rel_t* R, const join_rel_t* S, void* ws, size_t ws_bytes,
+              int32_t* pairs, uint64_t capacity, uint64_t* count, void* stream);
+
+/* One-shot theta join (Algorithm 3's GPU_theta_join; nested-loop evaluation of Section 3.3.1
+ * with the predicate of Section 2.3).  Same semantics as join_hash. */
+int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred, void* ws,
+               size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count,
+               void* stream);
+
+/* Message for the last non-zero status on the calling thread ("" if none). */
+const char* join_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JOIN_H */
