@@ -125,6 +125,20 @@ int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred
 /* Message for the last non-zero status on the calling thread ("" if none). */
 const char* join_last_error(void);
 
+/* ---- primitive: device exclusive scan ----------------------------------------------------
+ * The "scan" of count -> scan -> write, exported so it can be checked on its own.  The paper
+ * gives each thread a private result region and "sums" the regions at the end (Section 3.3.1);
+ * the exclusive prefix sum of per-unit counts is that summation made exact: out[i] = sum of
+ * in[0..i), computed on the device.
+ *   in, out : device arrays of n uint64 (out may equal in)
+ *   total   : device pointer receiving sum(in[0..n)), or NULL
+ *   ws      : device workspace of at least join_scan_workspace_bytes(n) bytes
+ * Asynchronous on `stream`.  Errors: JOIN_E_INVAL (n < 0, NULL arrays with n > 0),
+ * JOIN_E_WORKSPACE, JOIN_E_HIP. */
+size_t join_scan_workspace_bytes(int64_t n);
+int join_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total, void* ws,
+                  size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

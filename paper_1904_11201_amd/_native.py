@@ -1,0 +1,74 @@
+"""ctypes view of libjoin.so (include/join.h).  Argument marshalling only.
+
+The shared library is required: importing the package on a machine where it was not built raises
+ImportError instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjoin.so")
+
+JOIN_OK = 0
+JOIN_E_INVAL = 1
+JOIN_E_CAPACITY = 2
+JOIN_E_WORKSPACE = 3
+JOIN_E_HIP = 4
+JOIN_E_UNSUPPORTED = 5
+STATUS_NAMES = {0: "JOIN_OK", 1: "JOIN_E_INVAL", 2: "JOIN_E_CAPACITY", 3: "JOIN_E_WORKSPACE",
+                4: "JOIN_E_HIP", 5: "JOIN_E_UNSUPPORTED"}
+
+JOIN_KIND_HASH = 1
+JOIN_KIND_THETA = 2
+
+OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 7}
+
+# Every symbol include/join.h declares.
+EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash", "join_theta",
+           "join_last_error", "join_scan_workspace_bytes", "join_scan_u64")
+
+
+class JoinRel(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("key2", ctypes.c_void_p), ("rid", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
+class JoinPred(ctypes.Structure):
+    _fields_ = [("op_a", ctypes.c_int32), ("w", ctypes.c_int32), ("op_c", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1904_11201_amd.build` "
+            "(hipcc, gfx950).  There is no fallback path.")
+    lib = ctypes.CDLL(LIB_PATH)
+    R = ctypes.POINTER(JoinRel)
+    Pp = ctypes.POINTER(JoinPred)
+    vp, sz, i64, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_uint64
+    lib.join_workspace_bytes.restype = sz
+    lib.join_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, Pp]
+    lib.join_count.restype = ctypes.c_int
+    lib.join_count.argtypes = [ctypes.c_int, R, R, Pp, vp, sz, vp, ctypes.POINTER(u64)]
+    lib.join_materialize.restype = ctypes.c_int
+    lib.join_materialize.argtypes = [ctypes.c_int, R, R, Pp, vp, sz, vp, u64, vp]
+    lib.join_hash.restype = ctypes.c_int
+    lib.join_hash.argtypes = [R, R, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
+    lib.join_theta.restype = ctypes.c_int
+    lib.join_theta.argtypes = [R, R, Pp, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
+    lib.join_last_error.restype = ctypes.c_char_p
+    lib.join_last_error.argtypes = []
+    lib.join_scan_workspace_bytes.restype = sz
+    lib.join_scan_workspace_bytes.argtypes = [i64]
+    lib.join_scan_u64.restype = ctypes.c_int
+    lib.join_scan_u64.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return (lib.join_last_error() or b"").decode(errors="replace")

@@ -1,0 +1,330 @@
+// api.hip -- the C ABI of libjoin (include/join.h): validation, plans, launch sequencing and
+// the single 8-byte host read of the exact count.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "hash.hpp"
+#include "scan.hpp"
+#include "theta.hpp"
+
+namespace jl {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return JOIN_E_HIP;
+}
+
+}  // namespace jl
+
+using namespace jl;
+
+namespace {
+
+constexpr int64_t kMaxRows = 2147483647;  // rids and positions are int32
+
+int num_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
+}
+
+int64_t theta_target_waves()
+{
+    const char* s = getenv("JOIN_THETA_WAVES");
+    if (s && *s) return atoll(s);
+    return (int64_t)num_cus() * 4 * 16;  // 16 waves per SIMD, two rounds at occupancy 8
+}
+
+int64_t theta_ts_override()
+{
+    const char* s = getenv("JOIN_THETA_TS");
+    return (s && *s) ? atoll(s) : 0;
+}
+
+int check_rel(const join_rel_t* X, const char* name, bool need_key2)
+{
+    if (!X) {
+        set_error("%s is NULL", name);
+        return JOIN_E_INVAL;
+    }
+    if (X->n < 0) {
+        set_error("%s.n = %lld is negative", name, (long long)X->n);
+        return JOIN_E_INVAL;
+    }
+    if (X->n > kMaxRows) {
+        set_error("%s.n = %lld exceeds 2^31 - 1", name, (long long)X->n);
+        return JOIN_E_UNSUPPORTED;
+    }
+    if (X->n > 0 && !X->key) {
+        set_error("%s.key is NULL with n > 0", name);
+        return JOIN_E_INVAL;
+    }
+    if (need_key2 && X->n > 0 && !X->key2) {
+        set_error("%s.key2 is NULL but the predicate has a condition on column c", name);
+        return JOIN_E_INVAL;
+    }
+    return JOIN_OK;
+}
+
+int check_pred(const join_pred_t* p)
+{
+    if (!p) {
+        set_error("theta join needs a predicate");
+        return JOIN_E_INVAL;
+    }
+    if (p->op_a < JOIN_OP_EQ || p->op_a > JOIN_OP_BAND) {
+        set_error("op_a = %d is not one of EQ..BAND", (int)p->op_a);
+        return JOIN_E_INVAL;
+    }
+    if (p->op_c < JOIN_OP_NONE || p->op_c > JOIN_OP_GE) {
+        set_error("op_c = %d is not one of NONE..GE (BAND is only valid on column a)", (int)p->op_c);
+        return JOIN_E_INVAL;
+    }
+    if (p->op_a == JOIN_OP_BAND && p->w < 0) {
+        set_error("band half-width w = %d is negative", (int)p->w);
+        return JOIN_E_INVAL;
+    }
+    return JOIN_OK;
+}
+
+int check_args(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p)
+{
+    if (kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA) {
+        set_error("kind = %d is neither JOIN_KIND_HASH nor JOIN_KIND_THETA", kind);
+        return JOIN_E_INVAL;
+    }
+    int rc;
+    bool key2 = false;
+    if (kind == JOIN_KIND_THETA) {
+        if ((rc = check_pred(p)) != JOIN_OK) return rc;
+        key2 = p->op_c != JOIN_OP_NONE;
+    }
+    if ((rc = check_rel(R, "R", key2)) != JOIN_OK) return rc;
+    if ((rc = check_rel(S, "S", key2)) != JOIN_OK) return rc;
+    return JOIN_OK;
+}
+
+size_t ws_needed(int kind, int64_t nR, int64_t nS)
+{
+    if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).bytes;
+    return theta_plan(nR, nS, theta_target_waves(), theta_ts_override()).bytes;
+}
+
+int check_ws(int kind, const join_rel_t* R, const join_rel_t* S, void* ws, size_t ws_bytes)
+{
+    const size_t need = ws_needed(kind, R->n, S->n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace %p of %zu bytes is smaller than the %zu bytes this join needs", ws,
+                  ws_bytes, need);
+        return JOIN_E_WORKSPACE;
+    }
+    return JOIN_OK;
+}
+
+// The last exact count on this thread, so that join_materialize can refuse a too-small output
+// on the host without a device read.
+struct LastCount {
+    bool valid;
+    int kind;
+    join_rel_t R, S;
+    join_pred_t p;
+    void* ws;
+    uint64_t count;
+};
+thread_local LastCount g_last{};
+
+bool same_rel(const join_rel_t& a, const join_rel_t& b)
+{
+    return a.key == b.key && a.key2 == b.key2 && a.rid == b.rid && a.n == b.n;
+}
+
+bool matches_last(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws)
+{
+    if (!g_last.valid || g_last.kind != kind || g_last.ws != ws) return false;
+    if (!same_rel(g_last.R, *R) || !same_rel(g_last.S, *S)) return false;
+    if (kind == JOIN_KIND_THETA &&
+        (g_last.p.op_a != p->op_a || g_last.p.op_c != p->op_c || g_last.p.w != p->w))
+        return false;
+    return true;
+}
+
+// Pinned 8-byte landing slot for the count read (one per thread, kept for the process).
+uint64_t* pinned_slot()
+{
+    static thread_local uint64_t* slot = nullptr;
+    if (!slot) {
+        if (hipHostMalloc((void**)&slot, 64, hipHostMallocDefault) != hipSuccess) slot = nullptr;
+    }
+    return slot;
+}
+
+int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
+               hipStream_t st, uint64_t* count)
+{
+    g_last.valid = false;
+    if (R->n == 0 || S->n == 0) {
+        *count = 0;
+    } else {
+        char* w = static_cast<char*>(ws);
+        hipError_t e;
+        if (kind == JOIN_KIND_HASH) {
+            const HashPlan pl = hash_plan(R->n, S->n, num_cus());
+            e = hash_count(pl, *R, *S, w, st);
+        } else {
+            const ThetaPlan pl = theta_plan(R->n, S->n, theta_target_waves(), theta_ts_override());
+            e = theta_count(pl, *R, *S, *p, w, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash count pass" : "theta count pass");
+        uint64_t* slot = pinned_slot();
+        if (!slot) {
+            set_error("hipHostMalloc of the 8-byte count slot failed");
+            return JOIN_E_HIP;
+        }
+        JL_HIP(hipMemcpyAsync(slot, w, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        JL_HIP(hipStreamSynchronize(st));
+        *count = *slot;
+    }
+    g_last.valid = true;
+    g_last.kind = kind;
+    g_last.R = *R;
+    g_last.S = *S;
+    if (p) g_last.p = *p;
+    g_last.ws = ws;
+    g_last.count = *count;
+    return JOIN_OK;
+}
+
+int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
+               int32_t* pairs, uint64_t capacity, hipStream_t st)
+{
+    if (R->n == 0 || S->n == 0) return JOIN_OK;
+    if (capacity > 0 && !pairs) {
+        set_error("pairs is NULL with capacity %llu", (unsigned long long)capacity);
+        return JOIN_E_INVAL;
+    }
+    char* w = static_cast<char*>(ws);
+    hipError_t e;
+    if (kind == JOIN_KIND_HASH) {
+        const HashPlan pl = hash_plan(R->n, S->n, num_cus());
+        e = hash_write(pl, *R, *S, w, pairs, capacity, st);
+    } else {
+        const ThetaPlan pl = theta_plan(R->n, S->n, theta_target_waves(), theta_ts_override());
+        e = theta_write(pl, *R, *S, *p, w, pairs, capacity, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash write pass" : "theta write pass");
+    return JOIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t join_workspace_bytes(int kind, int64_t nR, int64_t nS, const join_pred_t* pred)
+{
+    (void)pred;
+    if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA) || nR < 0 || nS < 0) return 0;
+    return ws_needed(kind, nR, nS);
+}
+
+int join_count(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
+               void* ws, size_t ws_bytes, void* stream, uint64_t* count)
+{
+    int rc = check_args(kind, R, S, pred);
+    if (rc != JOIN_OK) return rc;
+    if (!count) {
+        set_error("count is NULL");
+        return JOIN_E_INVAL;
+    }
+    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    return count_impl(kind, R, S, pred, ws, static_cast<hipStream_t>(stream), count);
+}
+
+int join_materialize(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
+                     void* ws, size_t ws_bytes, int32_t* pairs, uint64_t capacity, void* stream)
+{
+    int rc = check_args(kind, R, S, pred);
+    if (rc != JOIN_OK) return rc;
+    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    if (matches_last(kind, R, S, pred, ws) && g_last.count > capacity) {
+        set_error("capacity %llu is below the exact count %llu", (unsigned long long)capacity,
+                  (unsigned long long)g_last.count);
+        return JOIN_E_CAPACITY;
+    }
+    return write_impl(kind, R, S, pred, ws, pairs, capacity, static_cast<hipStream_t>(stream));
+}
+
+static int one_shot(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
+                    void* ws, size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count,
+                    void* stream)
+{
+    int rc = check_args(kind, R, S, pred);
+    if (rc != JOIN_OK) return rc;
+    if (!count) {
+        set_error("count is NULL");
+        return JOIN_E_INVAL;
+    }
+    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = count_impl(kind, R, S, pred, ws, st, count)) != JOIN_OK) return rc;
+    if (*count > capacity) {
+        set_error("capacity %llu is below the exact count %llu", (unsigned long long)capacity,
+                  (unsigned long long)*count);
+        return JOIN_E_CAPACITY;
+    }
+    return write_impl(kind, R, S, pred, ws, pairs, capacity, st);
+}
+
+int join_hash(const join_rel_t* R, const join_rel_t* S, void* ws, size_t ws_bytes, int32_t* pairs,
+              uint64_t capacity, uint64_t* count, void* stream)
+{
+    return one_shot(JOIN_KIND_HASH, R, S, nullptr, ws, ws_bytes, pairs, capacity, count, stream);
+}
+
+int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred, void* ws,
+               size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count, void* stream)
+{
+    return one_shot(JOIN_KIND_THETA, R, S, pred, ws, ws_bytes, pairs, capacity, count, stream);
+}
+
+const char* join_last_error(void) { return g_err; }
+
+size_t join_scan_workspace_bytes(int64_t n)
+{
+    if (n < 0) return 0;
+    return scan_temp_elems<uint64_t>(n) * sizeof(uint64_t) + 256;
+}
+
+int join_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total, void* ws,
+                  size_t ws_bytes, void* stream)
+{
+    if (n < 0 || (n > 0 && (!in || !out))) {
+        set_error("join_scan_u64: bad arguments (n = %lld)", (long long)n);
+        return JOIN_E_INVAL;
+    }
+    const size_t need = join_scan_workspace_bytes(n);
+    if (!ws || ws_bytes < need) {
+        set_error("join_scan_u64: workspace of %zu bytes is below %zu", ws_bytes, need);
+        return JOIN_E_WORKSPACE;
+    }
+    hipError_t e = exclusive_scan<uint64_t>(in, out, n, total, static_cast<uint64_t*>(ws),
+                                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "join_scan_u64");
+    return JOIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,712 @@
+// hash.hip -- partitioned hash equi join on gfx950: histogram, scatter, unit planning, and the
+// LDS hash-table count and write passes.
+//
+// The paper's hash join (Section 3.3.2) hashes the smaller table T into fixed-size buckets and
+// lets each thread probe a contiguous range of the larger table S (equations NBSJ / IDSJ); its
+// MapReduce round first groups tuples by join_key / alpha so that each reducer joins one key
+// range (Algorithm 1, Map2 / Reduce2).  The gfx950 design keeps that shape but moves it on chip:
+//   1. histogram:   per chunk of input, LDS histogram of pid = hash(key) >> (32 - bits);
+//   2. scan:        exclusive scan of the partition-major histograms -> write offsets;
+//   3. scatter:     per tile, an LDS counting sort by pid, then runs of equal pid written out
+//                   contiguously (R and S, key and rid columns);
+//   4. plan:        per partition, work units = (R chunk that fits the LDS table) x (S slice);
+//   5. count pass:  per unit, build an LDS hash table from the R chunk and probe the S slice;
+//   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
+//                   computed exactly instead of estimated);
+//   7. write pass:  same units, re-probe, each match written at offset + block-scanned rank.
+// The LDS table is open addressing with linear probing in "ordered" form: along every probe run
+// entries are non-decreasing in (key, rid), so the layout does not depend on insertion order and
+// a lookup stops at the first key above the probe key.  Its empty marker is a 64-bit value
+// proven absent from the chunk, so every int32 key and rid value stays usable.
+#include "hash.hpp"
+
+#include "scan.hpp"
+
+namespace jl {
+
+namespace {
+
+constexpr int kHistBlock = 512;
+constexpr int kScatBlock = 1024;
+constexpr int kScatTile = 8192;  // tuples staged in LDS per scatter step
+constexpr int kJoinBlock = 1024;
+constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
+constexpr int kEmptyCands = 8;
+constexpr int kMaxBits = 13;     // scatter LDS: 2 * 2^13 * 4 B of counters + the staged tile
+
+__device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
+{
+    return sh >= 32 ? 0u : hmix((uint32_t)key) >> sh;
+}
+
+// ------------------------------------------------------------------------------- histogram --
+template <bool VEC>
+__global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__ key, int64_t n,
+                                                     int64_t chunk, int bits,
+                                                     uint32_t* __restrict__ hist, int64_t nCh)
+{
+    extern __shared__ uint32_t h[];
+    const int P = 1 << bits;
+    const int sh = 32 - bits;
+    for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    int64_t i = beg;
+    if constexpr (VEC) {
+        for (int64_t v = beg + 4 * (int64_t)threadIdx.x; v + 4 <= end; v += 4 * kHistBlock) {
+            const int4 k4 = *reinterpret_cast<const int4*>(key + v);
+            atomicAdd(&h[pid_of(k4.x, sh)], 1u);
+            atomicAdd(&h[pid_of(k4.y, sh)], 1u);
+            atomicAdd(&h[pid_of(k4.z, sh)], 1u);
+            atomicAdd(&h[pid_of(k4.w, sh)], 1u);
+        }
+        i = beg + ((end - beg) / 4) * 4;
+    }
+    for (i += threadIdx.x; i < end; i += kHistBlock) atomicAdd(&h[pid_of(key[i], sh)], 1u);
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += kHistBlock) hist[(int64_t)p * nCh + blockIdx.x] = h[p];
+}
+
+// --------------------------------------------------------------------------------- scatter --
+// LDS layout: cursor[P] | tstart[P + 1] | skey[TILE] | srid[TILE] | spid[TILE] (uint16)
+template <bool VEC, bool HAS_RID>
+__global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restrict__ key,
+                                                        const int32_t* __restrict__ rid, int64_t n,
+                                                        int64_t chunk, int bits,
+                                                        const uint32_t* __restrict__ off,
+                                                        int64_t nCh, int32_t* __restrict__ outk,
+                                                        int32_t* __restrict__ outr)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[kScatBlock / kWave + 1];
+    const int P = 1 << bits;
+    const int sh = 32 - bits;
+    uint32_t* cursor = lds;
+    uint32_t* tstart = lds + P;
+    int32_t* skey = reinterpret_cast<int32_t*>(tstart + P + 1);
+    int32_t* srid = skey + kScatTile;
+    uint16_t* spid = reinterpret_cast<uint16_t*>(srid + kScatTile);
+    constexpr int IT = kScatTile / kScatBlock;
+    const int tid = threadIdx.x;
+
+    for (int p = tid; p < P; p += kScatBlock) {
+        cursor[p] = off[(int64_t)p * nCh + blockIdx.x];
+        tstart[p] = 0;
+    }
+    __syncthreads();
+
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    const int seg = (P + kScatBlock - 1) / kScatBlock;  // scan segment per thread
+
+    for (int64_t t0 = beg; t0 < end; t0 += kScatTile) {
+        const int tn = (int)(end - t0 < kScatTile ? end - t0 : kScatTile);
+        int32_t k[IT], r[IT];
+        uint32_t p[IT], rank[IT];
+        // 1. load (4 consecutive tuples per thread per step when vectorised) and rank by pid
+        if constexpr (VEC) {
+#pragma unroll
+            for (int q = 0; q < IT / 4; ++q) {
+                const int e = (q * kScatBlock + tid) * 4;
+                if (e + 4 <= tn) {
+                    const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + e);
+                    k[4 * q] = k4.x; k[4 * q + 1] = k4.y; k[4 * q + 2] = k4.z; k[4 * q + 3] = k4.w;
+                    if constexpr (HAS_RID) {
+                        const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + e);
+                        r[4 * q] = r4.x; r[4 * q + 1] = r4.y; r[4 * q + 2] = r4.z; r[4 * q + 3] = r4.w;
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) r[4 * q + c] = (int32_t)(t0 + e + c);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const bool ok = e + c < tn;
+                        k[4 * q + c] = ok ? key[t0 + e + c] : 0;
+                        r[4 * q + c] = ok ? (HAS_RID ? rid[t0 + e + c] : (int32_t)(t0 + e + c)) : 0;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < IT; ++q) {
+                const int e = q * kScatBlock + tid;
+                const bool ok = e < tn;
+                k[q] = ok ? key[t0 + e] : 0;
+                r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
+            p[q] = pid_of(k[q], sh);
+            rank[q] = e < tn ? atomicAdd(&tstart[p[q]], 1u) : 0u;
+        }
+        __syncthreads();
+        // 2. exclusive scan of the tile histogram in place; tstart[P] = tn
+        {
+            uint32_t s = 0;
+            for (int i = 0; i < seg; ++i) {
+                const int pp = tid * seg + i;
+                s += pp < P ? tstart[pp] : 0u;
+            }
+            uint32_t tot;
+            uint32_t run = block_excl_scan<kScatBlock>(s, wsum, &tot);
+            for (int i = 0; i < seg; ++i) {
+                const int pp = tid * seg + i;
+                if (pp < P) {
+                    const uint32_t c = tstart[pp];
+                    tstart[pp] = run;
+                    run += c;
+                }
+            }
+            if (tid == 0) tstart[P] = (uint32_t)tn;
+        }
+        __syncthreads();
+        // 3. stage in pid order
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
+            if (e < tn) {
+                const uint32_t pos = tstart[p[q]] + rank[q];
+                skey[pos] = k[q];
+                srid[pos] = r[q];
+                spid[pos] = (uint16_t)p[q];
+            }
+        }
+        __syncthreads();
+        // 4. write runs: consecutive threads write consecutive slots of one partition's run
+        for (int e = tid; e < tn; e += kScatBlock) {
+            const uint32_t pp = spid[e];
+            const uint32_t g = cursor[pp] + ((uint32_t)e - tstart[pp]);
+            outk[g] = skey[e];
+            outr[g] = srid[e];
+        }
+        __syncthreads();
+        for (int pp = tid; pp < P; pp += kScatBlock) cursor[pp] += tstart[pp + 1] - tstart[pp];
+        __syncthreads();
+        for (int pp = tid; pp < P; pp += kScatBlock) tstart[pp] = 0;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------- planning --
+__global__ void plan_units_k(const uint32_t* __restrict__ offR, const uint32_t* __restrict__ offS,
+                             int64_t nChR, int64_t nChS, int P, uint32_t nR, uint32_t nS,
+                             uint32_t cap, uint32_t slice, PartInfo* __restrict__ info,
+                             uint32_t* __restrict__ units)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > P) return;
+    if (p == P) {
+        units[P] = 0;
+        return;
+    }
+    const uint32_t rs = offR[(int64_t)p * nChR];
+    const uint32_t re = p + 1 < P ? offR[(int64_t)(p + 1) * nChR] : nR;
+    const uint32_t ss = offS[(int64_t)p * nChS];
+    const uint32_t se = p + 1 < P ? offS[(int64_t)(p + 1) * nChS] : nS;
+    const uint32_t nr = re - rs, ns = se - ss;
+    const uint32_t nrc = (nr + cap - 1) / cap;
+    uint32_t nss = 0;
+    if (nr > 0 && ns > 0) {
+        const uint64_t per = (uint64_t)slice * nrc;
+        nss = (uint32_t)((ns + per - 1) / per);
+        if (nss < 1) nss = 1;
+    }
+    PartInfo pi;
+    pi.rStart = rs;
+    pi.nR = nr;
+    pi.sStart = ss;
+    pi.nS = ns;
+    pi.nSs = nss;
+    pi.nRc = nrc;
+    pi.pad0 = pi.pad1 = 0;
+    info[p] = pi;
+    units[p] = nrc * nss;
+}
+
+// ------------------------------------------------------------------------- join work units --
+struct Unit {
+    uint32_t rBeg, rN, sBeg, sN;
+};
+
+__device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
+{
+    PartInfo pi;
+    uint32_t local;
+    if (g.single) {
+        pi = g.one;
+        local = u;
+    } else {
+        // largest p with unitStart[p] <= u
+        int lo = 0, hi = g.P - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (g.unitStart[mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        pi = g.part[lo];
+        local = u - g.unitStart[lo];
+    }
+    const uint32_t rc = local / pi.nSs;
+    const uint32_t sc = local - rc * pi.nSs;
+    const uint32_t slen = (pi.nS + pi.nSs - 1) / pi.nSs;
+    Unit o;
+    o.rBeg = pi.rStart + rc * g.cap;
+    o.rN = min(g.cap, pi.nR - rc * g.cap);
+    o.sBeg = pi.sStart + sc * slen;
+    o.sN = sc * slen < pi.nS ? min(slen, pi.nS - sc * slen) : 0u;
+    return o;
+}
+
+__device__ __forceinline__ uint64_t empty_cand(int i)
+{
+    return ~0ull - (uint64_t)i * 0x9E3779B97F4A7C15ull;
+}
+
+__device__ __forceinline__ uint32_t home_of(uint32_t h, int bits, uint32_t C)
+{
+    return (uint32_t)(((uint64_t)(bits >= 32 ? 0u : (h << bits)) * C) >> 32);
+}
+
+// Build the ordered linear-probing table of one R chunk in LDS.  Returns the empty marker.
+__device__ __forceinline__ uint64_t build_table(const JoinGeom& g, const Unit& un, uint64_t* tab,
+                                                uint32_t C, uint32_t* flag)
+{
+    const int tid = threadIdx.x;
+    uint64_t v[kBuildItems];
+    uint32_t present = 0;
+#pragma unroll
+    for (int i = 0; i < kBuildItems; ++i) {
+        const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+        if (e < un.rN) {
+            const uint32_t idx = un.rBeg + e;
+            const uint32_t k = (uint32_t)g.rk[idx];
+            const uint32_t r = g.rr ? (uint32_t)g.rr[idx] : idx;
+            v[i] = ((uint64_t)k << 32) | r;
+#pragma unroll
+            for (int c = 0; c < kEmptyCands; ++c) present |= (v[i] == empty_cand(c)) ? (1u << c) : 0u;
+        }
+    }
+    uint64_t empty = 0;
+    // Pick the first candidate marker absent from the chunk.  A chunk holding all candidates
+    // (possible only for adversarial input) moves on to the next batch of candidates.
+    for (int batch = 0;; ++batch) {
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        if (batch > 0) {
+            present = 0;
+#pragma unroll
+            for (int i = 0; i < kBuildItems; ++i) {
+                const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+                if (e < un.rN)
+#pragma unroll
+                    for (int c = 0; c < kEmptyCands; ++c)
+                        present |= (v[i] == empty_cand(batch * kEmptyCands + c)) ? (1u << c) : 0u;
+            }
+        }
+        // wave-level OR, then one LDS atomic per wave
+        uint32_t wor = present;
+        for (int c = 0; c < kEmptyCands; ++c)
+            wor |= ballot((present >> c) & 1u) ? (1u << c) : 0u;
+        if (lane_id() == 0 && wor) atomicOr(flag, wor);
+        __syncthreads();
+        const uint32_t f = *flag;
+        __syncthreads();  // every thread has read the flag before it is reset
+        if (f != (1u << kEmptyCands) - 1) {
+            empty = empty_cand(batch * kEmptyCands + __builtin_ctz(~f));
+            break;
+        }
+    }
+    for (uint32_t s = tid; s < C; s += kJoinBlock) tab[s] = empty;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kBuildItems; ++i) {
+        const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+        if (e < un.rN) {
+            uint64_t x = v[i];
+            uint32_t pos = home_of(hmix((uint32_t)(x >> 32)), g.bits, C);
+            while (true) {
+                const uint64_t c = tab[pos];
+                if (c == empty) {
+                    if (atomicCAS((unsigned long long*)&tab[pos], (unsigned long long)empty,
+                                  (unsigned long long)x) == empty)
+                        break;
+                    continue;  // lost the race: look at this slot again
+                }
+                if (c <= x) {
+                    pos = pos + 1 == C ? 0 : pos + 1;
+                    continue;
+                }
+                // x goes before c: swap in x, carry c further along the run
+                if (atomicCAS((unsigned long long*)&tab[pos], (unsigned long long)c,
+                              (unsigned long long)x) == c) {
+                    x = c;
+                    pos = pos + 1 == C ? 0 : pos + 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return empty;
+}
+
+// Units of this join.  The device total never exceeds Umax (sum over partitions of
+// nRc * nSs <= P + nR / cap + nS / slice); the clamp keeps the counts array in bounds even so.
+__device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
+{
+    const uint32_t U = g.single ? g.Uhost : *g.Uptr;
+    return (int64_t)U < g.Umax ? U : (uint32_t)g.Umax;
+}
+
+__device__ __forceinline__ uint32_t table_slots(uint32_t rN)
+{
+    uint32_t c = 2 * rN;
+    c = (c + 63) & ~63u;
+    return c < 64 ? 64 : c;
+}
+
+__global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
+{
+    extern __shared__ uint64_t tab[];
+    __shared__ uint32_t flag;
+    __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
+    const uint32_t U = unit_total(g);
+    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+        const Unit un = decode_unit(g, u);
+        const uint32_t C = table_slots(un.rN);
+        const uint64_t empty = build_table(g, un, tab, C, &flag);
+        uint32_t cnt = 0;
+        for (uint32_t e = threadIdx.x; e < un.sN; e += kJoinBlock) {
+            const uint32_t x = (uint32_t)g.sk[un.sBeg + e];
+            uint32_t pos = home_of(hmix(x), g.bits, C);
+            while (true) {
+                const uint64_t c = tab[pos];
+                if (c == empty) break;
+                const uint32_t ck = (uint32_t)(c >> 32);
+                if (ck == x) ++cnt;
+                else if (ck > x) break;
+                pos = pos + 1 == C ? 0 : pos + 1;
+            }
+        }
+        uint32_t tot;
+        block_excl_scan<kJoinBlock>(cnt, wsum, &tot);
+        if (threadIdx.x == 0) counts[u] = tot;
+        __syncthreads();
+    }
+    // units past the device-side total must read as zero for the scan over Umax entries
+    for (int64_t i = (int64_t)U + (int64_t)blockIdx.x * kJoinBlock + threadIdx.x; i < g.Umax;
+         i += (int64_t)gridDim.x * kJoinBlock)
+        counts[i] = 0;
+}
+
+__global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
+                                                           const uint64_t* __restrict__ offsets,
+                                                           const uint64_t* __restrict__ total,
+                                                           int2* __restrict__ out, uint64_t cap)
+{
+    extern __shared__ uint64_t tab[];
+    __shared__ uint32_t flag;
+    __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
+    if (*total > cap) return;  // an output too small for the exact count receives nothing
+    const uint32_t U = unit_total(g);
+    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+        const Unit un = decode_unit(g, u);
+        const uint32_t C = table_slots(un.rN);
+        const uint64_t empty = build_table(g, un, tab, C, &flag);
+        uint64_t base = offsets[u];
+        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock) {
+            const uint32_t e = e0 + threadIdx.x;
+            const bool ok = e < un.sN;
+            const uint32_t idx = un.sBeg + e;
+            const uint32_t x = ok ? (uint32_t)g.sk[idx] : 0u;
+            const int32_t srid = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+            uint32_t m = 0;
+            int32_t r1 = 0, r2 = 0;
+            const uint32_t home = home_of(hmix(x), g.bits, C);
+            if (ok) {
+                uint32_t pos = home;
+                while (true) {
+                    const uint64_t c = tab[pos];
+                    if (c == empty) break;
+                    const uint32_t ck = (uint32_t)(c >> 32);
+                    if (ck == x) {
+                        if (m == 0) r1 = (int32_t)(uint32_t)c;
+                        else if (m == 1) r2 = (int32_t)(uint32_t)c;
+                        ++m;
+                    } else if (ck > x) {
+                        break;
+                    }
+                    pos = pos + 1 == C ? 0 : pos + 1;
+                }
+            }
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<kJoinBlock>(m, wsum, &tot);
+            const uint64_t slot = base + ex;
+            if (m >= 1 && slot < cap) out[slot] = make_int2(r1, srid);
+            if (m >= 2 && slot + 1 < cap) out[slot + 1] = make_int2(r2, srid);
+            if (m > 2) {  // more than two build matches: walk the run again for the rest
+                uint32_t pos = home, seen = 0;
+                while (true) {
+                    const uint64_t c = tab[pos];
+                    if (c == empty) break;
+                    const uint32_t ck = (uint32_t)(c >> 32);
+                    if (ck == x) {
+                        if (seen >= 2 && slot + seen < cap)
+                            out[slot + seen] = make_int2((int32_t)(uint32_t)c, srid);
+                        ++seen;
+                    } else if (ck > x) {
+                        break;
+                    }
+                    pos = pos + 1 == C ? 0 : pos + 1;
+                }
+            }
+            base += tot;
+        }
+        __syncthreads();
+    }
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+static int env_int(const char* name, int dflt)
+{
+    const char* s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
+{
+    HashPlan pl{};
+    pl.nR = nR;
+    pl.nS = nS;
+    int cap = env_int("JOIN_HASH_CAP", 9216);
+    if (cap < 64) cap = 64;
+    if (cap > kJoinBlock * kBuildItems) cap = kJoinBlock * kBuildItems;
+    pl.cap = cap;
+    pl.slice = env_int("JOIN_HASH_SLICE", 32768);
+    if (pl.slice < 1024) pl.slice = 1024;
+    const int64_t single_max = (int64_t)env_int("JOIN_HASH_SINGLE_MAX_CHUNKS", 16) * cap;
+    const int forced_bits = env_int("JOIN_HASH_BITS", -1);
+    pl.single = forced_bits == 0 || (forced_bits < 0 && nR <= single_max);
+    size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
+    if (pl.single) {
+        pl.bits = 0;
+        pl.P = 1;
+        const int64_t nrc = nR > 0 ? ceil_div(nR, cap) : 0;
+        // S slices: enough units to cover the chip, each at least 1024 probes
+        int64_t nss = 1;
+        if (nR > 0 && nS > 0) {
+            const int64_t want = (int64_t)num_cus * 2;
+            nss = ceil_div(want, nrc);
+            const int64_t max_ss = ceil_div(nS, 1024);
+            if (nss > max_ss) nss = max_ss;
+            if (nss < 1) nss = 1;
+        }
+        pl.nSs = nss;
+        pl.Umax = (nR > 0 && nS > 0) ? nrc * nss : 0;
+    } else {
+        int bits = forced_bits;
+        if (bits < 0) {
+            // mean partition size ~ cap * 0.85 keeps the largest partitions under cap
+            const double target = cap * 0.85;
+            bits = 1;
+            while (bits < kMaxBits && (double)nR / (double)(1 << bits) > target) ++bits;
+        }
+        if (bits > kMaxBits) bits = kMaxBits;
+        pl.bits = bits;
+        pl.P = 1 << bits;
+        auto chunk_for = [&](int64_t n) {
+            int64_t c = ceil_div(n, (int64_t)num_cus * 4);
+            c = ceil_div(c, kScatTile) * kScatTile;
+            if (c < kScatTile) c = kScatTile;
+            if (c > 256 * 1024) c = 256 * 1024;
+            return c;
+        };
+        pl.chR = chunk_for(nR);
+        pl.chS = chunk_for(nS);
+        pl.nChR = nR > 0 ? ceil_div(nR, pl.chR) : 0;
+        pl.nChS = nS > 0 ? ceil_div(nS, pl.chS) : 0;
+        pl.Umax = pl.P + ceil_div(nR, cap) + ceil_div(nS, pl.slice) + 2;
+        pl.off_histR = off;
+        off = align_up(off + (size_t)pl.P * pl.nChR * 4);
+        pl.off_histS = off;
+        off = align_up(off + (size_t)pl.P * pl.nChS * 4);
+        pl.off_pkR = off;
+        off = align_up(off + (size_t)nR * 4);
+        pl.off_prR = off;
+        off = align_up(off + (size_t)nR * 4);
+        pl.off_pkS = off;
+        off = align_up(off + (size_t)nS * 4);
+        pl.off_prS = off;
+        off = align_up(off + (size_t)nS * 4);
+        pl.off_info = off;
+        off = align_up(off + (size_t)pl.P * sizeof(PartInfo));
+        pl.off_units = off;
+        off = align_up(off + (size_t)(pl.P + 1) * 4);
+    }
+    pl.off_counts = off;
+    off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
+    size_t temp = scan_temp_elems<uint64_t>(pl.Umax) * 8;
+    if (!pl.single) {
+        const size_t t1 = scan_temp_elems<uint32_t>((int64_t)pl.P * pl.nChR) * 4;
+        const size_t t2 = scan_temp_elems<uint32_t>((int64_t)pl.P * pl.nChS) * 4;
+        const size_t t3 = scan_temp_elems<uint32_t>(pl.P + 1) * 4;
+        temp = temp > t1 ? temp : t1;
+        temp = temp > t2 ? temp : t2;
+        temp = temp > t3 ? temp : t3;
+    }
+    pl.off_temp = off;
+    off = align_up(off + temp + 8);
+    pl.bytes = off;
+    // persistent grid of the join kernels: one workgroup per CU (the table fills most of LDS)
+    pl.joinGrid = num_cus;
+    return pl;
+}
+
+static size_t scatter_lds(int P) { return (size_t)(2 * P + 1) * 4 + (size_t)kScatTile * 10; }
+static size_t join_lds(uint32_t cap) { return (size_t)2 * ((cap * 2 + 63) & ~63u) * 4 + 64; }
+
+static bool g_attr_done = false;
+
+static hipError_t set_attrs()
+{
+    if (g_attr_done) return hipSuccess;
+    const int big = 160 * 1024 - 4096;
+    hipError_t e;
+    e = hipFuncSetAttribute((const void*)scatter_k<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)scatter_k<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)scatter_k<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)scatter_k<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)hist_k<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)hist_k<false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)join_count_k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)join_write_k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    g_attr_done = true;
+    return hipSuccess;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+static hipError_t partition_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
+                                 uint32_t* hist, int32_t* outk, int32_t* outr, uint32_t* temp,
+                                 hipStream_t st)
+{
+    if (X.n <= 0) return hipSuccess;
+    const bool vec = aligned16(X.key) && (X.rid == nullptr || aligned16(X.rid));
+    const size_t hl = (size_t)pl.P * 4;
+    if (vec) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
+    else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = exclusive_scan<uint32_t>(hist, hist, (int64_t)pl.P * nCh, nullptr, temp, st);
+    if (e != hipSuccess) return e;
+    const size_t sl = scatter_lds(pl.P);
+    if (vec) {
+        if (X.rid) scatter_k<true, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+        else scatter_k<true, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+    } else {
+        if (X.rid) scatter_k<false, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+        else scatter_k<false, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+    }
+    return hipGetLastError();
+}
+
+static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws)
+{
+    JoinGeom g{};
+    g.bits = pl.bits;
+    g.cap = (uint32_t)pl.cap;
+    g.Umax = pl.Umax;
+    if (pl.single) {
+        g.single = 1;
+        g.rk = R.key;
+        g.rr = R.rid;
+        g.sk = S.key;
+        g.sr = S.rid;
+        g.one.rStart = 0;
+        g.one.nR = (uint32_t)R.n;
+        g.one.sStart = 0;
+        g.one.nS = (uint32_t)S.n;
+        g.one.nSs = (uint32_t)pl.nSs;
+        g.one.nRc = (uint32_t)ceil_div(R.n, pl.cap);
+        g.Uhost = (uint32_t)pl.Umax;
+        g.P = 1;
+    } else {
+        g.single = 0;
+        g.rk = reinterpret_cast<const int32_t*>(ws + pl.off_pkR);
+        g.rr = reinterpret_cast<const int32_t*>(ws + pl.off_prR);
+        g.sk = reinterpret_cast<const int32_t*>(ws + pl.off_pkS);
+        g.sr = reinterpret_cast<const int32_t*>(ws + pl.off_prS);
+        g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);
+        g.unitStart = reinterpret_cast<const uint32_t*>(ws + pl.off_units);
+        g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
+        g.P = pl.P;
+    }
+    return g;
+}
+
+hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                      hipStream_t st)
+{
+    hipError_t e = set_attrs();
+    if (e != hipSuccess) return e;
+    uint64_t* total = reinterpret_cast<uint64_t*>(ws);
+    uint64_t* counts = reinterpret_cast<uint64_t*>(ws + pl.off_counts);
+    char* temp = ws + pl.off_temp;
+    if (!pl.single) {
+        uint32_t* histR = reinterpret_cast<uint32_t*>(ws + pl.off_histR);
+        uint32_t* histS = reinterpret_cast<uint32_t*>(ws + pl.off_histS);
+        e = partition_side(pl, R, pl.chR, pl.nChR, histR, reinterpret_cast<int32_t*>(ws + pl.off_pkR),
+                           reinterpret_cast<int32_t*>(ws + pl.off_prR), reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+        e = partition_side(pl, S, pl.chS, pl.nChS, histS, reinterpret_cast<int32_t*>(ws + pl.off_pkS),
+                           reinterpret_cast<int32_t*>(ws + pl.off_prS), reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+        uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
+        plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
+            histR, histS, pl.nChR, pl.nChS, pl.P, (uint32_t)R.n, (uint32_t)S.n, (uint32_t)pl.cap,
+            (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = exclusive_scan<uint32_t>(units, units, pl.P + 1, reinterpret_cast<uint32_t*>(ws + 8),
+                                     reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+    }
+    if (pl.Umax > 0) {
+        const JoinGeom g = make_geom(pl, R, S, ws);
+        const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+        join_count_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return exclusive_scan<uint64_t>(counts, counts, pl.Umax, total, reinterpret_cast<uint64_t*>(temp), st);
+}
+
+hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                      int32_t* pairs, uint64_t cap, hipStream_t st)
+{
+    if (pl.Umax <= 0) return hipSuccess;
+    hipError_t e = set_attrs();
+    if (e != hipSuccess) return e;
+    const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
+    const JoinGeom g = make_geom(pl, R, S, ws);
+    const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+    join_write_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(
+        g, offsets, reinterpret_cast<const uint64_t*>(ws), reinterpret_cast<int2*>(pairs), cap);
+    return hipGetLastError();
+}
+
+}  // namespace jl

@@ -1,0 +1,55 @@
+// hash.hpp -- partitioned hash equi join (histogram, scatter, LDS-table count and write).
+#pragma once
+#include "common.hpp"
+
+namespace jl {
+
+// One radix partition after the scatter: its R and S ranges in the partitioned columns and its
+// work-unit split (nRc R chunks that fit the LDS table, nSs S slices).
+struct PartInfo {
+    uint32_t rStart, nR, sStart, nS, nSs, nRc, pad0, pad1;
+};
+
+// Everything the count and write kernels need to walk the work units.
+struct JoinGeom {
+    const int32_t* rk;  // build keys (partitioned, or the input column when single)
+    const int32_t* rr;  // build rids; NULL means position (single only)
+    const int32_t* sk;
+    const int32_t* sr;
+    const PartInfo* part;       // [P]
+    const uint32_t* unitStart;  // [P + 1], exclusive scan of units per partition
+    const uint32_t* Uptr;       // device total of units
+    PartInfo one;               // the single partition when single != 0
+    uint32_t Uhost;             // units when single != 0
+    uint32_t cap;               // R chunk capacity (entries)
+    int64_t Umax;               // size of the counts array
+    int bits;                   // partition bits; the table position uses the bits below them
+    int P;
+    int single;
+};
+
+struct HashPlan {
+    int64_t nR, nS;
+    int single;  // 1: no partitioning, units = R chunks x S slices of the inputs themselves
+    int bits, P;
+    int cap, slice;
+    int64_t nSs;  // S slices (single)
+    int64_t chR, chS, nChR, nChS;
+    int64_t Umax;
+    int joinGrid;
+    size_t off_histR, off_histS, off_pkR, off_prR, off_pkS, off_prS, off_info, off_units;
+    size_t off_counts, off_temp, bytes;
+};
+
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus);
+
+// Histogram, scatter, planning, count pass and the scan of counts.  Leaves the exact total at
+// ws[0..8) and the per-unit offsets in ws.
+hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                      hipStream_t st);
+
+// Write pass from the state hash_count left in ws.
+hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                      int32_t* pairs, uint64_t cap, hipStream_t st);
+
+}  // namespace jl

@@ -1,0 +1,419 @@
+// theta.hip -- tiled nested-loop theta join on gfx950: count pass and write pass.
+//
+// The paper evaluates theta joins (and its nested-loop equi join) by giving each GPU thread a
+// rectangle of the |T| x |S| pair matrix (Section 3.3.1, equations NBS/NBT/IDS/IDT; Section
+// 4.2: the GPU theta join uses the same thread organisation).  Here the matrix is cut into
+// work units of (R block of 64*kRB rows) x (S tile of TS rows), one wave per unit:
+//   - each lane keeps kRB R rows in VGPRs (precomputed predicate constants),
+//   - S values are wave-uniform: loaded with scalar loads and used as SGPR operands,
+//   - one v_cmp per (S row, R row) produces a 64-lane mask in SGPRs.
+// Selective predicates (BAND, EQ) first OR the masks of the first condition over a group of 8
+// S rows; only a group with a hit is evaluated exactly (short-circuit AND).  Predicates that
+// hold for a large share of pairs are counted directly with per-lane counters.
+//
+// Both passes walk the same units in the same order, so the write pass fills exactly
+// [offset[u], offset[u] + count[u]) for each unit: the exact result size of Section 3.3.3
+// with no over-allocation.
+#include "theta.hpp"
+
+#include "scan.hpp"
+
+namespace jl {
+
+namespace {
+
+constexpr int kThetaBlock = 256;                    // 4 waves, one unit each
+constexpr int kWavesPerBlock = kThetaBlock / kWave;
+constexpr int kRB = 8;                              // R rows per lane
+constexpr int64_t kRowsPerWave = (int64_t)kWave * kRB;
+constexpr int kSGroup = 8;                          // S rows per scalar-load group
+
+struct ThetaGeom {
+    const int32_t* Ra;
+    const int32_t* Rc;
+    const int32_t* Rrid;
+    int64_t nR;
+    const int32_t* Sa;
+    const int32_t* Sc;
+    const int32_t* Srid;
+    int64_t nS;
+    int64_t w;
+    int64_t TS;   // S rows per tile
+    int64_t nSt;  // S tiles
+    int64_t U;    // units = R blocks * S tiles
+};
+
+// Per-R-row constants of op_a.  BAND keeps [lo, lo + wid] with lo = max(a - w, INT32_MIN),
+// hi = min(a + w, INT32_MAX), wid = hi - lo (< 2^32): s is in the band iff
+// (uint32)(s - lo) <= wid, exact for every int32 s (no wrap-around can land inside).
+template <int OP>
+__device__ __forceinline__ void prep_a(int32_t a, int64_t w, int32_t& x0, uint32_t& x1)
+{
+    if constexpr (OP == JOIN_OP_BAND) {
+        int64_t lo = (int64_t)a - w, hi = (int64_t)a + w;
+        lo = lo < INT32_MIN ? INT32_MIN : lo;
+        hi = hi > INT32_MAX ? INT32_MAX : hi;
+        x0 = (int32_t)lo;
+        x1 = (uint32_t)(hi - lo);
+    } else {
+        x0 = a;
+        x1 = 0;
+    }
+}
+
+// op(r, s) with r from R (per lane) and s from S (wave-uniform).
+template <int OP>
+__device__ __forceinline__ bool holds(int32_t x0, uint32_t x1, int32_t s)
+{
+    if constexpr (OP == JOIN_OP_NONE) return true;
+    if constexpr (OP == JOIN_OP_EQ) return x0 == s;
+    if constexpr (OP == JOIN_OP_NE) return x0 != s;
+    if constexpr (OP == JOIN_OP_LT) return x0 < s;
+    if constexpr (OP == JOIN_OP_LE) return x0 <= s;
+    if constexpr (OP == JOIN_OP_GT) return x0 > s;
+    if constexpr (OP == JOIN_OP_GE) return x0 >= s;
+    if constexpr (OP == JOIN_OP_BAND) return (uint32_t)(s - x0) <= x1;
+    return false;
+}
+
+template <int OPA>
+constexpr bool selective() { return OPA == JOIN_OP_BAND || OPA == JOIN_OP_EQ; }
+
+struct RRows {
+    int32_t x0[kRB];
+    uint32_t x1[kRB];
+    int32_t xc[kRB];
+};
+
+// A copy of the R constants the compiler cannot prove equal to the originals.  The rare exact
+// path of a selective group evaluates on this copy, so the 64 masks of the fast OR-filter die
+// right after the OR instead of being kept alive (and spilled) for reuse.
+__device__ __forceinline__ RRows opaque_copy(const RRows& a)
+{
+    RRows b = a;
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) asm volatile("" : "+v"(b.x0[r]), "+v"(b.x1[r]), "+v"(b.xc[r]));
+    return b;
+}
+
+template <int OPA, int OPC>
+__device__ __forceinline__ void load_r(const ThetaGeom& g, int64_t r0, int lane, RRows& rr)
+{
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+        const int64_t row = r0 + r * kWave + lane;
+        const bool valid = row < g.nR;
+        const int32_t a = valid ? g.Ra[row] : 0;
+        prep_a<OPA>(a, g.w, rr.x0[r], rr.x1[r]);
+        if constexpr (OPC != JOIN_OP_NONE) rr.xc[r] = valid ? g.Rc[row] : 0;
+        else rr.xc[r] = 0;
+    }
+}
+
+__device__ __forceinline__ void unit_of(const ThetaGeom& g, int64_t u, int64_t& r0, int64_t& s0,
+                                        int64_t& s1)
+{
+    const int64_t rb = u / g.nSt;
+    const int64_t st = u - rb * g.nSt;
+    r0 = rb * kRowsPerWave;
+    s0 = st * g.TS;
+    s1 = s0 + g.TS < g.nS ? s0 + g.TS : g.nS;
+}
+
+// ------------------------------------------------------------------------------- count pass --
+template <int OPA, int OPC>
+__global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
+                                                             uint64_t* __restrict__ counts)
+{
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
+    if (u >= g.U) return;
+    const int lane = (int)lane_id();
+    int64_t r0, s0, s1;
+    unit_of(g, u, r0, s0, s1);
+    RRows rr;
+    load_r<OPA, OPC>(g, r0, lane, rr);
+    const cptr<int32_t> Sa = as_const(g.Sa);
+    const cptr<int32_t> Sc = as_const(g.Sc);
+
+    uint32_t cnt[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) cnt[r] = 0;
+
+    int64_t j = s0;
+    if constexpr (selective<OPA>()) {
+        for (; j + kSGroup <= s1; j += kSGroup) {
+            int32_t sa[kSGroup];
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
+            uint64_t any = 0;
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+                for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
+            if (any) {
+                const RRows q = opaque_copy(rr);
+#pragma unroll
+                for (int k = 0; k < kSGroup; ++k) {
+                    const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+#pragma unroll
+                    for (int r = 0; r < kRB; ++r)
+                        cnt[r] += (holds<OPA>(q.x0[r], q.x1[r], sa[k]) &&
+                                   holds<OPC>(q.xc[r], 0u, sc)) ? 1u : 0u;
+                }
+            }
+        }
+    } else {
+        for (; j + kSGroup <= s1; j += kSGroup) {
+            int32_t sa[kSGroup], sc[kSGroup];
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k) {
+                sa[k] = Sa[j + k];
+                sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+                for (int r = 0; r < kRB; ++r)
+                    cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa[k]) &&
+                               holds<OPC>(rr.xc[r], 0u, sc[k])) ? 1u : 0u;
+        }
+    }
+    for (; j < s1; ++j) {
+        const int32_t sa = Sa[j];
+        const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+#pragma unroll
+        for (int r = 0; r < kRB; ++r)
+            cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) ? 1u : 0u;
+    }
+
+    // Lanes past the end of R carry garbage counts: only valid rows are summed.
+    uint64_t mine = 0;
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) mine += (r0 + r * kWave + lane < g.nR) ? (uint64_t)cnt[r] : 0ull;
+    const uint64_t tot = wave_sum64(mine);
+    if (lane == 0) counts[u] = tot;
+}
+
+// ------------------------------------------------------------------------------- write pass --
+template <int OPA, int OPC>
+__device__ __forceinline__ void emit_row(const RRows& rr, const int32_t (&rid)[kRB],
+                                         const uint64_t (&vm)[kRB], int32_t sa, int32_t sc,
+                                         int32_t srid, uint64_t& base, int2* __restrict__ out,
+                                         uint64_t cap, int lane)
+{
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+        const uint64_t m =
+            ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) & vm[r];
+        if (m) {
+            if ((m >> lane) & 1ull) {
+                const uint64_t slot = base + mask_rank(m);
+                if (slot < cap) out[slot] = make_int2(rid[r], srid);
+            }
+            base += (uint64_t)__popcll(m);
+        }
+    }
+}
+
+template <int OPA, int OPC>
+__global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
+                                                             const uint64_t* __restrict__ offsets,
+                                                             const uint64_t* __restrict__ total,
+                                                             int2* __restrict__ out, uint64_t cap)
+{
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
+    if (u >= g.U) return;
+    if (*total > cap) return;  // an output too small for the exact count receives nothing
+    const int lane = (int)lane_id();
+    int64_t r0, s0, s1;
+    unit_of(g, u, r0, s0, s1);
+    RRows rr;
+    load_r<OPA, OPC>(g, r0, lane, rr);
+    int32_t rid[kRB];
+    uint64_t vm[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+        const int64_t row = r0 + r * kWave + lane;
+        const bool valid = row < g.nR;
+        rid[r] = valid ? (g.Rrid ? g.Rrid[row] : (int32_t)row) : 0;
+        vm[r] = ballot(valid);
+    }
+    uint64_t base = uniform(offsets[u]);
+    const cptr<int32_t> Sa = as_const(g.Sa);
+    const cptr<int32_t> Sc = as_const(g.Sc);
+    const cptr<int32_t> Srid = as_const(g.Srid);
+
+    int64_t j = s0;
+    if constexpr (selective<OPA>()) {
+        for (; j + kSGroup <= s1; j += kSGroup) {
+            int32_t sa[kSGroup];
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
+            uint64_t any = 0;
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+                for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
+            if (any) {
+                const RRows q = opaque_copy(rr);
+                for (int k = 0; k < kSGroup; ++k) {
+                    const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+                    const int32_t srid = Srid ? Srid[j + k] : (int32_t)(j + k);
+                    emit_row<OPA, OPC>(q, rid, vm, sa[k], sc, srid, base, out, cap, lane);
+                }
+            }
+        }
+    }
+    for (; j < s1; ++j) {
+        const int32_t sa = Sa[j];
+        const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+        const int32_t srid = Srid ? Srid[j] : (int32_t)j;
+        emit_row<OPA, OPC>(rr, rid, vm, sa, sc, srid, base, out, cap, lane);
+    }
+}
+
+// ------------------------------------------------------------------------------ dispatching --
+using CountFn = void (*)(ThetaGeom, uint64_t*);
+using WriteFn = void (*)(ThetaGeom, const uint64_t*, const uint64_t*, int2*, uint64_t);
+
+template <int OPA>
+struct Table {
+    static CountFn count(int opc)
+    {
+        switch (opc) {
+        case JOIN_OP_NONE: return theta_count_k<OPA, JOIN_OP_NONE>;
+        case JOIN_OP_EQ: return theta_count_k<OPA, JOIN_OP_EQ>;
+        case JOIN_OP_NE: return theta_count_k<OPA, JOIN_OP_NE>;
+        case JOIN_OP_LT: return theta_count_k<OPA, JOIN_OP_LT>;
+        case JOIN_OP_LE: return theta_count_k<OPA, JOIN_OP_LE>;
+        case JOIN_OP_GT: return theta_count_k<OPA, JOIN_OP_GT>;
+        case JOIN_OP_GE: return theta_count_k<OPA, JOIN_OP_GE>;
+        default: return nullptr;
+        }
+    }
+    static WriteFn write(int opc)
+    {
+        switch (opc) {
+        case JOIN_OP_NONE: return theta_write_k<OPA, JOIN_OP_NONE>;
+        case JOIN_OP_EQ: return theta_write_k<OPA, JOIN_OP_EQ>;
+        case JOIN_OP_NE: return theta_write_k<OPA, JOIN_OP_NE>;
+        case JOIN_OP_LT: return theta_write_k<OPA, JOIN_OP_LT>;
+        case JOIN_OP_LE: return theta_write_k<OPA, JOIN_OP_LE>;
+        case JOIN_OP_GT: return theta_write_k<OPA, JOIN_OP_GT>;
+        case JOIN_OP_GE: return theta_write_k<OPA, JOIN_OP_GE>;
+        default: return nullptr;
+        }
+    }
+};
+
+CountFn count_fn(int opa, int opc)
+{
+    switch (opa) {
+    case JOIN_OP_EQ: return Table<JOIN_OP_EQ>::count(opc);
+    case JOIN_OP_NE: return Table<JOIN_OP_NE>::count(opc);
+    case JOIN_OP_LT: return Table<JOIN_OP_LT>::count(opc);
+    case JOIN_OP_LE: return Table<JOIN_OP_LE>::count(opc);
+    case JOIN_OP_GT: return Table<JOIN_OP_GT>::count(opc);
+    case JOIN_OP_GE: return Table<JOIN_OP_GE>::count(opc);
+    case JOIN_OP_BAND: return Table<JOIN_OP_BAND>::count(opc);
+    default: return nullptr;
+    }
+}
+
+WriteFn write_fn(int opa, int opc)
+{
+    switch (opa) {
+    case JOIN_OP_EQ: return Table<JOIN_OP_EQ>::write(opc);
+    case JOIN_OP_NE: return Table<JOIN_OP_NE>::write(opc);
+    case JOIN_OP_LT: return Table<JOIN_OP_LT>::write(opc);
+    case JOIN_OP_LE: return Table<JOIN_OP_LE>::write(opc);
+    case JOIN_OP_GT: return Table<JOIN_OP_GT>::write(opc);
+    case JOIN_OP_GE: return Table<JOIN_OP_GE>::write(opc);
+    case JOIN_OP_BAND: return Table<JOIN_OP_BAND>::write(opc);
+    default: return nullptr;
+    }
+}
+
+ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, const join_pred_t& p)
+{
+    ThetaGeom g;
+    g.Ra = R.key;
+    g.Rc = R.key2;
+    g.Rrid = R.rid;
+    g.nR = R.n;
+    g.Sa = S.key;
+    g.Sc = S.key2;
+    g.Srid = S.rid;
+    g.nS = S.n;
+    g.w = p.op_a == JOIN_OP_BAND ? (int64_t)p.w : 0;
+    g.TS = pl.TS;
+    g.nSt = pl.nSt;
+    g.U = pl.U;
+    return g;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+ThetaPlan theta_plan(int64_t nR, int64_t nS, int64_t target_waves, int64_t ts_override)
+{
+    ThetaPlan pl{};
+    const int64_t nRb = nR > 0 ? ceil_div(nR, kRowsPerWave) : 0;
+    int64_t TS;
+    if (ts_override > 0) {
+        TS = ts_override;
+    } else {
+        int64_t nSt = nRb > 0 ? ceil_div(target_waves, nRb) : 1;
+        int64_t max_tiles = nS > 0 ? ceil_div(nS, 256) : 1;
+        if (nSt > max_tiles) nSt = max_tiles;
+        if (nSt < 1) nSt = 1;
+        TS = nS > 0 ? ceil_div(nS, nSt) : 1;
+    }
+    TS = ((TS + kSGroup - 1) / kSGroup) * kSGroup;
+    if (TS > (1ll << 24)) TS = 1ll << 24;  // per-lane uint32 counters hold kRB * TS
+    if (TS < kSGroup) TS = kSGroup;
+    pl.TS = TS;
+    pl.nSt = nS > 0 ? ceil_div(nS, TS) : 0;
+    pl.U = nRb * pl.nSt;
+    size_t off = 256;  // header: [0] total (uint64)
+    pl.off_counts = off;
+    off = align_up(off + (size_t)(pl.U > 0 ? pl.U : 1) * sizeof(uint64_t));
+    pl.off_temp = off;
+    off = align_up(off + scan_temp_elems<uint64_t>(pl.U) * sizeof(uint64_t) + 8);
+    pl.bytes = off;
+    return pl;
+}
+
+hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
+                       const join_pred_t& p, char* ws, hipStream_t st)
+{
+    uint64_t* total = reinterpret_cast<uint64_t*>(ws);
+    uint64_t* counts = reinterpret_cast<uint64_t*>(ws + pl.off_counts);
+    uint64_t* temp = reinterpret_cast<uint64_t*>(ws + pl.off_temp);
+    if (pl.U > 0) {
+        CountFn f = count_fn(p.op_a, p.op_c);
+        if (!f) return hipErrorInvalidValue;
+        const unsigned grid = (unsigned)ceil_div(pl.U, kWavesPerBlock);
+        hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p), counts);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return exclusive_scan<uint64_t>(counts, counts, pl.U, total, temp, st);
+}
+
+hipError_t theta_write(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
+                       const join_pred_t& p, char* ws, int32_t* pairs, uint64_t cap,
+                       hipStream_t st)
+{
+    if (pl.U <= 0) return hipSuccess;
+    const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
+    WriteFn f = write_fn(p.op_a, p.op_c);
+    if (!f) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)ceil_div(pl.U, kWavesPerBlock);
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p), offsets,
+                       reinterpret_cast<const uint64_t*>(ws), reinterpret_cast<int2*>(pairs), cap);
+    return hipGetLastError();
+}
+
+}  // namespace jl

@@ -1,0 +1,196 @@
+"""Python binding of libjoin: the same calls as include/join.h over torch device tensors.
+
+PyTorch provides device memory and the stream; every step of the join runs in libjoin's HIP
+kernels.  Typical use (the exact-size flow of count -> scan -> write):
+
+    R = Relation(key_r)                 # int32 cuda tensors (key2 / rid optional)
+    S = Relation(key_s)
+    pairs = hash_join(R, S)             # [count, 2] int32: (rid_R, rid_S)
+
+or step by step:
+
+    ws = workspace(JOIN_KIND_HASH, R.n, S.n)
+    n = join_count(JOIN_KIND_HASH, R, S, None, ws)
+    out = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    join_materialize(JOIN_KIND_HASH, R, S, None, ws, out)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _native
+from ._native import JOIN_KIND_HASH, JOIN_KIND_THETA, OPS, JoinPred, JoinRel
+
+__all__ = [
+    "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "join_workspace_bytes",
+    "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
+    "hash_join", "theta_join",
+]
+
+
+class JoinError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_native.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc: int):
+    if rc != _native.JOIN_OK:
+        raise JoinError(rc, _native.last_error())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.int32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("join columns must be contiguous int32 cuda tensors")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+
+
+@dataclasses.dataclass
+class Relation:
+    """One relation in column layout: key (or theta column a), optional key2 (theta column c)
+    and optional rid payload (absent = row position).  Device tensors."""
+    key: torch.Tensor
+    key2: torch.Tensor | None = None
+    rid: torch.Tensor | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.key.numel())
+
+    def c(self) -> JoinRel:
+        for t in (self.key2, self.rid):
+            if t is not None and t.numel() != self.key.numel():
+                raise ValueError("all columns of a relation need the same length")
+        return JoinRel(_ptr(self.key), _ptr(self.key2), _ptr(self.rid), self.n)
+
+
+@dataclasses.dataclass
+class Pred:
+    """Theta predicate op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; op names as in OPS."""
+    op_a: str = "eq"
+    w: int = 0
+    op_c: str = "none"
+
+    def c(self) -> JoinPred:
+        return JoinPred(OPS[self.op_a], int(self.w), OPS[self.op_c])
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _pred_ptr(pred):
+    return None if pred is None else ctypes.byref(pred.c())
+
+
+def join_workspace_bytes(kind: int, nR: int, nS: int, pred: Pred | None = None) -> int:
+    return int(_native.lib.join_workspace_bytes(kind, nR, nS, _pred_ptr(pred)))
+
+
+def workspace(kind: int, nR: int, nS: int, pred: Pred | None = None, device="cuda"):
+    """A uint8 device tensor large enough for a join of this kind and these sizes."""
+    return torch.empty(join_workspace_bytes(kind, nR, nS, pred), dtype=torch.uint8, device=device)
+
+
+def join_count(kind: int, R: Relation, S: Relation, pred: Pred | None, ws: torch.Tensor,
+               stream=None) -> int:
+    """Exact number of output pairs (count pass + device scan; one 8-byte host read)."""
+    cnt = ctypes.c_uint64(0)
+    rr, sr = R.c(), S.c()
+    _check(_native.lib.join_count(kind, ctypes.byref(rr), ctypes.byref(sr), _pred_ptr(pred),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                  ctypes.byref(cnt)))
+    return int(cnt.value)
+
+
+def join_materialize(kind: int, R: Relation, S: Relation, pred: Pred | None, ws: torch.Tensor,
+                     pairs: torch.Tensor, stream=None) -> None:
+    """Write pass into pairs ([capacity, 2] int32) from the state join_count left in ws."""
+    if pairs.dtype != torch.int32 or not pairs.is_contiguous():
+        raise ValueError("pairs must be a contiguous int32 tensor")
+    rr, sr = R.c(), S.c()
+    cap = pairs.numel() // 2
+    _check(_native.lib.join_materialize(kind, ctypes.byref(rr), ctypes.byref(sr), _pred_ptr(pred),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap,
+                                        _stream(stream)))
+
+
+def join_hash(R: Relation, S: Relation, ws: torch.Tensor, pairs: torch.Tensor | None,
+              stream=None) -> int:
+    """One-shot equi join with snprintf semantics: returns the exact count; writes only if
+    pairs holds at least that many pairs (else raises JoinError with JOIN_E_CAPACITY)."""
+    cnt = ctypes.c_uint64(0)
+    rr, sr = R.c(), S.c()
+    cap = 0 if pairs is None else pairs.numel() // 2
+    rc = _native.lib.join_hash(ctypes.byref(rr), ctypes.byref(sr), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap,
+                               ctypes.byref(cnt), _stream(stream))
+    if rc == _native.JOIN_E_CAPACITY:
+        err = JoinError(rc, _native.last_error())
+        err.count = int(cnt.value)
+        raise err
+    _check(rc)
+    return int(cnt.value)
+
+
+def join_theta(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor,
+               pairs: torch.Tensor | None, stream=None) -> int:
+    """One-shot theta join with snprintf semantics (see join_hash)."""
+    cnt = ctypes.c_uint64(0)
+    rr, sr = R.c(), S.c()
+    cap = 0 if pairs is None else pairs.numel() // 2
+    rc = _native.lib.join_theta(ctypes.byref(rr), ctypes.byref(sr), ctypes.byref(pred.c()),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap,
+                                ctypes.byref(cnt), _stream(stream))
+    if rc == _native.JOIN_E_CAPACITY:
+        err = JoinError(rc, _native.last_error())
+        err.count = int(cnt.value)
+        raise err
+    _check(rc)
+    return int(cnt.value)
+
+
+def join_scan_u64(x: torch.Tensor, stream=None):
+    """Device exclusive prefix sum of a uint64 (int64-typed) cuda tensor: (out, total)."""
+    if x.dtype not in (torch.int64, torch.uint64) or not x.is_contiguous():
+        raise ValueError("scan input must be a contiguous 64-bit tensor")
+    n = x.numel()
+    out = torch.empty_like(x)
+    total = torch.empty(1, dtype=x.dtype, device=x.device)
+    ws = torch.empty(int(_native.lib.join_scan_workspace_bytes(n)), dtype=torch.uint8,
+                     device=x.device)
+    _check(_native.lib.join_scan_u64(ctypes.c_void_p(x.data_ptr()) if n else None,
+                                     ctypes.c_void_p(out.data_ptr()) if n else None, n,
+                                     ctypes.c_void_p(total.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return out, total
+
+
+def _exact(kind, R, S, pred, ws, stream):
+    if ws is None:
+        ws = workspace(kind, R.n, S.n, pred, device=R.key.device)
+    n = join_count(kind, R, S, pred, ws, stream)
+    out = torch.empty((n, 2), dtype=torch.int32, device=R.key.device)
+    join_materialize(kind, R, S, pred, ws, out, stream)
+    return out
+
+
+def hash_join(R: Relation, S: Relation, ws: torch.Tensor | None = None, stream=None):
+    """Equi join R.key = S.key; returns the exact-size [count, 2] int32 tensor of (rid_R, rid_S)."""
+    return _exact(JOIN_KIND_HASH, R, S, None, ws, stream)
+
+
+def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = None, stream=None):
+    """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output."""
+    return _exact(JOIN_KIND_THETA, R, S, pred, ws, stream)

@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol include/join.h
+declares, sizes workspaces, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "join.h")
+
+n = pytest.importorskip("paper_1904_11201_amd._native",
+                        reason="libjoin.so not built (python -m paper_1904_11201_amd.build)")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(join_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    decl = declared_functions()
+    assert set(decl) == set(n.EXPORTS), decl
+    lib = ctypes.CDLL(n.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_workspace_sizes():
+    assert n.lib.join_workspace_bytes(0, 10, 10, None) == 0
+    assert n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, -1, 10, None) == 0
+    small = n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, 1 << 16, 1 << 16, None)
+    big = n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, 1 << 24, 1 << 26, None)
+    assert 0 < small < big
+    # the partitioned layout holds both sides' key and rid columns
+    assert big >= 4 * 2 * ((1 << 24) + (1 << 26))
+    assert n.lib.join_workspace_bytes(n.JOIN_KIND_THETA, 1 << 20, 1 << 20, None) > 0
+    assert n.lib.join_scan_workspace_bytes(0) > 0
+    assert n.lib.join_scan_workspace_bytes(-1) == 0
+
+
+def _rel(ptr, nrows):
+    return n.JoinRel(ptr, None, None, nrows)
+
+
+def _count(kind, R, S, pred=None, ws=None, ws_bytes=0):
+    c = ctypes.c_uint64(7)
+    rc = n.lib.join_count(kind, ctypes.byref(R), ctypes.byref(S),
+                          ctypes.byref(pred) if pred is not None else None, ws, ws_bytes, None,
+                          ctypes.byref(c))
+    return rc, c.value
+
+
+def test_argument_errors():
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ok = _rel(fake, 10)
+    assert _count(9, ok, ok)[0] == n.JOIN_E_INVAL
+    assert _count(n.JOIN_KIND_HASH, _rel(fake, -3), ok)[0] == n.JOIN_E_INVAL
+    assert _count(n.JOIN_KIND_HASH, _rel(None, 5), ok)[0] == n.JOIN_E_INVAL
+    assert _count(n.JOIN_KIND_HASH, _rel(fake, 1 << 31), ok)[0] == n.JOIN_E_UNSUPPORTED
+    assert _count(n.JOIN_KIND_THETA, ok, ok, None)[0] == n.JOIN_E_INVAL
+    bad = [n.JoinPred(0, 0, 0), n.JoinPred(8, 0, 0), n.JoinPred(3, 0, 7), n.JoinPred(7, -1, 0),
+           n.JoinPred(3, 0, -1)]
+    for p in bad:
+        assert _count(n.JOIN_KIND_THETA, ok, ok, p)[0] == n.JOIN_E_INVAL, (p.op_a, p.w, p.op_c)
+    # a condition on column c needs key2 on both sides
+    assert _count(n.JOIN_KIND_THETA, ok, ok, n.JoinPred(3, 0, 3))[0] == n.JOIN_E_INVAL
+    # workspace missing or too small
+    assert _count(n.JOIN_KIND_HASH, ok, ok)[0] == n.JOIN_E_WORKSPACE
+    assert _count(n.JOIN_KIND_HASH, ok, ok, ws=fake, ws_bytes=8)[0] == n.JOIN_E_WORKSPACE
+    assert "workspace" in n.last_error()
+    # count pointer is required
+    rc = n.lib.join_count(n.JOIN_KIND_HASH, ctypes.byref(ok), ctypes.byref(ok), None, fake, 1 << 30,
+                          None, None)
+    assert rc == n.JOIN_E_INVAL
+    # scan primitive
+    assert n.lib.join_scan_u64(None, None, -1, None, fake, 1 << 20, None) == n.JOIN_E_INVAL
+    assert n.lib.join_scan_u64(fake, fake, 10, None, None, 0, None) == n.JOIN_E_WORKSPACE
+
+
+def test_empty_relations_need_no_device():
+    """An empty side has an exact count of 0 without any kernel launch."""
+    fake = ctypes.c_void_p(0x1000)
+    ws_bytes = n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, 0, 10, None)
+    rc, c = _count(n.JOIN_KIND_HASH, _rel(None, 0), _rel(fake, 10), ws=fake, ws_bytes=ws_bytes)
+    assert rc == n.JOIN_OK and c == 0
+    p = n.JoinPred(n.OPS["lt"], 0, 0)
+    ws_bytes = n.lib.join_workspace_bytes(n.JOIN_KIND_THETA, 10, 0, None)
+    rc, c = _count(n.JOIN_KIND_THETA, _rel(fake, 10), _rel(None, 0), p, ws=fake, ws_bytes=ws_bytes)
+    assert rc == n.JOIN_OK and c == 0
