@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""Benchmark of the join hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic input, every input
+already resident in HBM:
+  * hash equi join 16M x 64M, S keys uniform over R's keys   (histogram, scan, scatter, plan,
+    LDS-table count, scan, exact allocation, write)
+  * the same with S keys bounded-Zipf(1.0)
+  * band theta join 1M x 1M, |R.a - S.a| <= 8 and R.c < S.c    (count, scan, exact allocation,
+    write)
+`value` is probe tuples/s of the two hash joins (2 * 2^26 probe tuples over their summed time
+inside the timed steps); the theta and latency figures ride along in their own fields.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("probe tuples/s + output pairs/s (16M⋈64M hash join, 1M×1M theta); "
+          "p99 latency")
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+M = 1 << 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-runs", type=int, default=200)
+    return ap.parse_args()
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1904_11201_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries (profiles/traffic.json),
+    valid only for the kernel sources they were taken on."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return {}
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("src_hash") != src_hash():
+        return {}
+    return t.get("kernels", {})
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is a design in DESIGN.md, not a measured path)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_11201_amd import _native, datagen
+    from paper_1904_11201_amd import join as J
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    def d(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(dev)
+
+    def rel(r):
+        return J.Relation(d(r.key), d(r.key2), d(r.rid))
+
+    t_gen = time.time()
+    Ru, Su, _ = datagen.large_equi(seed=2, zipf=False)
+    Rz, Sz, _ = datagen.large_equi(seed=3, zipf=True)
+    Rt, St = datagen.band_theta(seed=4, n=1 * M)
+    Rl, Sl = datagen.lt_theta(seed=5, n=64 * 1024)
+    Rc1, Sc1 = datagen.small_equi(seed=1)
+    dRu, dSu, dRz, dSz = rel(Ru), rel(Su), rel(Rz), rel(Sz)
+    dRt, dSt, dRl, dSl = rel(Rt), rel(St), rel(Rl), rel(Sl)
+    dRc1, dSc1 = rel(Rc1), rel(Sc1)
+    print(f"# inputs generated and resident in {time.time() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    nR, nS = Ru.n, Su.n
+    theta_pred = J.Pred("band", 8, "lt")
+    ws_h = J.workspace(J.JOIN_KIND_HASH, nR, nS)
+    ws_t = J.workspace(J.JOIN_KIND_THETA, Rt.n, St.n, theta_pred)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def run_join(kind, R, S, pred, ws):
+        a, b = ev(), ev()
+        a.record(stream)
+        n = J.join_count(kind, R, S, pred, ws, stream)
+        out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        J.join_materialize(kind, R, S, pred, ws, out, stream)
+        b.record(stream)
+        return n, out, (a, b)
+
+    def step():
+        hu = run_join(J.JOIN_KIND_HASH, dRu, dSu, None, ws_h)
+        hz = run_join(J.JOIN_KIND_HASH, dRz, dSz, None, ws_h)
+        th = run_join(J.JOIN_KIND_THETA, dRt, dSt, theta_pred, ws_t)
+        return hu, hz, th
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    _native.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = _native.prof_read()
+    _native.prof_enable(False)
+
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    hu_ms = [r[0][2][0].elapsed_time(r[0][2][1]) for r in recs]
+    hz_ms = [r[1][2][0].elapsed_time(r[1][2][1]) for r in recs]
+    th_ms = [r[2][2][0].elapsed_time(r[2][2][1]) for r in recs]
+    n_hu, n_hz, n_th = recs[-1][0][0], recs[-1][1][0], recs[-1][2][0]
+    assert n_hu == nS and n_hz == nS, "16M x 64M outputs must hold exactly |S| pairs"
+    del recs
+
+    hash_ms = statistics.mean(hu_ms) + statistics.mean(hz_ms)
+    probe_tps = 2 * nS / (hash_ms * 1e-3)
+    hash_pairs_ps = (n_hu + n_hz) / (hash_ms * 1e-3)
+    th_mean = statistics.mean(th_ms)
+    theta_pairs_eval_ps = Rt.n * St.n / (th_mean * 1e-3)
+
+    # count-only R.a < S.a, 64K x 64K (no write pass)
+    lt_pred = J.Pred("lt")
+    ws_l = J.workspace(J.JOIN_KIND_THETA, Rl.n, Sl.n, lt_pred)
+    lt_ms = []
+    for i in range(args.warmup + 20):
+        a, b = ev(), ev()
+        a.record(stream)
+        n_lt = J.join_count(J.JOIN_KIND_THETA, dRl, dSl, lt_pred, ws_l, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            lt_ms.append(a.elapsed_time(b))
+
+    # single-request latency of the small equi join (64K x 64K), host-observed, end to end
+    ws_c1 = J.workspace(J.JOIN_KIND_HASH, Rc1.n, Sc1.n)
+    lat = []
+    for i in range(args.latency_runs + 10):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        n_c1 = J.join_count(J.JOIN_KIND_HASH, dRc1, dSc1, None, ws_c1, stream)
+        out = torch.empty((n_c1, 2), dtype=torch.int32, device=dev)
+        J.join_materialize(J.JOIN_KIND_HASH, dRc1, dSc1, None, ws_c1, out, stream)
+        torch.cuda.synchronize()
+        if i >= 10:
+            lat.append((time.perf_counter() - s0) * 1e3)
+    lat.sort()
+
+    def pct(v, q):
+        return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+    # ---- per-kernel figures over the timed steps (HIP events on the launch stream) ----------
+    traffic = load_traffic()
+    pairs_band = Rt.n * St.n
+    alg = {
+        # algorithmic bytes per launch (HBM-bound kernels) or int32 lane-ops (ALU-bound)
+        "hash.hist.R": ("hbm", 4 * nR),
+        "hash.hist.S": ("hbm", 4 * nS),
+        "hash.scatter.R": ("hbm", 16 * nR),
+        "hash.scatter.S": ("hbm", 16 * nS),
+        "hash.count": ("hbm", 4 * nR + 4 * nS),
+        "hash.write": ("hbm", 8 * nR + 8 * nS + 8 * nS),
+        "theta.count": ("alu", 2 * pairs_band),
+        "theta.write": ("alu", 2 * pairs_band),
+    }
+    kernels = []
+    for name, (launches, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        avg = tot_ms / launches
+        k = {"name": name, "launches": launches, "avg_ms": round(avg, 4),
+             "share_of_step": round(tot_ms / args.steps / wall_ms, 4)}
+        if name in alg:
+            bound, work = alg[name]
+            per_launch = work
+            if bound == "hbm":
+                ach = per_launch / (avg * 1e-3) / 1e9
+                k.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach / HBM_PEAK_GBS, 4))
+            else:
+                ach = per_launch / (avg * 1e-3) / 1e12
+                k.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
+                         unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4))
+            t = traffic.get(name)
+            k["traffic"] = t
+        kernels.append(k)
+    dom = max((k for k in kernels if "bound" in k), key=lambda k: k["launches"] * k["avg_ms"])
+    roofline = {"kernel": dom["name"], "bound": dom["bound"], "achieved": dom["achieved"],
+                "peak": dom["peak"], "unit": dom["unit"], "frac": dom["frac"],
+                "traffic": dom.get("traffic")}
+    hash_kernels = [k for k in kernels if k["name"].startswith("hash.") and "bound" in k]
+    hash_dom = max(hash_kernels, key=lambda k: k["launches"] * k["avg_ms"]) if hash_kernels else None
+
+    # ---- CPU oracle on a bounded sample of the same workload --------------------------------
+    cpu = None
+    cpu_theta = None
+    if not args.no_cpu_baseline:
+        import oracle
+        samp = 8 * M
+        c0 = time.perf_counter()
+        oracle.equi_sortmerge(Ru.key, Su.key[:samp], Rrid=Ru.rid, Srid=Su.rid[:samp])
+        c1 = time.perf_counter()
+        cpu = {"value": round(samp / (c1 - c0), 1), "unit": "probe tuples/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"sort-merge oracle, all 16M R tuples x the first {samp} of the 64M "
+                         f"uniform S tuples, pairs materialised and sorted ({c1 - c0:.1f}s)"}
+        rows = 8192
+        thr = oracle.threads()
+        c0 = time.perf_counter()
+        oracle.theta_nlj(Rt.key[:rows], St.key, "band", w=8, Rc=Rt.key2[:rows], Sc=St.key2,
+                         op_c="lt", Rrid=Rt.rid[:rows], Srid=St.rid)
+        c1 = time.perf_counter()
+        cpu_theta = {"value": round(rows * St.n / (c1 - c0), 1), "unit": "pair evaluations/s",
+                     "cores": thr, "kind": "oracle",
+                     "sample": f"brute-force nested-loop oracle, {rows} R rows x all 1M S rows "
+                               f"({c1 - c0:.1f}s)"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(probe_tps, 1),
+        "unit": "probe tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "hash equi-join 16M x 64M (uniform and Zipf(1.0) S keys) + band theta "
+                        "join 1M x 1M (|R.a-S.a|<=8 and R.c<S.c)",
+            "R_rows": nR, "S_rows": nS, "theta_rows": Rt.n,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hash": {
+            "ms_uniform": round(statistics.mean(hu_ms), 4),
+            "ms_zipf": round(statistics.mean(hz_ms), 4),
+            "probe_tuples_per_s": round(probe_tps, 1),
+            "pairs_per_s": round(hash_pairs_ps, 1),
+            "p50_ms": round(statistics.median(hu_ms + hz_ms), 4),
+            "p99_ms": round(max(hu_ms + hz_ms), 4),
+            "roofline": hash_dom and {k: hash_dom[k] for k in
+                                      ("name", "bound", "achieved", "peak", "unit", "frac",
+                                       "traffic")},
+        },
+        "theta": {
+            "ms": round(th_mean, 3),
+            "pairs_out": n_th,
+            "pairs_per_s": round(n_th / (th_mean * 1e-3), 1),
+            "pair_evaluations_per_s": round(theta_pairs_eval_ps, 1),
+            "lt_count_64k_ms": round(statistics.median(lt_ms), 4),
+            "lt_count_64k_pair_evaluations_per_s": round(Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3), 1),
+            "lt_count_64k_frac_of_valu_peak": round(
+                2 * Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+            "lt_count_64k_count": n_lt,
+            "cpu_baseline": cpu_theta,
+        },
+        "latency": {"workload": "hash equi-join 64K x 64K, keys uniform in [0,16384), "
+                                "count + exact allocation + write, host-observed",
+                    "runs": len(lat), "p50_ms": round(pct(lat, 0.5), 4),
+                    "p99_ms": round(pct(lat, 0.99), 4), "pairs": n_c1},
+        "kernels": kernels,
+        "src_hash": src_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,9 +25,10 @@ JOIN_KIND_THETA = 2
 
 OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 7}
 
-# Every symbol include/join.h declares.
+# Every symbol include/*.h declares.
 EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash", "join_theta",
-           "join_last_error", "join_scan_workspace_bytes", "join_scan_u64")
+           "join_last_error", "join_scan_workspace_bytes", "join_scan_u64", "join_prof_enable",
+           "join_prof_collect", "join_prof_count", "join_prof_entry")
 
 
 class JoinRel(ctypes.Structure):
@@ -64,6 +65,15 @@ def _load():
     lib.join_scan_workspace_bytes.argtypes = [i64]
     lib.join_scan_u64.restype = ctypes.c_int
     lib.join_scan_u64.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    lib.join_prof_enable.restype = ctypes.c_int
+    lib.join_prof_enable.argtypes = [ctypes.c_int]
+    lib.join_prof_collect.restype = ctypes.c_int
+    lib.join_prof_collect.argtypes = []
+    lib.join_prof_count.restype = ctypes.c_int
+    lib.join_prof_count.argtypes = []
+    lib.join_prof_entry.restype = ctypes.c_int
+    lib.join_prof_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                    ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
     return lib
 
 
@@ -72,3 +82,21 @@ lib = _load()
 
 def last_error() -> str:
     return (lib.join_last_error() or b"").decode(errors="replace")
+
+
+def prof_enable(on: bool) -> None:
+    lib.join_prof_enable(1 if on else 0)
+
+
+def prof_read() -> dict:
+    """{kernel name: (launches, total_ms)} of the launches recorded since prof_enable(True)."""
+    if lib.join_prof_collect() != JOIN_OK:
+        raise RuntimeError(last_error())
+    out = {}
+    for i in range(lib.join_prof_count()):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        if lib.join_prof_entry(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)) == 0:
+            out[name.value.decode()] = (int(cnt.value), float(ms.value))
+    return out

@@ -56,6 +56,18 @@ int64_t theta_ts_override()
     return (s && *s) ? atoll(s) : 0;
 }
 
+int64_t theta_stash_k()
+{
+    const char* s = getenv("JOIN_THETA_STASH");
+    return (s && *s) ? atoll(s) : 128;
+}
+
+ThetaPlan plan_theta(int64_t nR, int64_t nS, const join_pred_t* p)
+{
+    return theta_plan(nR, nS, p ? p->op_a : JOIN_OP_NONE, theta_target_waves(), theta_ts_override(),
+                      theta_stash_k());
+}
+
 int check_rel(const join_rel_t* X, const char* name, bool need_key2)
 {
     if (!X) {
@@ -119,15 +131,16 @@ int check_args(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     return JOIN_OK;
 }
 
-size_t ws_needed(int kind, int64_t nR, int64_t nS)
+size_t ws_needed(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
 {
     if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).bytes;
-    return theta_plan(nR, nS, theta_target_waves(), theta_ts_override()).bytes;
+    return plan_theta(nR, nS, p).bytes;
 }
 
-int check_ws(int kind, const join_rel_t* R, const join_rel_t* S, void* ws, size_t ws_bytes)
+int check_ws(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
+             size_t ws_bytes)
 {
-    const size_t need = ws_needed(kind, R->n, S->n);
+    const size_t need = ws_needed(kind, R->n, S->n, p);
     if (!ws || ws_bytes < need) {
         set_error("workspace %p of %zu bytes is smaller than the %zu bytes this join needs", ws,
                   ws_bytes, need);
@@ -186,7 +199,7 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
             const HashPlan pl = hash_plan(R->n, S->n, num_cus());
             e = hash_count(pl, *R, *S, w, st);
         } else {
-            const ThetaPlan pl = theta_plan(R->n, S->n, theta_target_waves(), theta_ts_override());
+            const ThetaPlan pl = plan_theta(R->n, S->n, p);
             e = theta_count(pl, *R, *S, *p, w, st);
         }
         if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash count pass" : "theta count pass");
@@ -223,7 +236,7 @@ int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         const HashPlan pl = hash_plan(R->n, S->n, num_cus());
         e = hash_write(pl, *R, *S, w, pairs, capacity, st);
     } else {
-        const ThetaPlan pl = theta_plan(R->n, S->n, theta_target_waves(), theta_ts_override());
+        const ThetaPlan pl = plan_theta(R->n, S->n, p);
         e = theta_write(pl, *R, *S, *p, w, pairs, capacity, st);
     }
     if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash write pass" : "theta write pass");
@@ -236,9 +249,8 @@ extern "C" {
 
 size_t join_workspace_bytes(int kind, int64_t nR, int64_t nS, const join_pred_t* pred)
 {
-    (void)pred;
     if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA) || nR < 0 || nS < 0) return 0;
-    return ws_needed(kind, nR, nS);
+    return ws_needed(kind, nR, nS, pred);
 }
 
 int join_count(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred,
@@ -250,7 +262,7 @@ int join_count(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         set_error("count is NULL");
         return JOIN_E_INVAL;
     }
-    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    if ((rc = check_ws(kind, R, S, pred, ws, ws_bytes)) != JOIN_OK) return rc;
     return count_impl(kind, R, S, pred, ws, static_cast<hipStream_t>(stream), count);
 }
 
@@ -259,7 +271,7 @@ int join_materialize(int kind, const join_rel_t* R, const join_rel_t* S, const j
 {
     int rc = check_args(kind, R, S, pred);
     if (rc != JOIN_OK) return rc;
-    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    if ((rc = check_ws(kind, R, S, pred, ws, ws_bytes)) != JOIN_OK) return rc;
     if (matches_last(kind, R, S, pred, ws) && g_last.count > capacity) {
         set_error("capacity %llu is below the exact count %llu", (unsigned long long)capacity,
                   (unsigned long long)g_last.count);
@@ -278,7 +290,7 @@ static int one_shot(int kind, const join_rel_t* R, const join_rel_t* S, const jo
         set_error("count is NULL");
         return JOIN_E_INVAL;
     }
-    if ((rc = check_ws(kind, R, S, ws, ws_bytes)) != JOIN_OK) return rc;
+    if ((rc = check_ws(kind, R, S, pred, ws, ws_bytes)) != JOIN_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = count_impl(kind, R, S, pred, ws, st, count)) != JOIN_OK) return rc;
     if (*count > capacity) {

@@ -20,6 +20,7 @@
 // proven absent from the chunk, so every int32 key and rid value stays usable.
 #include "hash.hpp"
 
+#include "prof.hpp"
 #include "scan.hpp"
 
 namespace jl {
@@ -602,18 +603,22 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 static hipError_t partition_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
                                  uint32_t* hist, int32_t* outk, int32_t* outr, uint32_t* temp,
-                                 hipStream_t st)
+                                 hipStream_t st, bool is_r)
 {
     if (X.n <= 0) return hipSuccess;
     const bool vec = aligned16(X.key) && (X.rid == nullptr || aligned16(X.rid));
     const size_t hl = (size_t)pl.P * 4;
-    if (vec) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
-    else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
+    {
+        prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
+        if (vec) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
+        else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = exclusive_scan<uint32_t>(hist, hist, (int64_t)pl.P * nCh, nullptr, temp, st);
     if (e != hipSuccess) return e;
     const size_t sl = scatter_lds(pl.P);
+    prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
     if (vec) {
         if (X.rid) scatter_k<true, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
         else scatter_k<true, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
@@ -670,15 +675,18 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         uint32_t* histR = reinterpret_cast<uint32_t*>(ws + pl.off_histR);
         uint32_t* histS = reinterpret_cast<uint32_t*>(ws + pl.off_histS);
         e = partition_side(pl, R, pl.chR, pl.nChR, histR, reinterpret_cast<int32_t*>(ws + pl.off_pkR),
-                           reinterpret_cast<int32_t*>(ws + pl.off_prR), reinterpret_cast<uint32_t*>(temp), st);
+                           reinterpret_cast<int32_t*>(ws + pl.off_prR), reinterpret_cast<uint32_t*>(temp), st, true);
         if (e != hipSuccess) return e;
         e = partition_side(pl, S, pl.chS, pl.nChS, histS, reinterpret_cast<int32_t*>(ws + pl.off_pkS),
-                           reinterpret_cast<int32_t*>(ws + pl.off_prS), reinterpret_cast<uint32_t*>(temp), st);
+                           reinterpret_cast<int32_t*>(ws + pl.off_prS), reinterpret_cast<uint32_t*>(temp), st, false);
         if (e != hipSuccess) return e;
         uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
-        plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
-            histR, histS, pl.nChR, pl.nChS, pl.P, (uint32_t)R.n, (uint32_t)S.n, (uint32_t)pl.cap,
-            (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
+        {
+            prof::Scope pp(st, "hash.plan");
+            plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
+                histR, histS, pl.nChR, pl.nChS, pl.P, (uint32_t)R.n, (uint32_t)S.n, (uint32_t)pl.cap,
+                (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = exclusive_scan<uint32_t>(units, units, pl.P + 1, reinterpret_cast<uint32_t*>(ws + 8),
@@ -688,6 +696,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     if (pl.Umax > 0) {
         const JoinGeom g = make_geom(pl, R, S, ws);
         const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+        prof::Scope pc(st, "hash.count");
         join_count_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -704,6 +713,7 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
     const JoinGeom g = make_geom(pl, R, S, ws);
     const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+    prof::Scope pw(st, "hash.write");
     join_write_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(
         g, offsets, reinterpret_cast<const uint64_t*>(ws), reinterpret_cast<int2*>(pairs), cap);
     return hipGetLastError();

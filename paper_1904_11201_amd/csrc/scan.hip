@@ -7,6 +7,8 @@
 // sums, and a per-tile scan seeded with its prefix.  n <= one tile uses one launch.
 #include "scan.hpp"
 
+#include "prof.hpp"
+
 namespace jl {
 
 namespace {
@@ -120,6 +122,7 @@ template <typename T>
 hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* total, T* temp, hipStream_t st)
 {
     if (n < 0) n = 0;
+    prof::Scope ps(st, sizeof(T) == 8 ? "scan.u64" : "scan.u32");
     int64_t tiles = ceil_div(n, kScanTile);
     if (tiles <= 1) {  // also n == 0: writes *total = 0 without a memset node
         scan_single_k<T><<<1, kScanBlock, 0, st>>>(in, out, n, total);

@@ -16,6 +16,7 @@
 // with no over-allocation.
 #include "theta.hpp"
 
+#include "prof.hpp"
 #include "scan.hpp"
 
 namespace jl {
@@ -41,6 +42,8 @@ struct ThetaGeom {
     int64_t TS;   // S rows per tile
     int64_t nSt;  // S tiles
     int64_t U;    // units = R blocks * S tiles
+    int2* stash;  // [U][K] matches kept by the count pass (selective predicates), or NULL
+    int64_t K;
 };
 
 // Per-R-row constants of op_a.  BAND keeps [lo, lo + wid] with lo = max(a - w, INT32_MIN),
@@ -120,81 +123,9 @@ __device__ __forceinline__ void unit_of(const ThetaGeom& g, int64_t u, int64_t& 
     s1 = s0 + g.TS < g.nS ? s0 + g.TS : g.nS;
 }
 
-// ------------------------------------------------------------------------------- count pass --
-template <int OPA, int OPC>
-__global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
-                                                             uint64_t* __restrict__ counts)
-{
-    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
-    if (u >= g.U) return;
-    const int lane = (int)lane_id();
-    int64_t r0, s0, s1;
-    unit_of(g, u, r0, s0, s1);
-    RRows rr;
-    load_r<OPA, OPC>(g, r0, lane, rr);
-    const cptr<int32_t> Sa = as_const(g.Sa);
-    const cptr<int32_t> Sc = as_const(g.Sc);
-
-    uint32_t cnt[kRB];
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) cnt[r] = 0;
-
-    int64_t j = s0;
-    if constexpr (selective<OPA>()) {
-        for (; j + kSGroup <= s1; j += kSGroup) {
-            int32_t sa[kSGroup];
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
-            uint64_t any = 0;
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k)
-#pragma unroll
-                for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
-            if (any) {
-                const RRows q = opaque_copy(rr);
-#pragma unroll
-                for (int k = 0; k < kSGroup; ++k) {
-                    const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
-#pragma unroll
-                    for (int r = 0; r < kRB; ++r)
-                        cnt[r] += (holds<OPA>(q.x0[r], q.x1[r], sa[k]) &&
-                                   holds<OPC>(q.xc[r], 0u, sc)) ? 1u : 0u;
-                }
-            }
-        }
-    } else {
-        for (; j + kSGroup <= s1; j += kSGroup) {
-            int32_t sa[kSGroup], sc[kSGroup];
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k) {
-                sa[k] = Sa[j + k];
-                sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k)
-#pragma unroll
-                for (int r = 0; r < kRB; ++r)
-                    cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa[k]) &&
-                               holds<OPC>(rr.xc[r], 0u, sc[k])) ? 1u : 0u;
-        }
-    }
-    for (; j < s1; ++j) {
-        const int32_t sa = Sa[j];
-        const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
-#pragma unroll
-        for (int r = 0; r < kRB; ++r)
-            cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) ? 1u : 0u;
-    }
-
-    // Lanes past the end of R carry garbage counts: only valid rows are summed.
-    uint64_t mine = 0;
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) mine += (r0 + r * kWave + lane < g.nR) ? (uint64_t)cnt[r] : 0ull;
-    const uint64_t tot = wave_sum64(mine);
-    if (lane == 0) counts[u] = tot;
-}
-
-// ------------------------------------------------------------------------------- write pass --
+// Evaluate one S row against the wave's kRB R rows exactly and emit the matches in (r, lane)
+// order at base, base+1, ...: slots below `cap` are written to `out`, and base advances by the
+// number of matches either way (so a capacity-limited destination still counts exactly).
 template <int OPA, int OPC>
 __device__ __forceinline__ void emit_row(const RRows& rr, const int32_t (&rid)[kRB],
                                          const uint64_t (&vm)[kRB], int32_t sa, int32_t sc,
@@ -215,6 +146,130 @@ __device__ __forceinline__ void emit_row(const RRows& rr, const int32_t (&rid)[k
     }
 }
 
+__device__ __forceinline__ void load_rids(const ThetaGeom& g, int64_t r0, int lane,
+                                          int32_t (&rid)[kRB], uint64_t (&vm)[kRB])
+{
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+        const int64_t row = r0 + r * kWave + lane;
+        const bool valid = row < g.nR;
+        rid[r] = valid ? (g.Rrid ? g.Rrid[row] : (int32_t)row) : 0;
+        vm[r] = ballot(valid);
+    }
+}
+
+// Selective predicates: OR-filter 8 S rows at a time on op_a alone; a group with a hit is
+// evaluated exactly and its pairs go to `out` (capacity `cap`) starting at `base`.  The fast
+// filter keeps only op_a's two constants per R row live.  The rare exact path walks one R row
+// at a time and reloads that row's c value and rid (cache-resident), so it needs only a few
+// registers beyond the filter's and the filter keeps its occupancy.  Pairs of a group are
+// emitted in (R row r, S row j, lane) order.
+template <int OPA, int OPC>
+__device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows& rr, int64_t r0,
+                                                int64_t s0, int64_t s1, uint64_t& base,
+                                                int2* __restrict__ out, uint64_t cap, int lane)
+{
+    const cptr<int32_t> Sa = as_const(g.Sa);
+    const cptr<int32_t> Sc = as_const(g.Sc);
+    const cptr<int32_t> Srid = as_const(g.Srid);
+    auto exact = [&](int64_t jb, int64_t je) {
+        const RRows q = opaque_copy(rr);
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) {
+            const int64_t row = r0 + r * kWave + lane;
+            const bool valid = row < g.nR;
+            const uint64_t vm = ballot(valid);
+            if (!vm) continue;
+            const int32_t xc = (OPC != JOIN_OP_NONE && valid) ? g.Rc[row] : 0;
+            const int32_t rid = valid ? (g.Rrid ? g.Rrid[row] : (int32_t)row) : 0;
+#pragma unroll 1
+            for (int64_t j = jb; j < je; ++j) {
+                const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+                const uint64_t m =
+                    ballot(holds<OPA>(q.x0[r], q.x1[r], Sa[j]) && holds<OPC>(xc, 0u, sc)) & vm;
+                if (m) {
+                    if ((m >> lane) & 1ull) {
+                        const uint64_t slot = base + mask_rank(m);
+                        if (slot < cap) out[slot] = make_int2(rid, Srid ? Srid[j] : (int32_t)j);
+                    }
+                    base += (uint64_t)__popcll(m);
+                }
+            }
+        }
+    };
+    int64_t j = s0;
+    for (; j + kSGroup <= s1; j += kSGroup) {
+        int32_t sa[kSGroup];
+#pragma unroll
+        for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
+        uint64_t any = 0;
+#pragma unroll
+        for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+            for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
+        if (any) exact(j, j + kSGroup);
+    }
+    if (j < s1) exact(j, s1);
+}
+
+// ------------------------------------------------------------------------------- count pass --
+// Selective predicates also keep up to K matches of the unit in a per-unit stash, so the write
+// pass of a unit with at most K matches is a copy instead of a second sweep.
+template <int OPA, int OPC>
+__global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
+                                                             uint64_t* __restrict__ counts)
+{
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
+    if (u >= g.U) return;
+    const int lane = (int)lane_id();
+    int64_t r0, s0, s1;
+    unit_of(g, u, r0, s0, s1);
+    RRows rr;
+    load_r<OPA, selective<OPA>() ? JOIN_OP_NONE : OPC>(g, r0, lane, rr);
+
+    if constexpr (selective<OPA>()) {
+        uint64_t n = 0;
+        int2* st = g.stash ? g.stash + u * g.K : nullptr;
+        sweep_selective<OPA, OPC>(g, rr, r0, s0, s1, n, st, st ? (uint64_t)g.K : 0ull, lane);
+        if (lane == 0) counts[u] = n;
+    } else {
+        const cptr<int32_t> Sa = as_const(g.Sa);
+        const cptr<int32_t> Sc = as_const(g.Sc);
+        uint32_t cnt[kRB];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) cnt[r] = 0;
+        int64_t j = s0;
+        for (; j + kSGroup <= s1; j += kSGroup) {
+            int32_t sa[kSGroup], sc[kSGroup];
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k) {
+                sa[k] = Sa[j + k];
+                sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+                for (int r = 0; r < kRB; ++r)
+                    cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa[k]) &&
+                               holds<OPC>(rr.xc[r], 0u, sc[k])) ? 1u : 0u;
+        }
+        for (; j < s1; ++j) {
+            const int32_t sa = Sa[j];
+            const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+#pragma unroll
+            for (int r = 0; r < kRB; ++r)
+                cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) ? 1u : 0u;
+        }
+        // Lanes past the end of R carry garbage counts: only valid rows are summed.
+        uint64_t mine = 0;
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) mine += (r0 + r * kWave + lane < g.nR) ? (uint64_t)cnt[r] : 0ull;
+        const uint64_t tot = wave_sum64(mine);
+        if (lane == 0) counts[u] = tot;
+    }
+}
+
+// ------------------------------------------------------------------------------- write pass --
 template <int OPA, int OPC>
 __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
                                                              const uint64_t* __restrict__ offsets,
@@ -223,52 +278,38 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
 {
     const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
     if (u >= g.U) return;
-    if (*total > cap) return;  // an output too small for the exact count receives nothing
+    const uint64_t tot = *total;
+    if (tot > cap) return;  // an output too small for the exact count receives nothing
     const int lane = (int)lane_id();
+    const uint64_t off = uniform(offsets[u]);
+    const uint64_t cnt = (u + 1 < g.U ? uniform(offsets[u + 1]) : tot) - off;
+    if (cnt == 0) return;
+    if (g.stash && cnt <= (uint64_t)g.K) {  // the count pass kept every match of this unit
+        const int2* st = g.stash + u * g.K;
+        for (uint64_t i = lane; i < cnt; i += kWave) out[off + i] = st[i];
+        return;
+    }
     int64_t r0, s0, s1;
     unit_of(g, u, r0, s0, s1);
-    RRows rr;
-    load_r<OPA, OPC>(g, r0, lane, rr);
-    int32_t rid[kRB];
-    uint64_t vm[kRB];
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) {
-        const int64_t row = r0 + r * kWave + lane;
-        const bool valid = row < g.nR;
-        rid[r] = valid ? (g.Rrid ? g.Rrid[row] : (int32_t)row) : 0;
-        vm[r] = ballot(valid);
-    }
-    uint64_t base = uniform(offsets[u]);
-    const cptr<int32_t> Sa = as_const(g.Sa);
-    const cptr<int32_t> Sc = as_const(g.Sc);
-    const cptr<int32_t> Srid = as_const(g.Srid);
-
-    int64_t j = s0;
+    uint64_t base = off;
     if constexpr (selective<OPA>()) {
-        for (; j + kSGroup <= s1; j += kSGroup) {
-            int32_t sa[kSGroup];
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
-            uint64_t any = 0;
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k)
-#pragma unroll
-                for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
-            if (any) {
-                const RRows q = opaque_copy(rr);
-                for (int k = 0; k < kSGroup; ++k) {
-                    const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
-                    const int32_t srid = Srid ? Srid[j + k] : (int32_t)(j + k);
-                    emit_row<OPA, OPC>(q, rid, vm, sa[k], sc, srid, base, out, cap, lane);
-                }
-            }
+        RRows rr;
+        load_r<OPA, JOIN_OP_NONE>(g, r0, lane, rr);
+        sweep_selective<OPA, OPC>(g, rr, r0, s0, s1, base, out, cap, lane);
+    } else {
+        RRows rr;
+        load_r<OPA, OPC>(g, r0, lane, rr);
+        int32_t rid[kRB];
+        uint64_t vm[kRB];
+        load_rids(g, r0, lane, rid, vm);
+        const cptr<int32_t> Sa = as_const(g.Sa);
+        const cptr<int32_t> Sc = as_const(g.Sc);
+        const cptr<int32_t> Srid = as_const(g.Srid);
+        for (int64_t j = s0; j < s1; ++j) {
+            const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+            const int32_t srid = Srid ? Srid[j] : (int32_t)j;
+            emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, base, out, cap, lane);
         }
-    }
-    for (; j < s1; ++j) {
-        const int32_t sa = Sa[j];
-        const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
-        const int32_t srid = Srid ? Srid[j] : (int32_t)j;
-        emit_row<OPA, OPC>(rr, rid, vm, sa, sc, srid, base, out, cap, lane);
     }
 }
 
@@ -334,9 +375,12 @@ WriteFn write_fn(int opa, int opc)
     }
 }
 
-ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, const join_pred_t& p)
+ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, const join_pred_t& p,
+               char* ws)
 {
     ThetaGeom g;
+    g.K = pl.K;
+    g.stash = pl.K > 0 ? reinterpret_cast<int2*>(ws + pl.off_stash) : nullptr;
     g.Ra = R.key;
     g.Rc = R.key2;
     g.Rrid = R.rid;
@@ -356,7 +400,8 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-ThetaPlan theta_plan(int64_t nR, int64_t nS, int64_t target_waves, int64_t ts_override)
+ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int64_t ts_override,
+                     int64_t stash_k)
 {
     ThetaPlan pl{};
     const int64_t nRb = nR > 0 ? ceil_div(nR, kRowsPerWave) : 0;
@@ -381,6 +426,11 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int64_t target_waves, int64_t ts_ov
     off = align_up(off + (size_t)(pl.U > 0 ? pl.U : 1) * sizeof(uint64_t));
     pl.off_temp = off;
     off = align_up(off + scan_temp_elems<uint64_t>(pl.U) * sizeof(uint64_t) + 8);
+    // Only the selective operators (or an unknown one, for sizing) get the match stash.
+    const bool sel = op_a == JOIN_OP_BAND || op_a == JOIN_OP_EQ || op_a == JOIN_OP_NONE;
+    pl.K = sel && stash_k > 0 ? stash_k : 0;
+    pl.off_stash = off;
+    off = align_up(off + (size_t)pl.U * (size_t)pl.K * sizeof(int2));
     pl.bytes = off;
     return pl;
 }
@@ -395,7 +445,8 @@ hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_
         CountFn f = count_fn(p.op_a, p.op_c);
         if (!f) return hipErrorInvalidValue;
         const unsigned grid = (unsigned)ceil_div(pl.U, kWavesPerBlock);
-        hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p), counts);
+        prof::Scope ps(st, "theta.count");
+        hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p, ws), counts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -411,7 +462,8 @@ hipError_t theta_write(const ThetaPlan& pl, const join_rel_t& R, const join_rel_
     WriteFn f = write_fn(p.op_a, p.op_c);
     if (!f) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)ceil_div(pl.U, kWavesPerBlock);
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p), offsets,
+    prof::Scope ps(st, "theta.write");
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, geom(pl, R, S, p, ws), offsets,
                        reinterpret_cast<const uint64_t*>(ws), reinterpret_cast<int2*>(pairs), cap);
     return hipGetLastError();
 }
