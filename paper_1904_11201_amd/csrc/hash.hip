@@ -70,7 +70,67 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
 }
 
 // --------------------------------------------------------------------------------- scatter --
+// One thread's share of a staged tile: IT tuples (key, rid) and their tile-local indices.
+template <int IT>
+struct TileRegs {
+    int32_t k[IT], r[IT];
+};
+
+// Load tile [t0, t0 + tn) into registers.  With VEC, thread t owns the 4-tuple groups
+// (q * BLOCK + t) * 4 .. +3 and a full tile is read with 2 * IT / 4 unconditional 16-byte loads.
+template <bool VEC, bool HAS_RID, int IT>
+__device__ __forceinline__ void load_tile(const int32_t* __restrict__ key,
+                                          const int32_t* __restrict__ rid, int64_t t0, int tn,
+                                          TileRegs<IT>& tr)
+{
+    const int tid = threadIdx.x;
+    if constexpr (VEC) {
+        if (tn == kScatTile) {
+#pragma unroll
+            for (int q = 0; q < IT / 4; ++q) {
+                const int e = (q * kScatBlock + tid) * 4;
+                const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + e);
+                tr.k[4 * q] = k4.x; tr.k[4 * q + 1] = k4.y; tr.k[4 * q + 2] = k4.z; tr.k[4 * q + 3] = k4.w;
+                if constexpr (HAS_RID) {
+                    const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + e);
+                    tr.r[4 * q] = r4.x; tr.r[4 * q + 1] = r4.y; tr.r[4 * q + 2] = r4.z; tr.r[4 * q + 3] = r4.w;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) tr.r[4 * q + c] = (int32_t)(t0 + e + c);
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < IT / 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int e = (q * kScatBlock + tid) * 4 + c;
+                const bool ok = e < tn;
+                tr.k[4 * q + c] = ok ? key[t0 + e] : 0;
+                tr.r[4 * q + c] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = q * kScatBlock + tid;
+            const bool ok = e < tn;
+            tr.k[q] = ok ? key[t0 + e] : 0;
+            tr.r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
+        }
+    }
+}
+
+template <bool VEC, int IT>
+__device__ __forceinline__ int tile_index(int q)
+{
+    const int tid = threadIdx.x;
+    return VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
+}
+
 // LDS layout: cursor[P] | tstart[P + 1] | skey[TILE] | srid[TILE] | spid[TILE] (uint16)
+// The next tile's tuples are loaded into registers before the current tile's LDS phases, so
+// its HBM reads overlap the counting sort and the writes of the current tile.
 template <bool VEC, bool HAS_RID>
 __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restrict__ key,
                                                         const int32_t* __restrict__ rid, int64_t n,
@@ -101,48 +161,23 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restric
     const int64_t end = beg + chunk < n ? beg + chunk : n;
     const int seg = (P + kScatBlock - 1) / kScatBlock;  // scan segment per thread
 
+    TileRegs<IT> nxt;
+    if (beg < end)
+        load_tile<VEC, HAS_RID, IT>(key, rid, beg,
+                                    (int)(end - beg < kScatTile ? end - beg : kScatTile), nxt);
     for (int64_t t0 = beg; t0 < end; t0 += kScatTile) {
         const int tn = (int)(end - t0 < kScatTile ? end - t0 : kScatTile);
-        int32_t k[IT], r[IT];
+        const TileRegs<IT> cur = nxt;
+        const int64_t t1 = t0 + kScatTile;
+        if (t1 < end)
+            load_tile<VEC, HAS_RID, IT>(key, rid, t1,
+                                        (int)(end - t1 < kScatTile ? end - t1 : kScatTile), nxt);
+        // 1. rank each tuple within its partition (LDS atomics)
         uint32_t p[IT], rank[IT];
-        // 1. load (4 consecutive tuples per thread per step when vectorised) and rank by pid
-        if constexpr (VEC) {
-#pragma unroll
-            for (int q = 0; q < IT / 4; ++q) {
-                const int e = (q * kScatBlock + tid) * 4;
-                if (e + 4 <= tn) {
-                    const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + e);
-                    k[4 * q] = k4.x; k[4 * q + 1] = k4.y; k[4 * q + 2] = k4.z; k[4 * q + 3] = k4.w;
-                    if constexpr (HAS_RID) {
-                        const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + e);
-                        r[4 * q] = r4.x; r[4 * q + 1] = r4.y; r[4 * q + 2] = r4.z; r[4 * q + 3] = r4.w;
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) r[4 * q + c] = (int32_t)(t0 + e + c);
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const bool ok = e + c < tn;
-                        k[4 * q + c] = ok ? key[t0 + e + c] : 0;
-                        r[4 * q + c] = ok ? (HAS_RID ? rid[t0 + e + c] : (int32_t)(t0 + e + c)) : 0;
-                    }
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < IT; ++q) {
-                const int e = q * kScatBlock + tid;
-                const bool ok = e < tn;
-                k[q] = ok ? key[t0 + e] : 0;
-                r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
-            }
-        }
 #pragma unroll
         for (int q = 0; q < IT; ++q) {
-            const int e = VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
-            p[q] = pid_of(k[q], sh);
-            rank[q] = e < tn ? atomicAdd(&tstart[p[q]], 1u) : 0u;
+            p[q] = pid_of(cur.k[q], sh);
+            rank[q] = tile_index<VEC, IT>(q) < tn ? atomicAdd(&tstart[p[q]], 1u) : 0u;
         }
         __syncthreads();
         // 2. exclusive scan of the tile histogram in place; tstart[P] = tn
@@ -168,11 +203,10 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restric
         // 3. stage in pid order
 #pragma unroll
         for (int q = 0; q < IT; ++q) {
-            const int e = VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
-            if (e < tn) {
+            if (tile_index<VEC, IT>(q) < tn) {
                 const uint32_t pos = tstart[p[q]] + rank[q];
-                skey[pos] = k[q];
-                srid[pos] = r[q];
+                skey[pos] = cur.k[q];
+                srid[pos] = cur.r[q];
                 spid[pos] = (uint16_t)p[q];
             }
         }
@@ -368,6 +402,45 @@ __device__ __forceinline__ uint32_t table_slots(uint32_t rN)
     return c < 64 ? 64 : c;
 }
 
+// Probe one key: number of entries with this key, and the rids of the first two of them.
+__device__ __forceinline__ uint32_t probe(const uint64_t* tab, uint32_t C, uint64_t empty,
+                                          uint32_t home, uint32_t x, int32_t& r1, int32_t& r2)
+{
+    uint32_t m = 0, pos = home;
+    while (true) {
+        const uint64_t c = tab[pos];
+        if (c == empty) break;
+        const uint32_t ck = (uint32_t)(c >> 32);
+        if (ck == x) {
+            if (m == 0) r1 = (int32_t)(uint32_t)c;
+            else if (m == 1) r2 = (int32_t)(uint32_t)c;
+            ++m;
+        } else if (ck > x) {
+            break;
+        }
+        pos = pos + 1 == C ? 0 : pos + 1;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t probe_count(const uint64_t* tab, uint32_t C, uint64_t empty,
+                                                uint32_t home, uint32_t x)
+{
+    uint32_t m = 0, pos = home;
+    while (true) {
+        const uint64_t c = tab[pos];
+        if (c == empty) break;
+        const uint32_t ck = (uint32_t)(c >> 32);
+        if (ck == x) ++m;
+        else if (ck > x) break;
+        pos = pos + 1 == C ? 0 : pos + 1;
+    }
+    return m;
+}
+
+constexpr int kCountBatch = 8;  // S keys in flight per thread in the count pass
+constexpr int kWriteBatch = 4;  // S tuples per thread per round of the write pass
+
 __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
     extern __shared__ uint64_t tab[];
@@ -379,16 +452,17 @@ __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t*
         const uint32_t C = table_slots(un.rN);
         const uint64_t empty = build_table(g, un, tab, C, &flag);
         uint32_t cnt = 0;
-        for (uint32_t e = threadIdx.x; e < un.sN; e += kJoinBlock) {
-            const uint32_t x = (uint32_t)g.sk[un.sBeg + e];
-            uint32_t pos = home_of(hmix(x), g.bits, C);
-            while (true) {
-                const uint64_t c = tab[pos];
-                if (c == empty) break;
-                const uint32_t ck = (uint32_t)(c >> 32);
-                if (ck == x) ++cnt;
-                else if (ck > x) break;
-                pos = pos + 1 == C ? 0 : pos + 1;
+        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
+            uint32_t xs[kCountBatch];
+#pragma unroll
+            for (int i = 0; i < kCountBatch; ++i) {
+                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+                xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < kCountBatch; ++i) {
+                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+                if (e < un.sN) cnt += probe_count(tab, C, empty, home_of(hmix(xs[i]), g.bits, C), xs[i]);
             }
         }
         uint32_t tot;
@@ -417,51 +491,50 @@ __global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
         const uint32_t C = table_slots(un.rN);
         const uint64_t empty = build_table(g, un, tab, C, &flag);
         uint64_t base = offsets[u];
-        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock) {
-            const uint32_t e = e0 + threadIdx.x;
-            const bool ok = e < un.sN;
-            const uint32_t idx = un.sBeg + e;
-            const uint32_t x = ok ? (uint32_t)g.sk[idx] : 0u;
-            const int32_t srid = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
-            uint32_t m = 0;
-            int32_t r1 = 0, r2 = 0;
-            const uint32_t home = home_of(hmix(x), g.bits, C);
-            if (ok) {
-                uint32_t pos = home;
-                while (true) {
-                    const uint64_t c = tab[pos];
-                    if (c == empty) break;
-                    const uint32_t ck = (uint32_t)(c >> 32);
-                    if (ck == x) {
-                        if (m == 0) r1 = (int32_t)(uint32_t)c;
-                        else if (m == 1) r2 = (int32_t)(uint32_t)c;
-                        ++m;
-                    } else if (ck > x) {
-                        break;
-                    }
-                    pos = pos + 1 == C ? 0 : pos + 1;
-                }
+        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
+            uint32_t x[kWriteBatch], m[kWriteBatch];
+            int32_t srid[kWriteBatch], r1[kWriteBatch], r2[kWriteBatch];
+#pragma unroll
+            for (int i = 0; i < kWriteBatch; ++i) {
+                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+                const bool ok = e < un.sN;
+                const uint32_t idx = un.sBeg + e;
+                x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
+                srid[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+            }
+            uint32_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < kWriteBatch; ++i) {
+                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+                m[i] = 0;
+                r1[i] = r2[i] = 0;
+                if (e < un.sN)
+                    m[i] = probe(tab, C, empty, home_of(hmix(x[i]), g.bits, C), x[i], r1[i], r2[i]);
+                mine += m[i];
             }
             uint32_t tot;
-            const uint32_t ex = block_excl_scan<kJoinBlock>(m, wsum, &tot);
-            const uint64_t slot = base + ex;
-            if (m >= 1 && slot < cap) out[slot] = make_int2(r1, srid);
-            if (m >= 2 && slot + 1 < cap) out[slot + 1] = make_int2(r2, srid);
-            if (m > 2) {  // more than two build matches: walk the run again for the rest
-                uint32_t pos = home, seen = 0;
-                while (true) {
-                    const uint64_t c = tab[pos];
-                    if (c == empty) break;
-                    const uint32_t ck = (uint32_t)(c >> 32);
-                    if (ck == x) {
-                        if (seen >= 2 && slot + seen < cap)
-                            out[slot + seen] = make_int2((int32_t)(uint32_t)c, srid);
-                        ++seen;
-                    } else if (ck > x) {
-                        break;
+            uint64_t slot = base + block_excl_scan<kJoinBlock>(mine, wsum, &tot);
+#pragma unroll
+            for (int i = 0; i < kWriteBatch; ++i) {
+                if (m[i] >= 1 && slot < cap) out[slot] = make_int2(r1[i], srid[i]);
+                if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2(r2[i], srid[i]);
+                if (m[i] > 2) {  // more than two build matches: walk the run again for the rest
+                    uint32_t pos = home_of(hmix(x[i]), g.bits, C), seen = 0;
+                    while (true) {
+                        const uint64_t c = tab[pos];
+                        if (c == empty) break;
+                        const uint32_t ck = (uint32_t)(c >> 32);
+                        if (ck == x[i]) {
+                            if (seen >= 2 && slot + seen < cap)
+                                out[slot + seen] = make_int2((int32_t)(uint32_t)c, srid[i]);
+                            ++seen;
+                        } else if (ck > x[i]) {
+                            break;
+                        }
+                        pos = pos + 1 == C ? 0 : pos + 1;
                     }
-                    pos = pos + 1 == C ? 0 : pos + 1;
                 }
+                slot += m[i];
             }
             base += tot;
         }
