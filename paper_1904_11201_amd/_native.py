@@ -40,12 +40,29 @@ class JoinPred(ctypes.Structure):
     _fields_ = [("op_a", ctypes.c_int32), ("w", ctypes.c_int32), ("op_c", ctypes.c_int32)]
 
 
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({line.split()[-1] for line in f if "libamdhip64" in line})
+    except OSError:
+        return []
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1904_11201_amd.build` "
             "(hipcc, gfx950).  There is no fallback path.")
+    # PyTorch ships its own HIP runtime with the same soname as the system one.  Loading torch
+    # first makes libjoin bind to that same runtime, so device pointers and stream handles
+    # from torch are valid inside libjoin.  Loading libjoin first would map a second runtime.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are mapped into this process ({rts}); libjoin and "
+                          "torch must share one: import torch before loading libjoin")
     R = ctypes.POINTER(JoinRel)
     Pp = ctypes.POINTER(JoinPred)
     vp, sz, i64, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_uint64

@@ -92,3 +92,10 @@ def test_empty_relations_need_no_device():
     ws_bytes = n.lib.join_workspace_bytes(n.JOIN_KIND_THETA, 10, 0, None)
     rc, c = _count(n.JOIN_KIND_THETA, _rel(fake, 10), _rel(None, 0), p, ws=fake, ws_bytes=ws_bytes)
     assert rc == n.JOIN_OK and c == 0
+
+
+def test_single_hip_runtime_shared_with_torch():
+    """libjoin binds to the HIP runtime torch already loaded, so torch's device pointers and
+    stream handles are valid inside it."""
+    rts = n._hip_runtimes()
+    assert len(rts) == 1, rts
