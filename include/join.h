@@ -52,6 +52,12 @@ extern "C" {
 /* ---- join kinds -------------------------------------------------------------------------- */
 #define JOIN_KIND_HASH 1  /* equi join R.key = S.key (Section 3.3.2, hash join)                */
 #define JOIN_KIND_THETA 2 /* theta join, nested-loop evaluation (Sections 3.3.1 and 4.2)       */
+#define JOIN_KIND_THETA_REGION 3 /* theta join with the improved algorithm's region pruning
+                                  * (Section 4.2, Algorithm 3): key ranges cut into buckets shared
+                                  * by both tables; white regions skipped, green regions counted
+                                  * and cross-joined without evaluation, red regions evaluated by
+                                  * the nested loop.  Same predicates and results as
+                                  * JOIN_KIND_THETA. */
 
 /* ---- predicate operators (Section 2.3: =, <, >, <=, >=; Figure "greenc": not-equal) -------- */
 typedef enum {

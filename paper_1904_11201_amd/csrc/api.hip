@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include "hash.hpp"
+#include "region.hpp"
 #include "scan.hpp"
 #include "theta.hpp"
 
@@ -116,13 +117,13 @@ int check_pred(const join_pred_t* p)
 
 int check_args(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p)
 {
-    if (kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA) {
-        set_error("kind = %d is neither JOIN_KIND_HASH nor JOIN_KIND_THETA", kind);
+    if (kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION) {
+        set_error("kind = %d is not JOIN_KIND_HASH, JOIN_KIND_THETA or JOIN_KIND_THETA_REGION", kind);
         return JOIN_E_INVAL;
     }
     int rc;
     bool key2 = false;
-    if (kind == JOIN_KIND_THETA) {
+    if (kind != JOIN_KIND_HASH) {
         if ((rc = check_pred(p)) != JOIN_OK) return rc;
         key2 = p->op_c != JOIN_OP_NONE;
     }
@@ -131,9 +132,15 @@ int check_args(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     return JOIN_OK;
 }
 
+RegionPlan plan_region(int64_t nR, int64_t nS, const join_pred_t* p)
+{
+    return region_plan(nR, nS, p ? p->op_a : JOIN_OP_NONE, theta_stash_k());
+}
+
 size_t ws_needed(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
 {
     if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).bytes;
+    if (kind == JOIN_KIND_THETA_REGION) return plan_region(nR, nS, p).bytes;
     return plan_theta(nR, nS, p).bytes;
 }
 
@@ -170,7 +177,7 @@ bool matches_last(int kind, const join_rel_t* R, const join_rel_t* S, const join
 {
     if (!g_last.valid || g_last.kind != kind || g_last.ws != ws) return false;
     if (!same_rel(g_last.R, *R) || !same_rel(g_last.S, *S)) return false;
-    if (kind == JOIN_KIND_THETA &&
+    if (kind != JOIN_KIND_HASH &&
         (g_last.p.op_a != p->op_a || g_last.p.op_c != p->op_c || g_last.p.w != p->w))
         return false;
     return true;
@@ -198,6 +205,8 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         if (kind == JOIN_KIND_HASH) {
             const HashPlan pl = hash_plan(R->n, S->n, num_cus());
             e = hash_count(pl, *R, *S, w, st);
+        } else if (kind == JOIN_KIND_THETA_REGION) {
+            e = region_count(plan_region(R->n, S->n, p), *R, *S, *p, w, st);
         } else {
             const ThetaPlan pl = plan_theta(R->n, S->n, p);
             e = theta_count(pl, *R, *S, *p, w, st);
@@ -235,6 +244,8 @@ int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     if (kind == JOIN_KIND_HASH) {
         const HashPlan pl = hash_plan(R->n, S->n, num_cus());
         e = hash_write(pl, *R, *S, w, pairs, capacity, st);
+    } else if (kind == JOIN_KIND_THETA_REGION) {
+        e = region_write(plan_region(R->n, S->n, p), *R, *S, *p, w, pairs, capacity, st);
     } else {
         const ThetaPlan pl = plan_theta(R->n, S->n, p);
         e = theta_write(pl, *R, *S, *p, w, pairs, capacity, st);
@@ -249,7 +260,9 @@ extern "C" {
 
 size_t join_workspace_bytes(int kind, int64_t nR, int64_t nS, const join_pred_t* pred)
 {
-    if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA) || nR < 0 || nS < 0) return 0;
+    if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION) ||
+        nR < 0 || nS < 0)
+        return 0;
     return ws_needed(kind, nR, nS, pred);
 }
 

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
                                                      uint32_t* __restrict__ hist, int64_t nCh)
 {
     extern __shared__ uint32_t h[];
+    constexpr int V = 4;  // 16-byte loads in flight per thread
     const int P = 1 << bits;
     const int sh = 32 - bits;
     for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
@@ -55,14 +56,20 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
     const int64_t end = beg + chunk < n ? beg + chunk : n;
     int64_t i = beg;
     if constexpr (VEC) {
-        for (int64_t v = beg + 4 * (int64_t)threadIdx.x; v + 4 <= end; v += 4 * kHistBlock) {
-            const int4 k4 = *reinterpret_cast<const int4*>(key + v);
-            atomicAdd(&h[pid_of(k4.x, sh)], 1u);
-            atomicAdd(&h[pid_of(k4.y, sh)], 1u);
-            atomicAdd(&h[pid_of(k4.z, sh)], 1u);
-            atomicAdd(&h[pid_of(k4.w, sh)], 1u);
+        const int64_t step = 4 * kHistBlock;
+        for (; i + V * step <= end; i += V * step) {
+            int4 k4[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                k4[v] = *reinterpret_cast<const int4*>(key + i + v * step + 4 * threadIdx.x);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                atomicAdd(&h[pid_of(k4[v].x, sh)], 1u);
+                atomicAdd(&h[pid_of(k4[v].y, sh)], 1u);
+                atomicAdd(&h[pid_of(k4[v].z, sh)], 1u);
+                atomicAdd(&h[pid_of(k4[v].w, sh)], 1u);
+            }
         }
-        i = beg + ((end - beg) / 4) * 4;
     }
     for (i += threadIdx.x; i < end; i += kHistBlock) atomicAdd(&h[pid_of(key[i], sh)], 1u);
     __syncthreads();
@@ -262,6 +269,16 @@ __global__ void plan_units_k(const uint32_t* __restrict__ offR, const uint32_t* 
     units[p] = nrc * nss;
 }
 
+// Unit -> partition map: partition p owns units [unitStart[p], unitStart[p + 1]).
+__global__ void expand_units_k(const uint32_t* __restrict__ unitStart, int P, int64_t Umax,
+                               uint32_t* __restrict__ umap)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    for (uint32_t u = unitStart[p]; u < unitStart[p + 1] && (int64_t)u < Umax; ++u)
+        umap[u] = (uint32_t)p;
+}
+
 // ------------------------------------------------------------------------- join work units --
 struct Unit {
     uint32_t rBeg, rN, sBeg, sN;
@@ -275,14 +292,9 @@ __device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
         pi = g.one;
         local = u;
     } else {
-        // largest p with unitStart[p] <= u
-        int lo = 0, hi = g.P - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (g.unitStart[mid] <= u) lo = mid; else hi = mid - 1;
-        }
-        pi = g.part[lo];
-        local = u - g.unitStart[lo];
+        const uint32_t p = g.umap[u];
+        pi = g.part[p];
+        local = u - g.unitStart[p];
     }
     const uint32_t rc = local / pi.nSs;
     const uint32_t sc = local - rc * pi.nSs;
@@ -441,6 +453,29 @@ __device__ __forceinline__ uint32_t probe_count(const uint64_t* tab, uint32_t C,
 constexpr int kCountBatch = 8;  // S keys in flight per thread in the count pass
 constexpr int kWriteBatch = 4;  // S tuples per thread per round of the write pass
 
+__device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
+                                            uint32_t (&x)[kWriteBatch], int32_t (&r)[kWriteBatch])
+{
+#pragma unroll
+    for (int i = 0; i < kWriteBatch; ++i) {
+        const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+        const bool ok = e < un.sN;
+        const uint32_t idx = un.sBeg + e;
+        x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
+        r[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+    }
+}
+
+__device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
+                                          uint32_t (&xs)[kCountBatch])
+{
+#pragma unroll
+    for (int i = 0; i < kCountBatch; ++i) {
+        const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+        xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
     extern __shared__ uint64_t tab[];
@@ -450,19 +485,21 @@ __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t*
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         const Unit un = decode_unit(g, u);
         const uint32_t C = table_slots(un.rN);
+        // the first batch of S keys is in flight while the table is built; each later batch is
+        // loaded while the previous one probes
+        uint32_t xs[kCountBatch];
+        load_keys(g, un, 0, xs);
         const uint64_t empty = build_table(g, un, tab, C, &flag);
         uint32_t cnt = 0;
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
-            uint32_t xs[kCountBatch];
+            uint32_t cur[kCountBatch];
+#pragma unroll
+            for (int i = 0; i < kCountBatch; ++i) cur[i] = xs[i];
+            if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys(g, un, e0 + kJoinBlock * kCountBatch, xs);
 #pragma unroll
             for (int i = 0; i < kCountBatch; ++i) {
                 const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-                xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
-            }
-#pragma unroll
-            for (int i = 0; i < kCountBatch; ++i) {
-                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-                if (e < un.sN) cnt += probe_count(tab, C, empty, home_of(hmix(xs[i]), g.bits, C), xs[i]);
+                if (e < un.sN) cnt += probe_count(tab, C, empty, home_of(hmix(cur[i]), g.bits, C), cur[i]);
             }
         }
         uint32_t tot;
@@ -489,6 +526,9 @@ __global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         const Unit un = decode_unit(g, u);
         const uint32_t C = table_slots(un.rN);
+        uint32_t nx[kWriteBatch];
+        int32_t nr[kWriteBatch];
+        load_tuples(g, un, 0, nx, nr);  // in flight while the table is built
         const uint64_t empty = build_table(g, un, tab, C, &flag);
         uint64_t base = offsets[u];
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
@@ -496,12 +536,11 @@ __global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
             int32_t srid[kWriteBatch], r1[kWriteBatch], r2[kWriteBatch];
 #pragma unroll
             for (int i = 0; i < kWriteBatch; ++i) {
-                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-                const bool ok = e < un.sN;
-                const uint32_t idx = un.sBeg + e;
-                x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
-                srid[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+                x[i] = nx[i];
+                srid[i] = nr[i];
             }
+            if (e0 + kJoinBlock * kWriteBatch < un.sN)
+                load_tuples(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
             uint32_t mine = 0;
 #pragma unroll
             for (int i = 0; i < kWriteBatch; ++i) {
@@ -544,6 +583,9 @@ __global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// LDS bytes of the join kernels' table for R chunks of up to `cap` entries.
+size_t join_lds(uint32_t cap) { return (size_t)2 * ((cap * 2 + 63) & ~63u) * 4 + 64; }
+
 }  // namespace
 
 static int env_int(const char* name, int dflt)
@@ -558,7 +600,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     HashPlan pl{};
     pl.nR = nR;
     pl.nS = nS;
-    int cap = env_int("JOIN_HASH_CAP", 9216);
+    int cap = env_int("JOIN_HASH_CAP", 4608);
     if (cap < 64) cap = 64;
     if (cap > kJoinBlock * kBuildItems) cap = kJoinBlock * kBuildItems;
     pl.cap = cap;
@@ -586,8 +628,9 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     } else {
         int bits = forced_bits;
         if (bits < 0) {
-            // mean partition size ~ cap * 0.85 keeps the largest partitions under cap
-            const double target = cap * 0.85;
+            // mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma for
+            // hashed unique keys) under cap
+            const double target = cap * 0.9;
             bits = 1;
             while (bits < kMaxBits && (double)nR / (double)(1 << bits) > target) ++bits;
         }
@@ -622,6 +665,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         off = align_up(off + (size_t)pl.P * sizeof(PartInfo));
         pl.off_units = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
+        pl.off_umap = off;
+        off = align_up(off + (size_t)pl.Umax * 4);
     }
     pl.off_counts = off;
     off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
@@ -637,13 +682,16 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     pl.off_temp = off;
     off = align_up(off + temp + 8);
     pl.bytes = off;
-    // persistent grid of the join kernels: one workgroup per CU (the table fills most of LDS)
-    pl.joinGrid = num_cus;
+    // persistent grid of the join kernels: as many workgroups per CU as the LDS table allows
+    const size_t lds = join_lds((uint32_t)cap) + 128;
+    int per_cu = (int)((160 * 1024) / lds);
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 2) per_cu = 2;  // 1024-thread workgroups: at most 2 per CU
+    pl.joinGrid = num_cus * per_cu;
     return pl;
 }
 
 static size_t scatter_lds(int P) { return (size_t)(2 * P + 1) * 4 + (size_t)kScatTile * 10; }
-static size_t join_lds(uint32_t cap) { return (size_t)2 * ((cap * 2 + 63) & ~63u) * 4 + 64; }
 
 static bool g_attr_done = false;
 
@@ -730,6 +778,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.sr = reinterpret_cast<const int32_t*>(ws + pl.off_prS);
         g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);
         g.unitStart = reinterpret_cast<const uint32_t*>(ws + pl.off_units);
+        g.umap = reinterpret_cast<const uint32_t*>(ws + pl.off_umap);
         g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
         g.P = pl.P;
     }
@@ -764,6 +813,13 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         if (e != hipSuccess) return e;
         e = exclusive_scan<uint32_t>(units, units, pl.P + 1, reinterpret_cast<uint32_t*>(ws + 8),
                                      reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+        {
+            prof::Scope pe(st, "hash.plan");
+            expand_units_k<<<(unsigned)ceil_div(pl.P, 256), 256, 0, st>>>(
+                units, pl.P, pl.Umax, reinterpret_cast<uint32_t*>(ws + pl.off_umap));
+        }
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (pl.Umax > 0) {

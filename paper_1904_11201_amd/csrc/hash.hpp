@@ -18,6 +18,7 @@ struct JoinGeom {
     const int32_t* sr;
     const PartInfo* part;       // [P]
     const uint32_t* unitStart;  // [P + 1], exclusive scan of units per partition
+    const uint32_t* umap;       // [Umax], partition of each unit
     const uint32_t* Uptr;       // device total of units
     PartInfo one;               // the single partition when single != 0
     uint32_t Uhost;             // units when single != 0
@@ -37,7 +38,7 @@ struct HashPlan {
     int64_t chR, chS, nChR, nChS;
     int64_t Umax;
     int joinGrid;
-    size_t off_histR, off_histS, off_pkR, off_prR, off_pkS, off_prS, off_info, off_units;
+    size_t off_histR, off_histS, off_pkR, off_prR, off_pkS, off_prS, off_info, off_units, off_umap;
     size_t off_counts, off_temp, bytes;
 };
 

@@ -44,6 +44,11 @@ struct ThetaGeom {
     int64_t U;    // units = R blocks * S tiles
     int2* stash;  // [U][K] matches kept by the count pass (selective predicates), or NULL
     int64_t K;
+    // Explicit unit table (region-pruned theta join): unit u covers R rows [x, y) and S rows
+    // [z, w) of the arrays above; NULL means the dense grid of R blocks x S tiles.
+    const uint4* units;
+    const uint32_t* Uptr;  // device unit count when units != NULL (clamped to U)
+    int64_t nOff;          // entries of the offsets array the write pass reads
 };
 
 // Per-R-row constants of op_a.  BAND keeps [lo, lo + wid] with lo = max(a - w, INT32_MIN),
@@ -100,12 +105,13 @@ __device__ __forceinline__ RRows opaque_copy(const RRows& a)
 }
 
 template <int OPA, int OPC>
-__device__ __forceinline__ void load_r(const ThetaGeom& g, int64_t r0, int lane, RRows& rr)
+__device__ __forceinline__ void load_r(const ThetaGeom& g, int64_t r0, int64_t rEnd, int lane,
+                                       RRows& rr)
 {
 #pragma unroll
     for (int r = 0; r < kRB; ++r) {
         const int64_t row = r0 + r * kWave + lane;
-        const bool valid = row < g.nR;
+        const bool valid = row < rEnd;
         const int32_t a = valid ? g.Ra[row] : 0;
         prep_a<OPA>(a, g.w, rr.x0[r], rr.x1[r]);
         if constexpr (OPC != JOIN_OP_NONE) rr.xc[r] = valid ? g.Rc[row] : 0;
@@ -113,14 +119,31 @@ __device__ __forceinline__ void load_r(const ThetaGeom& g, int64_t r0, int lane,
     }
 }
 
-__device__ __forceinline__ void unit_of(const ThetaGeom& g, int64_t u, int64_t& r0, int64_t& s0,
-                                        int64_t& s1)
+// Unit u: R rows [r0, rEnd) (at most 64 * kRB of them) and S rows [s0, s1).
+__device__ __forceinline__ void unit_of(const ThetaGeom& g, int64_t u, int64_t& r0, int64_t& rEnd,
+                                        int64_t& s0, int64_t& s1)
 {
+    if (g.units) {
+        const uint4 q = g.units[u];
+        r0 = q.x;
+        rEnd = q.y;
+        s0 = q.z;
+        s1 = q.w;
+        return;
+    }
     const int64_t rb = u / g.nSt;
     const int64_t st = u - rb * g.nSt;
     r0 = rb * kRowsPerWave;
+    rEnd = r0 + kRowsPerWave < g.nR ? r0 + kRowsPerWave : g.nR;
     s0 = st * g.TS;
     s1 = s0 + g.TS < g.nS ? s0 + g.TS : g.nS;
+}
+
+__device__ __forceinline__ int64_t unit_count(const ThetaGeom& g)
+{
+    if (!g.units) return g.U;
+    const int64_t U = *g.Uptr;
+    return U < g.U ? U : g.U;
 }
 
 // Evaluate one S row against the wave's kRB R rows exactly and emit the matches in (r, lane)
@@ -146,13 +169,13 @@ __device__ __forceinline__ void emit_row(const RRows& rr, const int32_t (&rid)[k
     }
 }
 
-__device__ __forceinline__ void load_rids(const ThetaGeom& g, int64_t r0, int lane,
+__device__ __forceinline__ void load_rids(const ThetaGeom& g, int64_t r0, int64_t rEnd, int lane,
                                           int32_t (&rid)[kRB], uint64_t (&vm)[kRB])
 {
 #pragma unroll
     for (int r = 0; r < kRB; ++r) {
         const int64_t row = r0 + r * kWave + lane;
-        const bool valid = row < g.nR;
+        const bool valid = row < rEnd;
         rid[r] = valid ? (g.Rrid ? g.Rrid[row] : (int32_t)row) : 0;
         vm[r] = ballot(valid);
     }
@@ -166,7 +189,7 @@ __device__ __forceinline__ void load_rids(const ThetaGeom& g, int64_t r0, int la
 // emitted in (R row r, S row j, lane) order.
 template <int OPA, int OPC>
 __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows& rr, int64_t r0,
-                                                int64_t s0, int64_t s1, uint64_t& base,
+                                                int64_t rEnd, int64_t s0, int64_t s1, uint64_t& base,
                                                 int2* __restrict__ out, uint64_t cap, int lane)
 {
     const cptr<int32_t> Sa = as_const(g.Sa);
@@ -177,7 +200,7 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
 #pragma unroll
         for (int r = 0; r < kRB; ++r) {
             const int64_t row = r0 + r * kWave + lane;
-            const bool valid = row < g.nR;
+            const bool valid = row < rEnd;
             const uint64_t vm = ballot(valid);
             if (!vm) continue;
             const int32_t xc = (OPC != JOIN_OP_NONE && valid) ? g.Rc[row] : 0;
@@ -219,53 +242,56 @@ template <int OPA, int OPC>
 __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
                                                              uint64_t* __restrict__ counts)
 {
-    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
-    if (u >= g.U) return;
     const int lane = (int)lane_id();
-    int64_t r0, s0, s1;
-    unit_of(g, u, r0, s0, s1);
-    RRows rr;
-    load_r<OPA, selective<OPA>() ? JOIN_OP_NONE : OPC>(g, r0, lane, rr);
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
+    if (u >= unit_count(g)) return;
+    {
+        int64_t r0, rEnd, s0, s1;
+        unit_of(g, u, r0, rEnd, s0, s1);
+        RRows rr;
+        load_r<OPA, selective<OPA>() ? JOIN_OP_NONE : OPC>(g, r0, rEnd, lane, rr);
 
-    if constexpr (selective<OPA>()) {
-        uint64_t n = 0;
-        int2* st = g.stash ? g.stash + u * g.K : nullptr;
-        sweep_selective<OPA, OPC>(g, rr, r0, s0, s1, n, st, st ? (uint64_t)g.K : 0ull, lane);
-        if (lane == 0) counts[u] = n;
-    } else {
-        const cptr<int32_t> Sa = as_const(g.Sa);
-        const cptr<int32_t> Sc = as_const(g.Sc);
-        uint32_t cnt[kRB];
+        if constexpr (selective<OPA>()) {
+            uint64_t n = 0;
+            int2* st = g.stash ? g.stash + u * g.K : nullptr;
+            sweep_selective<OPA, OPC>(g, rr, r0, rEnd, s0, s1, n, st, st ? (uint64_t)g.K : 0ull,
+                                      lane);
+            if (lane == 0) counts[u] = n;
+        } else {
+            const cptr<int32_t> Sa = as_const(g.Sa);
+            const cptr<int32_t> Sc = as_const(g.Sc);
+            uint32_t cnt[kRB];
 #pragma unroll
-        for (int r = 0; r < kRB; ++r) cnt[r] = 0;
-        int64_t j = s0;
-        for (; j + kSGroup <= s1; j += kSGroup) {
-            int32_t sa[kSGroup], sc[kSGroup];
+            for (int r = 0; r < kRB; ++r) cnt[r] = 0;
+            int64_t j = s0;
+            for (; j + kSGroup <= s1; j += kSGroup) {
+                int32_t sa[kSGroup], sc[kSGroup];
 #pragma unroll
-            for (int k = 0; k < kSGroup; ++k) {
-                sa[k] = Sa[j + k];
-                sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+                for (int k = 0; k < kSGroup; ++k) {
+                    sa[k] = Sa[j + k];
+                    sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kSGroup; ++k)
+#pragma unroll
+                    for (int r = 0; r < kRB; ++r)
+                        cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa[k]) &&
+                                   holds<OPC>(rr.xc[r], 0u, sc[k])) ? 1u : 0u;
             }
-#pragma unroll
-            for (int k = 0; k < kSGroup; ++k)
+            for (; j < s1; ++j) {
+                const int32_t sa = Sa[j];
+                const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
 #pragma unroll
                 for (int r = 0; r < kRB; ++r)
-                    cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa[k]) &&
-                               holds<OPC>(rr.xc[r], 0u, sc[k])) ? 1u : 0u;
-        }
-        for (; j < s1; ++j) {
-            const int32_t sa = Sa[j];
-            const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+                    cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) ? 1u : 0u;
+            }
+            // Lanes past the end of the R block carry garbage counts: only valid rows are summed.
+            uint64_t mine = 0;
 #pragma unroll
-            for (int r = 0; r < kRB; ++r)
-                cnt[r] += (holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) ? 1u : 0u;
+            for (int r = 0; r < kRB; ++r) mine += (r0 + r * kWave + lane < rEnd) ? (uint64_t)cnt[r] : 0ull;
+            const uint64_t tot = wave_sum64(mine);
+            if (lane == 0) counts[u] = tot;
         }
-        // Lanes past the end of R carry garbage counts: only valid rows are summed.
-        uint64_t mine = 0;
-#pragma unroll
-        for (int r = 0; r < kRB; ++r) mine += (r0 + r * kWave + lane < g.nR) ? (uint64_t)cnt[r] : 0ull;
-        const uint64_t tot = wave_sum64(mine);
-        if (lane == 0) counts[u] = tot;
     }
 }
 
@@ -276,39 +302,41 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
                                                              const uint64_t* __restrict__ total,
                                                              int2* __restrict__ out, uint64_t cap)
 {
-    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
-    if (u >= g.U) return;
     const uint64_t tot = *total;
     if (tot > cap) return;  // an output too small for the exact count receives nothing
     const int lane = (int)lane_id();
-    const uint64_t off = uniform(offsets[u]);
-    const uint64_t cnt = (u + 1 < g.U ? uniform(offsets[u + 1]) : tot) - off;
-    if (cnt == 0) return;
-    if (g.stash && cnt <= (uint64_t)g.K) {  // the count pass kept every match of this unit
-        const int2* st = g.stash + u * g.K;
-        for (uint64_t i = lane; i < cnt; i += kWave) out[off + i] = st[i];
-        return;
-    }
-    int64_t r0, s0, s1;
-    unit_of(g, u, r0, s0, s1);
-    uint64_t base = off;
-    if constexpr (selective<OPA>()) {
-        RRows rr;
-        load_r<OPA, JOIN_OP_NONE>(g, r0, lane, rr);
-        sweep_selective<OPA, OPC>(g, rr, r0, s0, s1, base, out, cap, lane);
-    } else {
-        RRows rr;
-        load_r<OPA, OPC>(g, r0, lane, rr);
-        int32_t rid[kRB];
-        uint64_t vm[kRB];
-        load_rids(g, r0, lane, rid, vm);
-        const cptr<int32_t> Sa = as_const(g.Sa);
-        const cptr<int32_t> Sc = as_const(g.Sc);
-        const cptr<int32_t> Srid = as_const(g.Srid);
-        for (int64_t j = s0; j < s1; ++j) {
-            const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
-            const int32_t srid = Srid ? Srid[j] : (int32_t)j;
-            emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, base, out, cap, lane);
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
+    if (u >= unit_count(g)) return;
+    {
+        const uint64_t off = uniform(offsets[u]);
+        const uint64_t cnt = (u + 1 < g.nOff ? uniform(offsets[u + 1]) : tot) - off;
+        if (cnt == 0) return;
+        if (g.stash && cnt <= (uint64_t)g.K) {  // the count pass kept every match of this unit
+            const int2* st = g.stash + u * g.K;
+            for (uint64_t i = lane; i < cnt; i += kWave) out[off + i] = st[i];
+            return;
+        }
+        int64_t r0, rEnd, s0, s1;
+        unit_of(g, u, r0, rEnd, s0, s1);
+        uint64_t base = off;
+        if constexpr (selective<OPA>()) {
+            RRows rr;
+            load_r<OPA, JOIN_OP_NONE>(g, r0, rEnd, lane, rr);
+            sweep_selective<OPA, OPC>(g, rr, r0, rEnd, s0, s1, base, out, cap, lane);
+        } else {
+            RRows rr;
+            load_r<OPA, OPC>(g, r0, rEnd, lane, rr);
+            int32_t rid[kRB];
+            uint64_t vm[kRB];
+            load_rids(g, r0, rEnd, lane, rid, vm);
+            const cptr<int32_t> Sa = as_const(g.Sa);
+            const cptr<int32_t> Sc = as_const(g.Sc);
+            const cptr<int32_t> Srid = as_const(g.Srid);
+            for (int64_t j = s0; j < s1; ++j) {
+                const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+                const int32_t srid = Srid ? Srid[j] : (int32_t)j;
+                emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, base, out, cap, lane);
+            }
         }
     }
 }
@@ -393,12 +421,60 @@ ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, co
     g.TS = pl.TS;
     g.nSt = pl.nSt;
     g.U = pl.U;
+    g.units = nullptr;
+    g.Uptr = nullptr;
+    g.nOff = pl.U;
     return g;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+ThetaGeom unit_geom(const ThetaUnitArgs& a, const join_pred_t& p)
+{
+    ThetaGeom g{};
+    g.Ra = a.Ra;
+    g.Rc = a.Rc;
+    g.Rrid = a.Rrid;
+    g.Sa = a.Sa;
+    g.Sc = a.Sc;
+    g.Srid = a.Srid;
+    g.w = p.op_a == JOIN_OP_BAND ? (int64_t)p.w : 0;
+    g.U = a.Umax;
+    g.stash = a.stash;
+    g.K = a.stash ? a.K : 0;
+    g.units = a.units;
+    g.Uptr = a.Uptr;
+    g.nOff = a.nOff;
+    return g;
+}
+
 }  // namespace
+
+hipError_t theta_count_units(const ThetaUnitArgs& a, const join_pred_t& p, uint64_t* counts,
+                             hipStream_t st)
+{
+    if (a.Umax <= 0) return hipSuccess;
+    CountFn f = count_fn(p.op_a, p.op_c);
+    if (!f) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)ceil_div(a.Umax, kWavesPerBlock);
+    prof::Scope ps(st, "region.count");
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, unit_geom(a, p), counts);
+    return hipGetLastError();
+}
+
+hipError_t theta_write_units(const ThetaUnitArgs& a, const join_pred_t& p,
+                             const uint64_t* offsets, const uint64_t* total, int32_t* pairs,
+                             uint64_t cap, hipStream_t st)
+{
+    if (a.Umax <= 0) return hipSuccess;
+    WriteFn f = write_fn(p.op_a, p.op_c);
+    if (!f) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)ceil_div(a.Umax, kWavesPerBlock);
+    prof::Scope ps(st, "region.write");
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThetaBlock), 0, st, unit_geom(a, p), offsets, total,
+                       reinterpret_cast<int2*>(pairs), cap);
+    return hipGetLastError();
+}
 
 ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int64_t ts_override,
                      int64_t stash_k)

@@ -22,6 +22,24 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int
 hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
                        const join_pred_t& p, char* ws, hipStream_t st);
 
+// Theta kernels over an explicit unit table (the red regions of the region-pruned join).
+struct ThetaUnitArgs {
+    const int32_t *Ra, *Rc, *Rrid;  // bucketed R columns (rid materialised)
+    const int32_t *Sa, *Sc, *Srid;  // bucketed S columns
+    const uint4* units;             // [Umax] {r0, rEnd, s0, s1}
+    const uint32_t* Uptr;           // device unit count
+    int64_t Umax;
+    int2* stash;                    // [Umax][K] or NULL
+    int64_t K;
+    int64_t nOff;                   // entries of the offsets array
+};
+
+hipError_t theta_count_units(const ThetaUnitArgs& a, const join_pred_t& p, uint64_t* counts,
+                             hipStream_t st);
+hipError_t theta_write_units(const ThetaUnitArgs& a, const join_pred_t& p,
+                             const uint64_t* offsets, const uint64_t* total, int32_t* pairs,
+                             uint64_t cap, hipStream_t st);
+
 // Write pass from the offsets left by theta_count.
 hipError_t theta_write(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
                        const join_pred_t& p, char* ws, int32_t* pairs, uint64_t cap,

@@ -22,10 +22,11 @@ import dataclasses
 import torch
 
 from . import _native
-from ._native import JOIN_KIND_HASH, JOIN_KIND_THETA, OPS, JoinPred, JoinRel
+from ._native import JOIN_KIND_HASH, JOIN_KIND_THETA, JOIN_KIND_THETA_REGION, OPS, JoinPred, JoinRel
 
 __all__ = [
-    "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "join_workspace_bytes",
+    "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "JOIN_KIND_THETA_REGION",
+    "join_workspace_bytes",
     "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
     "hash_join", "theta_join",
 ]
@@ -191,6 +192,8 @@ def hash_join(R: Relation, S: Relation, ws: torch.Tensor | None = None, stream=N
     return _exact(JOIN_KIND_HASH, R, S, None, ws, stream)
 
 
-def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = None, stream=None):
-    """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output."""
-    return _exact(JOIN_KIND_THETA, R, S, pred, ws, stream)
+def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = None, stream=None,
+               region: bool = False):
+    """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output.
+    region=True uses the region-pruned algorithm (JOIN_KIND_THETA_REGION); same result."""
+    return _exact(JOIN_KIND_THETA_REGION if region else JOIN_KIND_THETA, R, S, pred, ws, stream)
