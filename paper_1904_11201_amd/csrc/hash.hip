@@ -14,10 +14,9 @@
 //   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
 //                   computed exactly instead of estimated);
 //   7. write pass:  same units, re-probe, each match written at offset + block-scanned rank.
-// The LDS table is open addressing with linear probing in "ordered" form: along every probe run
-// entries are non-decreasing in (key, rid), so the layout does not depend on insertion order and
-// a lookup stops at the first key above the probe key.  Its empty marker is a 64-bit value
-// proven absent from the chunk, so every int32 key and rid value stays usable.
+// The LDS table is 4-slot buckets with linear probing over buckets; keys are probed several at a
+// time per thread in lockstep, with predicated compares, so a wave issues its LDS reads together
+// and branches only on the wave-uniform exit.
 #include "hash.hpp"
 
 #include "prof.hpp"
@@ -32,8 +31,8 @@ constexpr int kScatBlock = 1024;
 constexpr int kScatTile = 8192;  // tuples staged in LDS per scatter step
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
-constexpr int kEmptyCands = 8;
 constexpr int kMaxBits = 13;     // scatter LDS: 2 * 2^13 * 4 B of counters + the staged tile
+constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
 
 __device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
 {
@@ -307,96 +306,226 @@ __device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
     return o;
 }
 
-__device__ __forceinline__ uint64_t empty_cand(int i)
+// ------------------------------------------------------------------------ the LDS table --
+// Fixed-size buckets of 4 slots, like the paper's hash buckets with a short search inside the
+// bucket (Section 3.3.2).  Bucket b holds 4 keys (one 16-byte LDS read), the 4 matching rids
+// (another) and a claim counter; min(claims, 4) slots are filled.  Each key has two candidate
+// buckets b1 != b2 from independent bits of its hash.  An insert claims a slot (LDS atomic add)
+// in the less loaded of the two, then in the other; a claim past the 4th slot fails.  If both
+// fail it walks on from b2 + 1, claiming bucket by bucket.  So every bucket an insert failed in
+// ends with more than 4 claims, and a lookup reads b1 and b2 and walks on from b2 + 1 only when
+// both hold more than 4 claims, stopping after the first bucket with at most 4.  At load 0.6 the
+// two choices keep that walk to about 2 lookups in 10^4, so a lookup is two bucket reads with
+// predicated compares.  No empty marker is needed: every int32 key and rid value stays usable.
+constexpr int kSlots = 4;
+#ifndef JL_HASH_PROBE
+#define JL_HASH_PROBE 2
+#endif
+constexpr int kProbe = JL_HASH_PROBE;  // keys probed together per thread
+
+__host__ __device__ __forceinline__ uint32_t table_buckets(uint32_t rN)
 {
-    return ~0ull - (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    const uint32_t nb = (rN * 5 + 11) / 12;  // 4 * nb * 0.6 >= rN
+    return nb < 2 ? 2u : nb;                 // two distinct candidates need two buckets
 }
 
-__device__ __forceinline__ uint32_t home_of(uint32_t h, int bits, uint32_t C)
+__device__ __forceinline__ uint32_t next_bucket(uint32_t b, uint32_t nb) { return b + 1 == nb ? 0 : b + 1; }
+
+// The two candidate buckets of hash h.  The partition id took the top `bits` bits of h, so b1
+// comes from the bits below it and b2 from a multiplicative remix of all of h.
+__device__ __forceinline__ void choices(uint32_t h, int bits, uint32_t nb, uint32_t& b1, uint32_t& b2)
 {
-    return (uint32_t)(((uint64_t)(bits >= 32 ? 0u : (h << bits)) * C) >> 32);
+    b1 = (uint32_t)(((uint64_t)(bits >= 32 ? 0u : (h << bits)) * nb) >> 32);
+    b2 = (uint32_t)(((uint64_t)(h * 0x9E3779B1u) * nb) >> 32);
+    b2 = b2 == b1 ? next_bucket(b1, nb) : b2;
 }
 
-// Build the ordered linear-probing table of one R chunk in LDS.  Returns the empty marker.
-__device__ __forceinline__ uint64_t build_table(const JoinGeom& g, const Unit& un, uint64_t* tab,
-                                                uint32_t C, uint32_t* flag)
+struct Table {
+    const uint4* keys;    // [nb]: the 4 keys of each bucket
+    const uint4* rids;    // [nb]: their rids
+    const uint32_t* cnt;  // [nb]: claims; min(cnt, 4) slots are filled
+    uint32_t nb;
+};
+
+// Build the table of one R chunk in LDS.
+__device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, uint4* lds)
 {
     const int tid = threadIdx.x;
-    uint64_t v[kBuildItems];
-    uint32_t present = 0;
+    const uint32_t nb = table_buckets(un.rN);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(lds);
+    uint32_t* rids = reinterpret_cast<uint32_t*>(lds + nb);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + 2 * nb);
+    // Issue every load of the chunk before any use (uniform guards only), so the chunk arrives
+    // in one memory round trip instead of one per item.
+    const uint32_t nIt = (un.rN + kJoinBlock - 1) / kJoinBlock;
+    const int32_t* __restrict__ rk = g.rk;
+    const int32_t* __restrict__ rr = g.rr;
+    uint32_t kk[kBuildItems], rv[kBuildItems];
 #pragma unroll
-    for (int i = 0; i < kBuildItems; ++i) {
-        const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
-        if (e < un.rN) {
-            const uint32_t idx = un.rBeg + e;
-            const uint32_t k = (uint32_t)g.rk[idx];
-            const uint32_t r = g.rr ? (uint32_t)g.rr[idx] : idx;
-            v[i] = ((uint64_t)k << 32) | r;
+    for (int i = 0; i < kBuildItems; ++i) kk[i] = rv[i] = 0u;
+    if (un.rN > 0) {  // every unit has rN >= 1; the guard keeps the clamped index in bounds
 #pragma unroll
-            for (int c = 0; c < kEmptyCands; ++c) present |= (v[i] == empty_cand(c)) ? (1u << c) : 0u;
+        for (int i = 0; i < kBuildItems; ++i) {
+            const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+            const uint32_t idx = un.rBeg + (e < un.rN ? e : un.rN - 1);
+            kk[i] = (uint32_t)i < nIt ? (uint32_t)rk[idx] : 0u;
+            rv[i] = (uint32_t)i < nIt ? (rr ? (uint32_t)rr[idx] : idx) : 0u;
         }
     }
-    uint64_t empty = 0;
-    // Pick the first candidate marker absent from the chunk.  A chunk holding all candidates
-    // (possible only for adversarial input) moves on to the next batch of candidates.
-    for (int batch = 0;; ++batch) {
-        if (tid == 0) *flag = 0;
-        __syncthreads();
-        if (batch > 0) {
-            present = 0;
-#pragma unroll
-            for (int i = 0; i < kBuildItems; ++i) {
-                const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
-                if (e < un.rN)
-#pragma unroll
-                    for (int c = 0; c < kEmptyCands; ++c)
-                        present |= (v[i] == empty_cand(batch * kEmptyCands + c)) ? (1u << c) : 0u;
-            }
-        }
-        // wave-level OR, then one LDS atomic per wave
-        uint32_t wor = present;
-        for (int c = 0; c < kEmptyCands; ++c)
-            wor |= ballot((present >> c) & 1u) ? (1u << c) : 0u;
-        if (lane_id() == 0 && wor) atomicOr(flag, wor);
-        __syncthreads();
-        const uint32_t f = *flag;
-        __syncthreads();  // every thread has read the flag before it is reset
-        if (f != (1u << kEmptyCands) - 1) {
-            empty = empty_cand(batch * kEmptyCands + __builtin_ctz(~f));
-            break;
-        }
-    }
-    for (uint32_t s = tid; s < C; s += kJoinBlock) tab[s] = empty;
+    for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
         const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
         if (e < un.rN) {
-            uint64_t x = v[i];
-            uint32_t pos = home_of(hmix((uint32_t)(x >> 32)), g.bits, C);
-            while (true) {
-                const uint64_t c = tab[pos];
-                if (c == empty) {
-                    if (atomicCAS((unsigned long long*)&tab[pos], (unsigned long long)empty,
-                                  (unsigned long long)x) == empty)
-                        break;
-                    continue;  // lost the race: look at this slot again
-                }
-                if (c <= x) {
-                    pos = pos + 1 == C ? 0 : pos + 1;
-                    continue;
-                }
-                // x goes before c: swap in x, carry c further along the run
-                if (atomicCAS((unsigned long long*)&tab[pos], (unsigned long long)c,
-                              (unsigned long long)x) == c) {
-                    x = c;
-                    pos = pos + 1 == C ? 0 : pos + 1;
+            uint32_t b1, b2;
+            choices(hmix(kk[i]), g.bits, nb, b1, b2);
+            const bool second = cnt[b2] < cnt[b1];  // a racy read only steers the choice
+            uint32_t b = second ? b2 : b1;
+            uint32_t old = atomicAdd(&cnt[b], 1u);
+            if (old >= (uint32_t)kSlots) {
+                b = second ? b1 : b2;
+                old = atomicAdd(&cnt[b], 1u);
+                if (old >= (uint32_t)kSlots) {
+                    b = b2;
+                    do {  // ends: 4 * nb slots > rN entries
+                        b = next_bucket(b, nb);
+                        old = atomicAdd(&cnt[b], 1u);
+                    } while (old >= (uint32_t)kSlots);
                 }
             }
+            keys[b * kSlots + old] = kk[i];
+            rids[b * kSlots + old] = rv[i];
         }
     }
     __syncthreads();
-    return empty;
+    Table t;
+    t.keys = lds;
+    t.rids = lds + nb;
+    t.cnt = cnt;
+    t.nb = nb;
+    return t;
+}
+
+// Matches of x among the filled slots of one bucket, as a 4-bit mask.
+__device__ __forceinline__ uint32_t bucket_hits(const uint4& k, uint32_t c, uint32_t x)
+{
+    return (uint32_t)(k.x == x && c > 0) | ((uint32_t)(k.y == x && c > 1) << 1) |
+           ((uint32_t)(k.z == x && c > 2) << 2) | ((uint32_t)(k.w == x && c > 3) << 3);
+}
+
+// The walk past b1 and b2 (rare): buckets from b2 + 1 while the previous one holds more than 4
+// claims.  A walk that wraps onto b1 or b2 skips their slots, which were already counted.
+template <typename Visit>
+__device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1, uint32_t b2, Visit visit)
+{
+    uint32_t b = b2;
+    while (true) {
+        b = next_bucket(b, t.nb);
+        const uint32_t c = t.cnt[b];
+        if (b != b1 && b != b2) visit(b, bucket_hits(t.keys[b], c, x));
+        if (c <= (uint32_t)kSlots) break;
+    }
+}
+
+// Count the entries of N keys: read both candidate buckets of every key (all reads issued
+// together), count the matching slots with predicated arithmetic, and walk on only for keys
+// whose two buckets both overflowed.
+template <int N>
+__device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
+                                                const bool (&valid)[N])
+{
+    uint32_t b1[N], b2[N], c1[N], c2[N];
+    uint4 k1[N], k2[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) choices(hmix(x[i]), bits, t.nb, b1[i], b2[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        k1[i] = t.keys[b1[i]];
+        c1[i] = t.cnt[b1[i]];
+        k2[i] = t.keys[b2[i]];
+        c2[i] = t.cnt[b2[i]];
+    }
+    uint32_t n = 0;
+    bool walk = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint32_t h = __builtin_popcount(bucket_hits(k1[i], c1[i], x[i])) +
+                           __builtin_popcount(bucket_hits(k2[i], c2[i], x[i]));
+        n += valid[i] ? h : 0u;
+        walk = walk || (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots);
+    }
+    if (ballot(walk)) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots)
+                walk_on(t, x[i], b1[i], b2[i], [&](uint32_t, uint32_t hm) { n += __builtin_popcount(hm); });
+    }
+    return n;
+}
+
+// Probe N keys for the write pass: per key the number of entries and the LDS word positions of
+// the first two, whose rids are read once the output slots are known (a key with more than two
+// build matches visits its buckets again when it is written).
+template <int N>
+__device__ __forceinline__ void probe_write(const Table& t, int bits, const uint32_t (&x)[N],
+                                            const bool (&valid)[N], uint32_t (&m)[N],
+                                            uint32_t (&p1)[N], uint32_t (&p2)[N])
+{
+    uint32_t b1[N], b2[N], c1[N], c2[N];
+    uint4 k1[N], k2[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) choices(hmix(x[i]), bits, t.nb, b1[i], b2[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        k1[i] = t.keys[b1[i]];
+        c1[i] = t.cnt[b1[i]];
+        k2[i] = t.keys[b2[i]];
+        c2[i] = t.cnt[b2[i]];
+    }
+    bool walk = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint32_t h1 = valid[i] ? bucket_hits(k1[i], c1[i], x[i]) : 0u;
+        const uint32_t h2 = valid[i] ? bucket_hits(k2[i], c2[i], x[i]) : 0u;
+        // slots of the two buckets as one 8-bit mask: bit j < 4 is b1's slot j, bit 4 + j b2's
+        const uint32_t hm = h1 | (h2 << 4);
+        const uint32_t j1 = __builtin_ctz(hm | 256u), j2 = __builtin_ctz((hm & (hm - 1)) | 256u);
+        p1[i] = j1 < 4 ? b1[i] * kSlots + j1 : b2[i] * kSlots + (j1 & 3);
+        p2[i] = j2 < 4 ? b1[i] * kSlots + j2 : b2[i] * kSlots + (j2 & 3);
+        m[i] = __builtin_popcount(hm);
+        walk = walk || (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots);
+    }
+    if (ballot(walk)) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots)
+                walk_on(t, x[i], b1[i], b2[i], [&](uint32_t b, uint32_t hm) {
+                    while (hm) {
+                        const uint32_t p = b * kSlots + __builtin_ctz(hm);
+                        p2[i] = m[i] == 1 ? p : p2[i];
+                        p1[i] = m[i] == 0 ? p : p1[i];
+                        ++m[i];
+                        hm &= hm - 1;
+                    }
+                });
+    }
+}
+
+// Every entry of key x in visiting order (b1's slots, b2's, then the walk), as LDS word
+// positions; used for keys with more than two build matches.
+template <typename F>
+__device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_t x, F f)
+{
+    uint32_t b1, b2;
+    choices(hmix(x), bits, t.nb, b1, b2);
+    const uint32_t c1 = t.cnt[b1], c2 = t.cnt[b2];
+    auto emit = [&](uint32_t b, uint32_t hm) {
+        for (; hm; hm &= hm - 1) f(b * kSlots + __builtin_ctz(hm));
+    };
+    emit(b1, bucket_hits(t.keys[b1], c1, x));
+    emit(b2, bucket_hits(t.keys[b2], c2, x));
+    if (c1 > (uint32_t)kSlots && c2 > (uint32_t)kSlots) walk_on(t, x, b1, b2, emit);
 }
 
 // Units of this join.  The device total never exceeds Umax (sum over partitions of
@@ -407,51 +536,20 @@ __device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
     return (int64_t)U < g.Umax ? U : (uint32_t)g.Umax;
 }
 
-__device__ __forceinline__ uint32_t table_slots(uint32_t rN)
-{
-    uint32_t c = 2 * rN;
-    c = (c + 63) & ~63u;
-    return c < 64 ? 64 : c;
-}
-
-// Probe one key: number of entries with this key, and the rids of the first two of them.
-__device__ __forceinline__ uint32_t probe(const uint64_t* tab, uint32_t C, uint64_t empty,
-                                          uint32_t home, uint32_t x, int32_t& r1, int32_t& r2)
-{
-    uint32_t m = 0, pos = home;
-    while (true) {
-        const uint64_t c = tab[pos];
-        if (c == empty) break;
-        const uint32_t ck = (uint32_t)(c >> 32);
-        if (ck == x) {
-            if (m == 0) r1 = (int32_t)(uint32_t)c;
-            else if (m == 1) r2 = (int32_t)(uint32_t)c;
-            ++m;
-        } else if (ck > x) {
-            break;
-        }
-        pos = pos + 1 == C ? 0 : pos + 1;
-    }
-    return m;
-}
-
-__device__ __forceinline__ uint32_t probe_count(const uint64_t* tab, uint32_t C, uint64_t empty,
-                                                uint32_t home, uint32_t x)
-{
-    uint32_t m = 0, pos = home;
-    while (true) {
-        const uint64_t c = tab[pos];
-        if (c == empty) break;
-        const uint32_t ck = (uint32_t)(c >> 32);
-        if (ck == x) ++m;
-        else if (ck > x) break;
-        pos = pos + 1 == C ? 0 : pos + 1;
-    }
-    return m;
-}
-
-constexpr int kCountBatch = 8;  // S keys in flight per thread in the count pass
-constexpr int kWriteBatch = 4;  // S tuples per thread per round of the write pass
+#ifndef JL_HASH_COUNT_BATCH
+#define JL_HASH_COUNT_BATCH 8
+#endif
+#if defined(JL_HASH_WPE) && JL_HASH_WPE > 0  // occupancy the join kernels are compiled for
+#define JL_JOIN_ATTR __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(JL_HASH_WPE)))
+#else
+#define JL_JOIN_ATTR __launch_bounds__(kJoinBlock)
+#endif
+constexpr int kCountBatch = JL_HASH_COUNT_BATCH;  // S keys in flight per thread in the count pass
+static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a time");
+#ifndef JL_HASH_WRITE_PROBE
+#define JL_HASH_WRITE_PROBE 2
+#endif
+constexpr int kWriteBatch = JL_HASH_WRITE_PROBE;  // S tuples per thread per round of the write pass
 
 __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
                                             uint32_t (&x)[kWriteBatch], int32_t (&r)[kWriteBatch])
@@ -476,20 +574,18 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
     }
 }
 
-__global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
+__global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
-    extern __shared__ uint64_t tab[];
-    __shared__ uint32_t flag;
+    extern __shared__ uint4 tab[];
     __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
     const uint32_t U = unit_total(g);
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         const Unit un = decode_unit(g, u);
-        const uint32_t C = table_slots(un.rN);
         // the first batch of S keys is in flight while the table is built; each later batch is
         // loaded while the previous one probes
         uint32_t xs[kCountBatch];
         load_keys(g, un, 0, xs);
-        const uint64_t empty = build_table(g, un, tab, C, &flag);
+        const Table t = build_table(g, un, tab);
         uint32_t cnt = 0;
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
             uint32_t cur[kCountBatch];
@@ -497,9 +593,15 @@ __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t*
             for (int i = 0; i < kCountBatch; ++i) cur[i] = xs[i];
             if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys(g, un, e0 + kJoinBlock * kCountBatch, xs);
 #pragma unroll
-            for (int i = 0; i < kCountBatch; ++i) {
-                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-                if (e < un.sN) cnt += probe_count(tab, C, empty, home_of(hmix(cur[i]), g.bits, C), cur[i]);
+            for (int h = 0; h < kCountBatch; h += kProbe) {
+                uint32_t x[kProbe];
+                bool ok[kProbe];
+#pragma unroll
+                for (int i = 0; i < kProbe; ++i) {
+                    x[i] = cur[h + i];
+                    ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+                }
+                cnt += probe_count(t, g.bits, x, ok);
             }
         }
         uint32_t tot;
@@ -513,69 +615,63 @@ __global__ __launch_bounds__(kJoinBlock) void join_count_k(JoinGeom g, uint64_t*
         counts[i] = 0;
 }
 
-__global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
+__global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
                                                            const uint64_t* __restrict__ offsets,
                                                            const uint64_t* __restrict__ total,
                                                            int2* __restrict__ out, uint64_t cap)
 {
-    extern __shared__ uint64_t tab[];
-    __shared__ uint32_t flag;
-    __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
+    extern __shared__ uint4 tab[];
+    __shared__ uint32_t cursor;  // output slots of the current unit handed out so far
     if (*total > cap) return;  // an output too small for the exact count receives nothing
     const uint32_t U = unit_total(g);
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         const Unit un = decode_unit(g, u);
-        const uint32_t C = table_slots(un.rN);
         uint32_t nx[kWriteBatch];
         int32_t nr[kWriteBatch];
         load_tuples(g, un, 0, nx, nr);  // in flight while the table is built
-        const uint64_t empty = build_table(g, un, tab, C, &flag);
-        uint64_t base = offsets[u];
+        if (threadIdx.x == 0) cursor = 0;  // the barrier inside the build publishes it
+        const Table t = build_table(g, un, tab);
+        const uint64_t base = offsets[u];
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
-            uint32_t x[kWriteBatch], m[kWriteBatch];
-            int32_t srid[kWriteBatch], r1[kWriteBatch], r2[kWriteBatch];
+            uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
+            int32_t srid[kWriteBatch];
+            bool ok[kWriteBatch];
 #pragma unroll
             for (int i = 0; i < kWriteBatch; ++i) {
                 x[i] = nx[i];
                 srid[i] = nr[i];
+                ok[i] = e0 + i * kJoinBlock + threadIdx.x < un.sN;
             }
             if (e0 + kJoinBlock * kWriteBatch < un.sN)
                 load_tuples(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
-            uint32_t mine = 0;
+            probe_write(t, g.bits, x, ok, m, p1, p2);
+            // Slots inside the unit's range: waves take theirs from an LDS cursor (no block-wide
+            // barrier); within a wave, the pairs of the i-th tuple of every lane are contiguous,
+            // so each store instruction writes one coalesced run.
+            uint32_t excl[kWriteBatch], wtot = 0;
 #pragma unroll
             for (int i = 0; i < kWriteBatch; ++i) {
-                const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-                m[i] = 0;
-                r1[i] = r2[i] = 0;
-                if (e < un.sN)
-                    m[i] = probe(tab, C, empty, home_of(hmix(x[i]), g.bits, C), x[i], r1[i], r2[i]);
-                mine += m[i];
+                const uint32_t inc = wave_incl_scan(m[i]);
+                excl[i] = wtot + inc - m[i];
+                wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
             }
-            uint32_t tot;
-            uint64_t slot = base + block_excl_scan<kJoinBlock>(mine, wsum, &tot);
+            uint32_t wb = 0;
+            if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
+            wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
 #pragma unroll
             for (int i = 0; i < kWriteBatch; ++i) {
-                if (m[i] >= 1 && slot < cap) out[slot] = make_int2(r1[i], srid[i]);
-                if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2(r2[i], srid[i]);
-                if (m[i] > 2) {  // more than two build matches: walk the run again for the rest
-                    uint32_t pos = home_of(hmix(x[i]), g.bits, C), seen = 0;
-                    while (true) {
-                        const uint64_t c = tab[pos];
-                        if (c == empty) break;
-                        const uint32_t ck = (uint32_t)(c >> 32);
-                        if (ck == x[i]) {
-                            if (seen >= 2 && slot + seen < cap)
-                                out[slot + seen] = make_int2((int32_t)(uint32_t)c, srid[i]);
-                            ++seen;
-                        } else if (ck > x[i]) {
-                            break;
-                        }
-                        pos = pos + 1 == C ? 0 : pos + 1;
-                    }
+                const uint64_t slot = base + wb + excl[i];
+                if (m[i] >= 1 && slot < cap) out[slot] = make_int2((int32_t)rw[p1[i]], srid[i]);
+                if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2((int32_t)rw[p2[i]], srid[i]);
+                if (m[i] > 2) {  // more than two build matches: visit the buckets again
+                    uint32_t seen = 0;
+                    for_each_match(t, g.bits, x[i], [&](uint32_t p) {
+                        if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
+                        ++seen;
+                    });
                 }
-                slot += m[i];
             }
-            base += tot;
         }
         __syncthreads();
     }
@@ -583,8 +679,9 @@ __global__ __launch_bounds__(kJoinBlock) void join_write_k(JoinGeom g,
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// LDS bytes of the join kernels' table for R chunks of up to `cap` entries.
-size_t join_lds(uint32_t cap) { return (size_t)2 * ((cap * 2 + 63) & ~63u) * 4 + 64; }
+// LDS bytes of the join kernels' table for R chunks of up to `cap` entries: 32-byte buckets
+// plus a 4-byte claim counter each.
+size_t join_lds(uint32_t cap) { return (size_t)table_buckets(cap) * (2 * sizeof(uint4) + 4) + 64; }
 
 }  // namespace
 
@@ -600,9 +697,9 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     HashPlan pl{};
     pl.nR = nR;
     pl.nS = nS;
-    int cap = env_int("JOIN_HASH_CAP", 4608);
+    int cap = env_int("JOIN_HASH_CAP", 9216);
     if (cap < 64) cap = 64;
-    if (cap > kJoinBlock * kBuildItems) cap = kJoinBlock * kBuildItems;
+    if (cap > kMaxCap) cap = kMaxCap;
     pl.cap = cap;
     pl.slice = env_int("JOIN_HASH_SLICE", 32768);
     if (pl.slice < 1024) pl.slice = 1024;
