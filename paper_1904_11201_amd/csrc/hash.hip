@@ -13,10 +13,10 @@
 //   5. count pass:  per unit, build an LDS hash table from the R chunk and probe the S slice;
 //   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
 //                   computed exactly instead of estimated);
-//   7. write pass:  same units, re-probe, each match written at offset + block-scanned rank.
-// The LDS table is 4-slot buckets with linear probing over buckets; keys are probed several at a
-// time per thread in lockstep, with predicated compares, so a wave issues its LDS reads together
-// and branches only on the wave-uniform exit.
+//   7. write pass:  same units, re-probe, each match written inside the unit's output range at
+//                   a slot taken from a per-unit LDS cursor (one atomic per wave and round).
+// The LDS table is 4-slot buckets with two candidate buckets per key; a lookup reads both with
+// predicated compares, so a wave issues its LDS reads together and does not branch per key.
 #include "hash.hpp"
 
 #include "prof.hpp"
