@@ -5,10 +5,12 @@
 // lets each thread probe a contiguous range of the larger table S (equations NBSJ / IDSJ); its
 // MapReduce round first groups tuples by join_key / alpha so that each reducer joins one key
 // range (Algorithm 1, Map2 / Reduce2).  The gfx950 design keeps that shape but moves it on chip:
-//   1. histogram:   per chunk of input, LDS histogram of pid = hash(key) >> (32 - bits);
-//   2. scan:        exclusive scan of the partition-major histograms -> write offsets;
-//   3. scatter:     per tile, an LDS counting sort by pid, then runs of equal pid written out
-//                   contiguously (R and S, key and rid columns);
+//   1. histogram:   per chunk of input, LDS histogram of pid = hash(key) >> (32 - bits); each
+//                   chunk reserves its range inside every partition with one global atomic;
+//   2. scan:        exclusive scan of the partition sizes -> partition starts;
+//   3. scatter:     per tile, LDS-atomic ranks, and (key, rid) tuples written partition-major
+//                   through per-partition LDS carry buffers, so writes cover whole 64-byte
+//                   HBM granules;
 //   4. plan:        per partition, work units = (R chunk that fits the LDS table) x (S slice);
 //   5. count pass:  per unit, build an LDS hash table from the R chunk and probe the S slice;
 //   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
@@ -26,12 +28,14 @@ namespace jl {
 
 namespace {
 
-constexpr int kHistBlock = 512;
+constexpr int kHistBlock = 1024;
 constexpr int kScatBlock = 1024;
-constexpr int kScatTile = 8192;  // tuples staged in LDS per scatter step
+constexpr int kScatIt = 4;                       // tuples per thread per scatter tile
+constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile
+constexpr int kCarry = 8;                        // 8-byte tuples per 64-byte HBM write granule
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
-constexpr int kMaxBits = 13;     // scatter LDS: 2 * 2^13 * 4 B of counters + the staged tile
+constexpr int kMaxBits = 11;     // scatter LDS: 2^11 partitions x (64 B carry + 12 B counters)
 constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
 
 __device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
@@ -39,11 +43,21 @@ __device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
     return sh >= 32 ? 0u : hmix((uint32_t)key) >> sh;
 }
 
+__global__ void zero_u32_k(uint32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 // ------------------------------------------------------------------------------- histogram --
+// Chunk c counts its tuples per partition in LDS, then reserves its range inside every partition
+// with one global atomic add per non-empty partition: offs[c][p] is the chunk's offset inside
+// partition p and tot[p] ends as the partition's size.  Ranges of different chunks are disjoint;
+// their order inside a partition follows the order of the atomics.
 template <bool VEC>
 __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__ key, int64_t n,
-                                                     int64_t chunk, int bits,
-                                                     uint32_t* __restrict__ hist, int64_t nCh)
+                                                     int64_t chunk, int bits, uint32_t* __restrict__ tot,
+                                                     uint32_t* __restrict__ offs)
 {
     extern __shared__ uint32_t h[];
     constexpr int V = 4;  // 16-byte loads in flight per thread
@@ -72,170 +86,150 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
     }
     for (i += threadIdx.x; i < end; i += kHistBlock) atomicAdd(&h[pid_of(key[i], sh)], 1u);
     __syncthreads();
-    for (int p = threadIdx.x; p < P; p += kHistBlock) hist[(int64_t)p * nCh + blockIdx.x] = h[p];
-}
-
-// --------------------------------------------------------------------------------- scatter --
-// One thread's share of a staged tile: IT tuples (key, rid) and their tile-local indices.
-template <int IT>
-struct TileRegs {
-    int32_t k[IT], r[IT];
-};
-
-// Load tile [t0, t0 + tn) into registers.  With VEC, thread t owns the 4-tuple groups
-// (q * BLOCK + t) * 4 .. +3 and a full tile is read with 2 * IT / 4 unconditional 16-byte loads.
-template <bool VEC, bool HAS_RID, int IT>
-__device__ __forceinline__ void load_tile(const int32_t* __restrict__ key,
-                                          const int32_t* __restrict__ rid, int64_t t0, int tn,
-                                          TileRegs<IT>& tr)
-{
-    const int tid = threadIdx.x;
-    if constexpr (VEC) {
-        if (tn == kScatTile) {
-#pragma unroll
-            for (int q = 0; q < IT / 4; ++q) {
-                const int e = (q * kScatBlock + tid) * 4;
-                const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + e);
-                tr.k[4 * q] = k4.x; tr.k[4 * q + 1] = k4.y; tr.k[4 * q + 2] = k4.z; tr.k[4 * q + 3] = k4.w;
-                if constexpr (HAS_RID) {
-                    const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + e);
-                    tr.r[4 * q] = r4.x; tr.r[4 * q + 1] = r4.y; tr.r[4 * q + 2] = r4.z; tr.r[4 * q + 3] = r4.w;
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) tr.r[4 * q + c] = (int32_t)(t0 + e + c);
-                }
-            }
-            return;
-        }
-#pragma unroll
-        for (int q = 0; q < IT / 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int e = (q * kScatBlock + tid) * 4 + c;
-                const bool ok = e < tn;
-                tr.k[4 * q + c] = ok ? key[t0 + e] : 0;
-                tr.r[4 * q + c] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
-            }
-    } else {
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const int e = q * kScatBlock + tid;
-            const bool ok = e < tn;
-            tr.k[q] = ok ? key[t0 + e] : 0;
-            tr.r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
-        }
+    for (int p = threadIdx.x; p < P; p += kHistBlock) {
+        const uint32_t v = h[p];
+        offs[(int64_t)blockIdx.x * P + p] = v ? atomicAdd(&tot[p], v) : 0u;
     }
 }
 
-template <bool VEC, int IT>
-__device__ __forceinline__ int tile_index(int q)
+// --------------------------------------------------------------------------------- scatter --
+// Partitioned tuples are written as 8-byte (key, rid) pairs, partition-major.  An HBM write that
+// covers only part of a 64-byte granule costs a read-modify-write, and with 2^11 partitions a
+// tile holds only a few tuples per partition, so the tuples of each partition are held back in
+// an LDS carry buffer (up to 7 of them) until they complete a granule: every write below then
+// ends on a granule boundary, and only the first and last granule of a chunk's range inside a
+// partition are written in part.  Per tile of kScatTile tuples:
+//   1. rank each tuple inside its partition's share of the tile (LDS atomic);
+//   2. for partition p with carried tuples k, tile tuples t and write position w, the share
+//      ends at e = w + k + t; everything before A = e rounded down to 8 tuples is written now
+//      (the carried tuples and the tile tuples that fall before A), the rest is carried;
+//   3. the carry buffers and positions are updated.
+// Tuples of a partition keep their tile order only up to the atomics' order, which does not
+// matter to the join.
+template <bool VEC, bool HAS_RID>
+__device__ __forceinline__ void scat_load(const int32_t* __restrict__ key, const int32_t* __restrict__ rid,
+                                          int64_t t0, int tn, int32_t (&k)[kScatIt], int32_t (&r)[kScatIt])
 {
     const int tid = threadIdx.x;
-    return VEC ? (q / 4 * kScatBlock + tid) * 4 + (q % 4) : q * kScatBlock + tid;
+    if (VEC && tn == kScatTile) {
+        const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + 4 * tid);
+        k[0] = k4.x; k[1] = k4.y; k[2] = k4.z; k[3] = k4.w;
+        if constexpr (HAS_RID) {
+            const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + 4 * tid);
+            r[0] = r4.x; r[1] = r4.y; r[2] = r4.z; r[3] = r4.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < kScatIt; ++q) r[q] = (int32_t)(t0 + 4 * tid + q);
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        const int e = 4 * tid + q;
+        const bool ok = e < tn;
+        k[q] = ok ? key[t0 + e] : 0;
+        r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
+    }
 }
 
-// LDS layout: cursor[P] | tstart[P + 1] | skey[TILE] | srid[TILE] | spid[TILE] (uint16)
-// The next tile's tuples are loaded into registers before the current tile's LDS phases, so
-// its HBM reads overlap the counting sort and the writes of the current tile.
 template <bool VEC, bool HAS_RID>
 __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restrict__ key,
                                                         const int32_t* __restrict__ rid, int64_t n,
                                                         int64_t chunk, int bits,
-                                                        const uint32_t* __restrict__ off,
-                                                        int64_t nCh, int32_t* __restrict__ outk,
-                                                        int32_t* __restrict__ outr)
+                                                        const uint32_t* __restrict__ base,
+                                                        const uint32_t* __restrict__ offs,
+                                                        int2* __restrict__ out)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[kScatBlock / kWave + 1];
     const int P = 1 << bits;
     const int sh = 32 - bits;
-    uint32_t* cursor = lds;
-    uint32_t* tstart = lds + P;
-    int32_t* skey = reinterpret_cast<int32_t*>(tstart + P + 1);
-    int32_t* srid = skey + kScatTile;
-    uint16_t* spid = reinterpret_cast<uint16_t*>(srid + kScatTile);
-    constexpr int IT = kScatTile / kScatBlock;
+    int2* carry = reinterpret_cast<int2*>(lds);           // [P][kCarry]
+    uint32_t* wpos = lds + (size_t)P * kCarry * 2;        // [P] next position not yet written
+    uint32_t* kc = wpos + P;                              // [P] tuples carried
+    uint32_t* tc = kc + P;                                // [P] tuples of the current tile
     const int tid = threadIdx.x;
-
     for (int p = tid; p < P; p += kScatBlock) {
-        cursor[p] = off[(int64_t)p * nCh + blockIdx.x];
-        tstart[p] = 0;
+        wpos[p] = base[p] + offs[(int64_t)blockIdx.x * P + p];
+        kc[p] = 0;
+        tc[p] = 0;
     }
     __syncthreads();
-
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < n ? beg + chunk : n;
-    const int seg = (P + kScatBlock - 1) / kScatBlock;  // scan segment per thread
-
-    TileRegs<IT> nxt;
+    int32_t nk[kScatIt], nr[kScatIt];
     if (beg < end)
-        load_tile<VEC, HAS_RID, IT>(key, rid, beg,
-                                    (int)(end - beg < kScatTile ? end - beg : kScatTile), nxt);
+        scat_load<VEC, HAS_RID>(key, rid, beg, (int)(end - beg < kScatTile ? end - beg : kScatTile), nk, nr);
     for (int64_t t0 = beg; t0 < end; t0 += kScatTile) {
         const int tn = (int)(end - t0 < kScatTile ? end - t0 : kScatTile);
-        const TileRegs<IT> cur = nxt;
+        int32_t k[kScatIt], r[kScatIt];
+#pragma unroll
+        for (int q = 0; q < kScatIt; ++q) {
+            k[q] = nk[q];
+            r[q] = nr[q];
+        }
         const int64_t t1 = t0 + kScatTile;
         if (t1 < end)
-            load_tile<VEC, HAS_RID, IT>(key, rid, t1,
-                                        (int)(end - t1 < kScatTile ? end - t1 : kScatTile), nxt);
-        // 1. rank each tuple within its partition (LDS atomics)
-        uint32_t p[IT], rank[IT];
+            scat_load<VEC, HAS_RID>(key, rid, t1, (int)(end - t1 < kScatTile ? end - t1 : kScatTile), nk, nr);
+        uint32_t p[kScatIt], j[kScatIt];
 #pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            p[q] = pid_of(cur.k[q], sh);
-            rank[q] = tile_index<VEC, IT>(q) < tn ? atomicAdd(&tstart[p[q]], 1u) : 0u;
+        for (int q = 0; q < kScatIt; ++q) {
+            p[q] = pid_of(k[q], sh);
+            j[q] = 4 * tid + q < tn ? atomicAdd(&tc[p[q]], 1u) : 0u;
         }
         __syncthreads();
-        // 2. exclusive scan of the tile histogram in place; tstart[P] = tn
-        {
-            uint32_t s = 0;
-            for (int i = 0; i < seg; ++i) {
-                const int pp = tid * seg + i;
-                s += pp < P ? tstart[pp] : 0u;
+        uint32_t slot[kScatIt];  // carry slot, or kCarry when written now or not a tuple
+#pragma unroll
+        for (int q = 0; q < kScatIt; ++q) {
+            slot[q] = kCarry;
+            if (4 * tid + q < tn) {
+                const uint32_t w = wpos[p[q]], c0 = kc[p[q]];
+                const uint32_t e = w + c0 + tc[p[q]];
+                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
+                const uint32_t pos = w + c0 + j[q];
+                if (pos < A) out[pos] = make_int2(k[q], r[q]);
+                else slot[q] = pos - (A > w ? A : w);
             }
-            uint32_t tot;
-            uint32_t run = block_excl_scan<kScatBlock>(s, wsum, &tot);
-            for (int i = 0; i < seg; ++i) {
-                const int pp = tid * seg + i;
-                if (pp < P) {
-                    const uint32_t c = tstart[pp];
-                    tstart[pp] = run;
-                    run += c;
+        }
+        for (int pp = tid; pp < P; pp += kScatBlock) {
+            const uint32_t t = tc[pp];
+            if (t) {
+                const uint32_t w = wpos[pp], c0 = kc[pp];
+                const uint32_t A = (w + c0 + t) & ~(uint32_t)(kCarry - 1);
+                if (A > w)
+                    for (uint32_t s = 0; s < c0; ++s) out[w + s] = carry[pp * kCarry + s];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kScatIt; ++q)
+            if (slot[q] < (uint32_t)kCarry) carry[p[q] * kCarry + slot[q]] = make_int2(k[q], r[q]);
+        for (int pp = tid; pp < P; pp += kScatBlock) {
+            const uint32_t t = tc[pp];
+            if (t) {
+                const uint32_t w = wpos[pp], c0 = kc[pp];
+                const uint32_t e = w + c0 + t;
+                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
+                if (A > w) {
+                    wpos[pp] = A;
+                    kc[pp] = e - A;
+                } else {
+                    kc[pp] = c0 + t;
                 }
-            }
-            if (tid == 0) tstart[P] = (uint32_t)tn;
-        }
-        __syncthreads();
-        // 3. stage in pid order
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            if (tile_index<VEC, IT>(q) < tn) {
-                const uint32_t pos = tstart[p[q]] + rank[q];
-                skey[pos] = cur.k[q];
-                srid[pos] = cur.r[q];
-                spid[pos] = (uint16_t)p[q];
+                tc[pp] = 0;
             }
         }
         __syncthreads();
-        // 4. write runs: consecutive threads write consecutive slots of one partition's run
-        for (int e = tid; e < tn; e += kScatBlock) {
-            const uint32_t pp = spid[e];
-            const uint32_t g = cursor[pp] + ((uint32_t)e - tstart[pp]);
-            outk[g] = skey[e];
-            outr[g] = srid[e];
-        }
-        __syncthreads();
-        for (int pp = tid; pp < P; pp += kScatBlock) cursor[pp] += tstart[pp + 1] - tstart[pp];
-        __syncthreads();
-        for (int pp = tid; pp < P; pp += kScatBlock) tstart[pp] = 0;
-        __syncthreads();
+    }
+    for (int pp = tid; pp < P; pp += kScatBlock) {
+        const uint32_t w = wpos[pp], c0 = kc[pp];
+        for (uint32_t s = 0; s < c0; ++s) out[w + s] = carry[pp * kCarry + s];
     }
 }
 
 // ------------------------------------------------------------------------------- planning --
-__global__ void plan_units_k(const uint32_t* __restrict__ offR, const uint32_t* __restrict__ offS,
-                             int64_t nChR, int64_t nChS, int P, uint32_t nR, uint32_t nS,
-                             uint32_t cap, uint32_t slice, PartInfo* __restrict__ info,
+__global__ void plan_units_k(const uint32_t* __restrict__ baseR, const uint32_t* __restrict__ totR,
+                             const uint32_t* __restrict__ baseS, const uint32_t* __restrict__ totS,
+                             int P, uint32_t cap, uint32_t slice, PartInfo* __restrict__ info,
                              uint32_t* __restrict__ units)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,11 +238,7 @@ __global__ void plan_units_k(const uint32_t* __restrict__ offR, const uint32_t* 
         units[P] = 0;
         return;
     }
-    const uint32_t rs = offR[(int64_t)p * nChR];
-    const uint32_t re = p + 1 < P ? offR[(int64_t)(p + 1) * nChR] : nR;
-    const uint32_t ss = offS[(int64_t)p * nChS];
-    const uint32_t se = p + 1 < P ? offS[(int64_t)(p + 1) * nChS] : nS;
-    const uint32_t nr = re - rs, ns = se - ss;
+    const uint32_t nr = totR[p], ns = totS[p];
     const uint32_t nrc = (nr + cap - 1) / cap;
     uint32_t nss = 0;
     if (nr > 0 && ns > 0) {
@@ -257,9 +247,9 @@ __global__ void plan_units_k(const uint32_t* __restrict__ offR, const uint32_t* 
         if (nss < 1) nss = 1;
     }
     PartInfo pi;
-    pi.rStart = rs;
+    pi.rStart = baseR[p];
     pi.nR = nr;
-    pi.sStart = ss;
+    pi.sStart = baseS[p];
     pi.nS = ns;
     pi.nSs = nss;
     pi.nRc = nrc;
@@ -347,7 +337,9 @@ struct Table {
     uint32_t nb;
 };
 
-// Build the table of one R chunk in LDS.
+// Build the table of one R chunk in LDS.  AOS: the chunk is partitioned (key, rid) tuples;
+// otherwise it is a range of the input columns.
+template <bool AOS>
 __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, uint4* lds)
 {
     const int tid = threadIdx.x;
@@ -360,6 +352,7 @@ __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, 
     const uint32_t nIt = (un.rN + kJoinBlock - 1) / kJoinBlock;
     const int32_t* __restrict__ rk = g.rk;
     const int32_t* __restrict__ rr = g.rr;
+    const int2* __restrict__ rt = g.rt;
     uint32_t kk[kBuildItems], rv[kBuildItems];
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) kk[i] = rv[i] = 0u;
@@ -368,8 +361,16 @@ __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, 
         for (int i = 0; i < kBuildItems; ++i) {
             const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
             const uint32_t idx = un.rBeg + (e < un.rN ? e : un.rN - 1);
-            kk[i] = (uint32_t)i < nIt ? (uint32_t)rk[idx] : 0u;
-            rv[i] = (uint32_t)i < nIt ? (rr ? (uint32_t)rr[idx] : idx) : 0u;
+            if ((uint32_t)i < nIt) {
+                if constexpr (AOS) {
+                    const int2 t = rt[idx];
+                    kk[i] = (uint32_t)t.x;
+                    rv[i] = (uint32_t)t.y;
+                } else {
+                    kk[i] = (uint32_t)rk[idx];
+                    rv[i] = rr ? (uint32_t)rr[idx] : idx;
+                }
+            }
         }
     }
     for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
@@ -551,6 +552,7 @@ static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a
 #endif
 constexpr int kWriteBatch = JL_HASH_WRITE_PROBE;  // S tuples per thread per round of the write pass
 
+template <bool AOS>
 __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
                                             uint32_t (&x)[kWriteBatch], int32_t (&r)[kWriteBatch])
 {
@@ -559,21 +561,30 @@ __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, u
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
         const bool ok = e < un.sN;
         const uint32_t idx = un.sBeg + e;
-        x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
-        r[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+        if constexpr (AOS) {
+            const int2 t = ok ? g.st[idx] : make_int2(0, 0);
+            x[i] = (uint32_t)t.x;
+            r[i] = t.y;
+        } else {
+            x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
+            r[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+        }
     }
 }
 
+template <bool AOS>
 __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
                                           uint32_t (&xs)[kCountBatch])
 {
 #pragma unroll
     for (int i = 0; i < kCountBatch; ++i) {
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-        xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
+        if constexpr (AOS) xs[i] = e < un.sN ? (uint32_t)g.st[un.sBeg + e].x : 0u;
+        else xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
     }
 }
 
+template <bool AOS>
 __global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
     extern __shared__ uint4 tab[];
@@ -584,14 +595,14 @@ __global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ cou
         // the first batch of S keys is in flight while the table is built; each later batch is
         // loaded while the previous one probes
         uint32_t xs[kCountBatch];
-        load_keys(g, un, 0, xs);
-        const Table t = build_table(g, un, tab);
+        load_keys<AOS>(g, un, 0, xs);
+        const Table t = build_table<AOS>(g, un, tab);
         uint32_t cnt = 0;
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
             uint32_t cur[kCountBatch];
 #pragma unroll
             for (int i = 0; i < kCountBatch; ++i) cur[i] = xs[i];
-            if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys(g, un, e0 + kJoinBlock * kCountBatch, xs);
+            if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys<AOS>(g, un, e0 + kJoinBlock * kCountBatch, xs);
 #pragma unroll
             for (int h = 0; h < kCountBatch; h += kProbe) {
                 uint32_t x[kProbe];
@@ -615,6 +626,7 @@ __global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ cou
         counts[i] = 0;
 }
 
+template <bool AOS>
 __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
                                                            const uint64_t* __restrict__ offsets,
                                                            const uint64_t* __restrict__ total,
@@ -628,9 +640,9 @@ __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
         const Unit un = decode_unit(g, u);
         uint32_t nx[kWriteBatch];
         int32_t nr[kWriteBatch];
-        load_tuples(g, un, 0, nx, nr);  // in flight while the table is built
+        load_tuples<AOS>(g, un, 0, nx, nr);  // in flight while the table is built
         if (threadIdx.x == 0) cursor = 0;  // the barrier inside the build publishes it
-        const Table t = build_table(g, un, tab);
+        const Table t = build_table<AOS>(g, un, tab);
         const uint64_t base = offsets[u];
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
@@ -644,7 +656,7 @@ __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
                 ok[i] = e0 + i * kJoinBlock + threadIdx.x < un.sN;
             }
             if (e0 + kJoinBlock * kWriteBatch < un.sN)
-                load_tuples(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
+                load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
             probe_write(t, g.bits, x, ok, m, p1, p2);
             // Slots inside the unit's range: waves take theirs from an LDS cursor (no block-wide
             // barrier); within a wave, the pairs of the i-th tuple of every lane are contiguous,
@@ -692,6 +704,8 @@ static int env_int(const char* name, int dflt)
     return atoi(s);
 }
 
+static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + 3 * sizeof(uint32_t)); }
+
 HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
 {
     HashPlan pl{};
@@ -726,7 +740,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         int bits = forced_bits;
         if (bits < 0) {
             // mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma for
-            // hashed unique keys) under cap
+            // hashed unique keys) under cap; past 2^kMaxBits partitions R chunks repeat per S slice
             const double target = cap * 0.9;
             bits = 1;
             while (bits < kMaxBits && (double)nR / (double)(1 << bits) > target) ++bits;
@@ -734,11 +748,15 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         if (bits > kMaxBits) bits = kMaxBits;
         pl.bits = bits;
         pl.P = 1 << bits;
+        // scatter chunks: one per resident scatter workgroup (the carry buffers decide how many
+        // fit a CU), each a whole number of tiles
+        int per_cu = (int)((160 * 1024) / scatter_lds(pl.P));
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 2) per_cu = 2;
         auto chunk_for = [&](int64_t n) {
-            int64_t c = ceil_div(n, (int64_t)num_cus * 4);
+            int64_t c = ceil_div(n, (int64_t)num_cus * per_cu);
             c = ceil_div(c, kScatTile) * kScatTile;
             if (c < kScatTile) c = kScatTile;
-            if (c > 256 * 1024) c = 256 * 1024;
             return c;
         };
         pl.chR = chunk_for(nR);
@@ -746,18 +764,20 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         pl.nChR = nR > 0 ? ceil_div(nR, pl.chR) : 0;
         pl.nChS = nS > 0 ? ceil_div(nS, pl.chS) : 0;
         pl.Umax = pl.P + ceil_div(nR, cap) + ceil_div(nS, pl.slice) + 2;
-        pl.off_histR = off;
+        pl.off_tot = off;  // totR[P] then totS[P], cleared together
+        off = align_up(off + (size_t)2 * pl.P * 4);
+        pl.off_baseR = off;
+        off = align_up(off + (size_t)(pl.P + 1) * 4);
+        pl.off_baseS = off;
+        off = align_up(off + (size_t)(pl.P + 1) * 4);
+        pl.off_offsR = off;
         off = align_up(off + (size_t)pl.P * pl.nChR * 4);
-        pl.off_histS = off;
+        pl.off_offsS = off;
         off = align_up(off + (size_t)pl.P * pl.nChS * 4);
-        pl.off_pkR = off;
-        off = align_up(off + (size_t)nR * 4);
-        pl.off_prR = off;
-        off = align_up(off + (size_t)nR * 4);
-        pl.off_pkS = off;
-        off = align_up(off + (size_t)nS * 4);
-        pl.off_prS = off;
-        off = align_up(off + (size_t)nS * 4);
+        pl.off_tupR = off;
+        off = align_up(off + (size_t)nR * 8);
+        pl.off_tupS = off;
+        off = align_up(off + (size_t)nS * 8);
         pl.off_info = off;
         off = align_up(off + (size_t)pl.P * sizeof(PartInfo));
         pl.off_units = off;
@@ -769,12 +789,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
     size_t temp = scan_temp_elems<uint64_t>(pl.Umax) * 8;
     if (!pl.single) {
-        const size_t t1 = scan_temp_elems<uint32_t>((int64_t)pl.P * pl.nChR) * 4;
-        const size_t t2 = scan_temp_elems<uint32_t>((int64_t)pl.P * pl.nChS) * 4;
-        const size_t t3 = scan_temp_elems<uint32_t>(pl.P + 1) * 4;
+        const size_t t1 = scan_temp_elems<uint32_t>(pl.P + 1) * 4;
         temp = temp > t1 ? temp : t1;
-        temp = temp > t2 ? temp : t2;
-        temp = temp > t3 ? temp : t3;
     }
     pl.off_temp = off;
     off = align_up(off + temp + 8);
@@ -788,61 +804,55 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     return pl;
 }
 
-static size_t scatter_lds(int P) { return (size_t)(2 * P + 1) * 4 + (size_t)kScatTile * 10; }
-
 static bool g_attr_done = false;
 
 static hipError_t set_attrs()
 {
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
-    hipError_t e;
-    e = hipFuncSetAttribute((const void*)scatter_k<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)scatter_k<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)scatter_k<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)scatter_k<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)hist_k<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)hist_k<false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)join_count_k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)join_write_k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
+    const void* fns[] = {
+        (const void*)scatter_k<true, true>, (const void*)scatter_k<true, false>,
+        (const void*)scatter_k<false, true>, (const void*)scatter_k<false, false>,
+        (const void*)hist_k<true>, (const void*)hist_k<false>,
+        (const void*)join_count_k<true>, (const void*)join_count_k<false>,
+        (const void*)join_write_k<true>, (const void*)join_write_k<false>,
+    };
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        if (e != hipSuccess) return e;
+    }
     g_attr_done = true;
     return hipSuccess;
 }
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
-static hipError_t partition_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
-                                 uint32_t* hist, int32_t* outk, int32_t* outr, uint32_t* temp,
-                                 hipStream_t st, bool is_r)
+static bool vec_ok(const join_rel_t& X) { return aligned16(X.key) && (X.rid == nullptr || aligned16(X.rid)); }
+
+static hipError_t hist_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
+                            uint32_t* tot, uint32_t* offs, hipStream_t st, bool is_r)
 {
     if (X.n <= 0) return hipSuccess;
-    const bool vec = aligned16(X.key) && (X.rid == nullptr || aligned16(X.rid));
     const size_t hl = (size_t)pl.P * 4;
-    {
-        prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
-        if (vec) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
-        else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, hist, nCh);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = exclusive_scan<uint32_t>(hist, hist, (int64_t)pl.P * nCh, nullptr, temp, st);
-    if (e != hipSuccess) return e;
+    prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
+    if (vec_ok(X)) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, tot, offs);
+    else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, tot, offs);
+    return hipGetLastError();
+}
+
+static hipError_t scatter_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
+                               const uint32_t* base, const uint32_t* offs, int2* out, hipStream_t st,
+                               bool is_r)
+{
+    if (X.n <= 0) return hipSuccess;
     const size_t sl = scatter_lds(pl.P);
     prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
-    if (vec) {
-        if (X.rid) scatter_k<true, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
-        else scatter_k<true, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+    if (vec_ok(X)) {
+        if (X.rid) scatter_k<true, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
+        else scatter_k<true, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
     } else {
-        if (X.rid) scatter_k<false, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
-        else scatter_k<false, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, hist, nCh, outk, outr);
+        if (X.rid) scatter_k<false, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
+        else scatter_k<false, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
     }
     return hipGetLastError();
 }
@@ -869,10 +879,8 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.P = 1;
     } else {
         g.single = 0;
-        g.rk = reinterpret_cast<const int32_t*>(ws + pl.off_pkR);
-        g.rr = reinterpret_cast<const int32_t*>(ws + pl.off_prR);
-        g.sk = reinterpret_cast<const int32_t*>(ws + pl.off_pkS);
-        g.sr = reinterpret_cast<const int32_t*>(ws + pl.off_prS);
+        g.rt = reinterpret_cast<const int2*>(ws + pl.off_tupR);
+        g.st = reinterpret_cast<const int2*>(ws + pl.off_tupS);
         g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);
         g.unitStart = reinterpret_cast<const uint32_t*>(ws + pl.off_units);
         g.umap = reinterpret_cast<const uint32_t*>(ws + pl.off_umap);
@@ -891,20 +899,38 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     uint64_t* counts = reinterpret_cast<uint64_t*>(ws + pl.off_counts);
     char* temp = ws + pl.off_temp;
     if (!pl.single) {
-        uint32_t* histR = reinterpret_cast<uint32_t*>(ws + pl.off_histR);
-        uint32_t* histS = reinterpret_cast<uint32_t*>(ws + pl.off_histS);
-        e = partition_side(pl, R, pl.chR, pl.nChR, histR, reinterpret_cast<int32_t*>(ws + pl.off_pkR),
-                           reinterpret_cast<int32_t*>(ws + pl.off_prR), reinterpret_cast<uint32_t*>(temp), st, true);
+        uint32_t* totR = reinterpret_cast<uint32_t*>(ws + pl.off_tot);
+        uint32_t* totS = totR + pl.P;
+        uint32_t* baseR = reinterpret_cast<uint32_t*>(ws + pl.off_baseR);
+        uint32_t* baseS = reinterpret_cast<uint32_t*>(ws + pl.off_baseS);
+        uint32_t* offsR = reinterpret_cast<uint32_t*>(ws + pl.off_offsR);
+        uint32_t* offsS = reinterpret_cast<uint32_t*>(ws + pl.off_offsS);
+        int2* tupR = reinterpret_cast<int2*>(ws + pl.off_tupR);
+        int2* tupS = reinterpret_cast<int2*>(ws + pl.off_tupS);
+        {
+            prof::Scope pz(st, "hash.plan");
+            zero_u32_k<<<(unsigned)ceil_div(2 * pl.P, 256), 256, 0, st>>>(totR, 2 * (int64_t)pl.P);
+        }
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = partition_side(pl, S, pl.chS, pl.nChS, histS, reinterpret_cast<int32_t*>(ws + pl.off_pkS),
-                           reinterpret_cast<int32_t*>(ws + pl.off_prS), reinterpret_cast<uint32_t*>(temp), st, false);
+        e = hist_side(pl, R, pl.chR, pl.nChR, totR, offsR, st, true);
+        if (e != hipSuccess) return e;
+        e = hist_side(pl, S, pl.chS, pl.nChS, totS, offsS, st, false);
+        if (e != hipSuccess) return e;
+        e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+        e = exclusive_scan<uint32_t>(totS, baseS, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+        if (e != hipSuccess) return e;
+        e = scatter_side(pl, R, pl.chR, pl.nChR, baseR, offsR, tupR, st, true);
+        if (e != hipSuccess) return e;
+        e = scatter_side(pl, S, pl.chS, pl.nChS, baseS, offsS, tupS, st, false);
         if (e != hipSuccess) return e;
         uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
         {
             prof::Scope pp(st, "hash.plan");
             plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
-                histR, histS, pl.nChR, pl.nChS, pl.P, (uint32_t)R.n, (uint32_t)S.n, (uint32_t)pl.cap,
-                (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
+                baseR, totR, baseS, totS, pl.P, (uint32_t)pl.cap, (uint32_t)pl.slice,
+                reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -923,7 +949,8 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         const JoinGeom g = make_geom(pl, R, S, ws);
         const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
         prof::Scope pc(st, "hash.count");
-        join_count_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
+        if (pl.single) join_count_k<false><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
+        else join_count_k<true><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -937,11 +964,13 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
     const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
+    const uint64_t* total = reinterpret_cast<const uint64_t*>(ws);
     const JoinGeom g = make_geom(pl, R, S, ws);
     const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+    int2* out = reinterpret_cast<int2*>(pairs);
     prof::Scope pw(st, "hash.write");
-    join_write_k<<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(
-        g, offsets, reinterpret_cast<const uint64_t*>(ws), reinterpret_cast<int2*>(pairs), cap);
+    if (pl.single) join_write_k<false><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, offsets, total, out, cap);
+    else join_write_k<true><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, offsets, total, out, cap);
     return hipGetLastError();
 }
 

@@ -12,10 +12,12 @@ struct PartInfo {
 
 // Everything the count and write kernels need to walk the work units.
 struct JoinGeom {
-    const int32_t* rk;  // build keys (partitioned, or the input column when single)
-    const int32_t* rr;  // build rids; NULL means position (single only)
-    const int32_t* sk;
-    const int32_t* sr;
+    const int32_t* rk;  // single: the input build keys
+    const int32_t* rr;  // single: the input build rids; NULL means position
+    const int32_t* sk;  // single: the input probe keys
+    const int32_t* sr;  // single: the input probe rids; NULL means position
+    const int2* rt;     // partitioned: (key, rid) build tuples, partition-major
+    const int2* st;     // partitioned: (key, rid) probe tuples, partition-major
     const PartInfo* part;       // [P]
     const uint32_t* unitStart;  // [P + 1], exclusive scan of units per partition
     const uint32_t* umap;       // [Umax], partition of each unit
@@ -38,7 +40,8 @@ struct HashPlan {
     int64_t chR, chS, nChR, nChS;
     int64_t Umax;
     int joinGrid;
-    size_t off_histR, off_histS, off_pkR, off_prR, off_pkS, off_prS, off_info, off_units, off_umap;
+    size_t off_tot, off_baseR, off_baseS, off_offsR, off_offsS, off_tupR, off_tupS;
+    size_t off_info, off_units, off_umap;
     size_t off_counts, off_temp, bytes;
 };
 

@@ -87,7 +87,7 @@ def test_partitioned_path_and_fanouts(monkeypatch):
     need_gpu()
     R, S = datagen.small_random(21, 200_000, 600_000, 0, 150_000, rid_mode="random")
     n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
-    for bits in ("0", "1", "5", "8", "13"):
+    for bits in ("0", "1", "5", "8", "11"):
         monkeypatch.setenv("JOIN_HASH_BITS", bits)
         log(f"hash fan-out bits={bits}")
         got = canon_gpu(_hash(R, S))
