@@ -332,30 +332,38 @@ __device__ __forceinline__ void choices(uint32_t h, int bits, uint32_t nb, uint3
 
 struct Table {
     const uint4* keys;    // [nb]: the 4 keys of each bucket
-    const uint4* rids;    // [nb]: their rids
+    const uint4* rids;    // [nb]: their rids (write pass only)
     const uint32_t* cnt;  // [nb]: claims; min(cnt, 4) slots are filled
     uint32_t nb;
 };
 
-// Build the table of one R chunk in LDS.  AOS: the chunk is partitioned (key, rid) tuples;
-// otherwise it is a range of the input columns.
-template <bool AOS>
-__device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, uint4* lds)
+// LDS bytes of a table for chunks of up to `cap` entries: 16 bytes of keys per bucket, 16 of
+// rids when the table keeps them (the count pass does not), and a 4-byte claim counter.
+__host__ __device__ __forceinline__ size_t table_lds(uint32_t cap, bool rids)
+{
+    return (size_t)table_buckets(cap) * (rids ? 36 : 20) + 64;
+}
+
+// One R chunk held in registers between its load and its insertion.
+template <bool RIDS>
+struct Chunk {
+    uint32_t k[kBuildItems];
+    uint32_t r[RIDS ? kBuildItems : 1];
+};
+
+// Issue every load of a chunk before any use (uniform guards only), so the chunk arrives in one
+// memory round trip.  AOS: the chunk is partitioned (key, rid) tuples; otherwise it is a range
+// of the input columns.
+template <bool AOS, bool RIDS>
+__device__ __forceinline__ void load_chunk(const JoinGeom& g, const Unit& un, Chunk<RIDS>& c)
 {
     const int tid = threadIdx.x;
-    const uint32_t nb = table_buckets(un.rN);
-    uint32_t* keys = reinterpret_cast<uint32_t*>(lds);
-    uint32_t* rids = reinterpret_cast<uint32_t*>(lds + nb);
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + 2 * nb);
-    // Issue every load of the chunk before any use (uniform guards only), so the chunk arrives
-    // in one memory round trip instead of one per item.
     const uint32_t nIt = (un.rN + kJoinBlock - 1) / kJoinBlock;
-    const int32_t* __restrict__ rk = g.rk;
-    const int32_t* __restrict__ rr = g.rr;
-    const int2* __restrict__ rt = g.rt;
-    uint32_t kk[kBuildItems], rv[kBuildItems];
 #pragma unroll
-    for (int i = 0; i < kBuildItems; ++i) kk[i] = rv[i] = 0u;
+    for (int i = 0; i < kBuildItems; ++i) {
+        c.k[i] = 0u;
+        if constexpr (RIDS) c.r[i] = 0u;
+    }
     if (un.rN > 0) {  // every unit has rN >= 1; the guard keeps the clamped index in bounds
 #pragma unroll
         for (int i = 0; i < kBuildItems; ++i) {
@@ -363,16 +371,28 @@ __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, 
             const uint32_t idx = un.rBeg + (e < un.rN ? e : un.rN - 1);
             if ((uint32_t)i < nIt) {
                 if constexpr (AOS) {
-                    const int2 t = rt[idx];
-                    kk[i] = (uint32_t)t.x;
-                    rv[i] = (uint32_t)t.y;
+                    const int2 t = g.rt[idx];
+                    c.k[i] = (uint32_t)t.x;
+                    if constexpr (RIDS) c.r[i] = (uint32_t)t.y;
                 } else {
-                    kk[i] = (uint32_t)rk[idx];
-                    rv[i] = rr ? (uint32_t)rr[idx] : idx;
+                    c.k[i] = (uint32_t)g.rk[idx];
+                    if constexpr (RIDS) c.r[i] = g.rr ? (uint32_t)g.rr[idx] : idx;
                 }
             }
         }
     }
+}
+
+// Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
+template <bool RIDS>
+__device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un, const Chunk<RIDS>& c,
+                                              uint4* lds)
+{
+    const int tid = threadIdx.x;
+    const uint32_t nb = table_buckets(un.rN);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(lds);
+    uint32_t* rids = reinterpret_cast<uint32_t*>(lds + nb);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
     for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
     __syncthreads();
 #pragma unroll
@@ -380,7 +400,7 @@ __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, 
         const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
         if (e < un.rN) {
             uint32_t b1, b2;
-            choices(hmix(kk[i]), g.bits, nb, b1, b2);
+            choices(hmix(c.k[i]), g.bits, nb, b1, b2);
             const bool second = cnt[b2] < cnt[b1];  // a racy read only steers the choice
             uint32_t b = second ? b2 : b1;
             uint32_t old = atomicAdd(&cnt[b], 1u);
@@ -395,14 +415,14 @@ __device__ __forceinline__ Table build_table(const JoinGeom& g, const Unit& un, 
                     } while (old >= (uint32_t)kSlots);
                 }
             }
-            keys[b * kSlots + old] = kk[i];
-            rids[b * kSlots + old] = rv[i];
+            keys[b * kSlots + old] = c.k[i];
+            if constexpr (RIDS) rids[b * kSlots + old] = c.r[i];
         }
     }
     __syncthreads();
     Table t;
     t.keys = lds;
-    t.rids = lds + nb;
+    t.rids = RIDS ? lds + nb : nullptr;
     t.cnt = cnt;
     t.nb = nb;
     return t;
@@ -538,13 +558,12 @@ __device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
 }
 
 #ifndef JL_HASH_COUNT_BATCH
-#define JL_HASH_COUNT_BATCH 8
+#define JL_HASH_COUNT_BATCH 4
 #endif
-#if defined(JL_HASH_WPE) && JL_HASH_WPE > 0  // occupancy the join kernels are compiled for
-#define JL_JOIN_ATTR __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(JL_HASH_WPE)))
-#else
-#define JL_JOIN_ATTR __launch_bounds__(kJoinBlock)
-#endif
+// The count kernel's keys-only table lets two 1024-thread workgroups share a CU, so it is
+// compiled for 8 waves per SIMD (64 VGPRs); the write kernel runs one workgroup per CU.
+#define JL_COUNT_ATTR __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(8)))
+#define JL_WRITE_ATTR __launch_bounds__(kJoinBlock)
 constexpr int kCountBatch = JL_HASH_COUNT_BATCH;  // S keys in flight per thread in the count pass
 static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a time");
 #ifndef JL_HASH_WRITE_PROBE
@@ -584,25 +603,34 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
     }
 }
 
+// Count pass.  A workgroup walks units u = blockIdx.x, + gridDim.x, ...  The first S batch of a
+// unit is in flight while its table is built, each later batch while the previous one probes,
+// and the next unit's first batch while the last one probes.
 template <bool AOS>
-__global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
+__global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
     extern __shared__ uint4 tab[];
     __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
     const uint32_t U = unit_total(g);
-    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
-        const Unit un = decode_unit(g, u);
-        // the first batch of S keys is in flight while the table is built; each later batch is
-        // loaded while the previous one probes
-        uint32_t xs[kCountBatch];
+    uint32_t xs[kCountBatch];
+    Unit un{};
+    if (blockIdx.x < U) {
+        un = decode_unit(g, blockIdx.x);
         load_keys<AOS>(g, un, 0, xs);
-        const Table t = build_table<AOS>(g, un, tab);
+    }
+    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+        Chunk<false> ch;
+        load_chunk<AOS, false>(g, un, ch);
+        const Table t = insert_chunk<false>(g, un, ch, tab);
+        const bool more = u + gridDim.x < U;
+        const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
         uint32_t cnt = 0;
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
             uint32_t cur[kCountBatch];
 #pragma unroll
             for (int i = 0; i < kCountBatch; ++i) cur[i] = xs[i];
             if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys<AOS>(g, un, e0 + kJoinBlock * kCountBatch, xs);
+            else if (more) load_keys<AOS>(g, nx, 0, xs);
 #pragma unroll
             for (int h = 0; h < kCountBatch; h += kProbe) {
                 uint32_t x[kProbe];
@@ -615,10 +643,12 @@ __global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ cou
                 cnt += probe_count(t, g.bits, x, ok);
             }
         }
+        if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xs);
         uint32_t tot;
         block_excl_scan<kJoinBlock>(cnt, wsum, &tot);
         if (threadIdx.x == 0) counts[u] = tot;
         __syncthreads();
+        un = nx;
     }
     // units past the device-side total must read as zero for the scan over Umax entries
     for (int64_t i = (int64_t)U + (int64_t)blockIdx.x * kJoinBlock + threadIdx.x; i < g.Umax;
@@ -627,7 +657,7 @@ __global__ JL_JOIN_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ cou
 }
 
 template <bool AOS>
-__global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
+__global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                                                            const uint64_t* __restrict__ offsets,
                                                            const uint64_t* __restrict__ total,
                                                            int2* __restrict__ out, uint64_t cap)
@@ -636,13 +666,23 @@ __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
     __shared__ uint32_t cursor;  // output slots of the current unit handed out so far
     if (*total > cap) return;  // an output too small for the exact count receives nothing
     const uint32_t U = unit_total(g);
+    // The next unit's R chunk is loaded into registers while the current unit probes, and the
+    // next unit's first S batch while its last batch probes.
+    Unit un{};
+    Chunk<true> ch;
+    uint32_t nx[kWriteBatch];
+    int32_t nr[kWriteBatch];
+    if (blockIdx.x < U) {
+        un = decode_unit(g, blockIdx.x);
+        load_chunk<AOS, true>(g, un, ch);
+        load_tuples<AOS>(g, un, 0, nx, nr);
+    }
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
-        const Unit un = decode_unit(g, u);
-        uint32_t nx[kWriteBatch];
-        int32_t nr[kWriteBatch];
-        load_tuples<AOS>(g, un, 0, nx, nr);  // in flight while the table is built
         if (threadIdx.x == 0) cursor = 0;  // the barrier inside the build publishes it
-        const Table t = build_table<AOS>(g, un, tab);
+        const Table t = insert_chunk<true>(g, un, ch, tab);
+        const bool more = u + gridDim.x < U;
+        const Unit nxt = more ? decode_unit(g, u + gridDim.x) : Unit{};
+        if (more) load_chunk<AOS, true>(g, nxt, ch);
         const uint64_t base = offsets[u];
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
@@ -657,6 +697,8 @@ __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
             }
             if (e0 + kJoinBlock * kWriteBatch < un.sN)
                 load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
+            else if (more)
+                load_tuples<AOS>(g, nxt, 0, nx, nr);
             probe_write(t, g.bits, x, ok, m, p1, p2);
             // Slots inside the unit's range: waves take theirs from an LDS cursor (no block-wide
             // barrier); within a wave, the pairs of the i-th tuple of every lane are contiguous,
@@ -685,15 +727,13 @@ __global__ JL_JOIN_ATTR void join_write_k(JoinGeom g,
                 }
             }
         }
+        if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
         __syncthreads();
+        un = nxt;
     }
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// LDS bytes of the join kernels' table for R chunks of up to `cap` entries: 32-byte buckets
-// plus a 4-byte claim counter each.
-size_t join_lds(uint32_t cap) { return (size_t)table_buckets(cap) * (2 * sizeof(uint4) + 4) + 64; }
 
 }  // namespace
 
@@ -795,12 +835,15 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     pl.off_temp = off;
     off = align_up(off + temp + 8);
     pl.bytes = off;
-    // persistent grid of the join kernels: as many workgroups per CU as the LDS table allows
-    const size_t lds = join_lds((uint32_t)cap) + 128;
-    int per_cu = (int)((160 * 1024) / lds);
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 2) per_cu = 2;  // 1024-thread workgroups: at most 2 per CU
-    pl.joinGrid = num_cus * per_cu;
+    // persistent grids of the join kernels: as many workgroups per CU as the LDS table allows
+    auto grid_for = [&](bool rids) {
+        int per_cu = (int)((160 * 1024) / (table_lds((uint32_t)cap, rids) + 128));
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 2) per_cu = 2;  // 1024-thread workgroups: at most 2 per CU
+        return num_cus * per_cu;
+    };
+    pl.gridCount = grid_for(false);
+    pl.gridWrite = grid_for(true);
     return pl;
 }
 
@@ -947,10 +990,11 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     }
     if (pl.Umax > 0) {
         const JoinGeom g = make_geom(pl, R, S, ws);
-        const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+        const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridCount);
+        const size_t lds = table_lds((uint32_t)pl.cap, false);
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
-        else join_count_k<true><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, counts);
+        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts);
+        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -966,11 +1010,12 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
     const uint64_t* total = reinterpret_cast<const uint64_t*>(ws);
     const JoinGeom g = make_geom(pl, R, S, ws);
-    const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.joinGrid);
+    const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridWrite);
+    const size_t lds = table_lds((uint32_t)pl.cap, true);
     int2* out = reinterpret_cast<int2*>(pairs);
     prof::Scope pw(st, "hash.write");
-    if (pl.single) join_write_k<false><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, offsets, total, out, cap);
-    else join_write_k<true><<<grid, kJoinBlock, join_lds((uint32_t)pl.cap), st>>>(g, offsets, total, out, cap);
+    if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
+    else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
     return hipGetLastError();
 }
 
