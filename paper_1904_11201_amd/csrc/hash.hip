@@ -30,12 +30,16 @@ namespace {
 
 constexpr int kHistBlock = 1024;
 constexpr int kScatBlock = 1024;
-constexpr int kScatIt = 4;                       // tuples per thread per scatter tile
+#ifndef JL_SCAT_IT
+#define JL_SCAT_IT 4
+#endif
+constexpr int kScatIt = JL_SCAT_IT;              // tuples per thread per scatter tile (multiple of 4)
 constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile
 constexpr int kCarry = 8;                        // 8-byte tuples per 64-byte HBM write granule
+static_assert(kScatTile < 65536, "tile counts share a 32-bit word with the carry count");
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
-constexpr int kMaxBits = 11;     // scatter LDS: 2^11 partitions x (64 B carry + 12 B counters)
+constexpr int kMaxBits = 11;     // scatter LDS: 2^11 partitions x (64 B carry + 8 B state)
 constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
 
 __device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
@@ -112,20 +116,24 @@ __device__ __forceinline__ void scat_load(const int32_t* __restrict__ key, const
 {
     const int tid = threadIdx.x;
     if (VEC && tn == kScatTile) {
-        const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + 4 * tid);
-        k[0] = k4.x; k[1] = k4.y; k[2] = k4.z; k[3] = k4.w;
-        if constexpr (HAS_RID) {
-            const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + 4 * tid);
-            r[0] = r4.x; r[1] = r4.y; r[2] = r4.z; r[3] = r4.w;
-        } else {
 #pragma unroll
-            for (int q = 0; q < kScatIt; ++q) r[q] = (int32_t)(t0 + 4 * tid + q);
+        for (int v = 0; v < kScatIt / 4; ++v) {
+            const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + kScatIt * tid + 4 * v);
+            k[4 * v] = k4.x; k[4 * v + 1] = k4.y; k[4 * v + 2] = k4.z; k[4 * v + 3] = k4.w;
+            if constexpr (HAS_RID) {
+                const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + kScatIt * tid + 4 * v);
+                r[4 * v] = r4.x; r[4 * v + 1] = r4.y; r[4 * v + 2] = r4.z; r[4 * v + 3] = r4.w;
+            }
+        }
+        if constexpr (!HAS_RID) {
+#pragma unroll
+            for (int q = 0; q < kScatIt; ++q) r[q] = (int32_t)(t0 + kScatIt * tid + q);
         }
         return;
     }
 #pragma unroll
     for (int q = 0; q < kScatIt; ++q) {
-        const int e = 4 * tid + q;
+        const int e = kScatIt * tid + q;
         const bool ok = e < tn;
         k[q] = ok ? key[t0 + e] : 0;
         r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
@@ -141,18 +149,15 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restric
                                                         int2* __restrict__ out)
 {
     extern __shared__ uint32_t lds[];
+    constexpr int kPpt = (1 << kMaxBits) / kScatBlock;  // partitions per thread in the per-partition steps
     const int P = 1 << bits;
     const int sh = 32 - bits;
-    int2* carry = reinterpret_cast<int2*>(lds);           // [P][kCarry]
-    uint32_t* wpos = lds + (size_t)P * kCarry * 2;        // [P] next position not yet written
-    uint32_t* kc = wpos + P;                              // [P] tuples carried
-    uint32_t* tc = kc + P;                                // [P] tuples of the current tile
+    int2* carry = reinterpret_cast<int2*>(lds);  // [P][kCarry]
+    // per partition: x = next position not yet written, y = carried tuples << 16 | tile tuples
+    uint2* pst = reinterpret_cast<uint2*>(lds + (size_t)P * kCarry * 2);
+    uint32_t* pcnt = reinterpret_cast<uint32_t*>(pst);  // pcnt[2p + 1] is pst[p].y
     const int tid = threadIdx.x;
-    for (int p = tid; p < P; p += kScatBlock) {
-        wpos[p] = base[p] + offs[(int64_t)blockIdx.x * P + p];
-        kc[p] = 0;
-        tc[p] = 0;
-    }
+    for (int p = tid; p < P; p += kScatBlock) pst[p] = make_uint2(base[p] + offs[(int64_t)blockIdx.x * P + p], 0u);
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < n ? beg + chunk : n;
@@ -174,55 +179,56 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restric
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q) {
             p[q] = pid_of(k[q], sh);
-            j[q] = 4 * tid + q < tn ? atomicAdd(&tc[p[q]], 1u) : 0u;
+            j[q] = kScatIt * tid + q < tn ? atomicAdd(&pcnt[2 * p[q] + 1], 1u) & 0xFFFFu : 0u;
         }
         __syncthreads();
         uint32_t slot[kScatIt];  // carry slot, or kCarry when written now or not a tuple
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q) {
             slot[q] = kCarry;
-            if (4 * tid + q < tn) {
-                const uint32_t w = wpos[p[q]], c0 = kc[p[q]];
-                const uint32_t e = w + c0 + tc[p[q]];
+            if (kScatIt * tid + q < tn) {
+                const uint2 v = pst[p[q]];
+                const uint32_t w = v.x, c0 = v.y >> 16;
+                const uint32_t e = w + c0 + (v.y & 0xFFFFu);
                 const uint32_t A = e & ~(uint32_t)(kCarry - 1);
                 const uint32_t pos = w + c0 + j[q];
                 if (pos < A) out[pos] = make_int2(k[q], r[q]);
                 else slot[q] = pos - (A > w ? A : w);
             }
         }
-        for (int pp = tid; pp < P; pp += kScatBlock) {
-            const uint32_t t = tc[pp];
-            if (t) {
-                const uint32_t w = wpos[pp], c0 = kc[pp];
-                const uint32_t A = (w + c0 + t) & ~(uint32_t)(kCarry - 1);
-                if (A > w)
-                    for (uint32_t s = 0; s < c0; ++s) out[w + s] = carry[pp * kCarry + s];
+        // flush carried tuples of partitions whose share crosses a granule boundary, and work out
+        // every partition's new state (written after the barrier)
+        uint2 ns[kPpt];
+#pragma unroll
+        for (int i = 0; i < kPpt; ++i) {
+            const int pp = tid + i * kScatBlock;
+            if (pp < P) {
+                const uint2 v = pst[pp];
+                const uint32_t w = v.x, c0 = v.y >> 16, t = v.y & 0xFFFFu;
+                const uint32_t e = w + c0 + t;
+                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
+                if (t && A > w) {
+                    for (uint32_t s2 = 0; s2 < c0; ++s2) out[w + s2] = carry[pp * kCarry + s2];
+                    ns[i] = make_uint2(A, (e - A) << 16);
+                } else {
+                    ns[i] = make_uint2(w, (c0 + t) << 16);
+                }
             }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q)
             if (slot[q] < (uint32_t)kCarry) carry[p[q] * kCarry + slot[q]] = make_int2(k[q], r[q]);
-        for (int pp = tid; pp < P; pp += kScatBlock) {
-            const uint32_t t = tc[pp];
-            if (t) {
-                const uint32_t w = wpos[pp], c0 = kc[pp];
-                const uint32_t e = w + c0 + t;
-                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
-                if (A > w) {
-                    wpos[pp] = A;
-                    kc[pp] = e - A;
-                } else {
-                    kc[pp] = c0 + t;
-                }
-                tc[pp] = 0;
-            }
+#pragma unroll
+        for (int i = 0; i < kPpt; ++i) {
+            const int pp = tid + i * kScatBlock;
+            if (pp < P) pst[pp] = ns[i];
         }
         __syncthreads();
     }
     for (int pp = tid; pp < P; pp += kScatBlock) {
-        const uint32_t w = wpos[pp], c0 = kc[pp];
-        for (uint32_t s = 0; s < c0; ++s) out[w + s] = carry[pp * kCarry + s];
+        const uint2 v = pst[pp];
+        for (uint32_t s2 = 0; s2 < (v.y >> 16); ++s2) out[v.x + s2] = carry[pp * kCarry + s2];
     }
 }
 
@@ -744,7 +750,7 @@ static int env_int(const char* name, int dflt)
     return atoi(s);
 }
 
-static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + 3 * sizeof(uint32_t)); }
+static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + sizeof(uint2)); }
 
 HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
 {
