@@ -128,6 +128,54 @@ int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred
                size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count,
                void* stream);
 
+/* ---- batched equi joins -----------------------------------------------------------------
+ * Many independent equi joins R_j.key = S_j.key (j = 0..njobs-1) in one pass of fused
+ * launches.  In the paper every MapReduce reducer runs its own GPU join and the reducer count
+ * is bounded so that reducers x blocks x threads fit the GPU (Section 3.3.4, equation "hier");
+ * here the reducers' joins share one set of launches instead: every join gets its own fan-out
+ * and partitions, and the work units of all joins form one list, so the count pass, the scan
+ * and the write pass are one launch each whatever njobs is.  Join j's pairs are written
+ * contiguously, in join order, to one output array: pairs [offsets[j], offsets[j+1]).
+ *
+ * Flow: join_batch_workspace_bytes -> join_batch_prepare (host planning, uploads the join
+ * tables, waits for the upload) -> join_batch_count (launches only: no host sync, so it can be
+ * captured in a HIP graph) -> read offsets[njobs] -> join_batch_materialize (launches only). */
+typedef struct {
+    join_rel_t R;     /* build side of join j (key, rid; key2 ignored) */
+    join_rel_t S;     /* probe side of join j */
+    int32_t bits;     /* log2 of join j's partition fan-out, 0..11; < 0: the library's default
+                       * for |R_j| (an autotuner may choose it) */
+    int32_t reserved; /* must be 0 */
+} join_job_t;
+
+/* Opaque host-side plan filled by join_batch_prepare and passed to the later calls.  Plain
+ * bytes: it may be copied, and it holds no pointers. */
+typedef struct {
+    uint64_t opaque[64];
+} join_batch_plan_t;
+
+/* Workspace bytes for this batch; 0 for invalid arguments or a batch whose total rows per side
+ * reach 2^32. */
+size_t join_batch_workspace_bytes(int njobs, const join_job_t* jobs);
+
+/* Plans the batch and uploads its tables into ws (stream-ordered, then waits on the stream).
+ * Validates every job like join_count does.  Errors: JOIN_E_INVAL, JOIN_E_WORKSPACE,
+ * JOIN_E_UNSUPPORTED (batch too large for 32-bit indices), JOIN_E_HIP. */
+int join_batch_prepare(int njobs, const join_job_t* jobs, void* ws, size_t ws_bytes,
+                       join_batch_plan_t* plan, void* stream);
+
+/* Count pass of every join.  Writes, on the device, offsets[j] = first output pair of join j
+ * for j < njobs and offsets[njobs] = total pairs.  `offsets` is a device array of njobs + 1
+ * uint64.  Asynchronous: no host sync.  Errors: JOIN_E_INVAL, JOIN_E_WORKSPACE, JOIN_E_HIP. */
+int join_batch_count(const join_batch_plan_t* plan, void* ws, size_t ws_bytes, uint64_t* offsets,
+                     void* stream);
+
+/* Write pass of every join into `pairs` (capacity pairs).  If the total exceeds capacity the
+ * device writes nothing (read offsets[njobs] first).  Asynchronous.  The inputs and ws must not
+ * change since join_batch_count.  Errors: JOIN_E_INVAL, JOIN_E_WORKSPACE, JOIN_E_HIP. */
+int join_batch_materialize(const join_batch_plan_t* plan, void* ws, size_t ws_bytes, int32_t* pairs,
+                           uint64_t capacity, void* stream);
+
 /* Message for the last non-zero status on the calling thread ("" if none). */
 const char* join_last_error(void);
 

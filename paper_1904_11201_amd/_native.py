@@ -28,8 +28,10 @@ OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 
 
 # Every symbol include/*.h declares.
 EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash", "join_theta",
-           "join_last_error", "join_scan_workspace_bytes", "join_scan_u64", "join_prof_enable",
-           "join_prof_collect", "join_prof_count", "join_prof_entry")
+           "join_batch_workspace_bytes", "join_batch_prepare", "join_batch_count",
+           "join_batch_materialize", "join_last_error", "join_scan_workspace_bytes",
+           "join_scan_u64", "join_prof_enable", "join_prof_collect", "join_prof_count",
+           "join_prof_entry")
 
 
 class JoinRel(ctypes.Structure):
@@ -39,6 +41,15 @@ class JoinRel(ctypes.Structure):
 
 class JoinPred(ctypes.Structure):
     _fields_ = [("op_a", ctypes.c_int32), ("w", ctypes.c_int32), ("op_c", ctypes.c_int32)]
+
+
+class JoinJob(ctypes.Structure):
+    _fields_ = [("R", JoinRel), ("S", JoinRel), ("bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class JoinBatchPlan(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_uint64 * 64)]
 
 
 def _hip_runtimes():
@@ -77,6 +88,16 @@ def _load():
     lib.join_hash.argtypes = [R, R, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
     lib.join_theta.restype = ctypes.c_int
     lib.join_theta.argtypes = [R, R, Pp, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
+    Jp = ctypes.POINTER(JoinJob)
+    Bp = ctypes.POINTER(JoinBatchPlan)
+    lib.join_batch_workspace_bytes.restype = sz
+    lib.join_batch_workspace_bytes.argtypes = [ctypes.c_int, Jp]
+    lib.join_batch_prepare.restype = ctypes.c_int
+    lib.join_batch_prepare.argtypes = [ctypes.c_int, Jp, vp, sz, Bp, vp]
+    lib.join_batch_count.restype = ctypes.c_int
+    lib.join_batch_count.argtypes = [Bp, vp, sz, vp, vp]
+    lib.join_batch_materialize.restype = ctypes.c_int
+    lib.join_batch_materialize.argtypes = [Bp, vp, sz, vp, u64, vp]
     lib.join_last_error.restype = ctypes.c_char_p
     lib.join_last_error.argtypes = []
     lib.join_scan_workspace_bytes.restype = sz

@@ -352,4 +352,103 @@ int join_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
     return JOIN_OK;
 }
 
+static_assert(sizeof(BatchPlan) <= sizeof(join_batch_plan_t), "batch plan must fit the opaque blob");
+
+static int check_jobs(int njobs, const join_job_t* jobs)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs)) {
+        set_error("njobs < 0 or jobs == NULL");
+        return JOIN_E_INVAL;
+    }
+    for (int j = 0; j < njobs; ++j) {
+        int rc = check_rel(&jobs[j].R, "R", false);
+        if (rc == JOIN_OK) rc = check_rel(&jobs[j].S, "S", false);
+        if (rc != JOIN_OK) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "job %d: %s", j, join_last_error());
+            set_error("%s", msg);
+            return rc;
+        }
+        if (jobs[j].bits > 11 || jobs[j].reserved != 0) {
+            set_error("job %d: bits must be < 0 (default) or 0..11, reserved must be 0", j);
+            return JOIN_E_INVAL;
+        }
+    }
+    return JOIN_OK;
+}
+
+size_t join_batch_workspace_bytes(int njobs, const join_job_t* jobs)
+{
+    if (check_jobs(njobs, jobs) != JOIN_OK) return 0;
+    BatchPlan bp;
+    if (hash_batch_plan(njobs, jobs, num_cus(), &bp) != 0) return 0;
+    return (size_t)bp.bytes;
+}
+
+int join_batch_prepare(int njobs, const join_job_t* jobs, void* ws, size_t ws_bytes,
+                       join_batch_plan_t* plan, void* stream)
+{
+    int rc = check_jobs(njobs, jobs);
+    if (rc != JOIN_OK) return rc;
+    if (!plan) {
+        set_error("plan == NULL");
+        return JOIN_E_INVAL;
+    }
+    BatchPlan bp;
+    if (hash_batch_plan(njobs, jobs, num_cus(), &bp) != 0) {
+        set_error("batch too large: rows per side, partitions or work units exceed 32-bit indices");
+        return JOIN_E_UNSUPPORTED;
+    }
+    if (!ws || ws_bytes < bp.bytes) {
+        set_error("workspace of %zu bytes, need %llu", ws_bytes, (unsigned long long)bp.bytes);
+        return JOIN_E_WORKSPACE;
+    }
+    memset(plan, 0, sizeof(*plan));
+    memcpy(plan, &bp, sizeof(bp));
+    const hipError_t e = hash_batch_upload(bp, jobs, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JOIN_OK : hip_fail(e, "join_batch_prepare");
+}
+
+static int batch_args(const join_batch_plan_t* plan, void* ws, size_t ws_bytes, BatchPlan* bp)
+{
+    if (!plan) {
+        set_error("plan == NULL");
+        return JOIN_E_INVAL;
+    }
+    memcpy(bp, plan, sizeof(*bp));
+    if (!ws || ws_bytes < bp->bytes) {
+        set_error("workspace of %zu bytes, need %llu", ws_bytes, (unsigned long long)bp->bytes);
+        return JOIN_E_WORKSPACE;
+    }
+    return JOIN_OK;
+}
+
+int join_batch_count(const join_batch_plan_t* plan, void* ws, size_t ws_bytes, uint64_t* offsets,
+                     void* stream)
+{
+    BatchPlan bp;
+    int rc = batch_args(plan, ws, ws_bytes, &bp);
+    if (rc != JOIN_OK) return rc;
+    if (!offsets) {
+        set_error("offsets == NULL");
+        return JOIN_E_INVAL;
+    }
+    const hipError_t e = hash_batch_count(bp, static_cast<char*>(ws), offsets, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JOIN_OK : hip_fail(e, "join_batch_count");
+}
+
+int join_batch_materialize(const join_batch_plan_t* plan, void* ws, size_t ws_bytes, int32_t* pairs,
+                           uint64_t capacity, void* stream)
+{
+    BatchPlan bp;
+    int rc = batch_args(plan, ws, ws_bytes, &bp);
+    if (rc != JOIN_OK) return rc;
+    if (!pairs && capacity > 0) {
+        set_error("pairs == NULL with capacity > 0");
+        return JOIN_E_INVAL;
+    }
+    const hipError_t e = hash_batch_write(bp, static_cast<char*>(ws), pairs, capacity, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JOIN_OK : hip_fail(e, "join_batch_materialize");
+}
+
 }  // extern "C"

@@ -21,6 +21,8 @@
 // predicated compares, so a wave issues its LDS reads together and does not branch per key.
 #include "hash.hpp"
 
+#include <vector>
+
 #include "prof.hpp"
 #include "scan.hpp"
 
@@ -54,25 +56,41 @@ __global__ void zero_u32_k(uint32_t* __restrict__ p, int64_t n)
 }
 
 // ------------------------------------------------------------------------------- histogram --
-// Chunk c counts its tuples per partition in LDS, then reserves its range inside every partition
-// with one global atomic add per non-empty partition: offs[c][p] is the chunk's offset inside
-// partition p and tot[p] ends as the partition's size.  Ranges of different chunks are disjoint;
-// their order inside a partition follows the order of the atomics.
-template <bool VEC>
-__global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__ key, int64_t n,
-                                                     int64_t chunk, int bits, uint32_t* __restrict__ tot,
+// Work items of the histogram and scatter kernels: one chunk of one relation side of one join.
+// A single join derives its items from the block index; a batch of joins reads them from a table.
+__device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items, const SideItem& one,
+                                              int64_t chunk, int64_t n)
+{
+    if (items) return items[blockIdx.x];
+    SideItem it = one;
+    it.beg = (int64_t)blockIdx.x * chunk;
+    const int64_t left = n - it.beg;
+    it.len = (uint32_t)(left < chunk ? left : chunk);
+    it.offs0 = (uint32_t)blockIdx.x << one.bits;
+    return it;
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// A chunk counts its tuples per partition in LDS, then reserves its range inside every partition
+// with one global atomic add per non-empty partition: offs[offs0 + p] is the chunk's offset
+// inside partition p and tot[part0 + p] ends as the partition's size.  Ranges of different
+// chunks are disjoint; their order inside a partition follows the order of the atomics.
+__global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict__ items, SideItem one,
+                                                     int64_t chunk, int64_t n, uint32_t* __restrict__ tot,
                                                      uint32_t* __restrict__ offs)
 {
     extern __shared__ uint32_t h[];
     constexpr int V = 4;  // 16-byte loads in flight per thread
-    const int P = 1 << bits;
-    const int sh = 32 - bits;
+    const SideItem it = side_item(items, one, chunk, n);
+    const int P = 1 << it.bits;
+    const int sh = 32 - it.bits;
     for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
     __syncthreads();
-    const int64_t beg = (int64_t)blockIdx.x * chunk;
-    const int64_t end = beg + chunk < n ? beg + chunk : n;
-    int64_t i = beg;
-    if constexpr (VEC) {
+    const int32_t* __restrict__ key = it.key + it.beg;
+    const int64_t end = it.len;
+    int64_t i = 0;
+    if (aligned16(key)) {
         const int64_t step = 4 * kHistBlock;
         for (; i + V * step <= end; i += V * step) {
             int4 k4[V];
@@ -92,7 +110,7 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += kHistBlock) {
         const uint32_t v = h[p];
-        offs[(int64_t)blockIdx.x * P + p] = v ? atomicAdd(&tot[p], v) : 0u;
+        offs[(int64_t)it.offs0 + p] = v ? atomicAdd(&tot[it.part0 + p], v) : 0u;
     }
 }
 
@@ -110,24 +128,23 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const int32_t* __restrict__
 //   3. the carry buffers and positions are updated.
 // Tuples of a partition keep their tile order only up to the atomics' order, which does not
 // matter to the join.
-template <bool VEC, bool HAS_RID>
 __device__ __forceinline__ void scat_load(const int32_t* __restrict__ key, const int32_t* __restrict__ rid,
-                                          int64_t t0, int tn, int32_t (&k)[kScatIt], int32_t (&r)[kScatIt])
+                                          int64_t rid0, bool vec, int t0, int tn,
+                                          int32_t (&k)[kScatIt], int32_t (&r)[kScatIt])
 {
     const int tid = threadIdx.x;
-    if (VEC && tn == kScatTile) {
+    if (vec && tn == kScatTile) {
 #pragma unroll
         for (int v = 0; v < kScatIt / 4; ++v) {
             const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + kScatIt * tid + 4 * v);
             k[4 * v] = k4.x; k[4 * v + 1] = k4.y; k[4 * v + 2] = k4.z; k[4 * v + 3] = k4.w;
-            if constexpr (HAS_RID) {
+            if (rid) {
                 const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + kScatIt * tid + 4 * v);
                 r[4 * v] = r4.x; r[4 * v + 1] = r4.y; r[4 * v + 2] = r4.z; r[4 * v + 3] = r4.w;
-            }
-        }
-        if constexpr (!HAS_RID) {
+            } else {
 #pragma unroll
-            for (int q = 0; q < kScatIt; ++q) r[q] = (int32_t)(t0 + kScatIt * tid + q);
+                for (int c = 0; c < 4; ++c) r[4 * v + c] = (int32_t)(rid0 + t0 + kScatIt * tid + 4 * v + c);
+            }
         }
         return;
     }
@@ -136,45 +153,45 @@ __device__ __forceinline__ void scat_load(const int32_t* __restrict__ key, const
         const int e = kScatIt * tid + q;
         const bool ok = e < tn;
         k[q] = ok ? key[t0 + e] : 0;
-        r[q] = ok ? (HAS_RID ? rid[t0 + e] : (int32_t)(t0 + e)) : 0;
+        r[q] = ok ? (rid ? rid[t0 + e] : (int32_t)(rid0 + t0 + e)) : 0;
     }
 }
 
-template <bool VEC, bool HAS_RID>
-__global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restrict__ key,
-                                                        const int32_t* __restrict__ rid, int64_t n,
-                                                        int64_t chunk, int bits,
+__global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restrict__ items, SideItem one,
+                                                        int64_t chunk, int64_t n,
                                                         const uint32_t* __restrict__ base,
                                                         const uint32_t* __restrict__ offs,
                                                         int2* __restrict__ out)
 {
     extern __shared__ uint32_t lds[];
     constexpr int kPpt = (1 << kMaxBits) / kScatBlock;  // partitions per thread in the per-partition steps
-    const int P = 1 << bits;
-    const int sh = 32 - bits;
+    const SideItem it = side_item(items, one, chunk, n);
+    const int P = 1 << it.bits;
+    const int sh = 32 - it.bits;
     int2* carry = reinterpret_cast<int2*>(lds);  // [P][kCarry]
     // per partition: x = next position not yet written, y = carried tuples << 16 | tile tuples
     uint2* pst = reinterpret_cast<uint2*>(lds + (size_t)P * kCarry * 2);
     uint32_t* pcnt = reinterpret_cast<uint32_t*>(pst);  // pcnt[2p + 1] is pst[p].y
     const int tid = threadIdx.x;
-    for (int p = tid; p < P; p += kScatBlock) pst[p] = make_uint2(base[p] + offs[(int64_t)blockIdx.x * P + p], 0u);
+    for (int p = tid; p < P; p += kScatBlock)
+        pst[p] = make_uint2(base[it.part0 + p] + offs[(int64_t)it.offs0 + p], 0u);
     __syncthreads();
-    const int64_t beg = (int64_t)blockIdx.x * chunk;
-    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    const int32_t* __restrict__ key = it.key + it.beg;
+    const int32_t* __restrict__ rid = it.rid ? it.rid + it.beg : nullptr;
+    const bool vec = aligned16(key) && (rid == nullptr || aligned16(rid));
+    const int end = (int)it.len;
     int32_t nk[kScatIt], nr[kScatIt];
-    if (beg < end)
-        scat_load<VEC, HAS_RID>(key, rid, beg, (int)(end - beg < kScatTile ? end - beg : kScatTile), nk, nr);
-    for (int64_t t0 = beg; t0 < end; t0 += kScatTile) {
-        const int tn = (int)(end - t0 < kScatTile ? end - t0 : kScatTile);
+    if (0 < end) scat_load(key, rid, it.beg, vec, 0, end < kScatTile ? end : kScatTile, nk, nr);
+    for (int t0 = 0; t0 < end; t0 += kScatTile) {
+        const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
         int32_t k[kScatIt], r[kScatIt];
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q) {
             k[q] = nk[q];
             r[q] = nr[q];
         }
-        const int64_t t1 = t0 + kScatTile;
-        if (t1 < end)
-            scat_load<VEC, HAS_RID>(key, rid, t1, (int)(end - t1 < kScatTile ? end - t1 : kScatTile), nk, nr);
+        const int t1 = t0 + kScatTile;
+        if (t1 < end) scat_load(key, rid, it.beg, vec, t1, end - t1 < kScatTile ? end - t1 : kScatTile, nk, nr);
         uint32_t p[kScatIt], j[kScatIt];
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q) {
@@ -233,16 +250,29 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const int32_t* __restric
 }
 
 // ------------------------------------------------------------------------------- planning --
+// Per partition: its ranges in the partitioned tuples and its work units.  In a batch the
+// partition's join (and so its fan-out) is found by binary search over the joins' first
+// partitions jpart0[0..nJobs]; a single join passes jpart0 = NULL and its own fan-out.
 __global__ void plan_units_k(const uint32_t* __restrict__ baseR, const uint32_t* __restrict__ totR,
                              const uint32_t* __restrict__ baseS, const uint32_t* __restrict__ totS,
-                             int P, uint32_t cap, uint32_t slice, PartInfo* __restrict__ info,
-                             uint32_t* __restrict__ units)
+                             int nParts, const uint32_t* __restrict__ jpart0,
+                             const int32_t* __restrict__ jbits, int nJobs, int bits, uint32_t cap,
+                             uint32_t slice, PartInfo* __restrict__ info, uint32_t* __restrict__ units)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > P) return;
-    if (p == P) {
-        units[P] = 0;
+    if (p > nParts) return;
+    if (p == nParts) {
+        units[nParts] = 0;
         return;
+    }
+    if (jpart0) {
+        int lo = 0, hi = nJobs - 1;  // last job whose first partition is <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jpart0[mid] <= (uint32_t)p) lo = mid;
+            else hi = mid - 1;
+        }
+        bits = jbits[lo];
     }
     const uint32_t nr = totR[p], ns = totS[p];
     const uint32_t nrc = (nr + cap - 1) / cap;
@@ -259,7 +289,8 @@ __global__ void plan_units_k(const uint32_t* __restrict__ baseR, const uint32_t*
     pi.nS = ns;
     pi.nSs = nss;
     pi.nRc = nrc;
-    pi.pad0 = pi.pad1 = 0;
+    pi.bits = (uint32_t)bits;
+    pi.pad = 0;
     info[p] = pi;
     units[p] = nrc * nss;
 }
@@ -277,6 +308,7 @@ __global__ void expand_units_k(const uint32_t* __restrict__ unitStart, int P, in
 // ------------------------------------------------------------------------- join work units --
 struct Unit {
     uint32_t rBeg, rN, sBeg, sN;
+    int bits;  // fan-out of the unit's join: the table position uses the hash bits below it
 };
 
 __device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
@@ -299,6 +331,7 @@ __device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
     o.rN = min(g.cap, pi.nR - rc * g.cap);
     o.sBeg = pi.sStart + sc * slen;
     o.sN = sc * slen < pi.nS ? min(slen, pi.nS - sc * slen) : 0u;
+    o.bits = (int)pi.bits;
     return o;
 }
 
@@ -406,7 +439,7 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
         const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
         if (e < un.rN) {
             uint32_t b1, b2;
-            choices(hmix(c.k[i]), g.bits, nb, b1, b2);
+            choices(hmix(c.k[i]), un.bits, nb, b1, b2);
             const bool second = cnt[b2] < cnt[b1];  // a racy read only steers the choice
             uint32_t b = second ? b2 : b1;
             uint32_t old = atomicAdd(&cnt[b], 1u);
@@ -646,7 +679,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
                     x[i] = cur[h + i];
                     ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
                 }
-                cnt += probe_count(t, g.bits, x, ok);
+                cnt += probe_count(t, un.bits, x, ok);
             }
         }
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xs);
@@ -705,7 +738,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                 load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
             else if (more)
                 load_tuples<AOS>(g, nxt, 0, nx, nr);
-            probe_write(t, g.bits, x, ok, m, p1, p2);
+            probe_write(t, un.bits, x, ok, m, p1, p2);
             // Slots inside the unit's range: waves take theirs from an LDS cursor (no block-wide
             // barrier); within a wave, the pairs of the i-th tuple of every lane are contiguous,
             // so each store instruction writes one coalesced run.
@@ -726,7 +759,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                 if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2((int32_t)rw[p2[i]], srid[i]);
                 if (m[i] > 2) {  // more than two build matches: visit the buckets again
                     uint32_t seen = 0;
-                    for_each_match(t, g.bits, x[i], [&](uint32_t p) {
+                    for_each_match(t, un.bits, x[i], [&](uint32_t p) {
                         if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
                         ++seen;
                     });
@@ -752,14 +785,30 @@ static int env_int(const char* name, int dflt)
 
 static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + sizeof(uint2)); }
 
+// Default fan-out: mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma
+// for hashed unique keys) under cap; past 2^kMaxBits partitions R chunks repeat per S slice.
+static int default_bits(int64_t nR, int cap)
+{
+    const double target = cap * 0.9;
+    int bits = 0;
+    while (bits < kMaxBits && (double)nR / (double)(1 << bits) > target) ++bits;
+    return bits;
+}
+
+static int env_cap()
+{
+    int cap = env_int("JOIN_HASH_CAP", 9216);
+    if (cap < 64) cap = 64;
+    if (cap > kMaxCap) cap = kMaxCap;
+    return cap;
+}
+
 HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
 {
     HashPlan pl{};
     pl.nR = nR;
     pl.nS = nS;
-    int cap = env_int("JOIN_HASH_CAP", 9216);
-    if (cap < 64) cap = 64;
-    if (cap > kMaxCap) cap = kMaxCap;
+    const int cap = env_cap();
     pl.cap = cap;
     pl.slice = env_int("JOIN_HASH_SLICE", 32768);
     if (pl.slice < 1024) pl.slice = 1024;
@@ -784,13 +833,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         pl.Umax = (nR > 0 && nS > 0) ? nrc * nss : 0;
     } else {
         int bits = forced_bits;
-        if (bits < 0) {
-            // mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma for
-            // hashed unique keys) under cap; past 2^kMaxBits partitions R chunks repeat per S slice
-            const double target = cap * 0.9;
-            bits = 1;
-            while (bits < kMaxBits && (double)nR / (double)(1 << bits) > target) ++bits;
-        }
+        if (bits < 0) bits = default_bits(nR, cap) < 1 ? 1 : default_bits(nR, cap);
         if (bits > kMaxBits) bits = kMaxBits;
         pl.bits = bits;
         pl.P = 1 << bits;
@@ -860,9 +903,7 @@ static hipError_t set_attrs()
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
     const void* fns[] = {
-        (const void*)scatter_k<true, true>, (const void*)scatter_k<true, false>,
-        (const void*)scatter_k<false, true>, (const void*)scatter_k<false, false>,
-        (const void*)hist_k<true>, (const void*)hist_k<false>,
+        (const void*)scatter_k, (const void*)hist_k,
         (const void*)join_count_k<true>, (const void*)join_count_k<false>,
         (const void*)join_write_k<true>, (const void*)join_write_k<false>,
     };
@@ -874,35 +915,34 @@ static hipError_t set_attrs()
     return hipSuccess;
 }
 
-static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
-
-static bool vec_ok(const join_rel_t& X) { return aligned16(X.key) && (X.rid == nullptr || aligned16(X.rid)); }
-
-static hipError_t hist_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
-                            uint32_t* tot, uint32_t* offs, hipStream_t st, bool is_r)
+static SideItem whole_side(const join_rel_t& X, int bits)
 {
-    if (X.n <= 0) return hipSuccess;
-    const size_t hl = (size_t)pl.P * 4;
+    SideItem it{};
+    it.key = X.key;
+    it.rid = X.rid;
+    it.bits = bits;
+    return it;
+}
+
+static hipError_t hist_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
+                            int64_t grid, int maxBits, uint32_t* tot, uint32_t* offs, hipStream_t st,
+                            bool is_r)
+{
+    if (grid <= 0) return hipSuccess;
+    const size_t hl = (size_t)4 << maxBits;
     prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
-    if (vec_ok(X)) hist_k<true><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, tot, offs);
-    else hist_k<false><<<(unsigned)nCh, kHistBlock, hl, st>>>(X.key, X.n, ch, pl.bits, tot, offs);
+    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, offs);
     return hipGetLastError();
 }
 
-static hipError_t scatter_side(const HashPlan& pl, const join_rel_t& X, int64_t ch, int64_t nCh,
-                               const uint32_t* base, const uint32_t* offs, int2* out, hipStream_t st,
-                               bool is_r)
+static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
+                               int64_t grid, int maxBits, const uint32_t* base, const uint32_t* offs,
+                               int2* out, hipStream_t st, bool is_r)
 {
-    if (X.n <= 0) return hipSuccess;
-    const size_t sl = scatter_lds(pl.P);
+    if (grid <= 0) return hipSuccess;
+    const size_t sl = scatter_lds(1 << maxBits);
     prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
-    if (vec_ok(X)) {
-        if (X.rid) scatter_k<true, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
-        else scatter_k<true, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
-    } else {
-        if (X.rid) scatter_k<false, true><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
-        else scatter_k<false, false><<<(unsigned)nCh, kScatBlock, sl, st>>>(X.key, X.rid, X.n, ch, pl.bits, base, offs, out);
-    }
+    scatter_k<<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, base, offs, out);
     return hipGetLastError();
 }
 
@@ -962,24 +1002,25 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = hist_side(pl, R, pl.chR, pl.nChR, totR, offsR, st, true);
+        const SideItem oneR = whole_side(R, pl.bits), oneS = whole_side(S, pl.bits);
+        e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, offsR, st, true);
         if (e != hipSuccess) return e;
-        e = hist_side(pl, S, pl.chS, pl.nChS, totS, offsS, st, false);
+        e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, offsS, st, false);
         if (e != hipSuccess) return e;
         e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
         e = exclusive_scan<uint32_t>(totS, baseS, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
-        e = scatter_side(pl, R, pl.chR, pl.nChR, baseR, offsR, tupR, st, true);
+        e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, baseR, offsR, tupR, st, true);
         if (e != hipSuccess) return e;
-        e = scatter_side(pl, S, pl.chS, pl.nChS, baseS, offsS, tupS, st, false);
+        e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, baseS, offsS, tupS, st, false);
         if (e != hipSuccess) return e;
         uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
         {
             prof::Scope pp(st, "hash.plan");
             plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
-                baseR, totR, baseS, totS, pl.P, (uint32_t)pl.cap, (uint32_t)pl.slice,
-                reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
+                baseR, totR, baseS, totS, pl.P, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
+                (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1022,6 +1063,252 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     prof::Scope pw(st, "hash.write");
     if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
     else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- batched joins --
+// Many independent joins go through the same kernels as one: every join gets its own fan-out
+// and a contiguous block of partitions in shared partition arrays; histogram and scatter items
+// are chunks of any join's sides; units of all joins form one list, so the count pass, the scan
+// of unit counts and the write pass are one launch each, and join j's pairs land contiguously,
+// in join order, in one output array.
+
+constexpr int64_t kBatchChunk = 16 * kScatTile;  // rows per histogram / scatter item
+
+static int job_bits(const join_job_t& j, int cap)
+{
+    int b = j.bits >= 0 ? j.bits : default_bits(j.R.n, cap);
+    return b > kMaxBits ? kMaxBits : b;
+}
+
+static int64_t side_items(int64_t n) { return n > 0 ? ceil_div(n, kBatchChunk) : 0; }
+
+static size_t take(size_t& off, size_t bytes)
+{
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+}
+
+int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* out)
+{
+    BatchPlan bp{};
+    bp.njobs = njobs;
+    bp.cap = env_cap();
+    bp.slice = env_int("JOIN_HASH_SLICE", 32768);
+    if (bp.slice < 1024) bp.slice = 1024;
+    int64_t umax = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const int b = job_bits(jobs[j], bp.cap);
+        if (b > bp.maxBits) bp.maxBits = b;
+        const int64_t P = (int64_t)1 << b;
+        bp.nParts += P;
+        bp.nItemsR += side_items(jobs[j].R.n);
+        bp.nItemsS += side_items(jobs[j].S.n);
+        bp.offsR += side_items(jobs[j].R.n) * P;
+        bp.offsS += side_items(jobs[j].S.n) * P;
+        bp.sumR += jobs[j].R.n;
+        bp.sumS += jobs[j].S.n;
+        umax += P + ceil_div(jobs[j].R.n, bp.cap) + ceil_div(jobs[j].S.n, bp.slice) + 1;
+    }
+    // partition starts, unit indices and item fields are 32-bit
+    if (bp.sumR >= ((int64_t)1 << 32) || bp.sumS >= ((int64_t)1 << 32) || umax >= ((int64_t)1 << 31) ||
+        bp.offsR >= ((int64_t)1 << 32) || bp.offsS >= ((int64_t)1 << 32))
+        return -1;
+    bp.Umax = umax;
+    size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
+    bp.off_jpart0 = take(off, (size_t)(njobs + 1) * 4);
+    bp.off_jbits = take(off, (size_t)njobs * 4);
+    bp.off_itemsR = take(off, (size_t)bp.nItemsR * sizeof(SideItem));
+    bp.off_itemsS = take(off, (size_t)bp.nItemsS * sizeof(SideItem));
+    bp.off_tot = take(off, (size_t)2 * bp.nParts * 4);
+    bp.off_baseR = take(off, (size_t)(bp.nParts + 1) * 4);
+    bp.off_baseS = take(off, (size_t)(bp.nParts + 1) * 4);
+    bp.off_offsR = take(off, (size_t)bp.offsR * 4);
+    bp.off_offsS = take(off, (size_t)bp.offsS * 4);
+    bp.off_tupR = take(off, (size_t)bp.sumR * 8);
+    bp.off_tupS = take(off, (size_t)bp.sumS * 8);
+    bp.off_info = take(off, (size_t)bp.nParts * sizeof(PartInfo));
+    bp.off_units = take(off, (size_t)(bp.nParts + 1) * 4);
+    bp.off_umap = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 4);
+    bp.off_counts = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 8);
+    size_t temp = scan_temp_elems<uint64_t>(bp.Umax) * 8;
+    const size_t t1 = scan_temp_elems<uint32_t>(bp.nParts + 1) * 4;
+    temp = temp > t1 ? temp : t1;
+    bp.off_temp = take(off, temp + 8);
+    bp.bytes = off;
+    auto grid_for = [&](bool rids) {
+        int per_cu = (int)((160 * 1024) / (table_lds((uint32_t)bp.cap, rids) + 128));
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 2) per_cu = 2;
+        return num_cus * per_cu;
+    };
+    bp.gridCount = grid_for(false);
+    bp.gridWrite = grid_for(true);
+    *out = bp;
+    return 0;
+}
+
+hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* ws, hipStream_t st)
+{
+    std::vector<uint32_t> jpart0((size_t)bp.njobs + 1);
+    std::vector<int32_t> jbits((size_t)bp.njobs);
+    std::vector<SideItem> itemsR((size_t)bp.nItemsR), itemsS((size_t)bp.nItemsS);
+    uint32_t part0 = 0, offsR = 0, offsS = 0;
+    size_t iR = 0, iS = 0;
+    for (int j = 0; j < bp.njobs; ++j) {
+        const int b = job_bits(jobs[j], bp.cap);
+        jpart0[j] = part0;
+        jbits[j] = b;
+        auto add = [&](const join_rel_t& X, std::vector<SideItem>& items, size_t& i, uint32_t& offs) {
+            for (int64_t beg = 0; beg < X.n; beg += kBatchChunk) {
+                SideItem it{};
+                it.key = X.key;
+                it.rid = X.rid;
+                it.beg = beg;
+                it.len = (uint32_t)(X.n - beg < kBatchChunk ? X.n - beg : kBatchChunk);
+                it.bits = b;
+                it.part0 = part0;
+                it.offs0 = offs;
+                offs += 1u << b;
+                items[i++] = it;
+            }
+        };
+        add(jobs[j].R, itemsR, iR, offsR);
+        add(jobs[j].S, itemsS, iS, offsS);
+        part0 += 1u << b;
+    }
+    jpart0[bp.njobs] = part0;
+    hipError_t e;
+    e = hipMemcpyAsync(ws + bp.off_jpart0, jpart0.data(), jpart0.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && bp.njobs > 0)
+        e = hipMemcpyAsync(ws + bp.off_jbits, jbits.data(), jbits.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !itemsR.empty())
+        e = hipMemcpyAsync(ws + bp.off_itemsR, itemsR.data(), itemsR.size() * sizeof(SideItem), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !itemsS.empty())
+        e = hipMemcpyAsync(ws + bp.off_itemsS, itemsS.data(), itemsS.size() * sizeof(SideItem), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host tables go out of scope
+    return e;
+}
+
+static JoinGeom batch_geom(const BatchPlan& bp, char* ws)
+{
+    JoinGeom g{};
+    g.cap = (uint32_t)bp.cap;
+    g.Umax = bp.Umax;
+    g.single = 0;
+    g.rt = reinterpret_cast<const int2*>(ws + bp.off_tupR);
+    g.st = reinterpret_cast<const int2*>(ws + bp.off_tupS);
+    g.part = reinterpret_cast<const PartInfo*>(ws + bp.off_info);
+    g.unitStart = reinterpret_cast<const uint32_t*>(ws + bp.off_units);
+    g.umap = reinterpret_cast<const uint32_t*>(ws + bp.off_umap);
+    g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
+    g.P = (int)bp.nParts;
+    return g;
+}
+
+namespace {
+// offsets[j] = first output slot of join j (its first unit's scanned offset); offsets[njobs] =
+// the total.  A join without units starts where the next one does.
+__global__ void job_offsets_k(const uint32_t* __restrict__ jpart0, int njobs,
+                              const uint32_t* __restrict__ unitStart, const uint64_t* __restrict__ scanned,
+                              int64_t Umax, const uint64_t* __restrict__ total, uint64_t* __restrict__ offsets)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > njobs) return;
+    if (j == njobs) {
+        offsets[j] = *total;
+        return;
+    }
+    const uint32_t u = unitStart[jpart0[j]];
+    offsets[j] = (int64_t)u < Umax ? scanned[u] : *total;
+}
+}  // namespace
+
+hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hipStream_t st)
+{
+    hipError_t e = set_attrs();
+    if (e != hipSuccess) return e;
+    uint64_t* total = reinterpret_cast<uint64_t*>(ws);
+    uint64_t* counts = reinterpret_cast<uint64_t*>(ws + bp.off_counts);
+    char* temp = ws + bp.off_temp;
+    const uint32_t* jpart0 = reinterpret_cast<const uint32_t*>(ws + bp.off_jpart0);
+    const int32_t* jbits = reinterpret_cast<const int32_t*>(ws + bp.off_jbits);
+    const SideItem* itemsR = reinterpret_cast<const SideItem*>(ws + bp.off_itemsR);
+    const SideItem* itemsS = reinterpret_cast<const SideItem*>(ws + bp.off_itemsS);
+    uint32_t* totR = reinterpret_cast<uint32_t*>(ws + bp.off_tot);
+    uint32_t* totS = totR + bp.nParts;
+    uint32_t* baseR = reinterpret_cast<uint32_t*>(ws + bp.off_baseR);
+    uint32_t* baseS = reinterpret_cast<uint32_t*>(ws + bp.off_baseS);
+    uint32_t* offsR = reinterpret_cast<uint32_t*>(ws + bp.off_offsR);
+    uint32_t* offsS = reinterpret_cast<uint32_t*>(ws + bp.off_offsS);
+    int2* tupR = reinterpret_cast<int2*>(ws + bp.off_tupR);
+    int2* tupS = reinterpret_cast<int2*>(ws + bp.off_tupS);
+    uint32_t* units = reinterpret_cast<uint32_t*>(ws + bp.off_units);
+    const SideItem none{};
+    if (bp.nParts > 0) {
+        prof::Scope pz(st, "hash.plan");
+        zero_u32_k<<<(unsigned)ceil_div(2 * bp.nParts, 256), 256, 0, st>>>(totR, 2 * bp.nParts);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hist_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, totR, offsR, st, true);
+    if (e != hipSuccess) return e;
+    e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, offsS, st, false);
+    if (e != hipSuccess) return e;
+    e = exclusive_scan<uint32_t>(totR, baseR, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+    if (e != hipSuccess) return e;
+    e = exclusive_scan<uint32_t>(totS, baseS, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+    if (e != hipSuccess) return e;
+    e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, baseR, offsR, tupR, st, true);
+    if (e != hipSuccess) return e;
+    e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, baseS, offsS, tupS, st, false);
+    if (e != hipSuccess) return e;
+    {
+        prof::Scope pp(st, "hash.plan");
+        plan_units_k<<<(unsigned)ceil_div(bp.nParts + 1, 256), 256, 0, st>>>(
+            baseR, totR, baseS, totS, (int)bp.nParts, jpart0, jbits, bp.njobs, 0, (uint32_t)bp.cap,
+            (uint32_t)bp.slice, reinterpret_cast<PartInfo*>(ws + bp.off_info), units);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = exclusive_scan<uint32_t>(units, units, bp.nParts + 1, reinterpret_cast<uint32_t*>(ws + 8),
+                                 reinterpret_cast<uint32_t*>(temp), st);
+    if (e != hipSuccess) return e;
+    if (bp.nParts > 0) {
+        prof::Scope pe(st, "hash.plan");
+        expand_units_k<<<(unsigned)ceil_div(bp.nParts, 256), 256, 0, st>>>(
+            units, (int)bp.nParts, bp.Umax, reinterpret_cast<uint32_t*>(ws + bp.off_umap));
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (bp.Umax > 0) {
+        const JoinGeom g = batch_geom(bp, ws);
+        prof::Scope pc(st, "hash.count");
+        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    e = exclusive_scan<uint64_t>(counts, counts, bp.Umax, total, reinterpret_cast<uint64_t*>(temp), st);
+    if (e != hipSuccess) return e;
+    {
+        prof::Scope po(st, "hash.plan");
+        job_offsets_k<<<(unsigned)ceil_div(bp.njobs + 1, 256), 256, 0, st>>>(
+            jpart0, bp.njobs, units, counts, bp.Umax, total, offsets);
+    }
+    return hipGetLastError();
+}
+
+hipError_t hash_batch_write(const BatchPlan& bp, char* ws, int32_t* pairs, uint64_t cap, hipStream_t st)
+{
+    if (bp.Umax <= 0) return hipSuccess;
+    hipError_t e = set_attrs();
+    if (e != hipSuccess) return e;
+    const JoinGeom g = batch_geom(bp, ws);
+    prof::Scope pw(st, "hash.write");
+    join_write_k<true><<<(unsigned)bp.gridWrite, kJoinBlock, table_lds((uint32_t)bp.cap, true), st>>>(
+        g, reinterpret_cast<const uint64_t*>(ws + bp.off_counts), reinterpret_cast<const uint64_t*>(ws),
+        reinterpret_cast<int2*>(pairs), cap);
     return hipGetLastError();
 }
 

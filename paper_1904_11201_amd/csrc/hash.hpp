@@ -4,10 +4,21 @@
 
 namespace jl {
 
-// One radix partition after the scatter: its R and S ranges in the partitioned columns and its
-// work-unit split (nRc R chunks that fit the LDS table, nSs S slices).
+// One radix partition after the scatter: its R and S ranges in the partitioned tuples, its
+// work-unit split (nRc R chunks that fit the LDS table, nSs S slices) and its join's fan-out.
 struct PartInfo {
-    uint32_t rStart, nR, sStart, nS, nSs, nRc, pad0, pad1;
+    uint32_t rStart, nR, sStart, nS, nSs, nRc, bits, pad;
+};
+
+// One chunk of one relation side of one join, for the histogram and scatter kernels.
+struct SideItem {
+    const int32_t* key;
+    const int32_t* rid;  // NULL: rid = row position
+    int64_t beg;         // first row of the chunk
+    uint32_t len;        // rows in the chunk
+    int32_t bits;        // the join's fan-out
+    uint32_t part0;      // the join's first partition in the partition arrays
+    uint32_t offs0;      // start of this chunk's 2^bits entries in the offsets array
 };
 
 // Everything the count and write kernels need to walk the work units.
@@ -55,5 +66,30 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
 // Write pass from the state hash_count left in ws.
 hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
                       int32_t* pairs, uint64_t cap, hipStream_t st);
+
+// A batch of independent equi joins: layout of the shared workspace and launch sizes.  Kept
+// by the caller as an opaque join_batch_plan_t between the prepare, count and write calls.
+struct BatchPlan {
+    int32_t njobs, maxBits, cap, slice;
+    int64_t nParts, nItemsR, nItemsS, offsR, offsS, sumR, sumS, Umax;
+    uint64_t off_jpart0, off_jbits, off_itemsR, off_itemsS, off_tot, off_baseR, off_baseS;
+    uint64_t off_offsR, off_offsS, off_tupR, off_tupS, off_info, off_units, off_umap;
+    uint64_t off_counts, off_temp, bytes;
+    int32_t gridCount, gridWrite;
+};
+
+// Plans the batch (fan-out per join, items, workspace layout).  Returns -1 when the batch
+// exceeds the 32-bit row, partition or unit indices.
+int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* out);
+
+// Uploads the join and item tables into ws and waits for the copies.
+hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* ws, hipStream_t st);
+
+// Histogram, scatter, planning and count pass of every join, the scan of unit counts, and the
+// per-join output offsets (offsets[0..njobs], offsets[njobs] = total).  Launches only.
+hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hipStream_t st);
+
+// Write pass of every join from the state hash_batch_count left in ws.  Launches only.
+hipError_t hash_batch_write(const BatchPlan& bp, char* ws, int32_t* pairs, uint64_t cap, hipStream_t st);
 
 }  // namespace jl

@@ -22,13 +22,14 @@ import dataclasses
 import torch
 
 from . import _native
-from ._native import JOIN_KIND_HASH, JOIN_KIND_THETA, JOIN_KIND_THETA_REGION, OPS, JoinPred, JoinRel
+from ._native import (JOIN_KIND_HASH, JOIN_KIND_THETA, JOIN_KIND_THETA_REGION, OPS, JoinBatchPlan,
+                      JoinJob, JoinPred, JoinRel)
 
 __all__ = [
     "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "JOIN_KIND_THETA_REGION",
     "join_workspace_bytes",
     "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
-    "hash_join", "theta_join",
+    "hash_join", "theta_join", "Job", "Batch", "hash_join_batch",
 ]
 
 
@@ -197,3 +198,62 @@ def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = N
     """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output.
     region=True uses the region-pruned algorithm (JOIN_KIND_THETA_REGION); same result."""
     return _exact(JOIN_KIND_THETA_REGION if region else JOIN_KIND_THETA, R, S, pred, ws, stream)
+
+
+# ---- batched equi joins ------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Job:
+    """One equi join of a batch: R.key = S.key.  bits < 0 lets the library pick the fan-out."""
+    R: Relation
+    S: Relation
+    bits: int = -1
+
+
+class Batch:
+    """A prepared batch of independent equi joins (join_batch_prepare).  count() and
+    materialize() only launch kernels, so they can run inside a captured HIP graph.  The
+    relations' tensors must stay alive and unchanged while the batch is in use."""
+
+    def __init__(self, jobs: list[Job], stream=None, device="cuda"):
+        self.jobs = list(jobs)
+        n = len(self.jobs)
+        self._c = (JoinJob * max(n, 1))()
+        for i, j in enumerate(self.jobs):
+            self._c[i] = JoinJob(j.R.c(), j.S.c(), int(j.bits), 0)
+        nbytes = int(_native.lib.join_batch_workspace_bytes(n, self._c))
+        if nbytes == 0:
+            raise JoinError(_native.JOIN_E_INVAL, _native.last_error() or "batch too large")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.plan = JoinBatchPlan()
+        self.offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+        _check(_native.lib.join_batch_prepare(n, self._c, ctypes.c_void_p(self.ws.data_ptr()),
+                                              self.ws.numel(), ctypes.byref(self.plan),
+                                              _stream(stream)))
+
+    def count(self, stream=None) -> torch.Tensor:
+        """Count pass of every join; returns the device offsets tensor ([njobs + 1] int64:
+        join j's pairs are [offsets[j], offsets[j+1]), offsets[-1] is the total)."""
+        _check(_native.lib.join_batch_count(ctypes.byref(self.plan), ctypes.c_void_p(self.ws.data_ptr()),
+                                            self.ws.numel(), ctypes.c_void_p(self.offsets.data_ptr()),
+                                            _stream(stream)))
+        return self.offsets
+
+    def materialize(self, pairs: torch.Tensor, stream=None) -> None:
+        """Write pass of every join into pairs ([capacity, 2] int32)."""
+        if pairs.dtype != torch.int32 or not pairs.is_contiguous():
+            raise ValueError("pairs must be a contiguous int32 tensor")
+        cap = pairs.numel() // 2
+        _check(_native.lib.join_batch_materialize(
+            ctypes.byref(self.plan), ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+            ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap, _stream(stream)))
+
+
+def hash_join_batch(jobs: list[Job], stream=None):
+    """All joins of the batch: (pairs [total, 2] int32, offsets host list of njobs + 1 ints)."""
+    b = Batch(jobs, stream)
+    offs = b.count(stream)
+    total = int(offs[-1].item())
+    out = torch.empty((total, 2), dtype=torch.int32, device=b.ws.device)
+    b.materialize(out, stream)
+    return out, [int(v) for v in offs.cpu().tolist()]

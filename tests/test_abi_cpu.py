@@ -99,3 +99,39 @@ def test_single_hip_runtime_shared_with_torch():
     stream handles are valid inside it."""
     rts = n._hip_runtimes()
     assert len(rts) == 1, rts
+
+
+def _jobs(specs):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced by the sizing and validation calls
+    arr = (n.JoinJob * max(len(specs), 1))()
+    for i, (nr, ns, bits, reserved) in enumerate(specs):
+        arr[i] = n.JoinJob(_rel(fake if nr else None, nr), _rel(fake if ns else None, ns), bits, reserved)
+    return arr
+
+
+def test_batch_workspace_sizes_and_argument_errors():
+    ws = n.lib.join_batch_workspace_bytes
+    assert ws(0, _jobs([])) > 0  # an empty batch still has its header
+    assert ws(-1, _jobs([])) == 0
+    one = ws(1, _jobs([(1000, 2000, -1, 0)]))
+    two = ws(2, _jobs([(1000, 2000, -1, 0), (1 << 20, 1 << 22, -1, 0)]))
+    assert 0 < one < two
+    # the partitioned tuples of both sides are part of the workspace
+    assert two >= 8 * (1000 + 2000 + (1 << 20) + (1 << 22))
+    assert ws(1, _jobs([(10, 10, 12, 0)])) == 0        # fan-out above 2^11
+    assert ws(1, _jobs([(10, 10, -1, 1)])) == 0        # reserved must be 0
+    assert ws(1, _jobs([(-1, 10, -1, 0)])) == 0        # negative size
+    arr = _jobs([(10, 10, -1, 0)])
+    arr[0].R.key = None                                # key NULL with n > 0
+    assert ws(1, arr) == 0
+    # 32-bit row indices: three probe sides of 2^31 - 1 rows exceed them, two do not
+    big = (1 << 31) - 1
+    assert ws(2, _jobs([(10, big, -1, 0), (10, big, -1, 0)])) > 0
+    assert ws(3, _jobs([(10, big, -1, 0)] * 3)) == 0
+    plan = n.JoinBatchPlan()
+    rc = n.lib.join_batch_prepare(1, _jobs([(10, 10, 12, 0)]), None, 0, ctypes.byref(plan), None)
+    assert rc == n.JOIN_E_INVAL and "bits" in n.last_error()
+    rc = n.lib.join_batch_prepare(1, _jobs([(10, 10, -1, 0)]), None, 0, ctypes.byref(plan), None)
+    assert rc == n.JOIN_E_WORKSPACE
+    assert n.lib.join_batch_count(None, None, 0, None, None) == n.JOIN_E_INVAL
+    assert n.lib.join_batch_materialize(None, None, 0, None, 0, None) == n.JOIN_E_INVAL
