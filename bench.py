@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-runs", type=int, default=200)
+    ap.add_argument("--batch-jobs", type=int, default=4096,
+                    help="joins in the batched-join comparison (0 skips it)")
     return ap.parse_args()
 
 
@@ -66,6 +68,110 @@ def load_traffic():
     if t.get("src_hash") != src_hash():
         return {}
     return t.get("kernels", {})
+
+
+def bench_batch(args, J, datagen, dev, stream):
+    """Batched equi joins (4096 joins, per-side sizes log-uniform in [1K, 4M], keys uniform over
+    the build size, 10% Zipf probe sides): one launch per join vs the batch, eager and with the
+    count pass replayed from a captured graph.  Each form: count, one total read, exact
+    allocation, write."""
+    import torch
+    from paper_1904_11201_amd import tune
+    t0 = time.time()
+    raw = datagen.batch_jobs_device(seed=6, jobs=args.batch_jobs, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    jobs = [J.Job(J.Relation(rk), J.Relation(sk)) for rk, sk, _ in raw]
+    rows_r = sum(j.R.n for j in jobs)
+    rows_s = sum(j.S.n for j in jobs)
+    print(f"# batch: {len(jobs)} joins, {rows_r} x {rows_s} rows generated in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    reps = 3
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3, r
+
+    # one launch sequence per join (count with its 8-byte read, allocation, write)
+    ws = J.workspace(J.JOIN_KIND_HASH, max(j.R.n for j in jobs), max(j.S.n for j in jobs))
+
+    def per_join():
+        tot = 0
+        for j in jobs:
+            n = J.join_count(J.JOIN_KIND_HASH, j.R, j.S, None, ws, stream)
+            out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+            J.join_materialize(J.JOIN_KIND_HASH, j.R, j.S, None, ws, out, stream)
+            tot += n
+        return tot
+
+    per_join()
+    pj = [wall(per_join) for _ in range(reps)]
+    per_ms = statistics.median(t for t, _ in pj)
+    total_pj = pj[-1][1]
+    del ws
+    torch.cuda.empty_cache()
+
+    cache = tune.load()
+    tuned = bool(cache.get("hash_bits"))
+    bjobs = tune.apply_bits([J.Job(j.R, j.S, -1) for j in jobs], cache) if tuned else jobs
+    tp, b = wall(lambda: J.Batch(bjobs, stream))
+
+    def batch_once():
+        offs = b.count(stream)
+        total = int(offs[-1].item())
+        out = torch.empty((total, 2), dtype=torch.int32, device=dev)
+        b.materialize(out, stream)
+        return total
+
+    batch_once()
+    bt = [wall(batch_once) for _ in range(reps)]
+    batch_ms = statistics.median(t for t, _ in bt)
+    total_b = bt[-1][1]
+    assert total_b == total_pj, (total_b, total_pj)
+
+    # the count pass captured once, replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.count(side)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.count()
+
+    def graph_once():
+        graph.replay()
+        total = int(b.offsets[-1].item())
+        out = torch.empty((total, 2), dtype=torch.int32, device=dev)
+        b.materialize(out)
+        return total
+
+    graph_once()
+    gt = [wall(graph_once) for _ in range(reps)]
+    graph_ms = statistics.median(t for t, _ in gt)
+    assert gt[-1][1] == total_pj
+    del graph, b
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{len(jobs)} independent equi joins, per-side sizes log-uniform in [1K, 4M], "
+                    "keys uniform over the build size, 10% Zipf(1.0) probe sides",
+        "jobs": len(jobs), "rows_R": rows_r, "rows_S": rows_s, "pairs": total_b,
+        "fanout": "autotuned" if tuned else "default rule",
+        "per_join_ms": round(per_ms, 2),
+        "batch_ms": round(batch_ms, 2),
+        "batch_prepare_ms": round(tp, 2),
+        "graph_ms": round(graph_ms, 2),
+        "per_join_probe_tuples_per_s": round(rows_s / (per_ms * 1e-3), 1),
+        "batch_probe_tuples_per_s": round(rows_s / (batch_ms * 1e-3), 1),
+        "graph_probe_tuples_per_s": round(rows_s / (graph_ms * 1e-3), 1),
+        "speedup_batch_vs_per_join": round(per_ms / batch_ms, 3),
+        "speedup_graph_vs_per_join": round(per_ms / graph_ms, 3),
+        "timing": "host wall clock, median of 3, count + total read + exact allocation + write; "
+                  "prepare (host planning and table upload) reported separately",
+    }
 
 
 def main():
@@ -166,6 +272,22 @@ def main():
         if i >= args.warmup:
             lt_ms.append(a.elapsed_time(b))
 
+    # the same band join by region pruning (shared value buckets; only red tiles evaluated)
+    ws_r = J.workspace(J.JOIN_KIND_THETA_REGION, Rt.n, St.n, theta_pred)
+    reg_ms = []
+    for i in range(args.warmup + 10):
+        a, b = ev(), ev()
+        a.record(stream)
+        n_reg = J.join_count(J.JOIN_KIND_THETA_REGION, dRt, dSt, theta_pred, ws_r, stream)
+        out = torch.empty((n_reg, 2), dtype=torch.int32, device=dev)
+        J.join_materialize(J.JOIN_KIND_THETA_REGION, dRt, dSt, theta_pred, ws_r, out, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            reg_ms.append(a.elapsed_time(b))
+    assert n_reg == n_th, (n_reg, n_th)
+    del ws_r, out
+
     # single-request latency of the small equi join (64K x 64K), host-observed, end to end
     ws_c1 = J.workspace(J.JOIN_KIND_HASH, Rc1.n, Sc1.n)
     lat = []
@@ -183,6 +305,8 @@ def main():
     def pct(v, q):
         return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
+    batch = bench_batch(args, J, datagen, dev, stream) if args.batch_jobs > 0 else None
+
     # ---- per-kernel figures over the timed steps (HIP events on the launch stream) ----------
     traffic = load_traffic()
     pairs_band = Rt.n * St.n
@@ -195,7 +319,7 @@ def main():
         "hash.count": ("hbm", 4 * nR + 4 * nS),
         "hash.write": ("hbm", 8 * nR + 8 * nS + 8 * nS),
         "theta.count": ("alu", 2 * pairs_band),
-        "theta.write": ("alu", 2 * pairs_band),
+        "theta.write": ("hbm", 16 * n_th),
     }
     kernels = []
     for name, (launches, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
@@ -288,12 +412,16 @@ def main():
             "lt_count_64k_frac_of_valu_peak": round(
                 2 * Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
             "lt_count_64k_count": n_lt,
+            "region_ms": round(statistics.median(reg_ms), 4),
+            "region_pairs_per_s": round(n_th / (statistics.median(reg_ms) * 1e-3), 1),
+            "region_speedup_vs_nested_loop": round(th_mean / statistics.median(reg_ms), 1),
             "cpu_baseline": cpu_theta,
         },
         "latency": {"workload": "hash equi-join 64K x 64K, keys uniform in [0,16384), "
                                 "count + exact allocation + write, host-observed",
                     "runs": len(lat), "p50_ms": round(pct(lat, 0.5), 4),
                     "p99_ms": round(pct(lat, 0.99), 4), "pairs": n_c1},
+        "batch": batch,
         "kernels": kernels,
         "src_hash": src_hash(),
     }

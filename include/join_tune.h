@@ -1,0 +1,45 @@
+/* join_tune.h -- process-wide tuning knobs of libjoin.
+ *
+ * The knobs change only how the work is cut up (table capacity, fan-out, tile shapes), never the
+ * result.  The paper tunes its own cut of the work, the reducer count alpha, by measurement
+ * (Section 3.3.4, equation "hier"; Sections 5.1.4 and 5.2.4); these knobs are what the
+ * project's autotuner sets from its measured cache.
+ *
+ * Every knob is read when a call plans its work, so a workspace sized under one setting must
+ * be counted and materialized under the same setting.  A value set here wins over the
+ * environment variable of the same knob, which wins over the built-in default.  Setting is
+ * atomic per knob; concurrent calls that plan while a knob changes may see either value.
+ *
+ * Knobs (name, environment variable, meaning):
+ *   "hash.cap"               JOIN_HASH_CAP                R entries per LDS table, 64..10240
+ *   "hash.slice"             JOIN_HASH_SLICE              S rows per work unit, >= 1024
+ *   "hash.bits"              JOIN_HASH_BITS               single-join fan-out log2, -1 automatic
+ *   "hash.single_max_chunks" JOIN_HASH_SINGLE_MAX_CHUNKS  R up to this many tables: no partitioning
+ *   "theta.ts"               JOIN_THETA_TS                S rows per theta tile, 0 automatic
+ *   "theta.waves"            JOIN_THETA_WAVES             waves a theta grid aims for, 0 automatic
+ *   "theta.stash"            JOIN_THETA_STASH             matches stashed per theta work unit
+ */
+#ifndef JOIN_TUNE_H
+#define JOIN_TUNE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JOIN_TUNE_UNKNOWN 1 /* no knob of that name (or value == NULL) */
+
+/* Sets knob `name` to `value`, or back to its environment/default value if clear != 0.
+ * Returns 0 or JOIN_TUNE_UNKNOWN. */
+int join_tune_set(const char* name, int64_t value, int clear);
+
+/* Current value of knob `name` (set value, else environment, else `dflt`) into *value.
+ * Returns 0 or JOIN_TUNE_UNKNOWN. */
+int join_tune_get(const char* name, int64_t dflt, int64_t* value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JOIN_TUNE_H */

@@ -31,7 +31,7 @@ EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash"
            "join_batch_workspace_bytes", "join_batch_prepare", "join_batch_count",
            "join_batch_materialize", "join_last_error", "join_scan_workspace_bytes",
            "join_scan_u64", "join_prof_enable", "join_prof_collect", "join_prof_count",
-           "join_prof_entry")
+           "join_prof_entry", "join_tune_set", "join_tune_get")
 
 
 class JoinRel(ctypes.Structure):
@@ -98,6 +98,10 @@ def _load():
     lib.join_batch_count.argtypes = [Bp, vp, sz, vp, vp]
     lib.join_batch_materialize.restype = ctypes.c_int
     lib.join_batch_materialize.argtypes = [Bp, vp, sz, vp, u64, vp]
+    lib.join_tune_set.restype = ctypes.c_int
+    lib.join_tune_set.argtypes = [ctypes.c_char_p, i64, ctypes.c_int]
+    lib.join_tune_get.restype = ctypes.c_int
+    lib.join_tune_get.argtypes = [ctypes.c_char_p, i64, ctypes.POINTER(i64)]
     lib.join_last_error.restype = ctypes.c_char_p
     lib.join_last_error.argtypes = []
     lib.join_scan_workspace_bytes.restype = sz
@@ -139,3 +143,17 @@ def prof_read() -> dict:
         if lib.join_prof_entry(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)) == 0:
             out[name.value.decode()] = (int(cnt.value), float(ms.value))
     return out
+
+
+def tune_set(name: str, value: int | None) -> None:
+    """Set tuning knob `name` (see include/join_tune.h); None restores environment/default."""
+    rc = lib.join_tune_set(name.encode(), 0 if value is None else int(value), 1 if value is None else 0)
+    if rc != 0:
+        raise KeyError(name)
+
+
+def tune_get(name: str, default: int) -> int:
+    v = ctypes.c_int64(0)
+    if lib.join_tune_get(name.encode(), int(default), ctypes.byref(v)) != 0:
+        raise KeyError(name)
+    return int(v.value)

@@ -8,6 +8,7 @@
 #include "region.hpp"
 #include "scan.hpp"
 #include "theta.hpp"
+#include "tune.hpp"
 
 namespace jl {
 
@@ -46,22 +47,13 @@ int num_cus()
 
 int64_t theta_target_waves()
 {
-    const char* s = getenv("JOIN_THETA_WAVES");
-    if (s && *s) return atoll(s);
-    return (int64_t)num_cus() * 4 * 16;  // 16 waves per SIMD, two rounds at occupancy 8
+    const int64_t w = tune_get(TUNE_THETA_WAVES, 0);
+    return w > 0 ? w : (int64_t)num_cus() * 4 * 16;  // 16 waves per SIMD, two rounds at occupancy 8
 }
 
-int64_t theta_ts_override()
-{
-    const char* s = getenv("JOIN_THETA_TS");
-    return (s && *s) ? atoll(s) : 0;
-}
+int64_t theta_ts_override() { return tune_get(TUNE_THETA_TS, 0); }
 
-int64_t theta_stash_k()
-{
-    const char* s = getenv("JOIN_THETA_STASH");
-    return (s && *s) ? atoll(s) : 128;
-}
+int64_t theta_stash_k() { return tune_get(TUNE_THETA_STASH, 128); }
 
 ThetaPlan plan_theta(int64_t nR, int64_t nS, const join_pred_t* p)
 {

@@ -25,6 +25,7 @@
 
 #include "prof.hpp"
 #include "scan.hpp"
+#include "tune.hpp"
 
 namespace jl {
 
@@ -776,12 +777,6 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-static int env_int(const char* name, int dflt)
-{
-    const char* s = getenv(name);
-    if (!s || !*s) return dflt;
-    return atoi(s);
-}
 
 static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + sizeof(uint2)); }
 
@@ -797,10 +792,10 @@ static int default_bits(int64_t nR, int cap)
 
 static int env_cap()
 {
-    int cap = env_int("JOIN_HASH_CAP", 9216);
+    int64_t cap = tune_get(TUNE_HASH_CAP, 9216);
     if (cap < 64) cap = 64;
     if (cap > kMaxCap) cap = kMaxCap;
-    return cap;
+    return (int)cap;
 }
 
 HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
@@ -810,10 +805,10 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     pl.nS = nS;
     const int cap = env_cap();
     pl.cap = cap;
-    pl.slice = env_int("JOIN_HASH_SLICE", 32768);
+    pl.slice = (int)tune_get(TUNE_HASH_SLICE, 32768);
     if (pl.slice < 1024) pl.slice = 1024;
-    const int64_t single_max = (int64_t)env_int("JOIN_HASH_SINGLE_MAX_CHUNKS", 16) * cap;
-    const int forced_bits = env_int("JOIN_HASH_BITS", -1);
+    const int64_t single_max = tune_get(TUNE_HASH_SINGLE_MAX, 16) * cap;
+    const int forced_bits = (int)tune_get(TUNE_HASH_BITS, -1);
     pl.single = forced_bits == 0 || (forced_bits < 0 && nR <= single_max);
     size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
     if (pl.single) {
@@ -1095,7 +1090,7 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     BatchPlan bp{};
     bp.njobs = njobs;
     bp.cap = env_cap();
-    bp.slice = env_int("JOIN_HASH_SLICE", 32768);
+    bp.slice = (int)tune_get(TUNE_HASH_SLICE, 32768);
     if (bp.slice < 1024) bp.slice = 1024;
     int64_t umax = 0;
     for (int j = 0; j < njobs; ++j) {

@@ -142,6 +142,37 @@ def batch_jobs(seed: int = 6, jobs: int = 4096, lo: int = 1 * K, hi: int = 4 * M
     return out
 
 
+def batch_jobs_device(seed: int = 6, jobs: int = 4096, lo: int = 1 * K, hi: int = 4 * M,
+                      zipf_frac: float = 0.10, device="cuda"):
+    """The batch workload of batch_jobs generated directly in device memory (for full-size
+    runs): the same size law and zipf_frac choice from PCG64(seed); keys drawn by a seeded
+    torch generator on the device; Zipf probe keys by the same inverse-CDF rule as zipf_ranks
+    (harmonic table, float64) through a per-job random permutation.  Returns a list of
+    (R key tensor, S key tensor, is_zipf); rids are row positions."""
+    import torch
+    g = rng_for(seed)
+    nR = log_uniform_sizes(g, jobs, lo, hi)
+    nS = log_uniform_sizes(g, jobs, lo, hi)
+    is_zipf = g.random(jobs) < zipf_frac
+    tg = torch.Generator(device=device)
+    tg.manual_seed(seed)
+    out = []
+    for j in range(jobs):
+        d = int(nR[j])
+        rk = torch.randint(0, d, (d,), device=device, dtype=torch.int32, generator=tg)
+        if is_zipf[j]:
+            harm = torch.cumsum(1.0 / torch.arange(1, d + 1, device=device, dtype=torch.float64), 0)
+            u = torch.rand(int(nS[j]), device=device, dtype=torch.float64, generator=tg)
+            r = torch.searchsorted(harm, u * harm[-1], right=True).clamp_(max=d - 1)
+            perm = torch.randperm(d, device=device, generator=tg).to(torch.int32)
+            sk = perm[r]
+            del harm, u, r, perm
+        else:
+            sk = torch.randint(0, d, (int(nS[j]),), device=device, dtype=torch.int32, generator=tg)
+        out.append((rk, sk, bool(is_zipf[j])))
+    return out
+
+
 @dataclasses.dataclass
 class Request:
     """One serving request.  kind is 'hash' or 'theta'; build_id >= 0 names a resident build

@@ -194,10 +194,23 @@ def hash_join(R: Relation, S: Relation, ws: torch.Tensor | None = None, stream=N
 
 
 def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = None, stream=None,
-               region: bool = False):
+               region: bool = False, tuned: bool = False):
     """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output.
-    region=True uses the region-pruned algorithm (JOIN_KIND_THETA_REGION); same result."""
-    return _exact(JOIN_KIND_THETA_REGION if region else JOIN_KIND_THETA, R, S, pred, ws, stream)
+    region=True uses the region-pruned algorithm (JOIN_KIND_THETA_REGION); same result.
+    tuned=True applies the autotuner's S tile for these sizes (process-wide knob, set for the
+    duration of the call)."""
+    kind = JOIN_KIND_THETA_REGION if region else JOIN_KIND_THETA
+    if not tuned:
+        return _exact(kind, R, S, pred, ws, stream)
+    from . import tune
+    ts = tune.theta_ts_for(R.n, S.n)
+    if ts <= 0:
+        return _exact(kind, R, S, pred, ws, stream)
+    _native.tune_set("theta.ts", ts)
+    try:
+        return _exact(kind, R, S, pred, None, stream)  # the workspace size depends on the tile
+    finally:
+        _native.tune_set("theta.ts", None)
 
 
 # ---- batched equi joins ------------------------------------------------------------------------
@@ -249,8 +262,12 @@ class Batch:
             ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap, _stream(stream)))
 
 
-def hash_join_batch(jobs: list[Job], stream=None):
-    """All joins of the batch: (pairs [total, 2] int32, offsets host list of njobs + 1 ints)."""
+def hash_join_batch(jobs: list[Job], stream=None, tuned: bool = False):
+    """All joins of the batch: (pairs [total, 2] int32, offsets host list of njobs + 1 ints).
+    tuned=True gives every job without a fan-out the autotuner's choice for its build size."""
+    if tuned:
+        from . import tune
+        jobs = tune.apply_bits([Job(j.R, j.S, j.bits) for j in jobs])
     b = Batch(jobs, stream)
     offs = b.count(stream)
     total = int(offs[-1].item())

@@ -135,3 +135,21 @@ def test_batch_workspace_sizes_and_argument_errors():
     assert rc == n.JOIN_E_WORKSPACE
     assert n.lib.join_batch_count(None, None, 0, None, None) == n.JOIN_E_INVAL
     assert n.lib.join_batch_materialize(None, None, 0, None, 0, None) == n.JOIN_E_INVAL
+
+
+def test_tuning_knobs_override_environment(monkeypatch):
+    monkeypatch.setenv("JOIN_HASH_CAP", "4096")
+    assert n.tune_get("hash.cap", 9216) == 4096
+    small = n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, 1 << 24, 1 << 26, None)
+    n.tune_set("hash.cap", 10240)
+    try:
+        assert n.tune_get("hash.cap", 9216) == 10240
+        # fewer, larger partitions: smaller histogram/offset arrays in the workspace
+        assert n.lib.join_workspace_bytes(n.JOIN_KIND_HASH, 1 << 24, 1 << 26, None) != small
+    finally:
+        n.tune_set("hash.cap", None)
+    assert n.tune_get("hash.cap", 9216) == 4096
+    monkeypatch.delenv("JOIN_HASH_CAP")
+    assert n.tune_get("hash.cap", 9216) == 9216
+    with pytest.raises(KeyError):
+        n.tune_set("no.such.knob", 1)

@@ -1,0 +1,31 @@
+"""Autotuner cache lookups (host logic only; the measurements themselves need a GPU)."""
+from paper_1904_11201_amd import tune
+
+
+class _J:
+    def __init__(self, n, bits=-1):
+        self.R = type("R", (), {"n": n})()
+        self.bits = bits
+
+
+CACHE = {"hash_bits": {"10": 0, "14": 1, "18": 6, "22": 10}, "theta_ts": {"12": 1024, "16": 4096}}
+
+
+def test_nearest_bucket_at_or_below():
+    assert tune.hash_bits_for(1 << 18, CACHE) == 6
+    assert tune.hash_bits_for((1 << 20) + 5, CACHE) == 6      # bucket 20 -> tuned 18
+    assert tune.hash_bits_for(1 << 23, CACHE) == 10
+    assert tune.hash_bits_for(100, CACHE) == 0                # below every bucket: the smallest
+    assert tune.hash_bits_for(1 << 18, {}) == -1              # nothing tuned: library default
+
+
+def test_theta_tile_clamped_to_probe_side():
+    assert tune.theta_ts_for(1 << 16, 1 << 16, CACHE) == 4096
+    assert tune.theta_ts_for(1 << 12, 300, CACHE) == 300
+    assert tune.theta_ts_for(1 << 16, 1 << 16, {}) == 0
+
+
+def test_apply_bits_keeps_explicit_choices():
+    jobs = [_J(1 << 14), _J(1 << 22, bits=3)]
+    tune.apply_bits(jobs, CACHE)
+    assert [j.bits for j in jobs] == [1, 3]
