@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--latency-runs", type=int, default=200)
     ap.add_argument("--batch-jobs", type=int, default=4096,
                     help="joins in the batched-join comparison (0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=1024,
+                    help="requests in the serving comparison (0 skips it)")
     return ap.parse_args()
 
 
@@ -172,6 +174,48 @@ def bench_batch(args, J, datagen, dev, stream):
         "timing": "host wall clock, median of 3, count + total read + exact allocation + write; "
                   "prepare (host planning and table upload) reported separately",
     }
+
+
+def bench_serve(args, J):
+    """Serving: Poisson stream, 80% equi / 20% band (w = 8) joins, per-side sizes log-uniform in
+    [1K, 8M], 30% of requests probing one of 16 resident builds, 64 GB HBM budget.  Closed-loop
+    capacity with 4 slots, then open loop at 0.5x and 0.8x that rate; the plain form (one slot,
+    no resident builds) closed loop beside it."""
+    import torch
+    from paper_1904_11201_amd import serve
+    t0 = time.time()
+    builds, reqs = serve.requests_device(seed=7, count=args.serve_requests)
+    torch.cuda.synchronize()
+    print(f"# serve: {len(reqs)} requests generated in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    eng = serve.Engine(builds, slots=4, budget_bytes=64 << 30)
+    plain = serve.Engine(builds, slots=1, budget_bytes=64 << 30, resident=False)
+    eng.serve(reqs[:16], open_loop=False, keep_pairs=False)  # warm-up
+    res, wall = eng.serve(reqs, open_loop=False, keep_pairs=False)
+    closed = serve.summary(res, wall)
+    mu = closed["requests_per_s"]
+    res, wall = plain.serve(reqs, open_loop=False, keep_pairs=False)
+    plain_closed = serve.summary(res, wall)
+    opened = {}
+    for f in (0.5, 0.8):
+        res, wall = eng.serve(serve.at_rate(reqs, f * mu), open_loop=True, keep_pairs=False)
+        opened[f"{f}x"] = dict(serve.summary(res, wall), qps=round(f * mu, 2))
+        print(f"# serve open loop {f}x: {opened[f'{f}x']}", file=sys.stderr, flush=True)
+    n_theta = sum(r.kind == "theta" for r in reqs)
+    n_res = sum(r.R is None for r in reqs)
+    out = {
+        "workload": f"{len(reqs)} requests: {len(reqs) - n_theta} equi ({n_res} on resident "
+                    f"builds), {n_theta} band w=8 (region pruned); sizes log-uniform [1K, 8M]",
+        "slots": eng.slots, "budget_bytes": eng.budget, "peak_reserved_bytes": eng.peak,
+        "resident_build_bytes": eng.resident_bytes, "admission_waits": eng.waits,
+        "closed_loop": closed, "plain_closed_loop": plain_closed,
+        "throughput_vs_plain": round(closed["pairs_per_s"] / plain_closed["pairs_per_s"], 3),
+        "open_loop": opened,
+        "latency": "arrival to completion on the host clock, count + admission + write",
+    }
+    del eng, plain, builds, reqs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -306,6 +350,7 @@ def main():
         return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
     batch = bench_batch(args, J, datagen, dev, stream) if args.batch_jobs > 0 else None
+    serving = bench_serve(args, J) if args.serve_requests > 0 else None
 
     # ---- per-kernel figures over the timed steps (HIP events on the launch stream) ----------
     traffic = load_traffic()
@@ -422,6 +467,7 @@ def main():
                     "runs": len(lat), "p50_ms": round(pct(lat, 0.5), 4),
                     "p99_ms": round(pct(lat, 0.99), 4), "pairs": n_c1},
         "batch": batch,
+        "serve": serving,
         "kernels": kernels,
         "src_hash": src_hash(),
     }

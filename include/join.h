@@ -128,6 +128,41 @@ int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred
                size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count,
                void* stream);
 
+/* ---- resident builds ---------------------------------------------------------------------
+ * The partitioned form of a build relation R, kept in caller-owned device memory and probed by
+ * many probe relations S_k: the R side's histogram and scatter run once (join_build) instead of
+ * once per join.  In the paper the smaller table T is the one hashed and S the one probed
+ * (Sections 2.3 and 3.3.2); a serving loop that sees the same T again keeps it partitioned.
+ * The result of join_probe_* equals join_hash(R, S) as a multiset of (rid_R, rid_S) pairs.
+ * The build buffer must stay unchanged while it is probed; R itself may be freed after
+ * join_build's work has completed on its stream. */
+typedef struct {
+    uint64_t opaque[16]; /* plain bytes: sizes, fan-out and layout of the build buffer */
+} join_build_t;
+
+/* Bytes of the build buffer for a build side of nR rows; 0 if nR < 0 or nR > 2^31 - 1. */
+size_t join_build_bytes(int64_t nR);
+
+/* Partitions R into `build` (device, join_build_bytes(R->n) bytes) and fills *desc.
+ * Asynchronous on `stream` (launches only).  Errors: JOIN_E_INVAL, JOIN_E_WORKSPACE,
+ * JOIN_E_UNSUPPORTED, JOIN_E_HIP. */
+int join_build(const join_rel_t* R, void* build, size_t build_bytes, join_build_t* desc,
+               void* stream);
+
+/* Workspace bytes for probing the build `desc` with nS rows; 0 for invalid arguments. */
+size_t join_probe_workspace_bytes(const join_build_t* desc, int64_t nS);
+
+/* Count pass of R ⋈ S with R taken from the build: same contract as join_count (one 8-byte
+ * host read, *count set). */
+int join_probe_count(const join_build_t* desc, const void* build, const join_rel_t* S, void* ws,
+                     size_t ws_bytes, void* stream, uint64_t* count);
+
+/* Write pass after join_probe_count (same desc, build, S, ws): same contract as
+ * join_materialize. */
+int join_probe_materialize(const join_build_t* desc, const void* build, const join_rel_t* S,
+                           void* ws, size_t ws_bytes, int32_t* pairs, uint64_t capacity,
+                           void* stream);
+
 /* ---- batched equi joins -----------------------------------------------------------------
  * Many independent equi joins R_j.key = S_j.key (j = 0..njobs-1) in one pass of fused
  * launches.  In the paper every MapReduce reducer runs its own GPU join and the reducer count

@@ -28,6 +28,8 @@ OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 
 
 # Every symbol include/*.h declares.
 EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash", "join_theta",
+           "join_build_bytes", "join_build", "join_probe_workspace_bytes", "join_probe_count",
+           "join_probe_materialize",
            "join_batch_workspace_bytes", "join_batch_prepare", "join_batch_count",
            "join_batch_materialize", "join_last_error", "join_scan_workspace_bytes",
            "join_scan_u64", "join_prof_enable", "join_prof_collect", "join_prof_count",
@@ -46,6 +48,10 @@ class JoinPred(ctypes.Structure):
 class JoinJob(ctypes.Structure):
     _fields_ = [("R", JoinRel), ("S", JoinRel), ("bits", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class JoinBuild(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_uint64 * 16)]
 
 
 class JoinBatchPlan(ctypes.Structure):
@@ -88,6 +94,17 @@ def _load():
     lib.join_hash.argtypes = [R, R, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
     lib.join_theta.restype = ctypes.c_int
     lib.join_theta.argtypes = [R, R, Pp, vp, sz, vp, u64, ctypes.POINTER(u64), vp]
+    Bd = ctypes.POINTER(JoinBuild)
+    lib.join_build_bytes.restype = sz
+    lib.join_build_bytes.argtypes = [i64]
+    lib.join_build.restype = ctypes.c_int
+    lib.join_build.argtypes = [R, vp, sz, Bd, vp]
+    lib.join_probe_workspace_bytes.restype = sz
+    lib.join_probe_workspace_bytes.argtypes = [Bd, i64]
+    lib.join_probe_count.restype = ctypes.c_int
+    lib.join_probe_count.argtypes = [Bd, vp, R, vp, sz, vp, ctypes.POINTER(u64)]
+    lib.join_probe_materialize.restype = ctypes.c_int
+    lib.join_probe_materialize.argtypes = [Bd, vp, R, vp, sz, vp, u64, vp]
     Jp = ctypes.POINTER(JoinJob)
     Bp = ctypes.POINTER(JoinBatchPlan)
     lib.join_batch_workspace_bytes.restype = sz

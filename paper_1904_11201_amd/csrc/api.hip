@@ -443,4 +443,139 @@ int join_batch_materialize(const join_batch_plan_t* plan, void* ws, size_t ws_by
     return e == hipSuccess ? JOIN_OK : hip_fail(e, "join_batch_materialize");
 }
 
+static_assert(sizeof(BuildPlan) <= sizeof(join_build_t), "build plan must fit the opaque blob");
+
+static thread_local struct {
+    bool valid;
+    const void* build;
+    join_rel_t S;
+    void* ws;
+    uint64_t count;
+} g_last_probe{};
+
+size_t join_build_bytes(int64_t nR)
+{
+    if (nR < 0 || nR > kMaxRows) return 0;
+    return (size_t)hash_build_plan(nR, num_cus()).bytes;
+}
+
+int join_build(const join_rel_t* R, void* build, size_t build_bytes, join_build_t* desc, void* stream)
+{
+    int rc = check_rel(R, "R", false);
+    if (rc != JOIN_OK) return rc;
+    if (!desc) {
+        set_error("desc == NULL");
+        return JOIN_E_INVAL;
+    }
+    const BuildPlan b = hash_build_plan(R->n, num_cus());
+    if (!build || build_bytes < b.bytes) {
+        set_error("build buffer of %zu bytes, need %llu", build_bytes, (unsigned long long)b.bytes);
+        return JOIN_E_WORKSPACE;
+    }
+    memset(desc, 0, sizeof(*desc));
+    memcpy(desc, &b, sizeof(b));
+    if (R->n == 0) return JOIN_OK;
+    const hipError_t e = hash_build(b, *R, static_cast<char*>(build), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JOIN_OK : hip_fail(e, "join_build");
+}
+
+static int probe_args(const join_build_t* desc, const void* build, const join_rel_t* S, BuildPlan* b)
+{
+    if (!desc) {
+        set_error("desc == NULL");
+        return JOIN_E_INVAL;
+    }
+    memcpy(b, desc, sizeof(*b));
+    if (b->nR < 0 || b->bits < 1 || b->bits > 11) {
+        set_error("desc does not describe a build");
+        return JOIN_E_INVAL;
+    }
+    if (b->nR > 0 && !build) {
+        set_error("build == NULL");
+        return JOIN_E_INVAL;
+    }
+    return check_rel(S, "S", false);
+}
+
+size_t join_probe_workspace_bytes(const join_build_t* desc, int64_t nS)
+{
+    BuildPlan b;
+    if (!desc || nS < 0 || nS > kMaxRows) return 0;
+    memcpy(&b, desc, sizeof(b));
+    if (b.bits < 1 || b.bits > 11) return 0;
+    return (size_t)hash_plan(b.nR, nS, num_cus(), b.bits).bytes;
+}
+
+int join_probe_count(const join_build_t* desc, const void* build, const join_rel_t* S, void* ws,
+                     size_t ws_bytes, void* stream, uint64_t* count)
+{
+    BuildPlan b;
+    int rc = probe_args(desc, build, S, &b);
+    if (rc != JOIN_OK) return rc;
+    if (!count) {
+        set_error("count == NULL");
+        return JOIN_E_INVAL;
+    }
+    g_last_probe.valid = false;
+    const HashPlan pl = hash_plan(b.nR, S->n, num_cus(), b.bits);
+    if (!ws || ws_bytes < pl.bytes) {
+        set_error("workspace of %zu bytes, need %llu", ws_bytes, (unsigned long long)pl.bytes);
+        return JOIN_E_WORKSPACE;
+    }
+    if (b.nR == 0 || S->n == 0) {
+        *count = 0;
+    } else {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        join_rel_t R{};
+        R.n = b.nR;
+        const RView v = build_view(b, build);
+        const hipError_t e = hash_count(pl, R, *S, static_cast<char*>(ws), st, &v);
+        if (e != hipSuccess) return hip_fail(e, "probe count pass");
+        uint64_t* slot = pinned_slot();
+        if (!slot) {
+            set_error("hipHostMalloc of the 8-byte count slot failed");
+            return JOIN_E_HIP;
+        }
+        JL_HIP(hipMemcpyAsync(slot, ws, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        JL_HIP(hipStreamSynchronize(st));
+        *count = *slot;
+    }
+    g_last_probe.valid = true;
+    g_last_probe.build = build;
+    g_last_probe.S = *S;
+    g_last_probe.ws = ws;
+    g_last_probe.count = *count;
+    return JOIN_OK;
+}
+
+int join_probe_materialize(const join_build_t* desc, const void* build, const join_rel_t* S,
+                           void* ws, size_t ws_bytes, int32_t* pairs, uint64_t capacity, void* stream)
+{
+    BuildPlan b;
+    int rc = probe_args(desc, build, S, &b);
+    if (rc != JOIN_OK) return rc;
+    const HashPlan pl = hash_plan(b.nR, S->n, num_cus(), b.bits);
+    if (!ws || ws_bytes < pl.bytes) {
+        set_error("workspace of %zu bytes, need %llu", ws_bytes, (unsigned long long)pl.bytes);
+        return JOIN_E_WORKSPACE;
+    }
+    if (capacity > 0 && !pairs) {
+        set_error("pairs is NULL with capacity %llu", (unsigned long long)capacity);
+        return JOIN_E_INVAL;
+    }
+    if (g_last_probe.valid && g_last_probe.build == build && g_last_probe.ws == ws &&
+        same_rel(g_last_probe.S, *S) && g_last_probe.count > capacity) {
+        set_error("capacity %llu < exact count %llu", (unsigned long long)capacity,
+                  (unsigned long long)g_last_probe.count);
+        return JOIN_E_CAPACITY;
+    }
+    if (b.nR == 0 || S->n == 0) return JOIN_OK;
+    join_rel_t R{};
+    R.n = b.nR;
+    const RView v = build_view(b, build);
+    const hipError_t e = hash_write(pl, R, *S, static_cast<char*>(ws), pairs, capacity,
+                                    static_cast<hipStream_t>(stream), &v);
+    return e == hipSuccess ? JOIN_OK : hip_fail(e, "probe write pass");
+}
+
 }  // extern "C"

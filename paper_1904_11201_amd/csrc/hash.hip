@@ -798,7 +798,7 @@ static int env_cap()
     return (int)cap;
 }
 
-HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
 {
     HashPlan pl{};
     pl.nR = nR;
@@ -808,8 +808,9 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
     pl.slice = (int)tune_get(TUNE_HASH_SLICE, 32768);
     if (pl.slice < 1024) pl.slice = 1024;
     const int64_t single_max = tune_get(TUNE_HASH_SINGLE_MAX, 16) * cap;
-    const int forced_bits = (int)tune_get(TUNE_HASH_BITS, -1);
-    pl.single = forced_bits == 0 || (forced_bits < 0 && nR <= single_max);
+    pl.prebuilt = prebuilt_bits >= 0;
+    const int forced_bits = pl.prebuilt ? prebuilt_bits : (int)tune_get(TUNE_HASH_BITS, -1);
+    pl.single = !pl.prebuilt && (forced_bits == 0 || (forced_bits < 0 && nR <= single_max));
     size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
     if (pl.single) {
         pl.bits = 0;
@@ -845,7 +846,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         };
         pl.chR = chunk_for(nR);
         pl.chS = chunk_for(nS);
-        pl.nChR = nR > 0 ? ceil_div(nR, pl.chR) : 0;
+        pl.nChR = nR > 0 && !pl.prebuilt ? ceil_div(nR, pl.chR) : 0;  // a prebuilt R has its own
         pl.nChS = nS > 0 ? ceil_div(nS, pl.chS) : 0;
         pl.Umax = pl.P + ceil_div(nR, cap) + ceil_div(nS, pl.slice) + 2;
         pl.off_tot = off;  // totR[P] then totS[P], cleared together
@@ -859,7 +860,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus)
         pl.off_offsS = off;
         off = align_up(off + (size_t)pl.P * pl.nChS * 4);
         pl.off_tupR = off;
-        off = align_up(off + (size_t)nR * 8);
+        off = align_up(off + (size_t)(pl.prebuilt ? 0 : nR) * 8);
         pl.off_tupS = off;
         off = align_up(off + (size_t)nS * 8);
         pl.off_info = off;
@@ -941,7 +942,8 @@ static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64
     return hipGetLastError();
 }
 
-static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws)
+static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                          const RView* pre)
 {
     JoinGeom g{};
     g.bits = pl.bits;
@@ -963,7 +965,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.P = 1;
     } else {
         g.single = 0;
-        g.rt = reinterpret_cast<const int2*>(ws + pl.off_tupR);
+        g.rt = pre ? pre->tup : reinterpret_cast<const int2*>(ws + pl.off_tupR);
         g.st = reinterpret_cast<const int2*>(ws + pl.off_tupS);
         g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);
         g.unitStart = reinterpret_cast<const uint32_t*>(ws + pl.off_units);
@@ -975,7 +977,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
 }
 
 hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      hipStream_t st)
+                      hipStream_t st, const RView* pre)
 {
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
@@ -992,29 +994,40 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         int2* tupR = reinterpret_cast<int2*>(ws + pl.off_tupR);
         int2* tupS = reinterpret_cast<int2*>(ws + pl.off_tupS);
         {
+            // a prebuilt R keeps its sizes: only the S sizes are cleared
             prof::Scope pz(st, "hash.plan");
-            zero_u32_k<<<(unsigned)ceil_div(2 * pl.P, 256), 256, 0, st>>>(totR, 2 * (int64_t)pl.P);
+            uint32_t* z = pre ? totS : totR;
+            const int64_t nz = pre ? pl.P : 2 * (int64_t)pl.P;
+            zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(z, nz);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         const SideItem oneR = whole_side(R, pl.bits), oneS = whole_side(S, pl.bits);
-        e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, offsR, st, true);
-        if (e != hipSuccess) return e;
+        if (!pre) {
+            e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, offsR, st, true);
+            if (e != hipSuccess) return e;
+        }
         e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, offsS, st, false);
         if (e != hipSuccess) return e;
-        e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
-        if (e != hipSuccess) return e;
+        if (!pre) {
+            e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+            if (e != hipSuccess) return e;
+        }
         e = exclusive_scan<uint32_t>(totS, baseS, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
-        e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, baseR, offsR, tupR, st, true);
-        if (e != hipSuccess) return e;
+        if (!pre) {
+            e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, baseR, offsR, tupR, st, true);
+            if (e != hipSuccess) return e;
+        }
         e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, baseS, offsS, tupS, st, false);
         if (e != hipSuccess) return e;
+        const uint32_t* pbaseR = pre ? pre->base : baseR;
+        const uint32_t* ptotR = pre ? pre->tot : totR;
         uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
         {
             prof::Scope pp(st, "hash.plan");
             plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
-                baseR, totR, baseS, totS, pl.P, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
+                pbaseR, ptotR, baseS, totS, pl.P, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
                 (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
         }
         e = hipGetLastError();
@@ -1031,7 +1044,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         if (e != hipSuccess) return e;
     }
     if (pl.Umax > 0) {
-        const JoinGeom g = make_geom(pl, R, S, ws);
+        const JoinGeom g = make_geom(pl, R, S, ws, pre);
         const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridCount);
         const size_t lds = table_lds((uint32_t)pl.cap, false);
         prof::Scope pc(st, "hash.count");
@@ -1044,14 +1057,14 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
 }
 
 hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      int32_t* pairs, uint64_t cap, hipStream_t st)
+                      int32_t* pairs, uint64_t cap, hipStream_t st, const RView* pre)
 {
     if (pl.Umax <= 0) return hipSuccess;
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
     const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
     const uint64_t* total = reinterpret_cast<const uint64_t*>(ws);
-    const JoinGeom g = make_geom(pl, R, S, ws);
+    const JoinGeom g = make_geom(pl, R, S, ws, pre);
     const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridWrite);
     const size_t lds = table_lds((uint32_t)pl.cap, true);
     int2* out = reinterpret_cast<int2*>(pairs);
@@ -1059,6 +1072,76 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
     else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
     return hipGetLastError();
+}
+
+static size_t take(size_t& off, size_t bytes)
+{
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+}
+
+// ------------------------------------------------------------------------ resident builds --
+// The partitioned form of a build relation (its tuples, partition sizes and starts), kept by the
+// caller and probed by many probe relations: only the probe side is partitioned per join.
+
+BuildPlan hash_build_plan(int64_t nR, int num_cus)
+{
+    BuildPlan b{};
+    b.nR = nR;
+    const int cap = env_cap();
+    int bits = default_bits(nR, cap);
+    if (bits < 1) bits = 1;
+    if (bits > kMaxBits) bits = kMaxBits;
+    b.bits = bits;
+    b.P = 1 << bits;
+    int per_cu = (int)((160 * 1024) / scatter_lds(b.P));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 2) per_cu = 2;
+    int64_t c = ceil_div(nR > 0 ? nR : 1, (int64_t)num_cus * per_cu);
+    c = ceil_div(c, kScatTile) * kScatTile;
+    b.chR = c < kScatTile ? kScatTile : c;
+    b.nChR = nR > 0 ? ceil_div(nR, b.chR) : 0;
+    size_t off = 256;
+    b.off_tot = take(off, (size_t)b.P * 4);
+    b.off_base = take(off, (size_t)(b.P + 1) * 4);
+    b.off_offs = take(off, (size_t)b.P * b.nChR * 4);
+    b.off_tup = take(off, (size_t)nR * 8);
+    b.off_temp = take(off, scan_temp_elems<uint32_t>(b.P + 1) * 4 + 8);
+    b.bytes = off;
+    return b;
+}
+
+hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipStream_t st)
+{
+    hipError_t e = set_attrs();
+    if (e != hipSuccess) return e;
+    uint32_t* tot = reinterpret_cast<uint32_t*>(build + b.off_tot);
+    uint32_t* base = reinterpret_cast<uint32_t*>(build + b.off_base);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(build + b.off_offs);
+    int2* tup = reinterpret_cast<int2*>(build + b.off_tup);
+    {
+        prof::Scope pz(st, "hash.plan");
+        zero_u32_k<<<(unsigned)ceil_div(b.P, 256), 256, 0, st>>>(tot, b.P);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const SideItem one = whole_side(R, b.bits);
+    e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, offs, st, true);
+    if (e != hipSuccess) return e;
+    e = exclusive_scan<uint32_t>(tot, base, b.P, nullptr, reinterpret_cast<uint32_t*>(build + b.off_temp), st);
+    if (e != hipSuccess) return e;
+    return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, base, offs, tup, st, true);
+}
+
+RView build_view(const BuildPlan& b, const void* build)
+{
+    const char* p = static_cast<const char*>(build);
+    RView v;
+    v.tot = reinterpret_cast<const uint32_t*>(p + b.off_tot);
+    v.base = reinterpret_cast<const uint32_t*>(p + b.off_base);
+    v.tup = reinterpret_cast<const int2*>(p + b.off_tup);
+    return v;
 }
 
 // ------------------------------------------------------------------------- batched joins --
@@ -1077,13 +1160,6 @@ static int job_bits(const join_job_t& j, int cap)
 }
 
 static int64_t side_items(int64_t n) { return n > 0 ? ceil_div(n, kBatchChunk) : 0; }
-
-static size_t take(size_t& off, size_t bytes)
-{
-    const size_t at = off;
-    off = align_up(off + bytes);
-    return at;
-}
 
 int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* out)
 {

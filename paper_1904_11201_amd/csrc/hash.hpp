@@ -44,7 +44,8 @@ struct JoinGeom {
 
 struct HashPlan {
     int64_t nR, nS;
-    int single;  // 1: no partitioning, units = R chunks x S slices of the inputs themselves
+    int single;    // 1: no partitioning, units = R chunks x S slices of the inputs themselves
+    int prebuilt;  // 1: R comes partitioned from a resident build (RView)
     int bits, P;
     int cap, slice;
     int64_t nSs;  // S slices (single)
@@ -56,16 +57,37 @@ struct HashPlan {
     size_t off_counts, off_temp, bytes;
 };
 
-HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus);
+// prebuilt_bits >= 0: R is a resident build partitioned with that fan-out (no single path, no
+// R arrays in the workspace).
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits = -1);
+
+// A build relation already partitioned (resident build): its partition sizes, starts, tuples.
+struct RView {
+    const uint32_t* tot;
+    const uint32_t* base;
+    const int2* tup;
+};
+
+// Layout of a resident build buffer.
+struct BuildPlan {
+    int64_t nR;
+    int32_t bits, P;
+    int64_t chR, nChR;
+    uint64_t off_tot, off_base, off_offs, off_tup, off_temp, bytes;
+};
+
+BuildPlan hash_build_plan(int64_t nR, int num_cus);
+hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipStream_t st);
+RView build_view(const BuildPlan& b, const void* build);
 
 // Histogram, scatter, planning, count pass and the scan of counts.  Leaves the exact total at
 // ws[0..8) and the per-unit offsets in ws.
 hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      hipStream_t st);
+                      hipStream_t st, const RView* pre = nullptr);
 
 // Write pass from the state hash_count left in ws.
 hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      int32_t* pairs, uint64_t cap, hipStream_t st);
+                      int32_t* pairs, uint64_t cap, hipStream_t st, const RView* pre = nullptr);
 
 // A batch of independent equi joins: layout of the shared workspace and launch sizes.  Kept
 // by the caller as an opaque join_batch_plan_t between the prepare, count and write calls.

@@ -23,13 +23,13 @@ import torch
 
 from . import _native
 from ._native import (JOIN_KIND_HASH, JOIN_KIND_THETA, JOIN_KIND_THETA_REGION, OPS, JoinBatchPlan,
-                      JoinJob, JoinPred, JoinRel)
+                      JoinBuild, JoinJob, JoinPred, JoinRel)
 
 __all__ = [
     "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "JOIN_KIND_THETA_REGION",
     "join_workspace_bytes",
     "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
-    "hash_join", "theta_join", "Job", "Batch", "hash_join_batch",
+    "hash_join", "theta_join", "Job", "Batch", "hash_join_batch", "ResidentBuild",
 ]
 
 
@@ -274,3 +274,54 @@ def hash_join_batch(jobs: list[Job], stream=None, tuned: bool = False):
     out = torch.empty((total, 2), dtype=torch.int32, device=b.ws.device)
     b.materialize(out, stream)
     return out, [int(v) for v in offs.cpu().tolist()]
+
+
+# ---- resident builds ---------------------------------------------------------------------------
+
+class ResidentBuild:
+    """A build relation partitioned once (join_build) and probed by many probe relations.  The
+    build buffer is device memory owned by this object; R may be dropped once the build's
+    work on `stream` has completed."""
+
+    def __init__(self, R: Relation, stream=None, device="cuda"):
+        self.n = R.n
+        nbytes = int(_native.lib.join_build_bytes(R.n))
+        if nbytes == 0:
+            raise JoinError(_native.JOIN_E_INVAL, "build side too large")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.desc = JoinBuild()
+        rr = R.c()
+        _check(_native.lib.join_build(ctypes.byref(rr), ctypes.c_void_p(self.buf.data_ptr()),
+                                      self.buf.numel(), ctypes.byref(self.desc), _stream(stream)))
+
+    def workspace_bytes(self, nS: int) -> int:
+        return int(_native.lib.join_probe_workspace_bytes(ctypes.byref(self.desc), nS))
+
+    def workspace(self, nS: int, device="cuda") -> torch.Tensor:
+        return torch.empty(self.workspace_bytes(nS), dtype=torch.uint8, device=device)
+
+    def count(self, S: Relation, ws: torch.Tensor, stream=None) -> int:
+        cnt = ctypes.c_uint64(0)
+        sr = S.c()
+        _check(_native.lib.join_probe_count(ctypes.byref(self.desc), ctypes.c_void_p(self.buf.data_ptr()),
+                                            ctypes.byref(sr), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            _stream(stream), ctypes.byref(cnt)))
+        return int(cnt.value)
+
+    def materialize(self, S: Relation, ws: torch.Tensor, pairs: torch.Tensor, stream=None) -> None:
+        if pairs.dtype != torch.int32 or not pairs.is_contiguous():
+            raise ValueError("pairs must be a contiguous int32 tensor")
+        cap = pairs.numel() // 2
+        sr = S.c()
+        _check(_native.lib.join_probe_materialize(
+            ctypes.byref(self.desc), ctypes.c_void_p(self.buf.data_ptr()), ctypes.byref(sr),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+            ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap, _stream(stream)))
+
+    def probe(self, S: Relation, stream=None) -> torch.Tensor:
+        """R ⋈ S with R from this build: the exact-size [count, 2] int32 pairs."""
+        ws = self.workspace(S.n, device=self.buf.device)
+        n = self.count(S, ws, stream)
+        out = torch.empty((n, 2), dtype=torch.int32, device=self.buf.device)
+        self.materialize(S, ws, out, stream)
+        return out

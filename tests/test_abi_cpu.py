@@ -153,3 +153,21 @@ def test_tuning_knobs_override_environment(monkeypatch):
     assert n.tune_get("hash.cap", 9216) == 9216
     with pytest.raises(KeyError):
         n.tune_set("no.such.knob", 1)
+
+
+def test_build_sizes_and_argument_errors():
+    assert n.lib.join_build_bytes(-1) == 0
+    assert n.lib.join_build_bytes(1 << 31) == 0
+    small, big = n.lib.join_build_bytes(1000), n.lib.join_build_bytes(1 << 24)
+    assert 0 < small < big and big >= 8 * (1 << 24)
+    desc = n.JoinBuild()
+    fake = ctypes.c_void_p(0x1000)
+    R = _rel(fake, 1000)
+    assert n.lib.join_build(ctypes.byref(R), None, 0, ctypes.byref(desc), None) == n.JOIN_E_WORKSPACE
+    assert n.lib.join_build(ctypes.byref(_rel(None, 5)), None, 0, ctypes.byref(desc), None) == n.JOIN_E_INVAL
+    # a zeroed descriptor is not a build
+    assert n.lib.join_probe_workspace_bytes(ctypes.byref(n.JoinBuild()), 10) == 0
+    S = _rel(fake, 10)
+    c = ctypes.c_uint64(0)
+    assert n.lib.join_probe_count(ctypes.byref(n.JoinBuild()), fake, ctypes.byref(S), None, 0, None,
+                                  ctypes.byref(c)) == n.JOIN_E_INVAL
