@@ -58,6 +58,16 @@ extern "C" {
                                   * and cross-joined without evaluation, red regions evaluated by
                                   * the nested loop.  Same predicates and results as
                                   * JOIN_KIND_THETA. */
+#define JOIN_KIND_HASH_PREFILTER 4 /* equi join preceded by the pre-filter of Algorithm 1
+                                    * (Section 3.1): a relation of at most 2^21 rows gets a bit
+                                    * filter of its keys (16 bits per row, at most 2^24 bits) and
+                                    * the other relation is reduced to the tuples whose key may
+                                    * occur in it (never dropping a matching tuple); with two
+                                    * small relations both are reduced.  Then joined as
+                                    * JOIN_KIND_HASH: same result.  Pays off when a small
+                                    * relation meets a large one with few matching keys.  Its
+                                    * join_materialize reads the surviving sizes from the device
+                                    * (one 8-byte host read). */
 
 /* ---- predicate operators (Section 2.3: =, <, >, <=, >=; Figure "greenc": not-equal) -------- */
 typedef enum {

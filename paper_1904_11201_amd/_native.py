@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "JOIN_OK", 1: "JOIN_E_INVAL", 2: "JOIN_E_CAPACITY", 3: "JOIN_
 JOIN_KIND_HASH = 1
 JOIN_KIND_THETA = 2
 JOIN_KIND_THETA_REGION = 3
+JOIN_KIND_HASH_PREFILTER = 4
 
 OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 7}
 

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include "hash.hpp"
+#include "prefilter.hpp"
 #include "region.hpp"
 #include "scan.hpp"
 #include "theta.hpp"
@@ -107,15 +108,18 @@ int check_pred(const join_pred_t* p)
     return JOIN_OK;
 }
 
+bool is_theta(int kind) { return kind == JOIN_KIND_THETA || kind == JOIN_KIND_THETA_REGION; }
+
 int check_args(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p)
 {
-    if (kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION) {
-        set_error("kind = %d is not JOIN_KIND_HASH, JOIN_KIND_THETA or JOIN_KIND_THETA_REGION", kind);
+    if (kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION &&
+        kind != JOIN_KIND_HASH_PREFILTER) {
+        set_error("kind = %d is not one of JOIN_KIND_HASH, _THETA, _THETA_REGION, _HASH_PREFILTER", kind);
         return JOIN_E_INVAL;
     }
     int rc;
     bool key2 = false;
-    if (kind != JOIN_KIND_HASH) {
+    if (is_theta(kind)) {
         if ((rc = check_pred(p)) != JOIN_OK) return rc;
         key2 = p->op_c != JOIN_OP_NONE;
     }
@@ -132,6 +136,7 @@ RegionPlan plan_region(int64_t nR, int64_t nS, const join_pred_t* p)
 size_t ws_needed(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
 {
     if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).bytes;
+    if (kind == JOIN_KIND_HASH_PREFILTER) return prefilter_plan(nR, nS, num_cus()).bytes;
     if (kind == JOIN_KIND_THETA_REGION) return plan_region(nR, nS, p).bytes;
     return plan_theta(nR, nS, p).bytes;
 }
@@ -169,7 +174,7 @@ bool matches_last(int kind, const join_rel_t* R, const join_rel_t* S, const join
 {
     if (!g_last.valid || g_last.kind != kind || g_last.ws != ws) return false;
     if (!same_rel(g_last.R, *R) || !same_rel(g_last.S, *S)) return false;
-    if (kind != JOIN_KIND_HASH &&
+    if (is_theta(kind) &&
         (g_last.p.op_a != p->op_a || g_last.p.op_c != p->op_c || g_last.p.w != p->w))
         return false;
     return true;
@@ -194,22 +199,27 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     } else {
         char* w = static_cast<char*>(ws);
         hipError_t e;
+        size_t total_at = 0;  // where the exact total lands in ws
         if (kind == JOIN_KIND_HASH) {
             const HashPlan pl = hash_plan(R->n, S->n, num_cus());
             e = hash_count(pl, *R, *S, w, st);
+        } else if (kind == JOIN_KIND_HASH_PREFILTER) {
+            const PrefilterPlan pl = prefilter_plan(R->n, S->n, num_cus());
+            e = prefilter_count(pl, *R, *S, w, st, num_cus());
+            total_at = prefilter_total_offset(pl);
         } else if (kind == JOIN_KIND_THETA_REGION) {
             e = region_count(plan_region(R->n, S->n, p), *R, *S, *p, w, st);
         } else {
             const ThetaPlan pl = plan_theta(R->n, S->n, p);
             e = theta_count(pl, *R, *S, *p, w, st);
         }
-        if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash count pass" : "theta count pass");
+        if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
         uint64_t* slot = pinned_slot();
         if (!slot) {
             set_error("hipHostMalloc of the 8-byte count slot failed");
             return JOIN_E_HIP;
         }
-        JL_HIP(hipMemcpyAsync(slot, w, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        JL_HIP(hipMemcpyAsync(slot, w + total_at, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
         JL_HIP(hipStreamSynchronize(st));
         *count = *slot;
     }
@@ -236,13 +246,15 @@ int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     if (kind == JOIN_KIND_HASH) {
         const HashPlan pl = hash_plan(R->n, S->n, num_cus());
         e = hash_write(pl, *R, *S, w, pairs, capacity, st);
+    } else if (kind == JOIN_KIND_HASH_PREFILTER) {
+        e = prefilter_write(prefilter_plan(R->n, S->n, num_cus()), *R, *S, w, pairs, capacity, st, num_cus());
     } else if (kind == JOIN_KIND_THETA_REGION) {
         e = region_write(plan_region(R->n, S->n, p), *R, *S, *p, w, pairs, capacity, st);
     } else {
         const ThetaPlan pl = plan_theta(R->n, S->n, p);
         e = theta_write(pl, *R, *S, *p, w, pairs, capacity, st);
     }
-    if (e != hipSuccess) return hip_fail(e, kind == JOIN_KIND_HASH ? "hash write pass" : "theta write pass");
+    if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta write pass" : "hash write pass");
     return JOIN_OK;
 }
 
@@ -252,7 +264,8 @@ extern "C" {
 
 size_t join_workspace_bytes(int kind, int64_t nR, int64_t nS, const join_pred_t* pred)
 {
-    if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION) ||
+    if ((kind != JOIN_KIND_HASH && kind != JOIN_KIND_THETA && kind != JOIN_KIND_THETA_REGION &&
+         kind != JOIN_KIND_HASH_PREFILTER) ||
         nR < 0 || nS < 0)
         return 0;
     return ws_needed(kind, nR, nS, pred);

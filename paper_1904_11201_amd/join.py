@@ -22,11 +22,13 @@ import dataclasses
 import torch
 
 from . import _native
-from ._native import (JOIN_KIND_HASH, JOIN_KIND_THETA, JOIN_KIND_THETA_REGION, OPS, JoinBatchPlan,
-                      JoinBuild, JoinJob, JoinPred, JoinRel)
+from ._native import (JOIN_KIND_HASH, JOIN_KIND_HASH_PREFILTER, JOIN_KIND_THETA,
+                      JOIN_KIND_THETA_REGION, OPS, JoinBatchPlan, JoinBuild, JoinJob, JoinPred,
+                      JoinRel)
 
 __all__ = [
     "JoinError", "Relation", "Pred", "JOIN_KIND_HASH", "JOIN_KIND_THETA", "JOIN_KIND_THETA_REGION",
+    "JOIN_KIND_HASH_PREFILTER",
     "join_workspace_bytes",
     "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
     "hash_join", "theta_join", "Job", "Batch", "hash_join_batch", "ResidentBuild",
@@ -188,9 +190,12 @@ def _exact(kind, R, S, pred, ws, stream):
     return out
 
 
-def hash_join(R: Relation, S: Relation, ws: torch.Tensor | None = None, stream=None):
-    """Equi join R.key = S.key; returns the exact-size [count, 2] int32 tensor of (rid_R, rid_S)."""
-    return _exact(JOIN_KIND_HASH, R, S, None, ws, stream)
+def hash_join(R: Relation, S: Relation, ws: torch.Tensor | None = None, stream=None,
+              prefilter: bool = False):
+    """Equi join R.key = S.key; returns the exact-size [count, 2] int32 tensor of (rid_R, rid_S).
+    prefilter=True first drops the tuples whose key cannot occur on the other side
+    (JOIN_KIND_HASH_PREFILTER); same result."""
+    return _exact(JOIN_KIND_HASH_PREFILTER if prefilter else JOIN_KIND_HASH, R, S, None, ws, stream)
 
 
 def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = None, stream=None,

@@ -1,0 +1,60 @@
+"""Pre-filtered equi join (JOIN_KIND_HASH_PREFILTER): the same pairs as the plain hash join and
+the oracle, from few to all keys matching, with empty survivors on one side, duplicates and rid
+payloads."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_1904_11201_amd import datagen
+from tests.gpu_util import canon_gpu, dev_rel, gpu, log, need_gpu
+
+
+def _check(R, S, label):
+    from paper_1904_11201_amd.join import hash_join
+    dR, dS = dev_rel(R), dev_rel(S)
+    log(f"prefilter {label}: {R.n} x {S.n}")
+    got = canon_gpu(hash_join(dR, dS, prefilter=True))
+    rr = R.rid if R.rid is not None else np.arange(R.n, dtype=np.int32)
+    sr = S.rid if S.rid is not None else np.arange(S.n, dtype=np.int32)
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=rr, Srid=sr)
+    assert len(got) == n and np.array_equal(got, ref), label
+    assert np.array_equal(got, canon_gpu(hash_join(dR, dS)))
+
+
+@gpu
+def test_few_and_all_keys_matching():
+    need_gpu()
+    g = datagen.rng_for(81)
+    R = datagen.Rel(key=datagen.uniform_keys(g, 200_000, 0, 1_000_000),
+                    rid=g.permutation(200_000).astype(np.int32))
+    S = datagen.Rel(key=datagen.uniform_keys(g, 600_000, 0, 50_000_000))
+    _check(R, S, "about 0.4% of probes match")
+    R, S = datagen.small_equi(seed=1)
+    _check(R, S, "every key shared")
+    R = datagen.Rel(key=datagen.uniform_keys(g, 50_000, 0, 5_000_000))
+    S = datagen.Rel(key=datagen.uniform_keys(g, 2_500_000, 0, 50_000_000))
+    _check(R, S, "large probe side: only the small side is filtered")
+
+
+@gpu
+def test_no_survivors_on_one_side_and_empty_inputs():
+    need_gpu()
+    g = datagen.rng_for(82)
+    R = datagen.Rel(key=np.arange(0, 3000, dtype=np.int32))
+    S = datagen.Rel(key=datagen.uniform_keys(g, 5000, 1 << 30, (1 << 30) + 100_000))
+    _check(R, S, "disjoint key ranges")
+    _check(datagen.Rel(key=np.zeros(0, np.int32)), S, "empty R")
+    _check(R, datagen.Rel(key=np.zeros(0, np.int32)), "empty S")
+
+
+@gpu
+def test_duplicates_and_extreme_keys():
+    need_gpu()
+    g = datagen.rng_for(83)
+    ext = np.array([-2**31, 2**31 - 1, 0, -1], np.int32)
+    rk = np.concatenate([g.choice(ext, 2000), datagen.uniform_keys(g, 30_000, -500, 500)])
+    sk = np.concatenate([g.choice(ext, 3000), datagen.uniform_keys(g, 40_000, 0, 100_000)])
+    R = datagen.Rel(key=rk.astype(np.int32), rid=g.integers(-2**31, 2**31 - 1, len(rk), dtype=np.int64).astype(np.int32))
+    S = datagen.Rel(key=sk.astype(np.int32))
+    _check(R, S, "duplicates and int32 extremes")
