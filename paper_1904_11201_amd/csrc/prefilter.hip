@@ -63,20 +63,23 @@ __global__ __launch_bounds__(kBlock) void compact_k(const int32_t* __restrict__ 
     const int64_t step = (int64_t)kBlock * kPer;
     for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += (int64_t)gridDim.x * step) {
         int32_t k[kPer], r[kPer];
+        uint32_t fw[kPer];
         uint64_t m[kPer];
         uint32_t mine = 0;
+        // all key and rid loads first, then all filter reads, then the ballots: every load of
+        // the round is in flight together
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
-            bool keep = false;
-            k[q] = 0;
-            r[q] = 0;
-            if (i < n) {
-                k[q] = key[i];
-                r[q] = rid ? rid[i] : (int32_t)i;
-                const uint32_t b = filter_bit(k[q], logm);
-                keep = (filter[b >> 5] >> (b & 31)) & 1u;
-            }
+            k[q] = i < n ? key[i] : 0;
+            r[q] = i < n ? (rid ? rid[i] : (int32_t)i) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) fw[q] = filter[filter_bit(k[q], logm) >> 5];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
+            const bool keep = i < n && ((fw[q] >> (filter_bit(k[q], logm) & 31)) & 1u);
             m[q] = ballot(keep);
             mine += (uint32_t)__builtin_popcountll(m[q]);
         }

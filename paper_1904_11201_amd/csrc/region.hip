@@ -326,18 +326,33 @@ __device__ __forceinline__ int region_class(int op, int64_t w, int64_t rlo, int6
     }
 }
 
-// One thread per R bucket: red span, adjacent green spans, units and green pair counts.
-__global__ void classify_k(const uint32_t* __restrict__ offR, int64_t nChR,
-                           const uint32_t* __restrict__ offS, int64_t nChS, uint32_t nR,
-                           uint32_t nS, const int64_t* __restrict__ vlo,
-                           const int64_t* __restrict__ vhi, int B, int op, int64_t w, int has_c,
-                           BucketInfo* __restrict__ info, uint32_t* __restrict__ units,
-                           uint64_t* __restrict__ green)
+__device__ __forceinline__ int wave_min_i(int v)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > B) return;
-    if (i == B) {
-        units[B] = 0;
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// One wave per R bucket: red span, adjacent green spans, units and green pair counts.  The S
+// buckets are classified by the wave's lanes together; every span end is a wave-wide min or max.
+__global__ __launch_bounds__(kWave) void classify_k(const uint32_t* __restrict__ offR, int64_t nChR,
+                                                    const uint32_t* __restrict__ offS, int64_t nChS,
+                                                    uint32_t nR, uint32_t nS,
+                                                    const int64_t* __restrict__ vlo,
+                                                    const int64_t* __restrict__ vhi, int B, int op,
+                                                    int64_t w, int has_c, BucketInfo* __restrict__ info,
+                                                    uint32_t* __restrict__ units,
+                                                    uint64_t* __restrict__ green)
+{
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= B) {
+        if (lane == 0) units[B] = 0;
         return;
     }
     auto rs = [&](int b) { return b < B ? offR[(int64_t)b * nChR] : nR; };
@@ -345,24 +360,29 @@ __global__ void classify_k(const uint32_t* __restrict__ offR, int64_t nChR,
     BucketInfo bi{};
     bi.rStart = rs(i);
     bi.nR = rs(i + 1) - bi.rStart;
+    const int64_t lo_i = vlo[i], hi_i = vhi[i];
     auto cls = [&](int j) -> int {
         if (ss(j + 1) == ss(j)) return -1;  // an empty S bucket: any class
-        int c = region_class(op, w, vlo[i], vhi[i], vlo[j], vhi[j]);
+        int c = region_class(op, w, lo_i, hi_i, vlo[j], vhi[j]);
         if (c == kGreen && has_c) c = kRed;  // a condition on c must still be checked
         return c;
     };
     int jr0 = B, jr1 = 0, jg0 = B, jg1 = 0;
     if (bi.nR > 0) {
-        for (int j = 0; j < B; ++j) {
+        for (int j = lane; j < B; j += kWave) {
             const int c = cls(j);
             if (c == kRed) {
-                jr0 = j < jr0 ? j : jr0;
-                jr1 = j + 1;
+                jr0 = min(jr0, j);
+                jr1 = max(jr1, j + 1);
             } else if (c == kGreen) {
-                jg0 = j < jg0 ? j : jg0;
-                jg1 = j + 1;
+                jg0 = min(jg0, j);
+                jg1 = max(jg1, j + 1);
             }
         }
+        jr0 = wave_min_i(jr0);
+        jr1 = wave_max_i(jr1);
+        jg0 = wave_min_i(jg0);
+        jg1 = wave_max_i(jg1);
     }
     // Spans of S buckets: red [jr0, jr1), green [gl, jr0) and [jr1, gr); every bucket outside
     // them is white or empty.  Empty buckets may join any span.
@@ -370,9 +390,9 @@ __global__ void classify_k(const uint32_t* __restrict__ offR, int64_t nChR,
     int gl = jr0, gr = jr1;
     if (jg0 < jg1) {
         if (jr0 == jr1) {
-            bool run = true;  // no red region: the greens must form one run without whites
-            for (int j = jg0; j < jg1; ++j) run = run && cls(j) != kWhite;
-            if (run) {
+            int white = 0;  // no red region: the greens must form one run without whites
+            for (int j = jg0 + lane; j < jg1; j += kWave) white |= cls(j) == kWhite;
+            if (!wave_max_i(white)) {
                 jr0 = jr1 = gl = jg0;
                 gr = jg1;
             } else {
@@ -380,14 +400,22 @@ __global__ void classify_k(const uint32_t* __restrict__ offR, int64_t nChR,
                 jr1 = gr = jg1;
             }
         } else {
-            while (gl > 0 && cls(gl - 1) != kWhite && cls(gl - 1) != kRed) --gl;
-            while (gr < B && cls(gr) != kWhite && cls(gr) != kRed) ++gr;
+            // greens reach from the red span to the nearest white on each side (no red lies
+            // outside [jr0, jr1))
+            int lw = -1, fw = B;
+            for (int j = lane; j < jr0; j += kWave)
+                if (cls(j) == kWhite) lw = max(lw, j);
+            for (int j = jr1 + lane; j < B; j += kWave)
+                if (cls(j) == kWhite) fw = min(fw, j);
+            gl = wave_max_i(lw) + 1;
+            gr = wave_min_i(fw);
             if (jg0 < gl || jg1 > gr) {  // greens cut off by whites: evaluate them as red
                 jr0 = gl = (jg0 < jr0 ? jg0 : jr0);
                 jr1 = gr = (jg1 > jr1 ? jg1 : jr1);
             }
         }
     }
+    if (lane != 0) return;
     bi.red0 = ss(jr0);
     bi.red1 = jr1 > jr0 ? ss(jr1) : bi.red0;
     bi.gl0 = ss(gl);
@@ -628,7 +656,7 @@ hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_re
     {
         prof::Scope ps(st, "region.classify");
         fill_u64_k<<<256, 256, 0, st>>>(counts, pl.Umax, 0);
-        classify_k<<<(unsigned)ceil_div(pl.B + 1, 128), 128, 0, st>>>(
+        classify_k<<<(unsigned)(pl.B + 1), kWave, 0, st>>>(
             reinterpret_cast<const uint32_t*>(ws + pl.off_hR), pl.nChR,
             reinterpret_cast<const uint32_t*>(ws + pl.off_hS), pl.nChS, (uint32_t)R.n,
             (uint32_t)S.n, reinterpret_cast<const int64_t*>(ws + pl.off_vlo),
