@@ -49,10 +49,11 @@ def parse():
     return ap.parse_args()
 
 
-def src_hash() -> str:
+def src_hash(files=None) -> str:
+    """Hash of the kernel sources (all of csrc/, or the named files of it)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1904_11201_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in sorted(files if files else os.listdir(d)):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
@@ -61,13 +62,13 @@ def src_hash() -> str:
 
 def load_traffic():
     """HBM bytes per launch from committed rocprofv3 --pmc summaries (profiles/traffic.json),
-    valid only for the kernel sources they were taken on."""
+    valid only while the sources of those kernels are the ones they were taken on."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return {}
     with open(p) as f:
         t = json.load(f)
-    if t.get("src_hash") != src_hash():
+    if t.get("src_hash") != src_hash(t.get("files")):
         return {}
     return t.get("kernels", {})
 
