@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict_
 }
 
 // --------------------------------------------------------------------------------- scatter --
-// Partitioned tuples are written as 8-byte (key, rid) pairs, partition-major.  An HBM write that
+// Partitioned tuples are written as 8-byte (hmix(key), rid) pairs, partition-major.  An HBM write that
 // covers only part of a 64-byte granule costs a read-modify-write, and with 2^11 partitions a
 // tile holds only a few tuples per partition, so the tuples of each partition are held back in
 // an LDS carry buffer (up to 7 of them) until they complete a granule: every write below then
@@ -193,10 +193,14 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
         }
         const int t1 = t0 + kScatTile;
         if (t1 < end) scat_load(key, rid, it.beg, vec, t1, end - t1 < kScatTile ? end - t1 : kScatTile, nk, nr);
+        // Tuples are written as (hmix(key), rid): the hash is a bijection of the key, so the join
+        // kernels compare hashes and never hash again.
         uint32_t p[kScatIt], j[kScatIt];
 #pragma unroll
         for (int q = 0; q < kScatIt; ++q) {
-            p[q] = pid_of(k[q], sh);
+            const uint32_t h = hmix((uint32_t)k[q]);
+            k[q] = (int32_t)h;
+            p[q] = sh >= 32 ? 0u : h >> sh;
             j[q] = kScatIt * tid + q < tn ? atomicAdd(&pcnt[2 * p[q] + 1], 1u) & 0xFFFFu : 0u;
         }
         __syncthreads();
@@ -424,7 +428,8 @@ __device__ __forceinline__ void load_chunk(const JoinGeom& g, const Unit& un, Ch
 }
 
 // Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
-template <bool RIDS>
+// HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.
+template <bool RIDS, bool HASHED>
 __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un, const Chunk<RIDS>& c,
                                               uint4* lds)
 {
@@ -440,7 +445,7 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
         const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
         if (e < un.rN) {
             uint32_t b1, b2;
-            choices(hmix(c.k[i]), un.bits, nb, b1, b2);
+            choices(HASHED ? c.k[i] : hmix(c.k[i]), un.bits, nb, b1, b2);
             const bool second = cnt[b2] < cnt[b1];  // a racy read only steers the choice
             uint32_t b = second ? b2 : b1;
             uint32_t old = atomicAdd(&cnt[b], 1u);
@@ -492,14 +497,14 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 // Count the entries of N keys: read both candidate buckets of every key (all reads issued
 // together), count the matching slots with predicated arithmetic, and walk on only for keys
 // whose two buckets both overflowed.
-template <int N>
+template <int N, bool HASHED>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
                                                 const bool (&valid)[N])
 {
     uint32_t b1[N], b2[N], c1[N], c2[N];
     uint4 k1[N], k2[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) choices(hmix(x[i]), bits, t.nb, b1[i], b2[i]);
+    for (int i = 0; i < N; ++i) choices(HASHED ? x[i] : hmix(x[i]), bits, t.nb, b1[i], b2[i]);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         k1[i] = t.keys[b1[i]];
@@ -528,7 +533,7 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 // Probe N keys for the write pass: per key the number of entries and the LDS word positions of
 // the first two, whose rids are read once the output slots are known (a key with more than two
 // build matches visits its buckets again when it is written).
-template <int N>
+template <int N, bool HASHED>
 __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint32_t (&x)[N],
                                             const bool (&valid)[N], uint32_t (&m)[N],
                                             uint32_t (&p1)[N], uint32_t (&p2)[N])
@@ -536,7 +541,7 @@ __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint
     uint32_t b1[N], b2[N], c1[N], c2[N];
     uint4 k1[N], k2[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) choices(hmix(x[i]), bits, t.nb, b1[i], b2[i]);
+    for (int i = 0; i < N; ++i) choices(HASHED ? x[i] : hmix(x[i]), bits, t.nb, b1[i], b2[i]);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         k1[i] = t.keys[b1[i]];
@@ -575,11 +580,11 @@ __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint
 
 // Every entry of key x in visiting order (b1's slots, b2's, then the walk), as LDS word
 // positions; used for keys with more than two build matches.
-template <typename F>
+template <bool HASHED, typename F>
 __device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_t x, F f)
 {
     uint32_t b1, b2;
-    choices(hmix(x), bits, t.nb, b1, b2);
+    choices(HASHED ? x : hmix(x), bits, t.nb, b1, b2);
     const uint32_t c1 = t.cnt[b1], c2 = t.cnt[b2];
     auto emit = [&](uint32_t b, uint32_t hm) {
         for (; hm; hm &= hm - 1) f(b * kSlots + __builtin_ctz(hm));
@@ -609,21 +614,32 @@ static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a
 #ifndef JL_HASH_WRITE_PROBE
 #define JL_HASH_WRITE_PROBE 2
 #endif
+#ifndef JL_HASH_WRITE_LOAD
+#define JL_HASH_WRITE_LOAD 4
+#endif
 constexpr int kWriteBatch = JL_HASH_WRITE_PROBE;  // S tuples per thread per round of the write pass
+constexpr int kWriteLoad = JL_HASH_WRITE_LOAD;    // S tuples per thread in flight in the write pass
+static_assert(kWriteLoad % kWriteBatch == 0, "write loads are probed kWriteBatch tuples at a time");
 
 template <bool AOS>
 __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
-                                            uint32_t (&x)[kWriteBatch], int32_t (&r)[kWriteBatch])
+                                            uint32_t (&x)[kWriteLoad], int32_t (&r)[kWriteLoad])
 {
+    const bool full = e0 + (uint32_t)(kWriteLoad * kJoinBlock) <= un.sN;  // uniform
+    if (un.sN == 0) {  // no tuple to stand in for the out-of-range lanes
 #pragma unroll
-    for (int i = 0; i < kWriteBatch; ++i) {
+        for (int i = 0; i < kWriteLoad; ++i) x[i] = 0u, r[i] = 0;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < kWriteLoad; ++i) {
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-        const bool ok = e < un.sN;
-        const uint32_t idx = un.sBeg + e;
+        const bool ok = full || e < un.sN;
+        const uint32_t idx = un.sBeg + (ok ? e : 0u);
         if constexpr (AOS) {
-            const int2 t = ok ? g.st[idx] : make_int2(0, 0);
-            x[i] = (uint32_t)t.x;
-            r[i] = t.y;
+            const int2 t = g.st[idx];
+            x[i] = ok ? (uint32_t)t.x : 0u;
+            r[i] = ok ? t.y : 0;
         } else {
             x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
             r[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
@@ -635,11 +651,23 @@ template <bool AOS>
 __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
                                           uint32_t (&xs)[kCountBatch])
 {
+    // Out-of-range lanes read the unit's first tuple (every unit with probes has one) and drop it,
+    // so the loads carry no branch.
+    const bool full = e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN;  // uniform
+    if (un.sN == 0) {  // no tuple to stand in for the out-of-range lanes
+#pragma unroll
+        for (int i = 0; i < kCountBatch; ++i) xs[i] = 0u;
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < kCountBatch; ++i) {
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
-        if constexpr (AOS) xs[i] = e < un.sN ? (uint32_t)g.st[un.sBeg + e].x : 0u;
-        else xs[i] = e < un.sN ? (uint32_t)g.sk[un.sBeg + e] : 0u;
+        const bool ok = full || e < un.sN;
+        const uint32_t idx = un.sBeg + (ok ? e : 0u);
+        uint32_t v;
+        if constexpr (AOS) v = (uint32_t)g.st[idx].x;
+        else v = (uint32_t)g.sk[idx];
+        xs[i] = ok ? v : 0u;
     }
 }
 
@@ -661,7 +689,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         Chunk<false> ch;
         load_chunk<AOS, false>(g, un, ch);
-        const Table t = insert_chunk<false>(g, un, ch, tab);
+        const Table t = insert_chunk<false, AOS>(g, un, ch, tab);
         const bool more = u + gridDim.x < U;
         const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
         uint32_t cnt = 0;
@@ -680,7 +708,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
                     x[i] = cur[h + i];
                     ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
                 }
-                cnt += probe_count(t, un.bits, x, ok);
+                cnt += probe_count<kProbe, AOS>(t, un.bits, x, ok);
             }
         }
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xs);
@@ -710,8 +738,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
     // next unit's first S batch while its last batch probes.
     Unit un{};
     Chunk<true> ch;
-    uint32_t nx[kWriteBatch];
-    int32_t nr[kWriteBatch];
+    uint32_t nx[kWriteLoad];
+    int32_t nr[kWriteLoad];
     if (blockIdx.x < U) {
         un = decode_unit(g, blockIdx.x);
         load_chunk<AOS, true>(g, un, ch);
@@ -719,51 +747,61 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
     }
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         if (threadIdx.x == 0) cursor = 0;  // the barrier inside the build publishes it
-        const Table t = insert_chunk<true>(g, un, ch, tab);
+        const Table t = insert_chunk<true, AOS>(g, un, ch, tab);
         const bool more = u + gridDim.x < U;
         const Unit nxt = more ? decode_unit(g, u + gridDim.x) : Unit{};
         if (more) load_chunk<AOS, true>(g, nxt, ch);
         const uint64_t base = offsets[u];
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
-        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteBatch) {
-            uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
-            int32_t srid[kWriteBatch];
-            bool ok[kWriteBatch];
+        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
+            uint32_t cx[kWriteLoad];
+            int32_t cr[kWriteLoad];
 #pragma unroll
-            for (int i = 0; i < kWriteBatch; ++i) {
-                x[i] = nx[i];
-                srid[i] = nr[i];
-                ok[i] = e0 + i * kJoinBlock + threadIdx.x < un.sN;
+            for (int i = 0; i < kWriteLoad; ++i) {
+                cx[i] = nx[i];
+                cr[i] = nr[i];
             }
-            if (e0 + kJoinBlock * kWriteBatch < un.sN)
-                load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteBatch, nx, nr);
+            if (e0 + kJoinBlock * kWriteLoad < un.sN)
+                load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
             else if (more)
                 load_tuples<AOS>(g, nxt, 0, nx, nr);
-            probe_write(t, un.bits, x, ok, m, p1, p2);
-            // Slots inside the unit's range: waves take theirs from an LDS cursor (no block-wide
-            // barrier); within a wave, the pairs of the i-th tuple of every lane are contiguous,
-            // so each store instruction writes one coalesced run.
-            uint32_t excl[kWriteBatch], wtot = 0;
 #pragma unroll
-            for (int i = 0; i < kWriteBatch; ++i) {
-                const uint32_t inc = wave_incl_scan(m[i]);
-                excl[i] = wtot + inc - m[i];
-                wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
-            }
-            uint32_t wb = 0;
-            if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
-            wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
+            for (int h = 0; h < kWriteLoad; h += kWriteBatch) {
+                uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
+                int32_t srid[kWriteBatch];
+                bool ok[kWriteBatch];
 #pragma unroll
-            for (int i = 0; i < kWriteBatch; ++i) {
-                const uint64_t slot = base + wb + excl[i];
-                if (m[i] >= 1 && slot < cap) out[slot] = make_int2((int32_t)rw[p1[i]], srid[i]);
-                if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2((int32_t)rw[p2[i]], srid[i]);
-                if (m[i] > 2) {  // more than two build matches: visit the buckets again
-                    uint32_t seen = 0;
-                    for_each_match(t, un.bits, x[i], [&](uint32_t p) {
-                        if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
-                        ++seen;
-                    });
+                for (int i = 0; i < kWriteBatch; ++i) {
+                    x[i] = cx[h + i];
+                    srid[i] = cr[h + i];
+                    ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+                }
+                probe_write<kWriteBatch, AOS>(t, un.bits, x, ok, m, p1, p2);
+                // Slots inside the unit's range: waves take theirs from an LDS cursor (no
+                // block-wide barrier); within a wave, the pairs of the i-th tuple of every lane
+                // are contiguous, so each store instruction writes one coalesced run.
+                uint32_t excl[kWriteBatch], wtot = 0;
+#pragma unroll
+                for (int i = 0; i < kWriteBatch; ++i) {
+                    const uint32_t inc = wave_incl_scan(m[i]);
+                    excl[i] = wtot + inc - m[i];
+                    wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+                }
+                uint32_t wb = 0;
+                if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
+                wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
+#pragma unroll
+                for (int i = 0; i < kWriteBatch; ++i) {
+                    const uint64_t slot = base + wb + excl[i];
+                    if (m[i] >= 1 && slot < cap) out[slot] = make_int2((int32_t)rw[p1[i]], srid[i]);
+                    if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2((int32_t)rw[p2[i]], srid[i]);
+                    if (m[i] > 2) {  // more than two build matches: visit the buckets again
+                        uint32_t seen = 0;
+                        for_each_match<AOS>(t, un.bits, x[i], [&](uint32_t p) {
+                            if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
+                            ++seen;
+                        });
+                    }
                 }
             }
         }
