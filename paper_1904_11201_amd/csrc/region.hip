@@ -33,7 +33,10 @@ constexpr int kBins = 1 << kBinBits;
 constexpr int kBlk = 256;
 constexpr int kTile = 2048;        // tuples staged per scatter step
 constexpr int kRBlockRows = 512;   // R rows per unit (one wave, 8 rows per lane)
-constexpr int kTileRows = 256;     // S rows per unit, at least
+#ifndef JL_REGION_TILE
+#define JL_REGION_TILE 128
+#endif
+constexpr int kTileRows = JL_REGION_TILE;     // S rows per unit, at least
 constexpr int kMaxTiles = 8;       // S tiles per R block, at most (the tile grows beyond)
 constexpr int kCrossWaves = 4;
 
@@ -469,26 +472,25 @@ __global__ __launch_bounds__(kCrossWaves * kWave) void cross_k(
     const int32_t* __restrict__ srid, const uint64_t* __restrict__ goff,
     const uint64_t* __restrict__ total, int2* __restrict__ out, uint64_t cap)
 {
+    (void)nR;
     if (*total > cap) return;
     const int lane = (int)lane_id();
-    const int64_t items = 2 * (int64_t)nR;
-    const int64_t nw = (int64_t)gridDim.x * kCrossWaves;
-    for (int64_t k = (int64_t)blockIdx.x * kCrossWaves + uniform((int32_t)(threadIdx.x >> 6));
-         k < items; k += nw) {
-        const uint32_t r = (uint32_t)(k >> 1);
-        const int side = (int)(k & 1);
-        int lo = 0, hi = B - 1;  // bucket of bucketed row r: last i with rStart <= r
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (info[mid].rStart <= r) lo = mid; else hi = mid - 1;
-        }
-        const BucketInfo bi = info[lo];
+    const int wv = uniform((int32_t)(threadIdx.x >> 6));
+    // one workgroup per (R bucket, side) item; its waves take the bucket's rows in turn, and a
+    // row's pairs with the green span are written by the wave's lanes, consecutive in S
+    for (int64_t item = blockIdx.x; item < 2 * (int64_t)B; item += gridDim.x) {
+        const int i = (int)(item >> 1);
+        const int side = (int)(item & 1);
+        const BucketInfo bi = info[i];
         const uint32_t g0 = side ? bi.gr0 : bi.gl0, g1 = side ? bi.gr1 : bi.gl1;
-        if (g1 <= g0) continue;
+        if (g1 <= g0 || bi.nR == 0) continue;
         const uint64_t len = g1 - g0;
-        const uint64_t base = goff[2 * lo + side] + (uint64_t)(r - bi.rStart) * len;
-        const int32_t rr = rrid[r];
-        for (uint64_t s = lane; s < len; s += kWave) out[base + s] = make_int2(rr, srid[g0 + s]);
+        const uint64_t base0 = goff[2 * i + side];
+        for (uint32_t r = (uint32_t)wv; r < bi.nR; r += kCrossWaves) {
+            const int32_t rr = rrid[bi.rStart + r];
+            const uint64_t base = base0 + (uint64_t)r * len;
+            for (uint64_t s2 = lane; s2 < len; s2 += kWave) out[base + s2] = make_int2(rr, srid[g0 + s2]);
+        }
     }
 }
 
@@ -519,7 +521,10 @@ RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k)
     pl.nChS = nS > 0 ? ceil_div(nS, pl.chS) : 0;
     pl.Umax = (int64_t)kMaxTiles * (ceil_div(nR, kRBlockRows) + pl.B);
     const bool sel = op_a == JOIN_OP_BAND || op_a == JOIN_OP_EQ || op_a == JOIN_OP_NONE;
-    pl.K = sel && stash_k > 0 ? stash_k : 0;
+#ifndef JL_REGION_STASH_MULT
+#define JL_REGION_STASH_MULT 2
+#endif
+    pl.K = sel && stash_k > 0 ? stash_k * JL_REGION_STASH_MULT : 0;
     pl.nOff = pl.Umax + 2 * (int64_t)pl.B;
     size_t off = 256;
     auto take = [&](size_t bytes) {
