@@ -238,7 +238,11 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
 // ------------------------------------------------------------------------------- count pass --
 // Selective predicates also keep up to K matches of the unit in a per-unit stash, so the write
 // pass of a unit with at most K matches is a copy instead of a second sweep.
-template <int OPA, int OPC>
+// DENSE (region units of a selective predicate): the units were chosen because their value
+// ranges are close, so most 8-row groups hold a match and the OR-filter would send nearly every
+// group down its exact path.  Instead every S row is evaluated exactly against the wave's R rows
+// (both columns and rids kept in registers), one ballot per R row.
+template <int OPA, int OPC, bool DENSE = false>
 __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
                                                              uint64_t* __restrict__ counts)
 {
@@ -249,9 +253,38 @@ __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
         int64_t r0, rEnd, s0, s1;
         unit_of(g, u, r0, rEnd, s0, s1);
         RRows rr;
-        load_r<OPA, selective<OPA>() ? JOIN_OP_NONE : OPC>(g, r0, rEnd, lane, rr);
+        load_r<OPA, selective<OPA>() && !DENSE ? JOIN_OP_NONE : OPC>(g, r0, rEnd, lane, rr);
 
-        if constexpr (selective<OPA>()) {
+        if constexpr (selective<OPA>() && DENSE) {
+            int32_t rid[kRB];
+            uint64_t vm[kRB];
+            load_rids(g, r0, rEnd, lane, rid, vm);
+            const cptr<int32_t> Sa = as_const(g.Sa);
+            const cptr<int32_t> Sc = as_const(g.Sc);
+            const cptr<int32_t> Srid = as_const(g.Srid);
+            uint64_t n = 0;
+            int2* st = g.stash ? g.stash + u * g.K : nullptr;
+            const uint64_t kcap = st ? (uint64_t)g.K : 0ull;
+            int64_t j = s0;
+            for (; j + kSGroup <= s1; j += kSGroup) {  // 8 S rows' scalar loads in flight together
+                int32_t sa[kSGroup], sc[kSGroup], sr[kSGroup];
+#pragma unroll
+                for (int k = 0; k < kSGroup; ++k) {
+                    sa[k] = Sa[j + k];
+                    sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
+                    sr[k] = Srid ? Srid[j + k] : (int32_t)(j + k);
+                }
+#pragma unroll
+                for (int k = 0; k < kSGroup; ++k)
+                    emit_row<OPA, OPC>(rr, rid, vm, sa[k], sc[k], sr[k], n, st, kcap, lane);
+            }
+            for (; j < s1; ++j) {
+                const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
+                const int32_t srid = Srid ? Srid[j] : (int32_t)j;
+                emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, n, st, kcap, lane);
+            }
+            if (lane == 0) counts[u] = n;
+        } else if constexpr (selective<OPA>()) {
             uint64_t n = 0;
             int2* st = g.stash ? g.stash + u * g.K : nullptr;
             sweep_selective<OPA, OPC>(g, rr, r0, rEnd, s0, s1, n, st, st ? (uint64_t)g.K : 0ull,
@@ -296,7 +329,7 @@ __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
 }
 
 // ------------------------------------------------------------------------------- write pass --
-template <int OPA, int OPC>
+template <int OPA, int OPC, bool DENSE = false>
 __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
                                                              const uint64_t* __restrict__ offsets,
                                                              const uint64_t* __restrict__ total,
@@ -319,7 +352,7 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
         int64_t r0, rEnd, s0, s1;
         unit_of(g, u, r0, rEnd, s0, s1);
         uint64_t base = off;
-        if constexpr (selective<OPA>()) {
+        if constexpr (selective<OPA>() && !DENSE) {
             RRows rr;
             load_r<OPA, JOIN_OP_NONE>(g, r0, rEnd, lane, rr);
             sweep_selective<OPA, OPC>(g, rr, r0, rEnd, s0, s1, base, out, cap, lane);
@@ -345,60 +378,61 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
 using CountFn = void (*)(ThetaGeom, uint64_t*);
 using WriteFn = void (*)(ThetaGeom, const uint64_t*, const uint64_t*, int2*, uint64_t);
 
-template <int OPA>
+template <int OPA, bool DENSE>
 struct Table {
     static CountFn count(int opc)
     {
         switch (opc) {
-        case JOIN_OP_NONE: return theta_count_k<OPA, JOIN_OP_NONE>;
-        case JOIN_OP_EQ: return theta_count_k<OPA, JOIN_OP_EQ>;
-        case JOIN_OP_NE: return theta_count_k<OPA, JOIN_OP_NE>;
-        case JOIN_OP_LT: return theta_count_k<OPA, JOIN_OP_LT>;
-        case JOIN_OP_LE: return theta_count_k<OPA, JOIN_OP_LE>;
-        case JOIN_OP_GT: return theta_count_k<OPA, JOIN_OP_GT>;
-        case JOIN_OP_GE: return theta_count_k<OPA, JOIN_OP_GE>;
+        case JOIN_OP_NONE: return theta_count_k<OPA, JOIN_OP_NONE, DENSE>;
+        case JOIN_OP_EQ: return theta_count_k<OPA, JOIN_OP_EQ, DENSE>;
+        case JOIN_OP_NE: return theta_count_k<OPA, JOIN_OP_NE, DENSE>;
+        case JOIN_OP_LT: return theta_count_k<OPA, JOIN_OP_LT, DENSE>;
+        case JOIN_OP_LE: return theta_count_k<OPA, JOIN_OP_LE, DENSE>;
+        case JOIN_OP_GT: return theta_count_k<OPA, JOIN_OP_GT, DENSE>;
+        case JOIN_OP_GE: return theta_count_k<OPA, JOIN_OP_GE, DENSE>;
         default: return nullptr;
         }
     }
     static WriteFn write(int opc)
     {
         switch (opc) {
-        case JOIN_OP_NONE: return theta_write_k<OPA, JOIN_OP_NONE>;
-        case JOIN_OP_EQ: return theta_write_k<OPA, JOIN_OP_EQ>;
-        case JOIN_OP_NE: return theta_write_k<OPA, JOIN_OP_NE>;
-        case JOIN_OP_LT: return theta_write_k<OPA, JOIN_OP_LT>;
-        case JOIN_OP_LE: return theta_write_k<OPA, JOIN_OP_LE>;
-        case JOIN_OP_GT: return theta_write_k<OPA, JOIN_OP_GT>;
-        case JOIN_OP_GE: return theta_write_k<OPA, JOIN_OP_GE>;
+        case JOIN_OP_NONE: return theta_write_k<OPA, JOIN_OP_NONE, DENSE>;
+        case JOIN_OP_EQ: return theta_write_k<OPA, JOIN_OP_EQ, DENSE>;
+        case JOIN_OP_NE: return theta_write_k<OPA, JOIN_OP_NE, DENSE>;
+        case JOIN_OP_LT: return theta_write_k<OPA, JOIN_OP_LT, DENSE>;
+        case JOIN_OP_LE: return theta_write_k<OPA, JOIN_OP_LE, DENSE>;
+        case JOIN_OP_GT: return theta_write_k<OPA, JOIN_OP_GT, DENSE>;
+        case JOIN_OP_GE: return theta_write_k<OPA, JOIN_OP_GE, DENSE>;
         default: return nullptr;
         }
     }
 };
 
-CountFn count_fn(int opa, int opc)
+// dense: region units (only the selective operators have a separate dense form)
+CountFn count_fn(int opa, int opc, bool dense = false)
 {
     switch (opa) {
-    case JOIN_OP_EQ: return Table<JOIN_OP_EQ>::count(opc);
-    case JOIN_OP_NE: return Table<JOIN_OP_NE>::count(opc);
-    case JOIN_OP_LT: return Table<JOIN_OP_LT>::count(opc);
-    case JOIN_OP_LE: return Table<JOIN_OP_LE>::count(opc);
-    case JOIN_OP_GT: return Table<JOIN_OP_GT>::count(opc);
-    case JOIN_OP_GE: return Table<JOIN_OP_GE>::count(opc);
-    case JOIN_OP_BAND: return Table<JOIN_OP_BAND>::count(opc);
+    case JOIN_OP_EQ: return dense ? Table<JOIN_OP_EQ, true>::count(opc) : Table<JOIN_OP_EQ, false>::count(opc);
+    case JOIN_OP_NE: return Table<JOIN_OP_NE, false>::count(opc);
+    case JOIN_OP_LT: return Table<JOIN_OP_LT, false>::count(opc);
+    case JOIN_OP_LE: return Table<JOIN_OP_LE, false>::count(opc);
+    case JOIN_OP_GT: return Table<JOIN_OP_GT, false>::count(opc);
+    case JOIN_OP_GE: return Table<JOIN_OP_GE, false>::count(opc);
+    case JOIN_OP_BAND: return dense ? Table<JOIN_OP_BAND, true>::count(opc) : Table<JOIN_OP_BAND, false>::count(opc);
     default: return nullptr;
     }
 }
 
-WriteFn write_fn(int opa, int opc)
+WriteFn write_fn(int opa, int opc, bool dense = false)
 {
     switch (opa) {
-    case JOIN_OP_EQ: return Table<JOIN_OP_EQ>::write(opc);
-    case JOIN_OP_NE: return Table<JOIN_OP_NE>::write(opc);
-    case JOIN_OP_LT: return Table<JOIN_OP_LT>::write(opc);
-    case JOIN_OP_LE: return Table<JOIN_OP_LE>::write(opc);
-    case JOIN_OP_GT: return Table<JOIN_OP_GT>::write(opc);
-    case JOIN_OP_GE: return Table<JOIN_OP_GE>::write(opc);
-    case JOIN_OP_BAND: return Table<JOIN_OP_BAND>::write(opc);
+    case JOIN_OP_EQ: return dense ? Table<JOIN_OP_EQ, true>::write(opc) : Table<JOIN_OP_EQ, false>::write(opc);
+    case JOIN_OP_NE: return Table<JOIN_OP_NE, false>::write(opc);
+    case JOIN_OP_LT: return Table<JOIN_OP_LT, false>::write(opc);
+    case JOIN_OP_LE: return Table<JOIN_OP_LE, false>::write(opc);
+    case JOIN_OP_GT: return Table<JOIN_OP_GT, false>::write(opc);
+    case JOIN_OP_GE: return Table<JOIN_OP_GE, false>::write(opc);
+    case JOIN_OP_BAND: return dense ? Table<JOIN_OP_BAND, true>::write(opc) : Table<JOIN_OP_BAND, false>::write(opc);
     default: return nullptr;
     }
 }
@@ -454,7 +488,7 @@ hipError_t theta_count_units(const ThetaUnitArgs& a, const join_pred_t& p, uint6
                              hipStream_t st)
 {
     if (a.Umax <= 0) return hipSuccess;
-    CountFn f = count_fn(p.op_a, p.op_c);
+    CountFn f = count_fn(p.op_a, p.op_c, true);
     if (!f) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)ceil_div(a.Umax, kWavesPerBlock);
     prof::Scope ps(st, "region.count");
@@ -467,7 +501,7 @@ hipError_t theta_write_units(const ThetaUnitArgs& a, const join_pred_t& p,
                              uint64_t cap, hipStream_t st)
 {
     if (a.Umax <= 0) return hipSuccess;
-    WriteFn f = write_fn(p.op_a, p.op_c);
+    WriteFn f = write_fn(p.op_a, p.op_c, true);
     if (!f) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)ceil_div(a.Umax, kWavesPerBlock);
     prof::Scope ps(st, "region.write");
