@@ -45,6 +45,21 @@ constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBloc
 constexpr int kMaxBits = 11;     // scatter LDS: 2^11 partitions x (64 B carry + 8 B state)
 constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
 
+// Stores of the join's output pairs, which nothing here reads again: optionally non-temporal.
+#ifndef JL_NT_PAIRS
+#define JL_NT_PAIRS 1
+#endif
+__device__ __forceinline__ void put(int2* p, int2 v) { *p = v; }
+__device__ __forceinline__ void put_pair(int2* p, int2 v)
+{
+#if JL_NT_PAIRS
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+#else
+    *p = v;
+#endif
+}
+
 __device__ __forceinline__ uint32_t pid_of(int32_t key, int sh)
 {
     return sh >= 32 ? 0u : hmix((uint32_t)key) >> sh;
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
                 const uint32_t e = w + c0 + (v.y & 0xFFFFu);
                 const uint32_t A = e & ~(uint32_t)(kCarry - 1);
                 const uint32_t pos = w + c0 + j[q];
-                if (pos < A) out[pos] = make_int2(k[q], r[q]);
+                if (pos < A) put(&out[pos], make_int2(k[q], r[q]));
                 else slot[q] = pos - (A > w ? A : w);
             }
         }
@@ -230,7 +245,7 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
                 const uint32_t e = w + c0 + t;
                 const uint32_t A = e & ~(uint32_t)(kCarry - 1);
                 if (t && A > w) {
-                    for (uint32_t s2 = 0; s2 < c0; ++s2) out[w + s2] = carry[pp * kCarry + s2];
+                    for (uint32_t s2 = 0; s2 < c0; ++s2) put(&out[w + s2], carry[pp * kCarry + s2]);
                     ns[i] = make_uint2(A, (e - A) << 16);
                 } else {
                     ns[i] = make_uint2(w, (c0 + t) << 16);
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
     }
     for (int pp = tid; pp < P; pp += kScatBlock) {
         const uint2 v = pst[pp];
-        for (uint32_t s2 = 0; s2 < (v.y >> 16); ++s2) out[v.x + s2] = carry[pp * kCarry + s2];
+        for (uint32_t s2 = 0; s2 < (v.y >> 16); ++s2) put(&out[v.x + s2], carry[pp * kCarry + s2]);
     }
 }
 
@@ -793,8 +808,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
 #pragma unroll
                 for (int i = 0; i < kWriteBatch; ++i) {
                     const uint64_t slot = base + wb + excl[i];
-                    if (m[i] >= 1 && slot < cap) out[slot] = make_int2((int32_t)rw[p1[i]], srid[i]);
-                    if (m[i] >= 2 && slot + 1 < cap) out[slot + 1] = make_int2((int32_t)rw[p2[i]], srid[i]);
+                    if (m[i] >= 1 && slot < cap) put_pair(&out[slot], make_int2((int32_t)rw[p1[i]], srid[i]));
+                    if (m[i] >= 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2((int32_t)rw[p2[i]], srid[i]));
                     if (m[i] > 2) {  // more than two build matches: visit the buckets again
                         uint32_t seen = 0;
                         for_each_match<AOS>(t, un.bits, x[i], [&](uint32_t p) {
