@@ -62,15 +62,17 @@ def src_hash(files=None) -> str:
 
 def load_traffic():
     """HBM bytes per launch from committed rocprofv3 --pmc summaries (profiles/traffic.json),
-    valid only while the sources of those kernels are the ones they were taken on."""
+    each group valid only while the sources of its kernels are the ones it was taken on."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return {}
     with open(p) as f:
         t = json.load(f)
-    if t.get("src_hash") != src_hash(t.get("files")):
-        return {}
-    return t.get("kernels", {})
+    kern = {}
+    for grp in t.get("groups", []):
+        if grp.get("src_hash") == src_hash(grp.get("files")):
+            kern.update(grp.get("kernels", {}))
+    return kern
 
 
 def bench_batch(args, J, datagen, dev, stream):
