@@ -52,6 +52,22 @@ __device__ __forceinline__ cptr<T> as_const(const T* p)
     return (cptr<T>)(p);
 }
 
+// A pointer known to be in global memory.  Loads through a generic pointer that the compiler
+// cannot trace to a kernel argument become FLAT loads, which count against the LDS wait counter
+// too: every wait for an LDS result would then also wait for them.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p)
+{
+    return (gptr<T>)(p);
+}
+
+// 16-byte load of four int32 through a global pointer (p 16-byte aligned).
+using i32x4 = int32_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ i32x4 load4(gptr<int32_t> p) { return *(const __attribute__((address_space(1))) i32x4*)p; }
+
 // DPP control codes (GFX9 encoding).
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowShr2 = 0x112;

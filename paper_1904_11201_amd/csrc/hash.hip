@@ -8,9 +8,9 @@
 //   1. histogram:   per chunk of input, LDS histogram of pid = hash(key) >> (32 - bits); each
 //                   chunk reserves its range inside every partition with one global atomic;
 //   2. scan:        exclusive scan of the partition sizes -> partition starts;
-//   3. scatter:     per tile, LDS-atomic ranks, and (key, rid) tuples written partition-major
-//                   through per-partition LDS carry buffers, so writes cover whole 64-byte
-//                   HBM granules;
+//   3. scatter:     per tile, LDS-atomic ranks, the tile sorted by partition in LDS, and
+//                   (hash, rid) tuples written partition-major in runs of consecutive
+//                   addresses;
 //   4. plan:        per partition, work units = (R chunk that fits the LDS table) x (S slice);
 //   5. count pass:  per unit, build an LDS hash table from the R chunk and probe the S slice;
 //   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
@@ -34,15 +34,15 @@ namespace {
 constexpr int kHistBlock = 1024;
 constexpr int kScatBlock = 1024;
 #ifndef JL_SCAT_IT
-#define JL_SCAT_IT 4
+#define JL_SCAT_IT 16
 #endif
 constexpr int kScatIt = JL_SCAT_IT;              // tuples per thread per scatter tile (multiple of 4)
-constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile
-constexpr int kCarry = 8;                        // 8-byte tuples per 64-byte HBM write granule
-static_assert(kScatTile < 65536, "tile counts share a 32-bit word with the carry count");
+constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile (sorted in LDS)
+constexpr int kChunkAlign = 4 * kScatBlock;      // scatter chunks: whole 16-byte loads per thread
+constexpr int kGroups = 8;                       // chunk groups (XCDs) writing through shared cursors
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
-constexpr int kMaxBits = 11;     // scatter LDS: 2^11 partitions x (64 B carry + 8 B state)
+constexpr int kMaxBits = 11;     // scatter: two partitions per thread; 2^11 x 8 B of LDS state
 constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
 
 // Stores of the join's output pairs, which nothing here reads again: optionally non-temporal.
@@ -77,24 +77,37 @@ __global__ void zero_u32_k(uint32_t* __restrict__ p, int64_t n)
 __device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items, const SideItem& one,
                                               int64_t chunk, int64_t n)
 {
-    if (items) return items[blockIdx.x];
+    if (items) {
+        // scalar loads: the item is the same for the whole workgroup
+        const cptr<SideItem> p = as_const(items) + blockIdx.x;
+        SideItem it;
+        it.key = p->key;
+        it.rid = p->rid;
+        it.beg = p->beg;
+        it.len = p->len;
+        it.bits = p->bits;
+        it.part0 = p->part0;
+        return it;
+    }
     SideItem it = one;
     it.beg = (int64_t)blockIdx.x * chunk;
     const int64_t left = n - it.beg;
     it.len = (uint32_t)(left < chunk ? left : chunk);
-    it.offs0 = (uint32_t)blockIdx.x << one.bits;
     return it;
 }
 
 __device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
-// A chunk counts its tuples per partition in LDS, then reserves its range inside every partition
-// with one global atomic add per non-empty partition: offs[offs0 + p] is the chunk's offset
-// inside partition p and tot[part0 + p] ends as the partition's size.  Ranges of different
-// chunks are disjoint; their order inside a partition follows the order of the atomics.
+// Chunks are grouped by their workgroup index modulo kGroups, which on this chip is the XCD the
+// workgroup runs on: a group's chunks write each partition through one shared cursor (see the
+// scatter), so the partially written 64-byte granules of a partition stay in one XCD's L2.
+// A chunk counts its tuples per partition in LDS, then adds the counts to tot[part0 + p] (the
+// partition's size) and grp[g * stride + part0 + p] (its group's share of the partition).
+__device__ __forceinline__ uint32_t group_of_block() { return blockIdx.x % kGroups; }
+
 __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict__ items, SideItem one,
                                                      int64_t chunk, int64_t n, uint32_t* __restrict__ tot,
-                                                     uint32_t* __restrict__ offs)
+                                                     uint32_t* __restrict__ grp, uint32_t stride)
 {
     extern __shared__ uint32_t h[];
     constexpr int V = 4;  // 16-byte loads in flight per thread
@@ -103,16 +116,16 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict_
     const int sh = 32 - it.bits;
     for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
     __syncthreads();
-    const int32_t* __restrict__ key = it.key + it.beg;
+    const gptr<int32_t> key = as_global(it.key + it.beg);
     const int64_t end = it.len;
     int64_t i = 0;
-    if (aligned16(key)) {
+    if (aligned16(it.key + it.beg)) {
         const int64_t step = 4 * kHistBlock;
         for (; i + V * step <= end; i += V * step) {
-            int4 k4[V];
+            i32x4 k4[V];
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                k4[v] = *reinterpret_cast<const int4*>(key + i + v * step + 4 * threadIdx.x);
+                k4[v] = load4(key + i + v * step + 4 * threadIdx.x);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 atomicAdd(&h[pid_of(k4[v].x, sh)], 1u);
@@ -124,148 +137,227 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict_
     }
     for (i += threadIdx.x; i < end; i += kHistBlock) atomicAdd(&h[pid_of(key[i], sh)], 1u);
     __syncthreads();
+    uint32_t* __restrict__ gs = grp + (size_t)group_of_block() * stride + it.part0;
     for (int p = threadIdx.x; p < P; p += kHistBlock) {
         const uint32_t v = h[p];
-        offs[(int64_t)it.offs0 + p] = v ? atomicAdd(&tot[it.part0 + p], v) : 0u;
+        if (v) {
+            atomicAdd(&tot[it.part0 + p], v);
+            atomicAdd(&gs[p], v);
+        }
+    }
+}
+
+// Group shares -> group cursors: the groups' ranges follow each other inside every partition,
+// cur[g * stride + p] = base[p] + shares of groups before g.  In place.
+__global__ void group_cursors_k(uint32_t* __restrict__ grp, const uint32_t* __restrict__ base,
+                                uint32_t stride, int64_t n)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t run = base[p];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const uint32_t c = grp[(size_t)g * stride + p];
+        grp[(size_t)g * stride + p] = run;
+        run += c;
     }
 }
 
 // --------------------------------------------------------------------------------- scatter --
-// Partitioned tuples are written as 8-byte (hmix(key), rid) pairs, partition-major.  An HBM write that
-// covers only part of a 64-byte granule costs a read-modify-write, and with 2^11 partitions a
-// tile holds only a few tuples per partition, so the tuples of each partition are held back in
-// an LDS carry buffer (up to 7 of them) until they complete a granule: every write below then
-// ends on a granule boundary, and only the first and last granule of a chunk's range inside a
-// partition are written in part.  Per tile of kScatTile tuples:
-//   1. rank each tuple inside its partition's share of the tile (LDS atomic);
-//   2. for partition p with carried tuples k, tile tuples t and write position w, the share
-//      ends at e = w + k + t; everything before A = e rounded down to 8 tuples is written now
-//      (the carried tuples and the tile tuples that fall before A), the rest is carried;
-//   3. the carry buffers and positions are updated.
-// Tuples of a partition keep their tile order only up to the atomics' order, which does not
-// matter to the join.
-__device__ __forceinline__ void scat_load(const int32_t* __restrict__ key, const int32_t* __restrict__ rid,
-                                          int64_t rid0, bool vec, int t0, int tn,
-                                          int32_t (&k)[kScatIt], int32_t (&r)[kScatIt])
+// Partitioned tuples are written as 8-byte (hmix(key), rid) pairs, partition-major.  Two costs
+// decide a scatter with 2^11 partitions: memory requests (a store instruction whose 64 lanes
+// write 64 partitions makes 64 of them), and 64-byte granules written in part (each is a
+// read-modify-write in HBM unless the rest of the granule reaches the L2 while the line is
+// still there).  Per tile of kScatTile tuples:
+//   1. each partition's share of the tile is counted (LDS atomics);
+//   2. the chunk's group takes that many output positions from its cursor for the partition
+//      (one global atomic per partition and tile), and an exclusive scan of the shares gives
+//      each partition's start in the sorted tile;
+//   3. each tuple takes the next slot of its partition in LDS (an LDS atomic on a cursor that
+//      starts at the partition's start) and is placed there: the tile is sorted by partition;
+//   4. the sorted tile is written out by consecutive lanes taking consecutive positions, so a
+//      store instruction covers runs of about kScatTile / 2^bits tuples and touches a few
+//      granules instead of 64.
+// A partition's runs from the chunks of one group follow each other at its group cursor, so the
+// granule a run leaves incomplete is completed by the next run of the same group soon after,
+// in the same XCD's L2.  Tuples of a partition keep no order, which does not matter to the join.
+// Thread t handles partitions 2t and 2t + 1 in the per-partition steps.
+// Element of thread tid, item 4v + c: tile position 4 * (v * kScatBlock + tid) + c, so every
+// 16-byte load instruction of a wave reads 1 KB of consecutive input.
+__device__ __forceinline__ int scat_pos(int q) { return 4 * ((q >> 2) * kScatBlock + (int)threadIdx.x) + (q & 3); }
+
+// Loads of a tile's keys or rids: FULL tiles read whole 16-byte vectors; a partial tile (a
+// chunk's last) reads element by element.
+template <bool FULL>
+__device__ __forceinline__ void scat_load(gptr<int32_t> col, int t0, int tn, int32_t (&x)[kScatIt])
 {
-    const int tid = threadIdx.x;
-    if (vec && tn == kScatTile) {
 #pragma unroll
-        for (int v = 0; v < kScatIt / 4; ++v) {
-            const int4 k4 = *reinterpret_cast<const int4*>(key + t0 + kScatIt * tid + 4 * v);
-            k[4 * v] = k4.x; k[4 * v + 1] = k4.y; k[4 * v + 2] = k4.z; k[4 * v + 3] = k4.w;
-            if (rid) {
-                const int4 r4 = *reinterpret_cast<const int4*>(rid + t0 + kScatIt * tid + 4 * v);
-                r[4 * v] = r4.x; r[4 * v + 1] = r4.y; r[4 * v + 2] = r4.z; r[4 * v + 3] = r4.w;
-            } else {
+    for (int v = 0; v < kScatIt / 4; ++v) {
+        const int e = scat_pos(4 * v);
+        if (FULL) {
+            const i32x4 x4 = load4(col + t0 + e);
+            x[4 * v] = x4.x; x[4 * v + 1] = x4.y; x[4 * v + 2] = x4.z; x[4 * v + 3] = x4.w;
+        } else {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) r[4 * v + c] = (int32_t)(rid0 + t0 + kScatIt * tid + 4 * v + c);
-            }
+            for (int c = 0; c < 4; ++c) x[4 * v + c] = e + c < tn ? col[t0 + e + c] : 0;
         }
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < kScatIt; ++q) {
-        const int e = kScatIt * tid + q;
-        const bool ok = e < tn;
-        k[q] = ok ? key[t0 + e] : 0;
-        r[q] = ok ? (rid ? rid[t0 + e] : (int32_t)(rid0 + t0 + e)) : 0;
     }
 }
 
+struct ScatLds {
+    int2* stg;      // [kScatTile] the tile sorted by partition
+    uint32_t* cnt;  // [P] tile shares, then sorted starts
+    uint32_t* dlt;  // [P] output position - sorted position
+    uint32_t* tmp;  // scan scratch
+};
+
+// One tile: k holds raw keys (hashed here), r the row ids (RIDS) or nothing (row id = pos0 + tile
+// position).  cur: this group's cursors of the join's partitions.
+template <bool RIDS, bool FULL>
+__device__ __forceinline__ void scat_tile(int32_t (&k)[kScatIt], const int32_t (&r)[kScatIt], int tn,
+                                          int64_t pos0, int P, int sh, const ScatLds& L,
+                                          uint32_t* __restrict__ cur, int2* __restrict__ out)
+{
+    const int tid = threadIdx.x;
+    const int pa = 2 * tid, pb = 2 * tid + 1;
+    // 1. shares.  Tuples are written as (hmix(key), rid): the hash is a bijection of the key, so
+    // the join kernels compare hashes and never hash again.
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        const uint32_t h = hmix((uint32_t)k[q]);
+        k[q] = (int32_t)h;
+        if (FULL || scat_pos(q) < tn) atomicAdd(&L.cnt[sh >= 32 ? 0u : h >> sh], 1u);
+    }
+    __syncthreads();
+    // 2. output positions from the group cursors; sorted starts (cnt becomes each partition's
+    // placing cursor)
+    const uint32_t ca = pa < P ? L.cnt[pa] : 0u, cb = pb < P ? L.cnt[pb] : 0u;
+    uint32_t oa = 0, ob = 0;
+    if (ca) oa = atomicAdd(&cur[pa], ca);
+    if (cb) ob = atomicAdd(&cur[pb], cb);
+    uint32_t tot;
+    const uint32_t sa = block_excl_scan<kScatBlock>(ca + cb, L.tmp, &tot);
+    if (pa < P) L.cnt[pa] = sa;
+    if (pb < P) L.cnt[pb] = sa + ca;
+    __syncthreads();
+    // 3. place in sorted order: each tuple takes the next slot of its partition
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        const int e = scat_pos(q);
+        if (FULL || e < tn) {
+            const uint32_t h = (uint32_t)k[q];
+            const uint32_t at = atomicAdd(&L.cnt[sh >= 32 ? 0u : h >> sh], 1u);
+            L.stg[at] = make_int2(k[q], RIDS ? r[q] : (int32_t)(pos0 + e));
+        }
+    }
+    // shift from sorted position to output position
+    if (pa < P) L.dlt[pa] = oa - sa;
+    if (pb < P) L.dlt[pb] = ob - (sa + ca);
+    __syncthreads();
+    if (pa < P) L.cnt[pa] = 0;  // the next tile's shares (nothing reads the cursors any more)
+    if (pb < P) L.cnt[pb] = 0;
+    // 4. write the sorted tile, eight LDS reads in flight at a time
+    constexpr int G = 8;
+#pragma unroll
+    for (int g = 0; g < kScatIt; g += G) {
+        int2 v[G];
+        uint32_t d[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = (g + u) * kScatBlock + tid;
+            v[u] = (FULL || i < tn) ? L.stg[i] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const uint32_t h = (uint32_t)v[u].x;
+            d[u] = L.dlt[sh >= 32 ? 0u : h >> sh];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = (g + u) * kScatBlock + tid;
+            if (FULL || i < tn) put(&out[d[u] + (uint32_t)i], v[u]);
+        }
+    }
+    __syncthreads();
+}
+
+// Full tile t of a chunk: the next tile's keys and rids are loaded into nk, nr while this one is
+// worked on, before this tile's stores, so that waiting for them does not wait for the stores
+// (the vector memory counter counts loads and stores in one queue).
+template <bool RIDS>
+__device__ __forceinline__ void scat_full_tile(int t, int nfull, gptr<int32_t> key, gptr<int32_t> rid,
+                                               int32_t (&nk)[kScatIt], int32_t (&nr)[kScatIt],
+                                               int64_t beg, int P, int sh, const ScatLds& L,
+                                               uint32_t* __restrict__ cur, int2* __restrict__ out)
+{
+    int32_t k[kScatIt], r[kScatIt];
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        k[q] = nk[q];
+        if (RIDS) r[q] = nr[q];
+    }
+    if (t + 1 < nfull) {
+        scat_load<true>(key, (t + 1) * kScatTile, kScatTile, nk);
+        if (RIDS) scat_load<true>(rid, (t + 1) * kScatTile, kScatTile, nr);
+    }
+    scat_tile<RIDS, true>(k, r, kScatTile, beg + (int64_t)t * kScatTile, P, sh, L, cur, out);
+}
+
+// A chunk: its full tiles, then the partial rest.  The first full tile is peeled off the loop,
+// so that every pass through the loop starts in the same state (the loads it needs issued before
+// the previous tile's stores) and waiting for those loads does not wait for the stores.
+template <bool RIDS>
+__device__ __forceinline__ void scat_chunk(gptr<int32_t> key, gptr<int32_t> rid, bool vec, int end,
+                                           int64_t beg, int P, int sh, const ScatLds& L,
+                                           uint32_t* __restrict__ cur, int2* __restrict__ out)
+{
+    const int nfull = vec ? end / kScatTile : 0;
+    int32_t nk[kScatIt], nr[kScatIt];
+    if (nfull > 0) {
+        scat_load<true>(key, 0, kScatTile, nk);
+        if (RIDS) scat_load<true>(rid, 0, kScatTile, nr);
+        scat_full_tile<RIDS>(0, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+    }
+    for (int t = 1; t < nfull; ++t)
+        scat_full_tile<RIDS>(t, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+    for (int t0 = nfull * kScatTile; t0 < end; t0 += kScatTile) {
+        const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
+        int32_t k[kScatIt], r[kScatIt];
+        scat_load<false>(key, t0, tn, k);
+        if (RIDS) scat_load<false>(rid, t0, tn, r);
+        scat_tile<RIDS, false>(k, r, tn, beg + t0, P, sh, L, cur, out);
+    }
+}
+
+// RIDS: the side has a rid column (a batch passes RIDS and may still leave it NULL per item;
+// without rids the row ids are positions).  cur: group cursors, [kGroups][stride].
+template <bool RIDS>
 __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restrict__ items, SideItem one,
                                                         int64_t chunk, int64_t n,
-                                                        const uint32_t* __restrict__ base,
-                                                        const uint32_t* __restrict__ offs,
+                                                        uint32_t* __restrict__ cur, uint32_t stride,
                                                         int2* __restrict__ out)
 {
     extern __shared__ uint32_t lds[];
-    constexpr int kPpt = (1 << kMaxBits) / kScatBlock;  // partitions per thread in the per-partition steps
     const SideItem it = side_item(items, one, chunk, n);
     const int P = 1 << it.bits;
     const int sh = 32 - it.bits;
-    int2* carry = reinterpret_cast<int2*>(lds);  // [P][kCarry]
-    // per partition: x = next position not yet written, y = carried tuples << 16 | tile tuples
-    uint2* pst = reinterpret_cast<uint2*>(lds + (size_t)P * kCarry * 2);
-    uint32_t* pcnt = reinterpret_cast<uint32_t*>(pst);  // pcnt[2p + 1] is pst[p].y
+    ScatLds L;
+    L.stg = reinterpret_cast<int2*>(lds);
+    L.cnt = lds + 2 * kScatTile;
+    L.dlt = L.cnt + P;
+    L.tmp = L.dlt + P;
     const int tid = threadIdx.x;
-    for (int p = tid; p < P; p += kScatBlock)
-        pst[p] = make_uint2(base[it.part0 + p] + offs[(int64_t)it.offs0 + p], 0u);
+    if (2 * tid < P) L.cnt[2 * tid] = 0;
+    if (2 * tid + 1 < P) L.cnt[2 * tid + 1] = 0;
     __syncthreads();
-    const int32_t* __restrict__ key = it.key + it.beg;
-    const int32_t* __restrict__ rid = it.rid ? it.rid + it.beg : nullptr;
-    const bool vec = aligned16(key) && (rid == nullptr || aligned16(rid));
-    const int end = (int)it.len;
-    int32_t nk[kScatIt], nr[kScatIt];
-    if (0 < end) scat_load(key, rid, it.beg, vec, 0, end < kScatTile ? end : kScatTile, nk, nr);
-    for (int t0 = 0; t0 < end; t0 += kScatTile) {
-        const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
-        int32_t k[kScatIt], r[kScatIt];
-#pragma unroll
-        for (int q = 0; q < kScatIt; ++q) {
-            k[q] = nk[q];
-            r[q] = nr[q];
-        }
-        const int t1 = t0 + kScatTile;
-        if (t1 < end) scat_load(key, rid, it.beg, vec, t1, end - t1 < kScatTile ? end - t1 : kScatTile, nk, nr);
-        // Tuples are written as (hmix(key), rid): the hash is a bijection of the key, so the join
-        // kernels compare hashes and never hash again.
-        uint32_t p[kScatIt], j[kScatIt];
-#pragma unroll
-        for (int q = 0; q < kScatIt; ++q) {
-            const uint32_t h = hmix((uint32_t)k[q]);
-            k[q] = (int32_t)h;
-            p[q] = sh >= 32 ? 0u : h >> sh;
-            j[q] = kScatIt * tid + q < tn ? atomicAdd(&pcnt[2 * p[q] + 1], 1u) & 0xFFFFu : 0u;
-        }
-        __syncthreads();
-        uint32_t slot[kScatIt];  // carry slot, or kCarry when written now or not a tuple
-#pragma unroll
-        for (int q = 0; q < kScatIt; ++q) {
-            slot[q] = kCarry;
-            if (kScatIt * tid + q < tn) {
-                const uint2 v = pst[p[q]];
-                const uint32_t w = v.x, c0 = v.y >> 16;
-                const uint32_t e = w + c0 + (v.y & 0xFFFFu);
-                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
-                const uint32_t pos = w + c0 + j[q];
-                if (pos < A) put(&out[pos], make_int2(k[q], r[q]));
-                else slot[q] = pos - (A > w ? A : w);
-            }
-        }
-        // flush carried tuples of partitions whose share crosses a granule boundary, and work out
-        // every partition's new state (written after the barrier)
-        uint2 ns[kPpt];
-#pragma unroll
-        for (int i = 0; i < kPpt; ++i) {
-            const int pp = tid + i * kScatBlock;
-            if (pp < P) {
-                const uint2 v = pst[pp];
-                const uint32_t w = v.x, c0 = v.y >> 16, t = v.y & 0xFFFFu;
-                const uint32_t e = w + c0 + t;
-                const uint32_t A = e & ~(uint32_t)(kCarry - 1);
-                if (t && A > w) {
-                    for (uint32_t s2 = 0; s2 < c0; ++s2) put(&out[w + s2], carry[pp * kCarry + s2]);
-                    ns[i] = make_uint2(A, (e - A) << 16);
-                } else {
-                    ns[i] = make_uint2(w, (c0 + t) << 16);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kScatIt; ++q)
-            if (slot[q] < (uint32_t)kCarry) carry[p[q] * kCarry + slot[q]] = make_int2(k[q], r[q]);
-#pragma unroll
-        for (int i = 0; i < kPpt; ++i) {
-            const int pp = tid + i * kScatBlock;
-            if (pp < P) pst[pp] = ns[i];
-        }
-        __syncthreads();
-    }
-    for (int pp = tid; pp < P; pp += kScatBlock) {
-        const uint2 v = pst[pp];
-        for (uint32_t s2 = 0; s2 < (v.y >> 16); ++s2) put(&out[v.x + s2], carry[pp * kCarry + s2]);
+    uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
+    const gptr<int32_t> key = as_global(it.key + it.beg);
+    const bool kvec = aligned16(it.key + it.beg);
+    if (!RIDS || it.rid == nullptr) {
+        scat_chunk<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, gc, out);
+    } else {
+        const bool vec = kvec && aligned16(it.rid + it.beg);
+        scat_chunk<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, gc, out);
     }
 }
 
@@ -831,7 +923,11 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 
-static size_t scatter_lds(int P) { return (size_t)P * (kCarry * sizeof(int2) + sizeof(uint2)); }
+// sorted tile, shares/starts and shifts per partition, scan scratch
+static size_t scatter_lds(int P)
+{
+    return (size_t)kScatTile * sizeof(int2) + (size_t)P * 8 + (kScatBlock / kWave + 1) * 4;
+}
 
 // Default fan-out: mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma
 // for hashed unique keys) under cap; past 2^kMaxBits partitions R chunks repeat per S slice.
@@ -886,15 +982,15 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         if (bits > kMaxBits) bits = kMaxBits;
         pl.bits = bits;
         pl.P = 1 << bits;
-        // scatter chunks: one per resident scatter workgroup (the carry buffers decide how many
-        // fit a CU), each a whole number of tiles
+        // scatter chunks: one per resident scatter workgroup (the sorted tile decides how many
+        // fit a CU), each a multiple of kChunkAlign rows
         int per_cu = (int)((160 * 1024) / scatter_lds(pl.P));
         if (per_cu < 1) per_cu = 1;
         if (per_cu > 2) per_cu = 2;
         auto chunk_for = [&](int64_t n) {
             int64_t c = ceil_div(n, (int64_t)num_cus * per_cu);
-            c = ceil_div(c, kScatTile) * kScatTile;
-            if (c < kScatTile) c = kScatTile;
+            c = ceil_div(c, kChunkAlign) * kChunkAlign;
+            if (c < kChunkAlign) c = kChunkAlign;
             return c;
         };
         pl.chR = chunk_for(nR);
@@ -902,16 +998,16 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         pl.nChR = nR > 0 && !pl.prebuilt ? ceil_div(nR, pl.chR) : 0;  // a prebuilt R has its own
         pl.nChS = nS > 0 ? ceil_div(nS, pl.chS) : 0;
         pl.Umax = pl.P + ceil_div(nR, cap) + ceil_div(nS, pl.slice) + 2;
-        pl.off_tot = off;  // totR[P] then totS[P], cleared together
-        off = align_up(off + (size_t)2 * pl.P * 4);
+        // totR[P], totS[P], group shares of S [kGroups][P], of R [kGroups][P]: cleared together
+        // (only the S half, from totS on, for a prebuilt R)
+        pl.off_tot = off;
+        pl.off_grpS = off + (size_t)2 * pl.P * 4;
+        pl.off_grpR = pl.off_grpS + (size_t)kGroups * pl.P * 4;
+        off = align_up(pl.off_grpR + (size_t)kGroups * pl.P * 4);
         pl.off_baseR = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
         pl.off_baseS = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
-        pl.off_offsR = off;
-        off = align_up(off + (size_t)pl.P * pl.nChR * 4);
-        pl.off_offsS = off;
-        off = align_up(off + (size_t)pl.P * pl.nChS * 4);
         pl.off_tupR = off;
         off = align_up(off + (size_t)(pl.prebuilt ? 0 : nR) * 8);
         pl.off_tupS = off;
@@ -952,7 +1048,7 @@ static hipError_t set_attrs()
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
     const void* fns[] = {
-        (const void*)scatter_k, (const void*)hist_k,
+        (const void*)scatter_k<true>, (const void*)scatter_k<false>, (const void*)hist_k,
         (const void*)join_count_k<true>, (const void*)join_count_k<false>,
         (const void*)join_write_k<true>, (const void*)join_write_k<false>,
     };
@@ -974,24 +1070,36 @@ static SideItem whole_side(const join_rel_t& X, int bits)
 }
 
 static hipError_t hist_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
-                            int64_t grid, int maxBits, uint32_t* tot, uint32_t* offs, hipStream_t st,
-                            bool is_r)
+                            int64_t grid, int maxBits, uint32_t* tot, uint32_t* grp, int64_t stride,
+                            hipStream_t st, bool is_r)
 {
     if (grid <= 0) return hipSuccess;
     const size_t hl = (size_t)4 << maxBits;
     prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
-    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, offs);
+    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, grp, (uint32_t)stride);
+    return hipGetLastError();
+}
+
+// group shares -> group cursors, after the partition starts are known
+static hipError_t cursors_side(uint32_t* grp, const uint32_t* base, int64_t stride, hipStream_t st)
+{
+    if (stride <= 0) return hipSuccess;
+    prof::Scope pc(st, "hash.plan");
+    group_cursors_k<<<(unsigned)ceil_div(stride, 256), 256, 0, st>>>(grp, base, (uint32_t)stride, stride);
     return hipGetLastError();
 }
 
 static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
-                               int64_t grid, int maxBits, const uint32_t* base, const uint32_t* offs,
-                               int2* out, hipStream_t st, bool is_r)
+                               int64_t grid, int maxBits, uint32_t* cur, int64_t stride, int2* out,
+                               hipStream_t st, bool is_r)
 {
     if (grid <= 0) return hipSuccess;
     const size_t sl = scatter_lds(1 << maxBits);
     prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
-    scatter_k<<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, base, offs, out);
+    if (items != nullptr || one.rid != nullptr)
+        scatter_k<true><<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out);
+    else
+        scatter_k<false><<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out);
     return hipGetLastError();
 }
 
@@ -1042,37 +1150,39 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         uint32_t* totS = totR + pl.P;
         uint32_t* baseR = reinterpret_cast<uint32_t*>(ws + pl.off_baseR);
         uint32_t* baseS = reinterpret_cast<uint32_t*>(ws + pl.off_baseS);
-        uint32_t* offsR = reinterpret_cast<uint32_t*>(ws + pl.off_offsR);
-        uint32_t* offsS = reinterpret_cast<uint32_t*>(ws + pl.off_offsS);
+        uint32_t* grpR = reinterpret_cast<uint32_t*>(ws + pl.off_grpR);
+        uint32_t* grpS = reinterpret_cast<uint32_t*>(ws + pl.off_grpS);
         int2* tupR = reinterpret_cast<int2*>(ws + pl.off_tupR);
         int2* tupS = reinterpret_cast<int2*>(ws + pl.off_tupS);
         {
-            // a prebuilt R keeps its sizes: only the S sizes are cleared
+            // a prebuilt R keeps its sizes: only the S sizes and shares are cleared
             prof::Scope pz(st, "hash.plan");
             uint32_t* z = pre ? totS : totR;
-            const int64_t nz = pre ? pl.P : 2 * (int64_t)pl.P;
+            const int64_t nz = (pre ? 1 + kGroups : 2 + 2 * kGroups) * (int64_t)pl.P;
             zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(z, nz);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         const SideItem oneR = whole_side(R, pl.bits), oneS = whole_side(S, pl.bits);
         if (!pre) {
-            e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, offsR, st, true);
+            e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, grpR, pl.P, st, true);
             if (e != hipSuccess) return e;
         }
-        e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, offsS, st, false);
+        e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, st, false);
         if (e != hipSuccess) return e;
         if (!pre) {
             e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+            if (e == hipSuccess) e = cursors_side(grpR, baseR, pl.P, st);
             if (e != hipSuccess) return e;
         }
         e = exclusive_scan<uint32_t>(totS, baseS, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+        if (e == hipSuccess) e = cursors_side(grpS, baseS, pl.P, st);
         if (e != hipSuccess) return e;
         if (!pre) {
-            e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, baseR, offsR, tupR, st, true);
+            e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, grpR, pl.P, tupR, st, true);
             if (e != hipSuccess) return e;
         }
-        e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, baseS, offsS, tupS, st, false);
+        e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, grpS, pl.P, tupS, st, false);
         if (e != hipSuccess) return e;
         const uint32_t* pbaseR = pre ? pre->base : baseR;
         const uint32_t* ptotR = pre ? pre->tot : totR;
@@ -1152,13 +1262,12 @@ BuildPlan hash_build_plan(int64_t nR, int num_cus)
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 2) per_cu = 2;
     int64_t c = ceil_div(nR > 0 ? nR : 1, (int64_t)num_cus * per_cu);
-    c = ceil_div(c, kScatTile) * kScatTile;
-    b.chR = c < kScatTile ? kScatTile : c;
+    c = ceil_div(c, kChunkAlign) * kChunkAlign;
+    b.chR = c < kChunkAlign ? kChunkAlign : c;
     b.nChR = nR > 0 ? ceil_div(nR, b.chR) : 0;
     size_t off = 256;
-    b.off_tot = take(off, (size_t)b.P * 4);
+    b.off_tot = take(off, (size_t)b.P * 4 * (1 + kGroups));  // sizes, then group shares: cleared together
     b.off_base = take(off, (size_t)(b.P + 1) * 4);
-    b.off_offs = take(off, (size_t)b.P * b.nChR * 4);
     b.off_tup = take(off, (size_t)nR * 8);
     b.off_temp = take(off, scan_temp_elems<uint32_t>(b.P + 1) * 4 + 8);
     b.bytes = off;
@@ -1171,20 +1280,22 @@ hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipS
     if (e != hipSuccess) return e;
     uint32_t* tot = reinterpret_cast<uint32_t*>(build + b.off_tot);
     uint32_t* base = reinterpret_cast<uint32_t*>(build + b.off_base);
-    uint32_t* offs = reinterpret_cast<uint32_t*>(build + b.off_offs);
+    uint32_t* grp = tot + b.P;
     int2* tup = reinterpret_cast<int2*>(build + b.off_tup);
     {
         prof::Scope pz(st, "hash.plan");
-        zero_u32_k<<<(unsigned)ceil_div(b.P, 256), 256, 0, st>>>(tot, b.P);
+        const int64_t nz = (int64_t)b.P * (1 + kGroups);
+        zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(tot, nz);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const SideItem one = whole_side(R, b.bits);
-    e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, offs, st, true);
+    e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, grp, b.P, st, true);
     if (e != hipSuccess) return e;
     e = exclusive_scan<uint32_t>(tot, base, b.P, nullptr, reinterpret_cast<uint32_t*>(build + b.off_temp), st);
+    if (e == hipSuccess) e = cursors_side(grp, base, b.P, st);
     if (e != hipSuccess) return e;
-    return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, base, offs, tup, st, true);
+    return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, grp, b.P, tup, st, true);
 }
 
 RView build_view(const BuildPlan& b, const void* build)
@@ -1204,7 +1315,7 @@ RView build_view(const BuildPlan& b, const void* build)
 // of unit counts and the write pass are one launch each, and join j's pairs land contiguously,
 // in join order, in one output array.
 
-constexpr int64_t kBatchChunk = 16 * kScatTile;  // rows per histogram / scatter item
+constexpr int64_t kBatchChunk = 65536;  // rows per histogram / scatter item
 
 static int job_bits(const join_job_t& j, int cap)
 {
@@ -1229,15 +1340,13 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
         bp.nParts += P;
         bp.nItemsR += side_items(jobs[j].R.n);
         bp.nItemsS += side_items(jobs[j].S.n);
-        bp.offsR += side_items(jobs[j].R.n) * P;
-        bp.offsS += side_items(jobs[j].S.n) * P;
         bp.sumR += jobs[j].R.n;
         bp.sumS += jobs[j].S.n;
         umax += P + ceil_div(jobs[j].R.n, bp.cap) + ceil_div(jobs[j].S.n, bp.slice) + 1;
     }
     // partition starts, unit indices and item fields are 32-bit
     if (bp.sumR >= ((int64_t)1 << 32) || bp.sumS >= ((int64_t)1 << 32) || umax >= ((int64_t)1 << 31) ||
-        bp.offsR >= ((int64_t)1 << 32) || bp.offsS >= ((int64_t)1 << 32))
+        bp.nParts * kGroups >= ((int64_t)1 << 32))
         return -1;
     bp.Umax = umax;
     size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
@@ -1245,11 +1354,10 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.off_jbits = take(off, (size_t)njobs * 4);
     bp.off_itemsR = take(off, (size_t)bp.nItemsR * sizeof(SideItem));
     bp.off_itemsS = take(off, (size_t)bp.nItemsS * sizeof(SideItem));
-    bp.off_tot = take(off, (size_t)2 * bp.nParts * 4);
+    // totR, totS, then the group shares of R and S: cleared together
+    bp.off_tot = take(off, (size_t)(2 + 2 * kGroups) * bp.nParts * 4);
     bp.off_baseR = take(off, (size_t)(bp.nParts + 1) * 4);
     bp.off_baseS = take(off, (size_t)(bp.nParts + 1) * 4);
-    bp.off_offsR = take(off, (size_t)bp.offsR * 4);
-    bp.off_offsS = take(off, (size_t)bp.offsS * 4);
     bp.off_tupR = take(off, (size_t)bp.sumR * 8);
     bp.off_tupS = take(off, (size_t)bp.sumS * 8);
     bp.off_info = take(off, (size_t)bp.nParts * sizeof(PartInfo));
@@ -1278,13 +1386,13 @@ hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* 
     std::vector<uint32_t> jpart0((size_t)bp.njobs + 1);
     std::vector<int32_t> jbits((size_t)bp.njobs);
     std::vector<SideItem> itemsR((size_t)bp.nItemsR), itemsS((size_t)bp.nItemsS);
-    uint32_t part0 = 0, offsR = 0, offsS = 0;
+    uint32_t part0 = 0;
     size_t iR = 0, iS = 0;
     for (int j = 0; j < bp.njobs; ++j) {
         const int b = job_bits(jobs[j], bp.cap);
         jpart0[j] = part0;
         jbits[j] = b;
-        auto add = [&](const join_rel_t& X, std::vector<SideItem>& items, size_t& i, uint32_t& offs) {
+        auto add = [&](const join_rel_t& X, std::vector<SideItem>& items, size_t& i) {
             for (int64_t beg = 0; beg < X.n; beg += kBatchChunk) {
                 SideItem it{};
                 it.key = X.key;
@@ -1293,13 +1401,11 @@ hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* 
                 it.len = (uint32_t)(X.n - beg < kBatchChunk ? X.n - beg : kBatchChunk);
                 it.bits = b;
                 it.part0 = part0;
-                it.offs0 = offs;
-                offs += 1u << b;
                 items[i++] = it;
             }
         };
-        add(jobs[j].R, itemsR, iR, offsR);
-        add(jobs[j].S, itemsS, iS, offsS);
+        add(jobs[j].R, itemsR, iR);
+        add(jobs[j].S, itemsS, iS);
         part0 += 1u << b;
     }
     jpart0[bp.njobs] = part0;
@@ -1364,29 +1470,32 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     uint32_t* totS = totR + bp.nParts;
     uint32_t* baseR = reinterpret_cast<uint32_t*>(ws + bp.off_baseR);
     uint32_t* baseS = reinterpret_cast<uint32_t*>(ws + bp.off_baseS);
-    uint32_t* offsR = reinterpret_cast<uint32_t*>(ws + bp.off_offsR);
-    uint32_t* offsS = reinterpret_cast<uint32_t*>(ws + bp.off_offsS);
+    uint32_t* grpR = totS + bp.nParts;
+    uint32_t* grpS = grpR + kGroups * bp.nParts;
     int2* tupR = reinterpret_cast<int2*>(ws + bp.off_tupR);
     int2* tupS = reinterpret_cast<int2*>(ws + bp.off_tupS);
     uint32_t* units = reinterpret_cast<uint32_t*>(ws + bp.off_units);
     const SideItem none{};
     if (bp.nParts > 0) {
         prof::Scope pz(st, "hash.plan");
-        zero_u32_k<<<(unsigned)ceil_div(2 * bp.nParts, 256), 256, 0, st>>>(totR, 2 * bp.nParts);
+        const int64_t nz = (2 + 2 * kGroups) * bp.nParts;
+        zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(totR, nz);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hist_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, totR, offsR, st, true);
+    e = hist_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, totR, grpR, bp.nParts, st, true);
     if (e != hipSuccess) return e;
-    e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, offsS, st, false);
+    e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, grpS, bp.nParts, st, false);
     if (e != hipSuccess) return e;
     e = exclusive_scan<uint32_t>(totR, baseR, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+    if (e == hipSuccess) e = cursors_side(grpR, baseR, bp.nParts, st);
     if (e != hipSuccess) return e;
     e = exclusive_scan<uint32_t>(totS, baseS, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
+    if (e == hipSuccess) e = cursors_side(grpS, baseS, bp.nParts, st);
     if (e != hipSuccess) return e;
-    e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, baseR, offsR, tupR, st, true);
+    e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, grpR, bp.nParts, tupR, st, true);
     if (e != hipSuccess) return e;
-    e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, baseS, offsS, tupS, st, false);
+    e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, grpS, bp.nParts, tupS, st, false);
     if (e != hipSuccess) return e;
     {
         prof::Scope pp(st, "hash.plan");

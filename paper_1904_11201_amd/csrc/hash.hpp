@@ -18,7 +18,6 @@ struct SideItem {
     uint32_t len;        // rows in the chunk
     int32_t bits;        // the join's fan-out
     uint32_t part0;      // the join's first partition in the partition arrays
-    uint32_t offs0;      // start of this chunk's 2^bits entries in the offsets array
 };
 
 // Everything the count and write kernels need to walk the work units.
@@ -52,7 +51,7 @@ struct HashPlan {
     int64_t chR, chS, nChR, nChS;
     int64_t Umax;
     int gridCount, gridWrite;  // persistent grids of the count and write kernels
-    size_t off_tot, off_baseR, off_baseS, off_offsR, off_offsS, off_tupR, off_tupS;
+    size_t off_tot, off_grpR, off_grpS, off_baseR, off_baseS, off_tupR, off_tupS;
     size_t off_info, off_units, off_umap;
     size_t off_counts, off_temp, bytes;
 };
@@ -73,7 +72,7 @@ struct BuildPlan {
     int64_t nR;
     int32_t bits, P;
     int64_t chR, nChR;
-    uint64_t off_tot, off_base, off_offs, off_tup, off_temp, bytes;
+    uint64_t off_tot, off_base, off_tup, off_temp, bytes;
 };
 
 BuildPlan hash_build_plan(int64_t nR, int num_cus);
@@ -93,9 +92,9 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
 // by the caller as an opaque join_batch_plan_t between the prepare, count and write calls.
 struct BatchPlan {
     int32_t njobs, maxBits, cap, slice;
-    int64_t nParts, nItemsR, nItemsS, offsR, offsS, sumR, sumS, Umax;
+    int64_t nParts, nItemsR, nItemsS, sumR, sumS, Umax;
     uint64_t off_jpart0, off_jbits, off_itemsR, off_itemsS, off_tot, off_baseR, off_baseS;
-    uint64_t off_offsR, off_offsS, off_tupR, off_tupS, off_info, off_units, off_umap;
+    uint64_t off_tupR, off_tupS, off_info, off_units, off_umap;
     uint64_t off_counts, off_temp, bytes;
     int32_t gridCount, gridWrite;
 };
