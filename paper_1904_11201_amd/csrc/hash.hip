@@ -743,55 +743,87 @@ __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, u
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
         const bool ok = full || e < un.sN;
         const uint32_t idx = un.sBeg + (ok ? e : 0u);
+        // no select on the loaded values: the probe masks the out-of-range lanes, and a select
+        // here would wait for the loads
         if constexpr (AOS) {
             const int2 t = g.st[idx];
-            x[i] = ok ? (uint32_t)t.x : 0u;
-            r[i] = ok ? t.y : 0;
+            x[i] = (uint32_t)t.x;
+            r[i] = t.y;
         } else {
-            x[i] = ok ? (uint32_t)g.sk[idx] : 0u;
-            r[i] = ok ? (g.sr ? g.sr[idx] : (int32_t)idx) : 0;
+            x[i] = (uint32_t)g.sk[idx];
+            r[i] = g.sr ? g.sr[idx] : (int32_t)idx;
         }
     }
 }
 
+// A batch of S keys of a unit with un.sN > 0.  Out-of-range lanes read the unit's first tuple and
+// drop it (the probe masks them), so the loads carry no branch.
 template <bool AOS>
-__device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
-                                          uint32_t (&xs)[kCountBatch])
+__device__ __forceinline__ void load_keys_of(const JoinGeom& g, const Unit& un, uint32_t e0,
+                                             uint32_t (&xs)[kCountBatch])
 {
-    // Out-of-range lanes read the unit's first tuple (every unit with probes has one) and drop it,
-    // so the loads carry no branch.
     const bool full = e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN;  // uniform
-    if (un.sN == 0) {  // no tuple to stand in for the out-of-range lanes
-#pragma unroll
-        for (int i = 0; i < kCountBatch; ++i) xs[i] = 0u;
-        return;
-    }
 #pragma unroll
     for (int i = 0; i < kCountBatch; ++i) {
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
         const bool ok = full || e < un.sN;
         const uint32_t idx = un.sBeg + (ok ? e : 0u);
-        uint32_t v;
-        if constexpr (AOS) v = (uint32_t)g.st[idx].x;
-        else v = (uint32_t)g.sk[idx];
-        xs[i] = ok ? v : 0u;
+        // no select on the loaded value: the probe masks the out-of-range lanes
+        if constexpr (AOS) xs[i] = (uint32_t)g.st[idx].x;
+        else xs[i] = (uint32_t)g.sk[idx];
     }
 }
 
-// Count pass.  A workgroup walks units u = blockIdx.x, + gridDim.x, ...  The first S batch of a
-// unit is in flight while its table is built, each later batch while the previous one probes,
-// and the next unit's first batch while the last one probes.
+// The same for any unit: a unit without probes loads nothing.
+template <bool AOS>
+__device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
+                                          uint32_t (&xs)[kCountBatch])
+{
+    if (un.sN == 0) {
+#pragma unroll
+        for (int i = 0; i < kCountBatch; ++i) xs[i] = 0u;
+        return;
+    }
+    load_keys_of<AOS>(g, un, e0, xs);
+}
+
+// Count pass.  A workgroup walks units u = blockIdx.x, + gridDim.x, ...  The S keys come in
+// batches of kCountBatch per thread through two register buffers used in turn: while one batch
+// is probed the next is in flight, and the next unit's first batch while the last one probes.
+// Every half of the loop issues the same loads (a batch past the unit reloads a valid one), and
+// the buffers swap roles instead of being copied, so the wait before a probe is for that
+// batch's loads alone, never for the loads issued after them.
+template <bool AOS>
+__device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
+                                                const uint32_t (&xs)[kCountBatch])
+{
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int h = 0; h < kCountBatch; h += kProbe) {
+        uint32_t x[kProbe];
+        bool ok[kProbe];
+#pragma unroll
+        for (int i = 0; i < kProbe; ++i) {
+            x[i] = xs[h + i];
+            ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+        }
+        cnt += probe_count<kProbe, AOS>(t, un.bits, x, ok);
+    }
+    return cnt;
+}
+
 template <bool AOS>
 __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
 {
     extern __shared__ uint4 tab[];
     __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
+    constexpr uint32_t kB = kJoinBlock * kCountBatch;  // keys per batch
     const uint32_t U = unit_total(g);
-    uint32_t xs[kCountBatch];
+    uint32_t xa[kCountBatch], xb[kCountBatch];
     Unit un{};
     if (blockIdx.x < U) {
         un = decode_unit(g, blockIdx.x);
-        load_keys<AOS>(g, un, 0, xs);
+        load_keys<AOS>(g, un, 0, xa);
     }
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         Chunk<false> ch;
@@ -800,25 +832,15 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         const bool more = u + gridDim.x < U;
         const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
         uint32_t cnt = 0;
-        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kCountBatch) {
-            uint32_t cur[kCountBatch];
-#pragma unroll
-            for (int i = 0; i < kCountBatch; ++i) cur[i] = xs[i];
-            if (e0 + kJoinBlock * kCountBatch < un.sN) load_keys<AOS>(g, un, e0 + kJoinBlock * kCountBatch, xs);
-            else if (more) load_keys<AOS>(g, nx, 0, xs);
-#pragma unroll
-            for (int h = 0; h < kCountBatch; h += kProbe) {
-                uint32_t x[kProbe];
-                bool ok[kProbe];
-#pragma unroll
-                for (int i = 0; i < kProbe; ++i) {
-                    x[i] = cur[h + i];
-                    ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
-                }
-                cnt += probe_count<kProbe, AOS>(t, un.bits, x, ok);
-            }
+        for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
+            const uint32_t e1 = e0 + kB, e2 = e1 + kB;
+            load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
+            cnt += count_batch<AOS>(t, un, e0, xa);
+            const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
+            load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
+            cnt += count_batch<AOS>(t, un, e1, xb);  // every lane masked past the unit
         }
-        if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xs);
+        if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
         uint32_t tot;
         block_excl_scan<kJoinBlock>(cnt, wsum, &tot);
         if (threadIdx.x == 0) counts[u] = tot;
