@@ -3,8 +3,8 @@
 // This is the "scan" of count -> scan -> write: the per-work-unit match counts become exact
 // output offsets on the device (the compaction the paper leaves unspecified when it says the
 // per-thread results are "summed", Section 3.3.1), and radix histograms become partition
-// offsets.  Three launches for n > one tile: per-tile sums, a single-workgroup scan of the tile
-// sums, and a per-tile scan seeded with its prefix.  n <= one tile uses one launch.
+// offsets.  Three launches for n > kSingleTiles tiles: per-tile sums, a single-workgroup scan of
+// the tile sums, and a per-tile scan seeded with its prefix.  Fewer tiles use one launch.
 #include "scan.hpp"
 
 #include "prof.hpp"
@@ -16,6 +16,8 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanItems;  // 4096 values per workgroup
+// Up to this many tiles one workgroup scans them in turn: cheaper than three launches.
+constexpr int64_t kSingleTiles = 4;
 
 template <typename T>
 __device__ __forceinline__ T wave_scan_t(T x);
@@ -115,7 +117,7 @@ template <typename T>
 size_t scan_temp_elems(int64_t n)
 {
     int64_t tiles = ceil_div(n, kScanTile);
-    return tiles <= 1 ? 0 : (size_t)tiles;
+    return tiles <= kSingleTiles ? 0 : (size_t)tiles;
 }
 
 template <typename T>
@@ -124,7 +126,7 @@ hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* total, T* temp, hip
     if (n < 0) n = 0;
     prof::Scope ps(st, sizeof(T) == 8 ? "scan.u64" : "scan.u32");
     int64_t tiles = ceil_div(n, kScanTile);
-    if (tiles <= 1) {  // also n == 0: writes *total = 0 without a memset node
+    if (tiles <= kSingleTiles) {  // also n == 0: writes *total = 0 without a memset node
         scan_single_k<T><<<1, kScanBlock, 0, st>>>(in, out, n, total);
         return hipGetLastError();
     }
