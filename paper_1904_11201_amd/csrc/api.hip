@@ -190,6 +190,38 @@ uint64_t* pinned_slot()
     return slot;
 }
 
+// The exact total, device -> pinned slot -> *count.  The host waits by polling an event instead
+// of a blocking stream synchronisation: the total is on the critical path of every join (the
+// output is allocated from it before the write pass), and a blocking wait adds the host thread's
+// wake-up to that path.
+hipError_t read_total(const void* src, hipStream_t st, uint64_t* count)
+{
+    uint64_t* slot = pinned_slot();
+    if (!slot) return hipErrorOutOfMemory;
+    static thread_local struct {
+        int dev = -1;
+        hipEvent_t ev = nullptr;
+    } w;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (w.dev != dev) {  // an event belongs to the device current when it was made
+        if (w.ev) (void)hipEventDestroy(w.ev);
+        w.ev = nullptr;
+        if (hipEventCreateWithFlags(&w.ev, hipEventDisableTiming) != hipSuccess) w.ev = nullptr;
+        w.dev = dev;
+    }
+    e = hipMemcpyAsync(slot, src, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    if (w.ev && hipEventRecord(w.ev, st) == hipSuccess) {
+        while ((e = hipEventQuery(w.ev)) == hipErrorNotReady) __builtin_ia32_pause();
+    } else {
+        e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess) *count = *slot;
+    return e;
+}
+
 int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
                hipStream_t st, uint64_t* count)
 {
@@ -214,14 +246,8 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
             e = theta_count(pl, *R, *S, *p, w, st);
         }
         if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
-        uint64_t* slot = pinned_slot();
-        if (!slot) {
-            set_error("hipHostMalloc of the 8-byte count slot failed");
-            return JOIN_E_HIP;
-        }
-        JL_HIP(hipMemcpyAsync(slot, w + total_at, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        JL_HIP(hipStreamSynchronize(st));
-        *count = *slot;
+        e = read_total(w + total_at, st, count);
+        if (e != hipSuccess) return hip_fail(e, "reading the exact total");
     }
     g_last.valid = true;
     g_last.kind = kind;
@@ -544,14 +570,8 @@ int join_probe_count(const join_build_t* desc, const void* build, const join_rel
         const RView v = build_view(b, build);
         const hipError_t e = hash_count(pl, R, *S, static_cast<char*>(ws), st, &v);
         if (e != hipSuccess) return hip_fail(e, "probe count pass");
-        uint64_t* slot = pinned_slot();
-        if (!slot) {
-            set_error("hipHostMalloc of the 8-byte count slot failed");
-            return JOIN_E_HIP;
-        }
-        JL_HIP(hipMemcpyAsync(slot, ws, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        JL_HIP(hipStreamSynchronize(st));
-        *count = *slot;
+        const hipError_t er = read_total(ws, st, count);
+        if (er != hipSuccess) return hip_fail(er, "reading the exact total");
     }
     g_last_probe.valid = true;
     g_last_probe.build = build;

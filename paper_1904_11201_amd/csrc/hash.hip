@@ -365,11 +365,53 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
 // Per partition: its ranges in the partitioned tuples and its work units.  In a batch the
 // partition's join (and so its fan-out) is found by binary search over the joins' first
 // partitions jpart0[0..nJobs]; a single join passes jpart0 = NULL and its own fan-out.
-__global__ void plan_units_k(const uint32_t* __restrict__ baseR, const uint32_t* __restrict__ totR,
-                             const uint32_t* __restrict__ baseS, const uint32_t* __restrict__ totS,
-                             int nParts, const uint32_t* __restrict__ jpart0,
-                             const int32_t* __restrict__ jbits, int nJobs, int bits, uint32_t cap,
-                             uint32_t slice, PartInfo* __restrict__ info, uint32_t* __restrict__ units)
+// The plan of partition p: its PartInfo and its number of units.
+struct PartPlan {
+    const uint32_t* baseR;
+    const uint32_t* totR;
+    const uint32_t* baseS;
+    const uint32_t* totS;
+    const uint32_t* jpart0;
+    const int32_t* jbits;
+    int nJobs, bits;
+    uint32_t cap, slice;
+};
+
+__device__ __forceinline__ uint32_t plan_part(const PartPlan& q, int p, PartInfo& pi)
+{
+    int bits = q.bits;
+    if (q.jpart0) {
+        int lo = 0, hi = q.nJobs - 1;  // last job whose first partition is <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.jpart0[mid] <= (uint32_t)p) lo = mid;
+            else hi = mid - 1;
+        }
+        bits = q.jbits[lo];
+    }
+    const uint32_t nr = q.totR[p], ns = q.totS[p];
+    const uint32_t nrc = (nr + q.cap - 1) / q.cap;
+    uint32_t nss = 0;
+    if (nr > 0 && ns > 0) {
+        // rounded, not ceiled: a partition a little over the slice stays one slice (an S slice
+        // costs a table build, and partitions of a uniform S sit around the mean)
+        const uint64_t per = (uint64_t)q.slice * nrc;
+        nss = (uint32_t)((ns + per / 2) / per);
+        if (nss < 1) nss = 1;
+    }
+    pi.rStart = q.baseR[p];
+    pi.nR = nr;
+    pi.sStart = q.baseS[p];
+    pi.nS = ns;
+    pi.nSs = nss;
+    pi.nRc = nrc;
+    pi.bits = (uint32_t)bits;
+    pi.pad = 0;
+    return nrc * nss;
+}
+
+__global__ void plan_units_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
+                             uint32_t* __restrict__ units)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > nParts) return;
@@ -377,34 +419,9 @@ __global__ void plan_units_k(const uint32_t* __restrict__ baseR, const uint32_t*
         units[nParts] = 0;
         return;
     }
-    if (jpart0) {
-        int lo = 0, hi = nJobs - 1;  // last job whose first partition is <= p
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jpart0[mid] <= (uint32_t)p) lo = mid;
-            else hi = mid - 1;
-        }
-        bits = jbits[lo];
-    }
-    const uint32_t nr = totR[p], ns = totS[p];
-    const uint32_t nrc = (nr + cap - 1) / cap;
-    uint32_t nss = 0;
-    if (nr > 0 && ns > 0) {
-        const uint64_t per = (uint64_t)slice * nrc;
-        nss = (uint32_t)((ns + per - 1) / per);
-        if (nss < 1) nss = 1;
-    }
     PartInfo pi;
-    pi.rStart = baseR[p];
-    pi.nR = nr;
-    pi.sStart = baseS[p];
-    pi.nS = ns;
-    pi.nSs = nss;
-    pi.nRc = nrc;
-    pi.bits = (uint32_t)bits;
-    pi.pad = 0;
+    units[p] = plan_part(q, p, pi);
     info[p] = pi;
-    units[p] = nrc * nss;
 }
 
 // Unit -> partition map: partition p owns units [unitStart[p], unitStart[p + 1]).
@@ -415,6 +432,88 @@ __global__ void expand_units_k(const uint32_t* __restrict__ unitStart, int P, in
     if (p >= P) return;
     for (uint32_t u = unitStart[p]; u < unitStart[p + 1] && (int64_t)u < Umax; ++u)
         umap[u] = (uint32_t)p;
+}
+
+// One workgroup for up to kFuseParts partitions, in place of several launches of a few
+// microseconds each.  part_starts_k: each side's partition starts (exclusive scan of the sizes)
+// and group cursors; a NULL tot skips that side.  plan_k: the plans, the units' exclusive scan
+// (unitStart[0..nParts], the total also at *Utotal) and the unit -> partition map.
+constexpr int kFuseBlock = 1024;
+constexpr int kFuseParts = 8192;
+
+__device__ __forceinline__ void group_cursors(uint32_t* __restrict__ grp, uint32_t stride, int p, uint32_t run)
+{
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const uint32_t c = grp[(size_t)g * stride + p];
+        grp[(size_t)g * stride + p] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kFuseBlock) void part_starts_k(const uint32_t* __restrict__ totR,
+                                                            uint32_t* __restrict__ baseR,
+                                                            uint32_t* __restrict__ grpR,
+                                                            const uint32_t* __restrict__ totS,
+                                                            uint32_t* __restrict__ baseS,
+                                                            uint32_t* __restrict__ grpS,
+                                                            uint32_t stride, int n)
+{
+    __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
+    for (int side = 0; side < 2; ++side) {
+        const uint32_t* tot = side ? totS : totR;
+        uint32_t* base = side ? baseS : baseR;
+        uint32_t* grp = side ? grpS : grpR;
+        if (!tot) continue;
+        uint32_t carry = 0;
+        for (int b0 = 0; b0 < n; b0 += 2 * kFuseBlock) {
+            const int pa = b0 + 2 * (int)threadIdx.x, pb = pa + 1;
+            const uint32_t ca = pa < n ? tot[pa] : 0u, cb = pb < n ? tot[pb] : 0u;
+            uint32_t t;
+            const uint32_t sa = carry + block_excl_scan<kFuseBlock>(ca + cb, tmp, &t);
+            if (pa < n) {
+                base[pa] = sa;
+                group_cursors(grp, stride, pa, sa);
+            }
+            if (pb < n) {
+                base[pb] = sa + ca;
+                group_cursors(grp, stride, pb, sa + ca);
+            }
+            carry += t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFuseBlock) void plan_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
+                                                     uint32_t* __restrict__ unitStart,
+                                                     uint32_t* __restrict__ Utotal, int64_t Umax,
+                                                     uint32_t* __restrict__ umap)
+{
+    __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nParts; b0 += 2 * kFuseBlock) {
+        const int pa = b0 + 2 * (int)threadIdx.x, pb = pa + 1;
+        PartInfo ia{}, ib{};
+        const uint32_t ua = pa < nParts ? plan_part(q, pa, ia) : 0u;
+        const uint32_t ub = pb < nParts ? plan_part(q, pb, ib) : 0u;
+        uint32_t t;
+        const uint32_t sa = carry + block_excl_scan<kFuseBlock>(ua + ub, tmp, &t);
+        if (pa < nParts) {
+            info[pa] = ia;
+            unitStart[pa] = sa;
+            for (uint32_t u = sa; u < sa + ua && (int64_t)u < Umax; ++u) umap[u] = (uint32_t)pa;
+        }
+        if (pb < nParts) {
+            info[pb] = ib;
+            unitStart[pb] = sa + ua;
+            for (uint32_t u = sa + ua; u < sa + ua + ub && (int64_t)u < Umax; ++u) umap[u] = (uint32_t)pb;
+        }
+        carry += t;
+    }
+    if (threadIdx.x == 0) {
+        unitStart[nParts] = carry;
+        *Utotal = carry;
+    }
 }
 
 // ------------------------------------------------------------------------- join work units --
@@ -1111,6 +1210,53 @@ static hipError_t cursors_side(uint32_t* grp, const uint32_t* base, int64_t stri
     return hipGetLastError();
 }
 
+// Partition starts and group cursors of both sides (a NULL totR or totS skips that side): one
+// launch up to kFuseParts partitions, else a scan and a cursor kernel per side.
+static hipError_t starts_sides(const uint32_t* totR, uint32_t* baseR, uint32_t* grpR,
+                               const uint32_t* totS, uint32_t* baseS, uint32_t* grpS, int64_t n,
+                               uint32_t* temp, hipStream_t st)
+{
+    if (n <= kFuseParts) {
+        prof::Scope pc(st, "hash.plan");
+        part_starts_k<<<1, kFuseBlock, 0, st>>>(totR, baseR, grpR, totS, baseS, grpS, (uint32_t)n, (int)n);
+        return hipGetLastError();
+    }
+    hipError_t e = hipSuccess;
+    if (totR) {
+        e = exclusive_scan<uint32_t>(totR, baseR, n, nullptr, temp, st);
+        if (e == hipSuccess) e = cursors_side(grpR, baseR, n, st);
+    }
+    if (e == hipSuccess && totS) {
+        e = exclusive_scan<uint32_t>(totS, baseS, n, nullptr, temp, st);
+        if (e == hipSuccess) e = cursors_side(grpS, baseS, n, st);
+    }
+    return e;
+}
+
+// Per-partition plans, unit starts (total at *Utotal) and the unit -> partition map.
+static hipError_t plan_parts(const PartPlan& q, int64_t nParts, PartInfo* info, uint32_t* units,
+                             uint32_t* Utotal, int64_t Umax, uint32_t* umap, uint32_t* temp,
+                             hipStream_t st)
+{
+    if (nParts <= kFuseParts) {
+        prof::Scope pp(st, "hash.plan");
+        plan_k<<<1, kFuseBlock, 0, st>>>(q, (int)nParts, info, units, Utotal, Umax, umap);
+        return hipGetLastError();
+    }
+    {
+        prof::Scope pp(st, "hash.plan");
+        plan_units_k<<<(unsigned)ceil_div(nParts + 1, 256), 256, 0, st>>>(q, (int)nParts, info, units);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = exclusive_scan<uint32_t>(units, units, nParts + 1, Utotal, temp, st);
+    if (e != hipSuccess) return e;
+    {
+        prof::Scope pe(st, "hash.plan");
+        expand_units_k<<<(unsigned)ceil_div(nParts, 256), 256, 0, st>>>(units, (int)nParts, Umax, umap);
+    }
+    return hipGetLastError();
+}
+
 static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
                                int64_t grid, int maxBits, uint32_t* cur, int64_t stride, int2* out,
                                hipStream_t st, bool is_r)
@@ -1192,13 +1338,8 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         }
         e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, st, false);
         if (e != hipSuccess) return e;
-        if (!pre) {
-            e = exclusive_scan<uint32_t>(totR, baseR, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
-            if (e == hipSuccess) e = cursors_side(grpR, baseR, pl.P, st);
-            if (e != hipSuccess) return e;
-        }
-        e = exclusive_scan<uint32_t>(totS, baseS, pl.P, nullptr, reinterpret_cast<uint32_t*>(temp), st);
-        if (e == hipSuccess) e = cursors_side(grpS, baseS, pl.P, st);
+        e = starts_sides(pre ? nullptr : totR, baseR, grpR, totS, baseS, grpS, pl.P,
+                         reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
         if (!pre) {
             e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, grpR, pl.P, tupR, st, true);
@@ -1208,24 +1349,12 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         if (e != hipSuccess) return e;
         const uint32_t* pbaseR = pre ? pre->base : baseR;
         const uint32_t* ptotR = pre ? pre->tot : totR;
-        uint32_t* units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
-        {
-            prof::Scope pp(st, "hash.plan");
-            plan_units_k<<<(unsigned)ceil_div(pl.P + 1, 256), 256, 0, st>>>(
-                pbaseR, ptotR, baseS, totS, pl.P, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
-                (uint32_t)pl.slice, reinterpret_cast<PartInfo*>(ws + pl.off_info), units);
-        }
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = exclusive_scan<uint32_t>(units, units, pl.P + 1, reinterpret_cast<uint32_t*>(ws + 8),
-                                     reinterpret_cast<uint32_t*>(temp), st);
-        if (e != hipSuccess) return e;
-        {
-            prof::Scope pe(st, "hash.plan");
-            expand_units_k<<<(unsigned)ceil_div(pl.P, 256), 256, 0, st>>>(
-                units, pl.P, pl.Umax, reinterpret_cast<uint32_t*>(ws + pl.off_umap));
-        }
-        e = hipGetLastError();
+        PartPlan q{pbaseR, ptotR, baseS, totS, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
+                   (uint32_t)pl.slice};
+        e = plan_parts(q, pl.P, reinterpret_cast<PartInfo*>(ws + pl.off_info),
+                       reinterpret_cast<uint32_t*>(ws + pl.off_units), reinterpret_cast<uint32_t*>(ws + 8),
+                       pl.Umax, reinterpret_cast<uint32_t*>(ws + pl.off_umap),
+                       reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
     }
     if (pl.Umax > 0) {
@@ -1314,8 +1443,8 @@ hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipS
     const SideItem one = whole_side(R, b.bits);
     e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, grp, b.P, st, true);
     if (e != hipSuccess) return e;
-    e = exclusive_scan<uint32_t>(tot, base, b.P, nullptr, reinterpret_cast<uint32_t*>(build + b.off_temp), st);
-    if (e == hipSuccess) e = cursors_side(grp, base, b.P, st);
+    e = starts_sides(tot, base, grp, nullptr, nullptr, nullptr, b.P,
+                     reinterpret_cast<uint32_t*>(build + b.off_temp), st);
     if (e != hipSuccess) return e;
     return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, grp, b.P, tup, st, true);
 }
@@ -1509,33 +1638,16 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (e != hipSuccess) return e;
     e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, grpS, bp.nParts, st, false);
     if (e != hipSuccess) return e;
-    e = exclusive_scan<uint32_t>(totR, baseR, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
-    if (e == hipSuccess) e = cursors_side(grpR, baseR, bp.nParts, st);
-    if (e != hipSuccess) return e;
-    e = exclusive_scan<uint32_t>(totS, baseS, bp.nParts, nullptr, reinterpret_cast<uint32_t*>(temp), st);
-    if (e == hipSuccess) e = cursors_side(grpS, baseS, bp.nParts, st);
+    e = starts_sides(totR, baseR, grpR, totS, baseS, grpS, bp.nParts, reinterpret_cast<uint32_t*>(temp), st);
     if (e != hipSuccess) return e;
     e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, grpR, bp.nParts, tupR, st, true);
     if (e != hipSuccess) return e;
     e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, grpS, bp.nParts, tupS, st, false);
     if (e != hipSuccess) return e;
-    {
-        prof::Scope pp(st, "hash.plan");
-        plan_units_k<<<(unsigned)ceil_div(bp.nParts + 1, 256), 256, 0, st>>>(
-            baseR, totR, baseS, totS, (int)bp.nParts, jpart0, jbits, bp.njobs, 0, (uint32_t)bp.cap,
-            (uint32_t)bp.slice, reinterpret_cast<PartInfo*>(ws + bp.off_info), units);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = exclusive_scan<uint32_t>(units, units, bp.nParts + 1, reinterpret_cast<uint32_t*>(ws + 8),
-                                 reinterpret_cast<uint32_t*>(temp), st);
-    if (e != hipSuccess) return e;
-    if (bp.nParts > 0) {
-        prof::Scope pe(st, "hash.plan");
-        expand_units_k<<<(unsigned)ceil_div(bp.nParts, 256), 256, 0, st>>>(
-            units, (int)bp.nParts, bp.Umax, reinterpret_cast<uint32_t*>(ws + bp.off_umap));
-    }
-    e = hipGetLastError();
+    PartPlan q{baseR, totR, baseS, totS, jpart0, jbits, bp.njobs, 0, (uint32_t)bp.cap, (uint32_t)bp.slice};
+    e = plan_parts(q, bp.nParts, reinterpret_cast<PartInfo*>(ws + bp.off_info), units,
+                   reinterpret_cast<uint32_t*>(ws + 8), bp.Umax, reinterpret_cast<uint32_t*>(ws + bp.off_umap),
+                   reinterpret_cast<uint32_t*>(temp), st);
     if (e != hipSuccess) return e;
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
