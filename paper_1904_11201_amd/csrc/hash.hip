@@ -187,14 +187,16 @@ __global__ void group_cursors_k(uint32_t* __restrict__ grp, const uint32_t* __re
 __device__ __forceinline__ int scat_pos(int q) { return 4 * ((q >> 2) * kScatBlock + (int)threadIdx.x) + (q & 3); }
 
 // Loads of a tile's keys or rids: FULL tiles read whole 16-byte vectors; a partial tile (a
-// chunk's last) reads element by element.
+// chunk's last) reads the vectors that lie inside it when the column is 16-byte aligned (vec),
+// and the rest element by element.
 template <bool FULL>
-__device__ __forceinline__ void scat_load(gptr<int32_t> col, int t0, int tn, int32_t (&x)[kScatIt])
+__device__ __forceinline__ void scat_load(gptr<int32_t> col, int t0, int tn, int32_t (&x)[kScatIt],
+                                          bool vec = true)
 {
 #pragma unroll
     for (int v = 0; v < kScatIt / 4; ++v) {
         const int e = scat_pos(4 * v);
-        if (FULL) {
+        if (FULL || (vec && e + 4 <= tn)) {
             const i32x4 x4 = load4(col + t0 + e);
             x[4 * v] = x4.x; x[4 * v + 1] = x4.y; x[4 * v + 2] = x4.z; x[4 * v + 3] = x4.w;
         } else {
@@ -323,8 +325,8 @@ __device__ __forceinline__ void scat_chunk(gptr<int32_t> key, gptr<int32_t> rid,
     for (int t0 = nfull * kScatTile; t0 < end; t0 += kScatTile) {
         const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
         int32_t k[kScatIt], r[kScatIt];
-        scat_load<false>(key, t0, tn, k);
-        if (RIDS) scat_load<false>(rid, t0, tn, r);
+        scat_load<false>(key, t0, tn, k, vec);
+        if (RIDS) scat_load<false>(rid, t0, tn, r, vec);
         scat_tile<RIDS, false>(k, r, tn, beg + t0, P, sh, L, cur, out);
     }
 }

@@ -94,6 +94,55 @@ def test_partitioned_path_and_fanouts(monkeypatch):
         assert len(got) == n and np.array_equal(got, ref), bits
 
 
+def _offset_rel(rel, shift, with_rid=True):
+    """The relation's columns as device views starting `shift` int32 past a buffer's start, so
+    that they are not 16-byte aligned."""
+    from paper_1904_11201_amd.join import Relation
+
+    def d(a):
+        if a is None:
+            return None
+        buf = torch.zeros(len(a) + shift, dtype=torch.int32, device="cuda")
+        buf[shift:] = torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+        return buf[shift:]
+
+    return Relation(d(rel.key), None, d(rel.rid) if with_rid else None)
+
+
+@gpu
+@pytest.mark.parametrize("kshift,with_rid", [(1, True), (0, True), (3, False), (2, True)])
+def test_unaligned_columns_and_partial_tiles(monkeypatch, kshift, with_rid):
+    """Columns that start off a 16-byte boundary take the element-by-element loads of the
+    histogram and scatter; sizes that are not a whole number of scatter tiles take the partial
+    tile path; both at a large and a small fan-out."""
+    from paper_1904_11201_amd.join import hash_join
+    need_gpu()
+    R, S = datagen.small_random(23 + kshift, 70_001, 4 * 16384 * 3 + 4097, 0, 60_000, rid_mode="random")
+    rr = R.rid if with_rid else None
+    sr = S.rid if with_rid else None
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=rr, Srid=sr)
+    for bits in ("11", "3"):
+        monkeypatch.setenv("JOIN_HASH_BITS", bits)
+        log(f"hash offset views shift={kshift} rid={with_rid} bits={bits}")
+        got = canon_gpu(hash_join(_offset_rel(R, kshift, with_rid), _offset_rel(S, kshift, with_rid)))
+        assert len(got) == n and np.array_equal(got, ref), (kshift, bits)
+
+
+@gpu
+@pytest.mark.parametrize("with_rid", [False, True])
+def test_full_scatter_tiles_with_and_without_rids(with_rid):
+    """Sides large enough for whole scatter tiles in every chunk (and a partial tile after
+    them), with rid columns and with row positions."""
+    from paper_1904_11201_amd.join import hash_join
+    need_gpu()
+    R, S = datagen.small_random(29, 1_200_001, 5_000_003, 0, 1_000_000,
+                                rid_mode="random" if with_rid else "none")
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
+    log(f"hash 1.2M x 5M rid={with_rid}")
+    got = canon_gpu(hash_join(dev_rel(R, with_rid), dev_rel(S, with_rid)))
+    assert len(got) == n and np.array_equal(got, ref)
+
+
 @gpu
 def test_lds_overflow_chunked_build(monkeypatch):
     """A small table capacity forces several R chunks per partition (each probed by all of the
