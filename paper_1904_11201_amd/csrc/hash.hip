@@ -21,6 +21,7 @@
 // predicated compares, so a wave issues its LDS reads together and does not branch per key.
 #include "hash.hpp"
 
+#include <type_traits>
 #include <vector>
 
 #include "prof.hpp"
@@ -582,11 +583,20 @@ __device__ __forceinline__ void choices(uint32_t h, int bits, uint32_t nb, uint3
     b2 = b2 == b1 ? next_bucket(b1, nb) : b2;
 }
 
+// Marked tables.  A partitioned unit with a fan-out of at least 2 bits holds only hashes whose
+// two top bits are the partition's.  Its empty slots then hold a marker whose top bit differs
+// (no probe of the partition equals it), and a bucket that overflowed (more than 4 claims) has
+// bit 30 of its fourth key flipped: lookups read only the two key vectors, with no claim
+// counter, and recover the fourth key by comparing the other 31 bits.  Other units (the single
+// path's raw keys, batch joins of fan-out 0 or 1) compare against the claim counters.
+constexpr uint32_t kOverflow = 1u << 30;
+
 struct Table {
     const uint4* keys;    // [nb]: the 4 keys of each bucket
     const uint4* rids;    // [nb]: their rids (write pass only)
     const uint32_t* cnt;  // [nb]: claims; min(cnt, 4) slots are filled
     uint32_t nb;
+    bool marked;          // uniform
 };
 
 // LDS bytes of a table for chunks of up to `cap` entries: 16 bytes of keys per bucket, 16 of
@@ -646,7 +656,17 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
     uint32_t* keys = reinterpret_cast<uint32_t*>(lds);
     uint32_t* rids = reinterpret_cast<uint32_t*>(lds + nb);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
-    for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
+    const bool marked = HASHED && un.bits >= 2;
+    if (marked) {
+        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed)
+        const uint32_t m = (((uint32_t)g.rt[un.rBeg].x) ^ 0x80000000u) & 0xC0000000u;
+        for (uint32_t b = tid; b < nb; b += kJoinBlock) {
+            cnt[b] = 0;
+            lds[b] = make_uint4(m, m, m, m);
+        }
+    } else {
+        for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
@@ -673,39 +693,75 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
         }
     }
     __syncthreads();
+    if (marked) {  // flag the overflowed buckets, now that every slot is written
+        for (uint32_t b = tid; b < nb; b += kJoinBlock)
+            if (cnt[b] > (uint32_t)kSlots) keys[b * kSlots + 3] ^= kOverflow;
+        __syncthreads();
+    }
     Table t;
     t.keys = lds;
     t.rids = RIDS ? lds + nb : nullptr;
     t.cnt = cnt;
     t.nb = nb;
+    t.marked = marked;
     return t;
 }
 
-// Matches of x among the filled slots of one bucket, as a 4-bit mask.
+// Matches of x among the filled slots of one bucket, as a 4-bit mask (claim-counter tables).
 __device__ __forceinline__ uint32_t bucket_hits(const uint4& k, uint32_t c, uint32_t x)
 {
     return (uint32_t)(k.x == x && c > 0) | ((uint32_t)(k.y == x && c > 1) << 1) |
            ((uint32_t)(k.z == x && c > 2) << 2) | ((uint32_t)(k.w == x && c > 3) << 3);
 }
 
-// The walk past b1 and b2 (rare): buckets from b2 + 1 while the previous one holds more than 4
-// claims.  A walk that wraps onto b1 or b2 skips their slots, which were already counted.
-template <typename Visit>
+// The lookup primitives, for marked tables (MARKED) or claim-counter ones; callers choose the
+// variant once per unit, by a uniform branch around the whole probe.
+// A bucket's claim counter, read only for tables that are not marked.
+template <bool MARKED>
+__device__ __forceinline__ uint32_t claims(const Table& t, uint32_t b)
+{
+    if constexpr (MARKED) return 0u;
+    else return t.cnt[b];
+}
+
+// Matches of x in a bucket (k its keys, c its claims when not marked), as a 4-bit mask.
+template <bool MARKED>
+__device__ __forceinline__ uint32_t hits(const uint4& k, uint32_t c, uint32_t x)
+{
+    if constexpr (MARKED)
+        return (uint32_t)(k.x == x) | ((uint32_t)(k.y == x) << 1) | ((uint32_t)(k.z == x) << 2) |
+               ((uint32_t)(((k.w ^ x) & ~kOverflow) == 0u) << 3);
+    else return bucket_hits(k, c, x);
+}
+
+// Whether a bucket holds more than 4 claims, so that lookups go on past it.  In a marked table x
+// (a hash of the partition) tells the fourth key's true bit 30.
+template <bool MARKED>
+__device__ __forceinline__ bool overflowed(const uint4& k, uint32_t c, uint32_t x)
+{
+    if constexpr (MARKED) return ((k.w ^ x) & 0xC0000000u) == kOverflow;
+    else return c > (uint32_t)kSlots;
+}
+
+// The walk past b1 and b2 (rare): buckets from b2 + 1 while the previous one overflowed.  A walk
+// that wraps onto b1 or b2 skips their slots, which were already counted.
+template <bool MARKED, typename Visit>
 __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1, uint32_t b2, Visit visit)
 {
     uint32_t b = b2;
     while (true) {
         b = next_bucket(b, t.nb);
-        const uint32_t c = t.cnt[b];
-        if (b != b1 && b != b2) visit(b, bucket_hits(t.keys[b], c, x));
-        if (c <= (uint32_t)kSlots) break;
+        const uint32_t c = claims<MARKED>(t, b);
+        const uint4 k = t.keys[b];
+        if (b != b1 && b != b2) visit(b, hits<MARKED>(k, c, x));
+        if (!overflowed<MARKED>(k, c, x)) break;
     }
 }
 
 // Count the entries of N keys: read both candidate buckets of every key (all reads issued
 // together), count the matching slots with predicated arithmetic, and walk on only for keys
 // whose two buckets both overflowed.
-template <int N, bool HASHED>
+template <int N, bool HASHED, bool MARKED>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
                                                 const bool (&valid)[N])
 {
@@ -716,24 +772,25 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         k1[i] = t.keys[b1[i]];
-        c1[i] = t.cnt[b1[i]];
+        c1[i] = claims<MARKED>(t, b1[i]);
         k2[i] = t.keys[b2[i]];
-        c2[i] = t.cnt[b2[i]];
+        c2[i] = claims<MARKED>(t, b2[i]);
     }
     uint32_t n = 0;
-    bool walk = false;
+    bool walk[N], any = false;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const uint32_t h = __builtin_popcount(bucket_hits(k1[i], c1[i], x[i])) +
-                           __builtin_popcount(bucket_hits(k2[i], c2[i], x[i]));
+        const uint32_t h = __builtin_popcount(hits<MARKED>(k1[i], c1[i], x[i])) +
+                           __builtin_popcount(hits<MARKED>(k2[i], c2[i], x[i]));
         n += valid[i] ? h : 0u;
-        walk = walk || (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots);
+        walk[i] = valid[i] && overflowed<MARKED>(k1[i], c1[i], x[i]) && overflowed<MARKED>(k2[i], c2[i], x[i]);
+        any = any || walk[i];
     }
-    if (ballot(walk)) {
+    if (ballot(any)) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots)
-                walk_on(t, x[i], b1[i], b2[i], [&](uint32_t, uint32_t hm) { n += __builtin_popcount(hm); });
+            if (walk[i])
+                walk_on<MARKED>(t, x[i], b1[i], b2[i], [&](uint32_t, uint32_t hm) { n += __builtin_popcount(hm); });
     }
     return n;
 }
@@ -741,7 +798,7 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 // Probe N keys for the write pass: per key the number of entries and the LDS word positions of
 // the first two, whose rids are read once the output slots are known (a key with more than two
 // build matches visits its buckets again when it is written).
-template <int N, bool HASHED>
+template <int N, bool HASHED, bool MARKED>
 __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint32_t (&x)[N],
                                             const bool (&valid)[N], uint32_t (&m)[N],
                                             uint32_t (&p1)[N], uint32_t (&p2)[N])
@@ -753,28 +810,29 @@ __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         k1[i] = t.keys[b1[i]];
-        c1[i] = t.cnt[b1[i]];
+        c1[i] = claims<MARKED>(t, b1[i]);
         k2[i] = t.keys[b2[i]];
-        c2[i] = t.cnt[b2[i]];
+        c2[i] = claims<MARKED>(t, b2[i]);
     }
-    bool walk = false;
+    bool walk[N], any = false;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const uint32_t h1 = valid[i] ? bucket_hits(k1[i], c1[i], x[i]) : 0u;
-        const uint32_t h2 = valid[i] ? bucket_hits(k2[i], c2[i], x[i]) : 0u;
+        const uint32_t h1 = valid[i] ? hits<MARKED>(k1[i], c1[i], x[i]) : 0u;
+        const uint32_t h2 = valid[i] ? hits<MARKED>(k2[i], c2[i], x[i]) : 0u;
         // slots of the two buckets as one 8-bit mask: bit j < 4 is b1's slot j, bit 4 + j b2's
         const uint32_t hm = h1 | (h2 << 4);
         const uint32_t j1 = __builtin_ctz(hm | 256u), j2 = __builtin_ctz((hm & (hm - 1)) | 256u);
         p1[i] = j1 < 4 ? b1[i] * kSlots + j1 : b2[i] * kSlots + (j1 & 3);
         p2[i] = j2 < 4 ? b1[i] * kSlots + j2 : b2[i] * kSlots + (j2 & 3);
         m[i] = __builtin_popcount(hm);
-        walk = walk || (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots);
+        walk[i] = valid[i] && overflowed<MARKED>(k1[i], c1[i], x[i]) && overflowed<MARKED>(k2[i], c2[i], x[i]);
+        any = any || walk[i];
     }
-    if (ballot(walk)) {
+    if (ballot(any)) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (valid[i] && c1[i] > (uint32_t)kSlots && c2[i] > (uint32_t)kSlots)
-                walk_on(t, x[i], b1[i], b2[i], [&](uint32_t b, uint32_t hm) {
+            if (walk[i])
+                walk_on<MARKED>(t, x[i], b1[i], b2[i], [&](uint32_t b, uint32_t hm) {
                     while (hm) {
                         const uint32_t p = b * kSlots + __builtin_ctz(hm);
                         p2[i] = m[i] == 1 ? p : p2[i];
@@ -788,18 +846,19 @@ __device__ __forceinline__ void probe_write(const Table& t, int bits, const uint
 
 // Every entry of key x in visiting order (b1's slots, b2's, then the walk), as LDS word
 // positions; used for keys with more than two build matches.
-template <bool HASHED, typename F>
+template <bool HASHED, bool MARKED, typename F>
 __device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_t x, F f)
 {
     uint32_t b1, b2;
     choices(HASHED ? x : hmix(x), bits, t.nb, b1, b2);
-    const uint32_t c1 = t.cnt[b1], c2 = t.cnt[b2];
+    const uint32_t c1 = claims<MARKED>(t, b1), c2 = claims<MARKED>(t, b2);
+    const uint4 k1 = t.keys[b1], k2 = t.keys[b2];
     auto emit = [&](uint32_t b, uint32_t hm) {
         for (; hm; hm &= hm - 1) f(b * kSlots + __builtin_ctz(hm));
     };
-    emit(b1, bucket_hits(t.keys[b1], c1, x));
-    emit(b2, bucket_hits(t.keys[b2], c2, x));
-    if (c1 > (uint32_t)kSlots && c2 > (uint32_t)kSlots) walk_on(t, x, b1, b2, emit);
+    emit(b1, hits<MARKED>(k1, c1, x));
+    emit(b2, hits<MARKED>(k2, c2, x));
+    if (overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x)) walk_on<MARKED>(t, x, b1, b2, emit);
 }
 
 // Units of this join.  The device total never exceeds Umax (sum over partitions of
@@ -894,7 +953,7 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // Every half of the loop issues the same loads (a batch past the unit reloads a valid one), and
 // the buffers swap roles instead of being copied, so the wait before a probe is for that
 // batch's loads alone, never for the loads issued after them.
-template <bool AOS>
+template <bool AOS, bool MARKED>
 __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
                                                 const uint32_t (&xs)[kCountBatch])
 {
@@ -908,7 +967,7 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
             x[i] = xs[h + i];
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
-        cnt += probe_count<kProbe, AOS>(t, un.bits, x, ok);
+        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok);
     }
     return cnt;
 }
@@ -933,14 +992,19 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         const bool more = u + gridDim.x < U;
         const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
         uint32_t cnt = 0;
-        for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
-            const uint32_t e1 = e0 + kB, e2 = e1 + kB;
-            load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
-            cnt += count_batch<AOS>(t, un, e0, xa);
-            const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
-            load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
-            cnt += count_batch<AOS>(t, un, e1, xb);  // every lane masked past the unit
-        }
+        auto batches = [&](auto marked) {
+            constexpr bool M = decltype(marked)::value;
+            for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
+                const uint32_t e1 = e0 + kB, e2 = e1 + kB;
+                load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
+                cnt += count_batch<AOS, M>(t, un, e0, xa);
+                const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
+                load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
+                cnt += count_batch<AOS, M>(t, un, e1, xb);  // every lane masked past the unit
+            }
+        };
+        if (AOS && t.marked) batches(std::true_type{});
+        else batches(std::false_type{});
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
         uint32_t tot;
         block_excl_scan<kJoinBlock>(cnt, wsum, &tot);
@@ -983,58 +1047,63 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
         if (more) load_chunk<AOS, true>(g, nxt, ch);
         const uint64_t base = offsets[u];
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
-        for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
-            uint32_t cx[kWriteLoad];
-            int32_t cr[kWriteLoad];
+        auto batches = [&](auto marked) {
+            constexpr bool M = decltype(marked)::value;
+            for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
+                uint32_t cx[kWriteLoad];
+                int32_t cr[kWriteLoad];
 #pragma unroll
-            for (int i = 0; i < kWriteLoad; ++i) {
-                cx[i] = nx[i];
-                cr[i] = nr[i];
-            }
-            if (e0 + kJoinBlock * kWriteLoad < un.sN)
-                load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
-            else if (more)
-                load_tuples<AOS>(g, nxt, 0, nx, nr);
-#pragma unroll
-            for (int h = 0; h < kWriteLoad; h += kWriteBatch) {
-                uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
-                int32_t srid[kWriteBatch];
-                bool ok[kWriteBatch];
-#pragma unroll
-                for (int i = 0; i < kWriteBatch; ++i) {
-                    x[i] = cx[h + i];
-                    srid[i] = cr[h + i];
-                    ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+                for (int i = 0; i < kWriteLoad; ++i) {
+                    cx[i] = nx[i];
+                    cr[i] = nr[i];
                 }
-                probe_write<kWriteBatch, AOS>(t, un.bits, x, ok, m, p1, p2);
-                // Slots inside the unit's range: waves take theirs from an LDS cursor (no
-                // block-wide barrier); within a wave, the pairs of the i-th tuple of every lane
-                // are contiguous, so each store instruction writes one coalesced run.
-                uint32_t excl[kWriteBatch], wtot = 0;
+                if (e0 + kJoinBlock * kWriteLoad < un.sN)
+                    load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
+                else if (more)
+                    load_tuples<AOS>(g, nxt, 0, nx, nr);
 #pragma unroll
-                for (int i = 0; i < kWriteBatch; ++i) {
-                    const uint32_t inc = wave_incl_scan(m[i]);
-                    excl[i] = wtot + inc - m[i];
-                    wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
-                }
-                uint32_t wb = 0;
-                if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
-                wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
+                for (int h = 0; h < kWriteLoad; h += kWriteBatch) {
+                    uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
+                    int32_t srid[kWriteBatch];
+                    bool ok[kWriteBatch];
 #pragma unroll
-                for (int i = 0; i < kWriteBatch; ++i) {
-                    const uint64_t slot = base + wb + excl[i];
-                    if (m[i] >= 1 && slot < cap) put_pair(&out[slot], make_int2((int32_t)rw[p1[i]], srid[i]));
-                    if (m[i] >= 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2((int32_t)rw[p2[i]], srid[i]));
-                    if (m[i] > 2) {  // more than two build matches: visit the buckets again
-                        uint32_t seen = 0;
-                        for_each_match<AOS>(t, un.bits, x[i], [&](uint32_t p) {
-                            if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
-                            ++seen;
-                        });
+                    for (int i = 0; i < kWriteBatch; ++i) {
+                        x[i] = cx[h + i];
+                        srid[i] = cr[h + i];
+                        ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+                    }
+                    probe_write<kWriteBatch, AOS, M>(t, un.bits, x, ok, m, p1, p2);
+                    // Slots inside the unit's range: waves take theirs from an LDS cursor (no
+                    // block-wide barrier); within a wave, the pairs of the i-th tuple of every lane
+                    // are contiguous, so each store instruction writes one coalesced run.
+                    uint32_t excl[kWriteBatch], wtot = 0;
+#pragma unroll
+                    for (int i = 0; i < kWriteBatch; ++i) {
+                        const uint32_t inc = wave_incl_scan(m[i]);
+                        excl[i] = wtot + inc - m[i];
+                        wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+                    }
+                    uint32_t wb = 0;
+                    if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
+                    wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
+#pragma unroll
+                    for (int i = 0; i < kWriteBatch; ++i) {
+                        const uint64_t slot = base + wb + excl[i];
+                        if (m[i] >= 1 && slot < cap) put_pair(&out[slot], make_int2((int32_t)rw[p1[i]], srid[i]));
+                        if (m[i] >= 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2((int32_t)rw[p2[i]], srid[i]));
+                        if (m[i] > 2) {  // more than two build matches: visit the buckets again
+                            uint32_t seen = 0;
+                            for_each_match<AOS, M>(t, un.bits, x[i], [&](uint32_t p) {
+                                if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
+                                ++seen;
+                            });
+                        }
                     }
                 }
             }
-        }
+        };
+        if (AOS && t.marked) batches(std::true_type{});
+        else batches(std::false_type{});
         if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
         __syncthreads();
         un = nxt;

@@ -144,6 +144,26 @@ def test_full_scatter_tiles_with_and_without_rids(with_rid):
 
 
 @gpu
+def test_partitioned_heavy_duplicates(monkeypatch):
+    """A few build keys with about a thousand copies each, through partitioned plans: long chains
+    of overflowed buckets in the tables of fan-out 2 and more (marked tables) and of fan-out 1
+    (claim counters)."""
+    need_gpu()
+    g = datagen.rng_for(41)
+    keys = g.integers(-2**31, 2**31 - 1, 40, dtype=np.int64).astype(np.int32)
+    R = datagen.Rel(key=keys[g.integers(0, 40, 50_000)], rid=g.permutation(50_000).astype(np.int32))
+    S = datagen.Rel(key=np.concatenate([keys[g.integers(0, 40, 8_000)],
+                                        g.integers(-2**31, 2**31 - 1, 2_000, dtype=np.int64).astype(np.int32)]),
+                    rid=np.arange(10_000, dtype=np.int32))
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
+    for bits in ("1", "2", "3", "6"):
+        monkeypatch.setenv("JOIN_HASH_BITS", bits)
+        log(f"hash heavy duplicates bits={bits}")
+        got = canon_gpu(_hash(R, S))
+        assert len(got) == n and np.array_equal(got, ref), bits
+
+
+@gpu
 def test_lds_overflow_chunked_build(monkeypatch):
     """A small table capacity forces several R chunks per partition (each probed by all of the
     partition's S tuples), in both the single and the partitioned path."""
