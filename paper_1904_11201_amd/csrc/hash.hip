@@ -645,6 +645,21 @@ __device__ __forceinline__ void load_chunk(const JoinGeom& g, const Unit& un, Ch
     }
 }
 
+// The table of a unit's R chunk in LDS (built by insert_chunk; the same for every unit of that
+// chunk).
+template <bool RIDS, bool HASHED>
+__device__ __forceinline__ Table table_of(const Unit& un, uint4* lds)
+{
+    const uint32_t nb = table_buckets(un.rN);
+    Table t;
+    t.keys = lds;
+    t.rids = RIDS ? lds + nb : nullptr;
+    t.cnt = reinterpret_cast<const uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
+    t.nb = nb;
+    t.marked = HASHED && un.bits >= 2;
+    return t;
+}
+
 // Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
 // HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.
 template <bool RIDS, bool HASHED>
@@ -698,13 +713,7 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
             if (cnt[b] > (uint32_t)kSlots) keys[b * kSlots + 3] ^= kOverflow;
         __syncthreads();
     }
-    Table t;
-    t.keys = lds;
-    t.rids = RIDS ? lds + nb : nullptr;
-    t.cnt = cnt;
-    t.nb = nb;
-    t.marked = marked;
-    return t;
+    return table_of<RIDS, HASHED>(un, lds);
 }
 
 // Matches of x among the filled slots of one bucket, as a 4-bit mask (claim-counter tables).
@@ -869,6 +878,16 @@ __device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
     return (int64_t)U < g.Umax ? U : (uint32_t)g.Umax;
 }
 
+// The write pass's units per workgroup: a contiguous run [u0, u1) of the unit list.  Units of
+// one partition follow each other R chunk by R chunk, S slice by S slice, so consecutive slices
+// of one chunk keep its table (a skewed probe side cuts its hot partitions into many slices);
+// the count pass keeps the round-robin order, which balances its shorter units better.
+__device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u1)
+{
+    u0 = (uint32_t)(((uint64_t)U * blockIdx.x) / gridDim.x);
+    u1 = (uint32_t)(((uint64_t)U * (blockIdx.x + 1)) / gridDim.x);
+}
+
 #ifndef JL_HASH_COUNT_BATCH
 #define JL_HASH_COUNT_BATCH 4
 #endif
@@ -989,6 +1008,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         Chunk<false> ch;
         load_chunk<AOS, false>(g, un, ch);
         const Table t = insert_chunk<false, AOS>(g, un, ch, tab);
+        __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
         const bool more = u + gridDim.x < U;
         const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
         uint32_t cnt = 0;
@@ -1025,27 +1045,37 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                                                            int2* __restrict__ out, uint64_t cap)
 {
     extern __shared__ uint4 tab[];
-    __shared__ uint32_t cursor;  // output slots of the current unit handed out so far
+    // Output slots of this workgroup handed out so far: its units are contiguous, so their pairs
+    // fill [offsets[u0], offsets[u1]) and one running cursor serves all of them.
+    __shared__ uint32_t cursor;
     if (*total > cap) return;  // an output too small for the exact count receives nothing
     const uint32_t U = unit_total(g);
-    // The next unit's R chunk is loaded into registers while the current unit probes, and the
-    // next unit's first S batch while its last batch probes.
+    uint32_t u0, u1;
+    unit_range(U, u0, u1);
+    // The next unit's R chunk (when it needs a new table) is loaded into registers while the
+    // current unit probes, and the next unit's first S batch while its last batch probes.
     Unit un{};
     Chunk<true> ch;
     uint32_t nx[kWriteLoad];
     int32_t nr[kWriteLoad];
-    if (blockIdx.x < U) {
-        un = decode_unit(g, blockIdx.x);
+    if (u0 < u1) {
+        un = decode_unit(g, u0);
         load_chunk<AOS, true>(g, un, ch);
         load_tuples<AOS>(g, un, 0, nx, nr);
     }
-    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
-        if (threadIdx.x == 0) cursor = 0;  // the barrier inside the build publishes it
-        const Table t = insert_chunk<true, AOS>(g, un, ch, tab);
-        const bool more = u + gridDim.x < U;
-        const Unit nxt = more ? decode_unit(g, u + gridDim.x) : Unit{};
-        if (more) load_chunk<AOS, true>(g, nxt, ch);
-        const uint64_t base = offsets[u];
+    if (threadIdx.x == 0) cursor = 0;  // published by the first build's barriers
+    const uint64_t base = u0 < u1 ? offsets[u0] : 0;
+    uint32_t tBeg = 0, tN = 0;  // R chunk in the table (tN == 0: none yet)
+    for (uint32_t u = u0; u < u1; ++u) {
+        if (un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
+            insert_chunk<true, AOS>(g, un, ch, tab);
+            tBeg = un.rBeg;
+            tN = un.rN;
+        }
+        const Table t = table_of<true, AOS>(un, tab);
+        const bool more = u + 1 < u1;
+        const Unit nxt = more ? decode_unit(g, u + 1) : Unit{};
+        if (more && (nxt.rBeg != un.rBeg || nxt.rN != un.rN)) load_chunk<AOS, true>(g, nxt, ch);
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
@@ -1073,7 +1103,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                         ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
                     }
                     probe_write<kWriteBatch, AOS, M>(t, un.bits, x, ok, m, p1, p2);
-                    // Slots inside the unit's range: waves take theirs from an LDS cursor (no
+                    // Slots inside the workgroup's range: waves take theirs from an LDS cursor (no
                     // block-wide barrier); within a wave, the pairs of the i-th tuple of every lane
                     // are contiguous, so each store instruction writes one coalesced run.
                     uint32_t excl[kWriteBatch], wtot = 0;
