@@ -123,12 +123,12 @@ __device__ __forceinline__ void load_r(const ThetaGeom& g, int64_t r0, int64_t r
 __device__ __forceinline__ void unit_of(const ThetaGeom& g, int64_t u, int64_t& r0, int64_t& rEnd,
                                         int64_t& s0, int64_t& s1)
 {
-    if (g.units) {
-        const uint4 q = g.units[u];
-        r0 = q.x;
-        rEnd = q.y;
-        s0 = q.z;
-        s1 = q.w;
+    if (g.units) {  // u is uniform: scalar loads, so the unit's bounds live in SGPRs
+        const cptr<uint32_t> q = as_const(reinterpret_cast<const uint32_t*>(g.units)) + 4 * u;
+        r0 = q[0];
+        rEnd = q[1];
+        s0 = q[2];
+        s1 = q[3];
         return;
     }
     const int64_t rb = u / g.nSt;
@@ -157,8 +157,10 @@ __device__ __forceinline__ void emit_row(const RRows& rr, const int32_t (&rid)[k
 {
 #pragma unroll
     for (int r = 0; r < kRB; ++r) {
-        const uint64_t m =
-            ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa) && holds<OPC>(rr.xc[r], 0u, sc)) & vm[r];
+        // one ballot per condition: each compare lands in a lane mask and the masks are ANDed
+        // on the scalar unit (a ballot of the combined bool would first widen it to a VGPR)
+        uint64_t m = ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa)) & vm[r];
+        if constexpr (OPC != JOIN_OP_NONE) m &= ballot(holds<OPC>(rr.xc[r], 0u, sc));
         if (m) {
             if ((m >> lane) & 1ull) {
                 const uint64_t slot = base + mask_rank(m);
@@ -265,23 +267,37 @@ __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
             uint64_t n = 0;
             int2* st = g.stash ? g.stash + u * g.K : nullptr;
             const uint64_t kcap = st ? (uint64_t)g.K : 0ull;
+            // Region units always come with the bucketed rid column (positions when the input
+            // has none), so the rids load unconditionally with the other columns.
+            // 8 S rows' scalar loads in flight together, the next group's while this one is
+            // evaluated
             int64_t j = s0;
-            for (; j + kSGroup <= s1; j += kSGroup) {  // 8 S rows' scalar loads in flight together
+            int32_t na[kSGroup], nc[kSGroup], nr[kSGroup];
+            auto fetch = [&](int64_t j0) {
+#pragma unroll
+                for (int k = 0; k < kSGroup; ++k) {
+                    na[k] = Sa[j0 + k];
+                    nc[k] = (OPC != JOIN_OP_NONE) ? Sc[j0 + k] : 0;
+                    nr[k] = Srid[j0 + k];
+                }
+            };
+            if (j + kSGroup <= s1) fetch(j);
+            for (; j + kSGroup <= s1; j += kSGroup) {
                 int32_t sa[kSGroup], sc[kSGroup], sr[kSGroup];
 #pragma unroll
                 for (int k = 0; k < kSGroup; ++k) {
-                    sa[k] = Sa[j + k];
-                    sc[k] = (OPC != JOIN_OP_NONE) ? Sc[j + k] : 0;
-                    sr[k] = Srid ? Srid[j + k] : (int32_t)(j + k);
+                    sa[k] = na[k];
+                    sc[k] = nc[k];
+                    sr[k] = nr[k];
                 }
+                if (j + 2 * kSGroup <= s1) fetch(j + kSGroup);
 #pragma unroll
                 for (int k = 0; k < kSGroup; ++k)
                     emit_row<OPA, OPC>(rr, rid, vm, sa[k], sc[k], sr[k], n, st, kcap, lane);
             }
             for (; j < s1; ++j) {
                 const int32_t sc = (OPC != JOIN_OP_NONE) ? Sc[j] : 0;
-                const int32_t srid = Srid ? Srid[j] : (int32_t)j;
-                emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, n, st, kcap, lane);
+                emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, Srid[j], n, st, kcap, lane);
             }
             if (lane == 0) counts[u] = n;
         } else if constexpr (selective<OPA>()) {
