@@ -441,6 +441,7 @@ __global__ void expand_units_k(const uint32_t* __restrict__ unitStart, int P, in
 // microseconds each.  part_starts_k: each side's partition starts (exclusive scan of the sizes)
 // and group cursors; a NULL tot skips that side.  plan_k: the plans, the units' exclusive scan
 // (unitStart[0..nParts], the total also at *Utotal) and the unit -> partition map.
+// part_starts_k runs one workgroup per side.
 constexpr int kFuseBlock = 1024;
 constexpr int kFuseParts = 8192;
 
@@ -463,11 +464,12 @@ __global__ __launch_bounds__(kFuseBlock) void part_starts_k(const uint32_t* __re
                                                             uint32_t stride, int n)
 {
     __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
-    for (int side = 0; side < 2; ++side) {
+    {
+        const int side = blockIdx.x;  // workgroup 0: R, workgroup 1: S
         const uint32_t* tot = side ? totS : totR;
         uint32_t* base = side ? baseS : baseR;
         uint32_t* grp = side ? grpS : grpR;
-        if (!tot) continue;
+        if (!tot) return;
         uint32_t carry = 0;
         for (int b0 = 0; b0 < n; b0 += 2 * kFuseBlock) {
             const int pa = b0 + 2 * (int)threadIdx.x, pb = pa + 1;
@@ -1319,7 +1321,7 @@ static hipError_t starts_sides(const uint32_t* totR, uint32_t* baseR, uint32_t* 
 {
     if (n <= kFuseParts) {
         prof::Scope pc(st, "hash.plan");
-        part_starts_k<<<1, kFuseBlock, 0, st>>>(totR, baseR, grpR, totS, baseS, grpS, (uint32_t)n, (int)n);
+        part_starts_k<<<2, kFuseBlock, 0, st>>>(totR, baseR, grpR, totS, baseS, grpS, (uint32_t)n, (int)n);
         return hipGetLastError();
     }
     hipError_t e = hipSuccess;
