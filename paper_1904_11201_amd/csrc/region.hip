@@ -39,7 +39,7 @@ constexpr int kRBlockRows = 512;   // R rows per unit (one wave, 8 rows per lane
 constexpr int kTileRows = JL_REGION_TILE;     // S rows per unit, at least
 constexpr int kMaxTiles = 8;       // S tiles per R block, at most (the tile grows beyond)
 constexpr int kCrossWaves = 4;
-constexpr int kSortCap = 2048;     // S rows of a bucket sorted in LDS for band trimming, at most
+constexpr int kSortCap = 2048;     // S rows of a bucket split in LDS for band trimming, at most
 constexpr int kSortBlk = 256;
 
 enum : int { kWhite = 0, kGreen = 1, kRed = 2 };
@@ -343,69 +343,74 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
-// Band joins: the S rows of every bucket of at most kSortCap rows are sorted by a (with their c
-// and rid), so that classify_k can trim a red span's first and last bucket to the rows whose a
-// lies within w of the R bucket's value range.  One workgroup per bucket: a bitonic sort in LDS
-// of keys (a, position in the bucket), unique, so the order is deterministic.
-__global__ __launch_bounds__(kSortBlk) void bsort_k(const uint32_t* __restrict__ offS, int64_t nChS,
-                                                    uint32_t nS, int B, int32_t* __restrict__ Sa,
-                                                    int32_t* __restrict__ Sc, int32_t* __restrict__ Sr)
+// Band joins: the S rows of every bucket of at most kSortCap rows are split three ways by a:
+// low (a < vlo + w), middle, high (a > vhi - w), each keeping its c and rid, and the two split
+// points are recorded.  An R bucket's band reaches into a neighbouring S bucket only through that
+// bucket's near edge: a left neighbour contributes only its high rows, a right neighbour only
+// its low rows, so classify_k trims the red span to them.  A bucket that is not split (larger
+// than kSortCap, or narrower than 2w, where the parts would overlap) records split points that
+// trim nothing.  One workgroup per bucket, the rows staged in LDS, kSplitRows per thread.
+constexpr int kSplitRows = kSortCap / kSortBlk;
+
+__global__ __launch_bounds__(kSortBlk) void bsplit_k(const uint32_t* __restrict__ offS, int64_t nChS,
+                                                     uint32_t nS, int B, const int64_t* __restrict__ vlo,
+                                                     const int64_t* __restrict__ vhi, int64_t w,
+                                                     int32_t* __restrict__ Sa, int32_t* __restrict__ Sc,
+                                                     int32_t* __restrict__ Sr, uint32_t* __restrict__ split)
 {
-    __shared__ uint64_t key[kSortCap];
-    __shared__ int32_t cc[kSortCap], rr[kSortCap];
+    __shared__ int32_t ta[kSortCap], tc[kSortCap], tr[kSortCap];
+    __shared__ uint32_t tmp[kSortBlk / kWave + 1];
     const int b = blockIdx.x;
+    const int tid = threadIdx.x;
     const uint32_t s0 = offS[(int64_t)b * nChS];
     const uint32_t s1 = b + 1 < B ? offS[(int64_t)(b + 1) * nChS] : nS;
     const uint32_t n = s1 - s0;
-    if (n < 2 || n > (uint32_t)kSortCap) return;
-    uint32_t np = 2;
-    while (np < n) np <<= 1;
-    for (uint32_t i = threadIdx.x; i < np; i += kSortBlk) {
-        if (i < n) {
-            key[i] = ((uint64_t)((uint32_t)Sa[s0 + i] ^ 0x80000000u) << 32) | i;
-            if (Sc) cc[i] = Sc[s0 + i];
-            rr[i] = Sr[s0 + i];
-        } else {
-            key[i] = ~0ull;  // padding sorts last
+    const int64_t lo = vlo[b], hi = vhi[b];
+    if (n == 0 || n > (uint32_t)kSortCap || hi - lo < 2 * w) {  // uniform
+        if (tid == 0) {
+            split[2 * b] = s1;      // low rows end: the whole bucket
+            split[2 * b + 1] = s0;  // high rows start: the whole bucket
         }
+        return;
+    }
+    for (uint32_t i = tid; i < n; i += kSortBlk) {
+        ta[i] = Sa[s0 + i];
+        if (Sc) tc[i] = Sc[s0 + i];
+        tr[i] = Sr[s0 + i];
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= np; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < np; i += kSortBlk) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = key[i], y = key[l];
-                    const bool up = (i & k) == 0;
-                    if (up ? x > y : x < y) {
-                        key[i] = y;
-                        key[l] = x;
-                    }
-                }
-            }
-            __syncthreads();
+    // thread t holds rows [t * kSplitRows, ...): category 0 low, 1 middle, 2 high
+    const uint32_t r0 = (uint32_t)tid * kSplitRows;
+    uint32_t cl = 0, cm = 0;
+    uint8_t cat[kSplitRows];
+#pragma unroll
+    for (int k = 0; k < kSplitRows; ++k) {
+        const uint32_t i = r0 + k;
+        const int64_t a = i < n ? (int64_t)ta[i] : 0;
+        cat[k] = a < lo + w ? 0 : (a > hi - w ? 2 : 1);
+        if (i < n) {
+            cl += cat[k] == 0;
+            cm += cat[k] == 1;
         }
     }
-    for (uint32_t i = threadIdx.x; i < n; i += kSortBlk) {
-        const uint64_t k2 = key[i];
-        const uint32_t from = (uint32_t)k2;
-        Sa[s0 + i] = (int32_t)((uint32_t)(k2 >> 32) ^ 0x80000000u);
-        if (Sc) Sc[s0 + i] = cc[from];
-        Sr[s0 + i] = rr[from];
+    uint32_t L, M;
+    const uint32_t pl = block_excl_scan<kSortBlk>(cl, tmp, &L);
+    const uint32_t pm = block_excl_scan<kSortBlk>(cm, tmp, &M);
+    uint32_t ql = pl, qm = L + pm, qh = L + M + ((r0 < n ? r0 : n) - pl - pm);
+#pragma unroll
+    for (int k = 0; k < kSplitRows; ++k) {
+        const uint32_t i = r0 + k;
+        if (i < n) {
+            const uint32_t d = cat[k] == 0 ? ql++ : (cat[k] == 1 ? qm++ : qh++);
+            Sa[s0 + d] = ta[i];
+            if (Sc) Sc[s0 + d] = tc[i];
+            Sr[s0 + d] = tr[i];
+        }
     }
-}
-
-// First position in the sorted rows [b0, b1) of Sa whose value is >= v (upper: > v).
-__device__ __forceinline__ uint32_t bound_in(const int32_t* __restrict__ Sa, uint32_t b0, uint32_t b1,
-                                             int64_t v, bool upper)
-{
-    while (b0 < b1) {
-        const uint32_t m = b0 + ((b1 - b0) >> 1);
-        const int64_t x = Sa[m];
-        if (upper ? x <= v : x < v) b0 = m + 1;
-        else b1 = m;
+    if (tid == 0) {
+        split[2 * b] = s0 + L;
+        split[2 * b + 1] = s0 + L + M;
     }
-    return b0;
 }
 
 // One wave per R bucket: red span, adjacent green spans, units and green pair counts.  The S
@@ -415,7 +420,7 @@ __global__ __launch_bounds__(kWave) void classify_k(const uint32_t* __restrict__
                                                     uint32_t nR, uint32_t nS,
                                                     const int64_t* __restrict__ vlo,
                                                     const int64_t* __restrict__ vhi, int B, int op,
-                                                    int64_t w, int has_c, const int32_t* __restrict__ Sa,
+                                                    int64_t w, int has_c, const uint32_t* __restrict__ split,
                                                     BucketInfo* __restrict__ info,
                                                     uint32_t* __restrict__ units,
                                                     uint64_t* __restrict__ green)
@@ -489,12 +494,11 @@ __global__ __launch_bounds__(kWave) void classify_k(const uint32_t* __restrict__
     if (lane != 0) return;
     bi.red0 = ss(jr0);
     bi.red1 = jr1 > jr0 ? ss(jr1) : bi.red0;
-    if (op == JOIN_OP_BAND && jr1 > jr0) {
-        // sorted end buckets of the red span (bsort_k) keep only rows within w of [lo_i, hi_i]
-        // (not next to a green span, which must stay adjacent)
-        const uint32_t a0 = ss(jr0), a1 = ss(jr0 + 1), z0 = ss(jr1 - 1), z1 = ss(jr1);
-        if (gl == jr0 && a1 - a0 <= (uint32_t)kSortCap) bi.red0 = bound_in(Sa, a0, a1, lo_i - w, false);
-        if (gr == jr1 && z1 - z0 <= (uint32_t)kSortCap) bi.red1 = bound_in(Sa, z0 > bi.red0 ? z0 : bi.red0, z1, hi_i + w, true);
+    if (split && jr1 > jr0) {
+        // band: a left neighbour of the R bucket contributes only its high rows, a right one only
+        // its low rows (bsplit_k); not next to a green span, which must stay adjacent
+        if (gl == jr0 && jr0 < i) bi.red0 = split[2 * jr0 + 1];
+        if (gr == jr1 && jr1 - 1 > i) bi.red1 = split[2 * (jr1 - 1)];
         if (bi.red1 < bi.red0) bi.red1 = bi.red0;
     }
     bi.gl0 = ss(gl);
@@ -621,6 +625,7 @@ RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k)
     pl.off_Sc = take((size_t)nS * 4);
     pl.off_Sr = take((size_t)nS * 4);
     pl.off_info = take((size_t)pl.B * sizeof(BucketInfo));
+    pl.off_split = take((size_t)pl.B * 8);
     pl.off_units = take((size_t)(pl.B + 1) * 4);
     pl.off_table = take((size_t)pl.Umax * sizeof(uint4));
     pl.off_counts = take((size_t)pl.nOff * 8);
@@ -731,12 +736,15 @@ hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_re
     if (e != hipSuccess) return e;
     e = part_side(pl, S, has_c, pl.chS, pl.nChS, pl.off_hS, pl.off_Sa, pl.off_Sc, pl.off_Sr, ws, st, "region.partition.S");
     if (e != hipSuccess) return e;
-    if (p.op_a == JOIN_OP_BAND) {
-        prof::Scope ps(st, "region.sort");
-        bsort_k<<<(unsigned)pl.B, kSortBlk, 0, st>>>(
+    uint32_t* split = p.op_a == JOIN_OP_BAND ? reinterpret_cast<uint32_t*>(ws + pl.off_split) : nullptr;
+    if (split) {
+        prof::Scope ps(st, "region.split");
+        bsplit_k<<<(unsigned)pl.B, kSortBlk, 0, st>>>(
             reinterpret_cast<const uint32_t*>(ws + pl.off_hS), pl.nChS, (uint32_t)S.n, pl.B,
-            reinterpret_cast<int32_t*>(ws + pl.off_Sa), has_c ? reinterpret_cast<int32_t*>(ws + pl.off_Sc) : nullptr,
-            reinterpret_cast<int32_t*>(ws + pl.off_Sr));
+            reinterpret_cast<const int64_t*>(ws + pl.off_vlo), reinterpret_cast<const int64_t*>(ws + pl.off_vhi),
+            (int64_t)p.w, reinterpret_cast<int32_t*>(ws + pl.off_Sa),
+            has_c ? reinterpret_cast<int32_t*>(ws + pl.off_Sc) : nullptr,
+            reinterpret_cast<int32_t*>(ws + pl.off_Sr), split);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -751,8 +759,8 @@ hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_re
             reinterpret_cast<const uint32_t*>(ws + pl.off_hS), pl.nChS, (uint32_t)R.n,
             (uint32_t)S.n, reinterpret_cast<const int64_t*>(ws + pl.off_vlo),
             reinterpret_cast<const int64_t*>(ws + pl.off_vhi), pl.B, p.op_a,
-            p.op_a == JOIN_OP_BAND ? (int64_t)p.w : 0, has_c ? 1 : 0,
-            reinterpret_cast<const int32_t*>(ws + pl.off_Sa), info, units, counts + pl.Umax);
+            p.op_a == JOIN_OP_BAND ? (int64_t)p.w : 0, has_c ? 1 : 0, split, info, units,
+            counts + pl.Umax);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
