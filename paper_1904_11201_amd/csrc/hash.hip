@@ -880,10 +880,11 @@ __device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
     return (int64_t)U < g.Umax ? U : (uint32_t)g.Umax;
 }
 
-// The write pass's units per workgroup: a contiguous run [u0, u1) of the unit list.  Units of
-// one partition follow each other R chunk by R chunk, S slice by S slice, so consecutive slices
-// of one chunk keep its table (a skewed probe side cuts its hot partitions into many slices);
-// the count pass keeps the round-robin order, which balances its shorter units better.
+// The write pass's units per workgroup of one join: a contiguous run [u0, u1) of the unit list.
+// Units of one partition follow each other R chunk by R chunk, S slice by S slice, so
+// consecutive slices of one chunk keep its table (a skewed probe side cuts its hot partitions
+// into many slices).  Batches of joins, whose units differ widely in size, and the count pass
+// keep the round-robin order, which balances better.
 __device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u1)
 {
     u0 = (uint32_t)(((uint64_t)U * blockIdx.x) / gridDim.x);
@@ -1047,13 +1048,22 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                                                            int2* __restrict__ out, uint64_t cap)
 {
     extern __shared__ uint4 tab[];
-    // Output slots of this workgroup handed out so far: its units are contiguous, so their pairs
-    // fill [offsets[u0], offsets[u1]) and one running cursor serves all of them.
+    // Output slots handed out so far.  Contiguous runs (g.contig): the run's pairs fill
+    // [offsets[u0], offsets[u1]) and one running cursor serves all its units.  Round robin: each
+    // unit fills [offsets[u], offsets[u + 1]) and the cursor restarts with the unit's build.
     __shared__ uint32_t cursor;
     if (*total > cap) return;  // an output too small for the exact count receives nothing
     const uint32_t U = unit_total(g);
-    uint32_t u0, u1;
-    unit_range(U, u0, u1);
+    const bool contig = g.contig != 0;  // uniform
+    uint32_t u0, u1, step;
+    if (contig) {
+        unit_range(U, u0, u1);
+        step = 1;
+    } else {
+        u0 = blockIdx.x;
+        u1 = U;
+        step = gridDim.x;
+    }
     // The next unit's R chunk (when it needs a new table) is loaded into registers while the
     // current unit probes, and the next unit's first S batch while its last batch probes.
     Unit un{};
@@ -1066,18 +1076,20 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
         load_tuples<AOS>(g, un, 0, nx, nr);
     }
     if (threadIdx.x == 0) cursor = 0;  // published by the first build's barriers
-    const uint64_t base = u0 < u1 ? offsets[u0] : 0;
+    const uint64_t base0 = contig && u0 < u1 ? offsets[u0] : 0;
     uint32_t tBeg = 0, tN = 0;  // R chunk in the table (tN == 0: none yet)
-    for (uint32_t u = u0; u < u1; ++u) {
-        if (un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
+    for (uint32_t u = u0; u < u1; u += step) {
+        if (!contig || un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
+            if (!contig && threadIdx.x == 0) cursor = 0;   // the build's barriers publish it
             insert_chunk<true, AOS>(g, un, ch, tab);
             tBeg = un.rBeg;
             tN = un.rN;
         }
+        const uint64_t base = contig ? base0 : offsets[u];
         const Table t = table_of<true, AOS>(un, tab);
-        const bool more = u + 1 < u1;
-        const Unit nxt = more ? decode_unit(g, u + 1) : Unit{};
-        if (more && (nxt.rBeg != un.rBeg || nxt.rN != un.rN)) load_chunk<AOS, true>(g, nxt, ch);
+        const bool more = u + step < u1;
+        const Unit nxt = more ? decode_unit(g, u + step) : Unit{};
+        if (more && (!contig || nxt.rBeg != un.rBeg || nxt.rN != un.rN)) load_chunk<AOS, true>(g, nxt, ch);
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
@@ -1397,6 +1409,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.P = 1;
     } else {
         g.single = 0;
+        g.contig = 1;
         g.rt = pre ? pre->tup : reinterpret_cast<const int2*>(ws + pl.off_tupR);
         g.st = reinterpret_cast<const int2*>(ws + pl.off_tupS);
         g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);

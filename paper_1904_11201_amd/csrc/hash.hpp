@@ -39,6 +39,7 @@ struct JoinGeom {
     int bits;                   // partition bits; the table position uses the bits below them
     int P;
     int single;
+    int contig;  // write pass: contiguous runs of units per workgroup (else round robin)
 };
 
 struct HashPlan {
