@@ -221,6 +221,55 @@ def bench_serve(args, J):
     return out
 
 
+def measure_ceilings(J, _native, dev, stream, reps=5):
+    """What the chip sustains: a plain 1 GiB device copy (HBM) and an int32 VALU spin whose
+    workgroup 0 also reads the shader clock against the constant real-time counter."""
+    import torch
+    props = torch.cuda.get_device_properties(dev)
+    nb = 1 << 30
+    src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    blocks, iters = props.multi_processor_count * 8, 1 << 14
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+    clk = torch.zeros(2, dtype=torch.int64, device=dev)
+    J.prof_copy(src, dst, stream)
+    ops = J.prof_valu(blocks, iters, sink, clk, stream, mix=0)
+    J.prof_valu(blocks, iters, sink, clk, stream, mix=1)
+    torch.cuda.synchronize()
+    _native.prof_enable(True)
+    for _ in range(reps):
+        J.prof_copy(src, dst, stream)
+    for mix in (0, 1):
+        for _ in range(reps):
+            J.prof_valu(blocks, iters, sink, clk, stream, mix=mix)
+    torch.cuda.synchronize()
+    p = _native.prof_read()
+    _native.prof_enable(False)
+    cyc, ticks = (int(v) for v in clk.cpu().tolist())
+    del src, dst, sink, clk
+    torch.cuda.empty_cache()
+    copy_ms = p["ceiling.copy"][1] / p["ceiling.copy"][0]
+    valu_ms = p["ceiling.valu"][1] / p["ceiling.valu"][0]
+    band_ms = p["ceiling.valu.band"][1] / p["ceiling.valu.band"][0]
+    clock_ghz = cyc / (ticks / J.prof_wall_clock_hz()) / 1e9 if ticks > 0 else None
+    return {
+        "compute_units": props.multi_processor_count,
+        "copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
+        "copy_workload": "1 GiB device-to-device copy, 16-byte non-temporal loads and stores "
+                         f"(2 GiB of HBM traffic per launch, mean of {reps})",
+        "valu_Tops": round(ops / (valu_ms * 1e-3) / 1e12, 2),
+        "valu_workload": f"{blocks} workgroups x 256 lanes x {32 * iters} v_add_u32/v_xor_b32 "
+                         f"(mean of {reps})",
+        "valu_band_Tops": round(ops / (band_ms * 1e-3) / 1e12, 2),
+        "valu_band_workload": f"{blocks} workgroups x 256 lanes x {16 * iters} (v_sub_u32 from "
+                              "a scalar, v_cmp_le_u32 into VCC, s_or_b64), the nested-loop "
+                              f"band test's sequence (mean of {reps})",
+        "shader_clock_GHz": clock_ghz and round(clock_ghz, 3),
+        "valu_peak_at_shader_clock_Tops": clock_ghz and round(
+            props.multi_processor_count * 64 * clock_ghz * 1e9 / 1e12, 2),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -297,6 +346,7 @@ def main():
     _native.prof_enable(False)
 
     wall_ms = (t1 - t0) * 1e3 / args.steps
+    ceilings = measure_ceilings(J, _native, dev, stream)
     hu_ms = [r[0][2][0].elapsed_time(r[0][2][1]) for r in recs]
     hz_ms = [r[1][2][0].elapsed_time(r[1][2][1]) for r in recs]
     th_ms = [r[2][2][0].elapsed_time(r[2][2][1]) for r in recs]
@@ -393,13 +443,12 @@ def main():
     pairs_band = Rt.n * St.n
     alg = {
         # algorithmic bytes per launch (HBM-bound kernels) or int32 lane-ops (ALU-bound)
-        "hash.hist.R": ("hbm", 4 * nR),
-        "hash.hist.S": ("hbm", 4 * nS),
-        "hash.scatter.R": ("hbm", 16 * nR),
-        "hash.scatter.S": ("hbm", 16 * nS),
+        "hash.hist": ("hbm", 4 * (nR + nS)),  # both sides in one launch
+        "hash.scatter": ("hbm", 16 * (nR + nS)),
         "hash.count": ("hbm", 4 * nR + 4 * nS),
         "hash.write": ("hbm", 8 * nR + 8 * nS + 8 * nS),
-        "theta.count": ("alu", 2 * pairs_band),
+        # the band filter: one subtract per pair, one three-input min per two pairs
+        "theta.count": ("alu", 1.5 * pairs_band),
         "theta.write": ("hbm", 16 * n_th),
     }
     kernels = []
@@ -418,6 +467,8 @@ def main():
                 ach = per_launch / (avg * 1e-3) / 1e12
                 k.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
                          unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4))
+            meas = ceilings["copy_GBps"] if bound == "hbm" else ceilings["valu_band_Tops"]
+            k["frac_of_measured_ceiling"] = round(k["achieved"] / meas, 4)
             t = traffic.get(name)
             k["traffic"] = t
         kernels.append(k)
@@ -506,6 +557,7 @@ def main():
         "batch": batch,
         "serve": serving,
         "kernels": kernels,
+        "ceilings": ceilings,
         "src_hash": src_hash(),
     }
     print(json.dumps(out), flush=True)

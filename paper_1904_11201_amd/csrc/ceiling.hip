@@ -1,0 +1,147 @@
+// ceiling.hip -- what the chip sustains, for roofline fractions against measured rather than
+// published peaks (include/join_prof.h): a streaming copy and an int32 VALU spin.
+#include "common.hpp"
+#include "join_prof.h"
+#include "prof.hpp"
+
+namespace jl {
+namespace {
+
+constexpr int kCopyBlock = 256;
+constexpr int kCopyUnroll = 4;
+constexpr int kSpinBlock = 256;
+constexpr int kSpinChains = 16;
+constexpr uint32_t kSpinWidth = 1u << 20;  // band width of the MIX 1 compares
+
+// Grid-stride copy of 16-byte vectors: each lane issues kCopyUnroll loads, then the stores.
+__global__ __launch_bounds__(kCopyBlock) void copy_k(const i32x4* __restrict__ src,
+                                                      i32x4* __restrict__ dst, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kCopyBlock;
+    uint64_t i = (uint64_t)blockIdx.x * kCopyBlock + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n; i += kCopyUnroll * stride) {
+        i32x4 v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// Each iteration issues exactly 2 * kSpinChains VALU instructions per lane, written as assembly
+// so that the compiler can neither fuse nor drop them.  MIX 0: kSpinChains independent chains of
+// v_add_u32 + v_xor_b32.  MIX 1: the band test of the nested-loop join, v_sub_u32 of a lane value
+// from a scalar, v_cmp_le_u32 into VCC and s_or_b64 of VCC into a scalar mask (on the scalar
+// unit).  Workgroup 0 reads the shader clock counter and the constant-rate real-time counter
+// around its loop.
+// One step of the band spin: subtract the next lane value, or the previous mask into %0, compare.
+#define SPIN_BAND_STEP(A) "v_sub_u32 %1, %2, " A "\n\ts_or_b64 %0, %0, vcc\n\tv_cmp_le_u32 vcc, %1, %3\n\t"
+
+template <int MIX>
+__global__ __launch_bounds__(kSpinBlock) void spin_k(uint32_t seed, uint32_t iters, uint32_t* sink,
+                                                     uint64_t* clk)
+{
+    const uint32_t gid = blockIdx.x * kSpinBlock + threadIdx.x;
+    const uint32_t b = seed ^ blockIdx.x;
+    const uint32_t wv = kSpinWidth;
+    uint32_t a[kSpinChains];
+#pragma unroll
+    for (int j = 0; j < kSpinChains; ++j) a[j] = gid * kSpinChains + j;
+    uint64_t acc = 0;
+    const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
+    uint64_t c0 = 0, r0 = 0;
+    if (timer) {
+        c0 = __builtin_amdgcn_s_memtime();
+        r0 = __builtin_amdgcn_s_memrealtime();
+    }
+    for (uint32_t it = 0; it < iters; ++it) {
+        if (MIX == 0) {
+#pragma unroll
+            for (int j = 0; j < kSpinChains; ++j)
+                asm volatile("v_add_u32 %0, %0, %1\n\tv_xor_b32 %0, %0, %1" : "+v"(a[j]) : "v"(b));
+        } else {
+            // the nested-loop join's order: each subtract is issued before the previous compare's
+            // mask is or-ed in, through one temporary and VCC
+            uint32_t t;
+            asm volatile(
+                "v_sub_u32 %1, %2, %4\n\tv_cmp_le_u32 vcc, %1, %3\n\t"
+                SPIN_BAND_STEP("%5") SPIN_BAND_STEP("%6") SPIN_BAND_STEP("%7") SPIN_BAND_STEP("%8")
+                SPIN_BAND_STEP("%9") SPIN_BAND_STEP("%10") SPIN_BAND_STEP("%11") SPIN_BAND_STEP("%12")
+                SPIN_BAND_STEP("%13") SPIN_BAND_STEP("%14") SPIN_BAND_STEP("%15") SPIN_BAND_STEP("%16")
+                SPIN_BAND_STEP("%17") SPIN_BAND_STEP("%18") SPIN_BAND_STEP("%19")
+                "s_or_b64 %0, %0, vcc"
+                : "+s"(acc), "=&v"(t)
+                : "s"(b), "v"(wv), "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]),
+                  "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]),
+                  "v"(a[12]), "v"(a[13]), "v"(a[14]), "v"(a[15])
+                : "vcc", "scc");  // s_or_b64 sets SCC
+        }
+    }
+    if (timer) {
+        const uint64_t c1 = __builtin_amdgcn_s_memtime();
+        const uint64_t r1 = __builtin_amdgcn_s_memrealtime();
+        clk[0] = c1 - c0;
+        clk[1] = r1 - r0;
+    }
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < kSpinChains; ++j) f ^= a[j];
+    sink[gid] = MIX == 0 ? f : (uint32_t)acc ^ (uint32_t)(acc >> 32);
+}
+
+}  // namespace
+}  // namespace jl
+
+using namespace jl;
+
+extern "C" {
+
+int join_prof_copy(const void* src, void* dst, uint64_t bytes, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if ((bytes && (!src || !dst)) || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16) {
+        set_error("join_prof_copy: bytes must be a multiple of 16 and both pointers 16-byte aligned");
+        return JOIN_E_INVAL;
+    }
+    if (!bytes) return JOIN_OK;
+    int dev = 0, cus = 0;
+    JL_HIP(hipGetDevice(&dev));
+    JL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint64_t n = bytes / 16;
+    const uint64_t want = ceil_div((int64_t)n, (int64_t)kCopyBlock * kCopyUnroll);
+    const uint32_t grid = (uint32_t)(want < (uint64_t)cus * 16 ? want : (uint64_t)cus * 16);
+    prof::Scope ps(st, "ceiling.copy");
+    copy_k<<<grid, kCopyBlock, 0, st>>>((const i32x4*)src, (i32x4*)dst, n);
+    JL_LAUNCH("copy_k");
+    return JOIN_OK;
+}
+
+int join_prof_valu(uint32_t blocks, uint32_t iters, int mix, uint32_t* sink, uint64_t* clk,
+                   void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (!blocks || blocks > (1u << 22) || !sink || !clk || (mix != 0 && mix != 1)) {
+        set_error("join_prof_valu: blocks must be in [1, 2^22], mix 0 or 1, sink and clk non-null");
+        return JOIN_E_INVAL;
+    }
+    prof::Scope ps(st, mix ? "ceiling.valu.band" : "ceiling.valu");
+    if (mix) spin_k<1><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
+    else spin_k<0><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
+    JL_LAUNCH("spin_k");
+    return JOIN_OK;
+}
+
+int join_prof_wall_clock_khz(int* khz)
+{
+    if (!khz) {
+        set_error("join_prof_wall_clock_khz: null pointer");
+        return JOIN_E_INVAL;
+    }
+    int dev = 0;
+    JL_HIP(hipGetDevice(&dev));
+    JL_HIP(hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev));
+    return JOIN_OK;
+}
+
+}  // extern "C"

@@ -75,12 +75,24 @@ __global__ void zero_u32_k(uint32_t* __restrict__ p, int64_t n)
 // ------------------------------------------------------------------------------- histogram --
 // Work items of the histogram and scatter kernels: one chunk of one relation side of one join.
 // A single join derives its items from the block index; a batch of joins reads them from a table.
+// The second side of a single join, launched together with the first so that one launch covers
+// both: workgroups from `split` on take its chunks.  split = the grid size when the launch has
+// one side only.
+struct SideTwo {
+    SideItem one;
+    int64_t chunk, n;
+    uint32_t* tot;  // histogram: its partition sizes
+    uint32_t* grp;  // histogram: its group shares; scatter: its group cursors
+    int2* out;      // scatter: its partitioned tuples
+    uint32_t split;
+};
+
 __device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items, const SideItem& one,
-                                              int64_t chunk, int64_t n)
+                                              int64_t chunk, int64_t n, uint32_t blk)
 {
     if (items) {
         // scalar loads: the item is the same for the whole workgroup
-        const cptr<SideItem> p = as_const(items) + blockIdx.x;
+        const cptr<SideItem> p = as_const(items) + blk;
         SideItem it;
         it.key = p->key;
         it.rid = p->rid;
@@ -91,7 +103,7 @@ __device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items
         return it;
     }
     SideItem it = one;
-    it.beg = (int64_t)blockIdx.x * chunk;
+    it.beg = (int64_t)blk * chunk;
     const int64_t left = n - it.beg;
     it.len = (uint32_t)(left < chunk ? left : chunk);
     return it;
@@ -107,12 +119,18 @@ __device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p 
 __device__ __forceinline__ uint32_t group_of_block() { return blockIdx.x % kGroups; }
 
 __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict__ items, SideItem one,
-                                                     int64_t chunk, int64_t n, uint32_t* __restrict__ tot,
-                                                     uint32_t* __restrict__ grp, uint32_t stride)
+                                                     int64_t chunk, int64_t n, uint32_t* tot,
+                                                     uint32_t* grp, uint32_t stride, SideTwo two)
 {
     extern __shared__ uint32_t h[];
     constexpr int V = 4;  // 16-byte loads in flight per thread
-    const SideItem it = side_item(items, one, chunk, n);
+    const bool second = blockIdx.x >= two.split;
+    const SideItem it = second ? side_item(nullptr, two.one, two.chunk, two.n, blockIdx.x - two.split)
+                               : side_item(items, one, chunk, n, blockIdx.x);
+    if (second) {
+        tot = two.tot;
+        grp = two.grp;
+    }
     const int P = 1 << it.bits;
     const int sh = 32 - it.bits;
     for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
@@ -332,38 +350,6 @@ __device__ __forceinline__ void scat_chunk(gptr<int32_t> key, gptr<int32_t> rid,
     }
 }
 
-// RIDS: the side has a rid column (a batch passes RIDS and may still leave it NULL per item;
-// without rids the row ids are positions).  cur: group cursors, [kGroups][stride].
-template <bool RIDS>
-__global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restrict__ items, SideItem one,
-                                                        int64_t chunk, int64_t n,
-                                                        uint32_t* __restrict__ cur, uint32_t stride,
-                                                        int2* __restrict__ out)
-{
-    extern __shared__ uint32_t lds[];
-    const SideItem it = side_item(items, one, chunk, n);
-    const int P = 1 << it.bits;
-    const int sh = 32 - it.bits;
-    ScatLds L;
-    L.stg = reinterpret_cast<int2*>(lds);
-    L.cnt = lds + 2 * kScatTile;
-    L.dlt = L.cnt + P;
-    L.tmp = L.dlt + P;
-    const int tid = threadIdx.x;
-    if (2 * tid < P) L.cnt[2 * tid] = 0;
-    if (2 * tid + 1 < P) L.cnt[2 * tid + 1] = 0;
-    __syncthreads();
-    uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
-    const gptr<int32_t> key = as_global(it.key + it.beg);
-    const bool kvec = aligned16(it.key + it.beg);
-    if (!RIDS || it.rid == nullptr) {
-        scat_chunk<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, gc, out);
-    } else {
-        const bool vec = kvec && aligned16(it.rid + it.beg);
-        scat_chunk<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, gc, out);
-    }
-}
-
 // ------------------------------------------------------------------------------- planning --
 // Per partition: its ranges in the partitioned tuples and its work units.  In a batch the
 // partition's join (and so its fan-out) is found by binary search over the joins' first
@@ -489,20 +475,21 @@ __global__ __launch_bounds__(kFuseBlock) void part_starts_k(const uint32_t* __re
     }
 }
 
-__global__ __launch_bounds__(kFuseBlock) void plan_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
-                                                     uint32_t* __restrict__ unitStart,
-                                                     uint32_t* __restrict__ Utotal, int64_t Umax,
-                                                     uint32_t* __restrict__ umap)
+// The plans of all partitions by one workgroup of BLOCK threads, two partitions per thread and
+// pass; tmp: BLOCK / 64 + 1 words of LDS.
+template <int BLOCK>
+__device__ void plan_block(const PartPlan& q, int nParts, PartInfo* __restrict__ info,
+                           uint32_t* __restrict__ unitStart, uint32_t* __restrict__ Utotal,
+                           int64_t Umax, uint32_t* __restrict__ umap, uint32_t* tmp)
 {
-    __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
     uint32_t carry = 0;
-    for (int b0 = 0; b0 < nParts; b0 += 2 * kFuseBlock) {
+    for (int b0 = 0; b0 < nParts; b0 += 2 * BLOCK) {
         const int pa = b0 + 2 * (int)threadIdx.x, pb = pa + 1;
         PartInfo ia{}, ib{};
         const uint32_t ua = pa < nParts ? plan_part(q, pa, ia) : 0u;
         const uint32_t ub = pb < nParts ? plan_part(q, pb, ib) : 0u;
         uint32_t t;
-        const uint32_t sa = carry + block_excl_scan<kFuseBlock>(ua + ub, tmp, &t);
+        const uint32_t sa = carry + block_excl_scan<BLOCK>(ua + ub, tmp, &t);
         if (pa < nParts) {
             info[pa] = ia;
             unitStart[pa] = sa;
@@ -518,6 +505,72 @@ __global__ __launch_bounds__(kFuseBlock) void plan_k(PartPlan q, int nParts, Par
     if (threadIdx.x == 0) {
         unitStart[nParts] = carry;
         *Utotal = carry;
+    }
+}
+
+__global__ __launch_bounds__(kFuseBlock) void plan_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
+                                                     uint32_t* __restrict__ unitStart,
+                                                     uint32_t* __restrict__ Utotal, int64_t Umax,
+                                                     uint32_t* __restrict__ umap)
+{
+    __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
+    plan_block<kFuseBlock>(q, nParts, info, unitStart, Utotal, Umax, umap, tmp);
+}
+
+// The per-partition plan can ride along with the scatter of a single join: with pa.info set, the
+// last workgroup computes it (the partition starts it reads come from the launch before).
+struct PlanArgs {
+    PartPlan q;
+    int nParts;
+    PartInfo* info;
+    uint32_t* units;
+    uint32_t* Utotal;
+    int64_t Umax;
+    uint32_t* umap;
+};
+
+// RIDS: the side has a rid column (a batch passes RIDS and may still leave it NULL per item;
+// without rids the row ids are positions).  cur: group cursors, [kGroups][stride].
+template <bool RIDS>
+__global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restrict__ items, SideItem one,
+                                                        int64_t chunk, int64_t n, uint32_t* cur,
+                                                        uint32_t stride, int2* out, SideTwo two,
+                                                        PlanArgs pa)
+{
+    extern __shared__ uint32_t lds[];
+    // The chunk of workgroup b is the one the histogram counted in workgroup b: its group shares
+    // were counted under the same group, so the plan's workgroup comes after every chunk.
+    const uint32_t blk = blockIdx.x;
+    if (pa.info && blk == gridDim.x - 1) {
+        plan_block<kScatBlock>(pa.q, pa.nParts, pa.info, pa.units, pa.Utotal, pa.Umax, pa.umap, lds);
+        return;
+    }
+    const bool second = blk >= two.split;
+    const SideItem it = second ? side_item(nullptr, two.one, two.chunk, two.n, blk - two.split)
+                               : side_item(items, one, chunk, n, blk);
+    if (second) {
+        cur = two.grp;
+        out = two.out;
+    }
+    const int P = 1 << it.bits;
+    const int sh = 32 - it.bits;
+    ScatLds L;
+    L.stg = reinterpret_cast<int2*>(lds);
+    L.cnt = lds + 2 * kScatTile;
+    L.dlt = L.cnt + P;
+    L.tmp = L.dlt + P;
+    const int tid = threadIdx.x;
+    if (2 * tid < P) L.cnt[2 * tid] = 0;
+    if (2 * tid + 1 < P) L.cnt[2 * tid + 1] = 0;
+    __syncthreads();
+    uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
+    const gptr<int32_t> key = as_global(it.key + it.beg);
+    const bool kvec = aligned16(it.key + it.beg);
+    if (!RIDS || it.rid == nullptr) {
+        scat_chunk<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, gc, out);
+    } else {
+        const bool vec = kvec && aligned16(it.rid + it.beg);
+        scat_chunk<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, gc, out);
     }
 }
 
@@ -994,8 +1047,49 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
     return cnt;
 }
 
+// Up to kFuseScanMax units, the count kernel's last workgroup to finish also scans the counts,
+// which saves the launch of a separate scan (a launch boundary costs several microseconds).
+constexpr int kFuseScanPer = 8;
+constexpr int64_t kFuseScanMax = (int64_t)kJoinBlock * kFuseScanPer;
+
+// Exclusive scan of counts[0, U) in place by one workgroup, kFuseScanPer consecutive counts per
+// thread; entries U..Umax-1 are set to the sum, and *total receives it.  wsum: kJoinBlock / 64
+// words of LDS.
+__device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, uint64_t* total,
+                                  uint64_t* wsum)
+{
+    const int64_t i0 = (int64_t)threadIdx.x * kFuseScanPer;
+    uint64_t v[kFuseScanPer];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kFuseScanPer; ++k) {
+        v[k] = i0 + k < (int64_t)U ? counts[i0 + k] : 0;
+        s += v[k];
+    }
+    const uint64_t inc = wave_incl_scan64(s);
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[wv] = inc;
+    __syncthreads();
+    uint64_t run = inc - s, sum = 0;
+#pragma unroll
+    for (int w = 0; w < kJoinBlock / kWave; ++w) {
+        const uint64_t t = wsum[w];
+        run += w < wv ? t : 0;
+        sum += t;
+    }
+#pragma unroll
+    for (int k = 0; k < kFuseScanPer; ++k) {
+        if (i0 + k < Umax) counts[i0 + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) *total = sum;
+}
+
+// done: NULL, or a zeroed arrival counter; then the last workgroup to arrive scans the counts
+// (Umax <= kFuseScanMax) and writes the sum to *total.
 template <bool AOS>
-__global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts)
+__global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
+                                           uint32_t* __restrict__ done, uint64_t* __restrict__ total)
 {
     extern __shared__ uint4 tab[];
     __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
@@ -1034,6 +1128,22 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         if (threadIdx.x == 0) counts[u] = tot;
         __syncthreads();
         un = nx;
+    }
+    if (done) {
+        // Thread 0 wrote every count of this workgroup: a device-scope release orders them before
+        // its arrival.  Only the last to arrive acquires (an acquire also drops the L2 lines that
+        // workgroups still running on this XCD are reading).
+        __shared__ uint32_t last;
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            last = atomicAdd(done, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            scan_counts_block(counts, U, g.Umax, total, reinterpret_cast<uint64_t*>(tab));
+        }
+        return;
     }
     // units past the device-side total must read as zero for the scan over Umax entries
     for (int64_t i = (int64_t)U + (int64_t)blockIdx.x * kJoinBlock + threadIdx.x; i < g.Umax;
@@ -1239,7 +1349,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         pl.off_tot = off;
         pl.off_grpS = off + (size_t)2 * pl.P * 4;
         pl.off_grpR = pl.off_grpS + (size_t)kGroups * pl.P * 4;
-        off = align_up(pl.off_grpR + (size_t)kGroups * pl.P * 4);
+        pl.off_done = pl.off_grpR + (size_t)kGroups * pl.P * 4;  // cleared with the sizes and shares
+        off = align_up(pl.off_done + 4);
         pl.off_baseR = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
         pl.off_baseS = off;
@@ -1311,8 +1422,31 @@ static hipError_t hist_side(const SideItem* items, const SideItem& one, int64_t 
 {
     if (grid <= 0) return hipSuccess;
     const size_t hl = (size_t)4 << maxBits;
+    SideTwo none{};
+    none.split = (uint32_t)grid;
     prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
-    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, grp, (uint32_t)stride);
+    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, grp, (uint32_t)stride, none);
+    return hipGetLastError();
+}
+
+// Both sides of a single join in one launch, R's chunks first: a launch boundary costs about as
+// much as a small kernel.
+static hipError_t hist_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64_t gridR,
+                            uint32_t* totR, uint32_t* grpR, const SideItem& oneS, int64_t chS,
+                            int64_t nS, int64_t gridS, uint32_t* totS, uint32_t* grpS, int bits,
+                            int64_t stride, hipStream_t st)
+{
+    if (gridR + gridS <= 0) return hipSuccess;
+    SideTwo two{};
+    two.one = oneS;
+    two.chunk = chS;
+    two.n = nS;
+    two.tot = totS;
+    two.grp = grpS;
+    two.split = (uint32_t)gridR;
+    prof::Scope ph(st, "hash.hist");
+    hist_k<<<(unsigned)(gridR + gridS), kHistBlock, (size_t)4 << bits, st>>>(
+        nullptr, oneR, chR, nR, totR, grpR, (uint32_t)stride, two);
     return hipGetLastError();
 }
 
@@ -1374,15 +1508,44 @@ static hipError_t plan_parts(const PartPlan& q, int64_t nParts, PartInfo* info, 
 
 static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
                                int64_t grid, int maxBits, uint32_t* cur, int64_t stride, int2* out,
-                               hipStream_t st, bool is_r)
+                               hipStream_t st, bool is_r, const PlanArgs* plan = nullptr)
 {
-    if (grid <= 0) return hipSuccess;
+    const PlanArgs pa = plan ? *plan : PlanArgs{};
+    const int64_t all = grid + (plan ? 1 : 0);
+    if (all <= 0) return hipSuccess;
     const size_t sl = scatter_lds(1 << maxBits);
+    SideTwo none{};
+    none.split = (uint32_t)grid;
     prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
     if (items != nullptr || one.rid != nullptr)
-        scatter_k<true><<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out);
+        scatter_k<true><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, none, pa);
     else
-        scatter_k<false><<<(unsigned)grid, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out);
+        scatter_k<false><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, none, pa);
+    return hipGetLastError();
+}
+
+// Both sides of a single join in one launch, R's chunks first (the plan's workgroup last).
+static hipError_t scatter_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64_t gridR,
+                               uint32_t* curR, int2* outR, const SideItem& oneS, int64_t chS,
+                               int64_t nS, int64_t gridS, uint32_t* curS, int2* outS, int bits,
+                               int64_t stride, hipStream_t st, const PlanArgs* plan)
+{
+    const PlanArgs pa = plan ? *plan : PlanArgs{};
+    const int64_t all = gridR + gridS + (plan ? 1 : 0);
+    if (all <= 0) return hipSuccess;
+    SideTwo two{};
+    two.one = oneS;
+    two.chunk = chS;
+    two.n = nS;
+    two.grp = curS;
+    two.out = outS;
+    two.split = (uint32_t)gridR;
+    const size_t sl = scatter_lds(1 << bits);
+    prof::Scope ps(st, "hash.scatter");
+    if (oneR.rid != nullptr || oneS.rid != nullptr)
+        scatter_k<true><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, two, pa);
+    else
+        scatter_k<false><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, two, pa);
     return hipGetLastError();
 }
 
@@ -1442,46 +1605,59 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
             // a prebuilt R keeps its sizes: only the S sizes and shares are cleared
             prof::Scope pz(st, "hash.plan");
             uint32_t* z = pre ? totS : totR;
-            const int64_t nz = (pre ? 1 + kGroups : 2 + 2 * kGroups) * (int64_t)pl.P;
+            const int64_t nz = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 1 - z;
             zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(z, nz);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         const SideItem oneR = whole_side(R, pl.bits), oneS = whole_side(S, pl.bits);
-        if (!pre) {
-            e = hist_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, totR, grpR, pl.P, st, true);
-            if (e != hipSuccess) return e;
-        }
-        e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, st, false);
+        if (pre)
+            e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, st, false);
+        else
+            e = hist_pair(oneR, pl.chR, R.n, pl.nChR, totR, grpR, oneS, pl.chS, S.n, pl.nChS, totS,
+                          grpS, pl.bits, pl.P, st);
         if (e != hipSuccess) return e;
         e = starts_sides(pre ? nullptr : totR, baseR, grpR, totS, baseS, grpS, pl.P,
                          reinterpret_cast<uint32_t*>(temp), st);
         if (e != hipSuccess) return e;
-        if (!pre) {
-            e = scatter_side(nullptr, oneR, pl.chR, R.n, pl.nChR, pl.bits, grpR, pl.P, tupR, st, true);
-            if (e != hipSuccess) return e;
-        }
-        e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, grpS, pl.P, tupS, st, false);
-        if (e != hipSuccess) return e;
         const uint32_t* pbaseR = pre ? pre->base : baseR;
         const uint32_t* ptotR = pre ? pre->tot : totR;
-        PartPlan q{pbaseR, ptotR, baseS, totS, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
-                   (uint32_t)pl.slice};
-        e = plan_parts(q, pl.P, reinterpret_cast<PartInfo*>(ws + pl.off_info),
-                       reinterpret_cast<uint32_t*>(ws + pl.off_units), reinterpret_cast<uint32_t*>(ws + 8),
-                       pl.Umax, reinterpret_cast<uint32_t*>(ws + pl.off_umap),
-                       reinterpret_cast<uint32_t*>(temp), st);
+        PlanArgs pa{};
+        pa.q = PartPlan{pbaseR, ptotR, baseS, totS, nullptr, nullptr, 0, pl.bits, (uint32_t)pl.cap,
+                        (uint32_t)pl.slice};
+        pa.nParts = (int)pl.P;
+        pa.info = reinterpret_cast<PartInfo*>(ws + pl.off_info);
+        pa.units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
+        pa.Utotal = reinterpret_cast<uint32_t*>(ws + 8);
+        pa.Umax = pl.Umax;
+        pa.umap = reinterpret_cast<uint32_t*>(ws + pl.off_umap);
+        // up to kFuseParts partitions the plan is one workgroup of the scatter launch
+        const PlanArgs* fused = pl.P <= kFuseParts ? &pa : nullptr;
+        if (pre)
+            e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, grpS, pl.P, tupS, st, false,
+                             fused);
+        else
+            e = scatter_pair(oneR, pl.chR, R.n, pl.nChR, grpR, tupR, oneS, pl.chS, S.n, pl.nChS, grpS,
+                             tupS, pl.bits, pl.P, st, fused);
         if (e != hipSuccess) return e;
+        if (!fused) {
+            e = plan_parts(pa.q, pl.P, pa.info, pa.units, pa.Utotal, pl.Umax, pa.umap,
+                           reinterpret_cast<uint32_t*>(temp), st);
+            if (e != hipSuccess) return e;
+        }
     }
     if (pl.Umax > 0) {
         const JoinGeom g = make_geom(pl, R, S, ws, pre);
         const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridCount);
         const size_t lds = table_lds((uint32_t)pl.cap, false);
+        // the partitioned path cleared the arrival counter with the partition sizes
+        uint32_t* done = !pl.single && pl.Umax <= kFuseScanMax
+                             ? reinterpret_cast<uint32_t*>(ws + pl.off_done) : nullptr;
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts);
-        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts);
+        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, nullptr, total);
+        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, done, total);
         e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || done) return e;
     }
     return exclusive_scan<uint64_t>(counts, counts, pl.Umax, total, reinterpret_cast<uint64_t*>(temp), st);
 }
@@ -1768,7 +1944,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
         prof::Scope pc(st, "hash.count");
-        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts);
+        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -52,7 +52,7 @@ struct HashPlan {
     int64_t chR, chS, nChR, nChS;
     int64_t Umax;
     int gridCount, gridWrite;  // persistent grids of the count and write kernels
-    size_t off_tot, off_grpR, off_grpS, off_baseR, off_baseS, off_tupR, off_tupS;
+    size_t off_tot, off_grpR, off_grpS, off_done, off_baseR, off_baseS, off_tupR, off_tupS;
     size_t off_info, off_units, off_umap;
     size_t off_counts, off_temp, bytes;
 };

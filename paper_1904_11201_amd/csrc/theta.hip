@@ -222,17 +222,28 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
             }
         }
     };
+    // A pair can hold only if s - x0 <= x1 for its R row (equality: s - x0 == 0), and x1 <= wmax
+    // for every row (rows clamped at the ends of the int32 range have narrower bands), so a
+    // group with min(s - x0) over its 64 pairs above wmax holds no pair.  The running minimum
+    // costs one subtract per pair and one three-input min per two pairs, with one compare per
+    // group; two minima alternate so consecutive mins do not wait on each other.
+    const uint32_t wmax = OPA == JOIN_OP_BAND ? (uint32_t)(2 * (int64_t)g.w) : 0u;
     int64_t j = s0;
     for (; j + kSGroup <= s1; j += kSGroup) {
         int32_t sa[kSGroup];
 #pragma unroll
         for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
-        uint64_t any = 0;
+        uint32_t m0 = ~0u, m1 = ~0u;
 #pragma unroll
         for (int k = 0; k < kSGroup; ++k)
 #pragma unroll
-            for (int r = 0; r < kRB; ++r) any |= ballot(holds<OPA>(rr.x0[r], rr.x1[r], sa[k]));
-        if (any) exact(j, j + kSGroup);
+            for (int r = 0; r < kRB; r += 2) {
+                const uint32_t d0 = (uint32_t)(sa[k] - rr.x0[r]);
+                const uint32_t d1 = (uint32_t)(sa[k] - rr.x0[r + 1]);
+                if (k & 1) m1 = min(min(m1, d0), d1);
+                else m0 = min(min(m0, d0), d1);
+            }
+        if (ballot(min(m0, m1) <= wmax)) exact(j, j + kSGroup);
     }
     if (j < s1) exact(j, s1);
 }

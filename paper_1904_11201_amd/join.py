@@ -181,6 +181,37 @@ def join_scan_u64(x: torch.Tensor, stream=None):
     return out, total
 
 
+def prof_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Plain device copy src -> dst (same byte size, multiple of 16): the HBM ceiling."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("prof_copy: src and dst sizes differ")
+    _check(_native.lib.join_prof_copy(ctypes.c_void_p(src.data_ptr()),
+                                      ctypes.c_void_p(dst.data_ptr()), nb, _stream(stream)))
+
+
+def prof_valu(blocks: int, iters: int, sink: torch.Tensor, clk: torch.Tensor, stream=None,
+              mix: int = 0) -> int:
+    """int32 VALU spin: blocks x 256 lanes x 32 x iters lane-operations (returned); mix 0 add/xor
+    chains, mix 1 the band test's subtract, compare and mask.  sink is an int32 tensor of
+    blocks * 256 elements, clk an int64 tensor of 2 (shader cycles, real-time ticks of
+    workgroup 0)."""
+    if sink.dtype != torch.int32 or sink.numel() < blocks * 256:
+        raise ValueError("prof_valu: sink must be int32 with blocks * 256 elements")
+    if clk.dtype != torch.int64 or clk.numel() < 2:
+        raise ValueError("prof_valu: clk must be int64 with 2 elements")
+    _check(_native.lib.join_prof_valu(blocks, iters, mix, ctypes.c_void_p(sink.data_ptr()),
+                                      ctypes.c_void_p(clk.data_ptr()), _stream(stream)))
+    return blocks * 256 * 32 * iters
+
+
+def prof_wall_clock_hz() -> float:
+    """Rate of the device's constant real-time counter."""
+    khz = ctypes.c_int()
+    _check(_native.lib.join_prof_wall_clock_khz(ctypes.byref(khz)))
+    return khz.value * 1e3
+
+
 def _exact(kind, R, S, pred, ws, stream):
     if ws is None:
         ws = workspace(kind, R.n, S.n, pred, device=R.key.device)

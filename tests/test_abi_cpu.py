@@ -171,3 +171,18 @@ def test_build_sizes_and_argument_errors():
     c = ctypes.c_uint64(0)
     assert n.lib.join_probe_count(ctypes.byref(n.JoinBuild()), fake, ctypes.byref(S), None, 0, None,
                                   ctypes.byref(c)) == n.JOIN_E_INVAL
+
+
+def test_ceiling_calls_reject_bad_arguments():
+    lib = n.lib
+    # size not a multiple of 16, null pointers with bytes > 0, misaligned pointers
+    assert lib.join_prof_copy(None, None, 8, None) == 1
+    assert lib.join_prof_copy(None, None, 16, None) == 1
+    assert lib.join_prof_copy(ctypes.c_void_p(8), ctypes.c_void_p(64), 16, None) == 1
+    assert lib.join_prof_copy(None, None, 0, None) == 0
+    sink = ctypes.c_void_p(256)
+    assert lib.join_prof_valu(0, 1, 0, sink, sink, None) == 1
+    assert lib.join_prof_valu((1 << 22) + 1, 1, 0, sink, sink, None) == 1
+    assert lib.join_prof_valu(1, 1, 0, None, sink, None) == 1
+    assert lib.join_prof_valu(1, 1, 2, sink, sink, None) == 1
+    assert "join_prof_valu" in n.last_error()
