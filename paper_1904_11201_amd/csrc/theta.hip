@@ -94,8 +94,8 @@ struct RRows {
 };
 
 // A copy of the R constants the compiler cannot prove equal to the originals.  The rare exact
-// path of a selective group evaluates on this copy, so the 64 masks of the fast OR-filter die
-// right after the OR instead of being kept alive (and spilled) for reuse.
+// path of a selective group evaluates on this copy, so the filter's 64 differences die right
+// after the minimum instead of being kept alive (and spilled) for reuse.
 __device__ __forceinline__ RRows opaque_copy(const RRows& a)
 {
     RRows b = a;
@@ -183,9 +183,9 @@ __device__ __forceinline__ void load_rids(const ThetaGeom& g, int64_t r0, int64_
     }
 }
 
-// Selective predicates: OR-filter 8 S rows at a time on op_a alone; a group with a hit is
+// Selective predicates: filter 8 S rows at a time on op_a alone; a group that may hold a pair is
 // evaluated exactly and its pairs go to `out` (capacity `cap`) starting at `base`.  The fast
-// filter keeps only op_a's two constants per R row live.  The rare exact path walks one R row
+// filter keeps only op_a's constants per R row live.  The rare exact path walks one R row
 // at a time and reloads that row's c value and rid (cache-resident), so it needs only a few
 // registers beyond the filter's and the filter keeps its occupancy.  Pairs of a group are
 // emitted in (R row r, S row j, lane) order.
@@ -252,8 +252,8 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
 // Selective predicates also keep up to K matches of the unit in a per-unit stash, so the write
 // pass of a unit with at most K matches is a copy instead of a second sweep.
 // DENSE (region units of a selective predicate): the units were chosen because their value
-// ranges are close, so most 8-row groups hold a match and the OR-filter would send nearly every
-// group down its exact path.  Instead every S row is evaluated exactly against the wave's R rows
+// ranges are close, so most 8-row groups hold a match and the group filter would send nearly
+// every group down its exact path.  Instead every S row is evaluated exactly against the wave's R rows
 // (both columns and rids kept in registers), one ballot per R row.
 template <int OPA, int OPC, bool DENSE = false>
 __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
