@@ -34,20 +34,23 @@ int join_prof_entry(int i, const char** name, uint64_t* launches, double* total_
  * Two plain kernels whose rates are what the chip sustains, so that roofline fractions can be
  * given against measured ceilings beside the published ones.  Both are stream-ordered on `stream`
  * (a hipStream_t passed as void*, NULL = the null stream),
- * allocate nothing, and are timed as "ceiling.copy", "ceiling.valu" (mix 0) and "ceiling.valu.band" (mix 1) while
- * profiling is on. */
+ * allocate nothing, and are timed as "ceiling.copy", "ceiling.valu" (mix 0), "ceiling.valu.band" (mix 1) and
+ * "ceiling.valu.min" (mix 2) while profiling is on. */
 
 /* Copy `bytes` from device buffer src to device buffer dst (both 16-byte aligned, bytes a
  * multiple of 16, not overlapping) with a grid-stride kernel of 16-byte non-temporal loads and
  * stores.  HBM traffic is 2 * bytes.  JOIN_E_INVAL for a misaligned or null argument. */
 int join_prof_copy(const void* src, void* dst, uint64_t bytes, void* stream);
 
-/* Run `blocks` workgroups of 256 lanes; every lane issues 32 * iters int32 VALU instructions, so
- * the launch performs blocks * 256 * 32 * iters lane-operations.  mix 0: 16 independent chains
- * of v_add_u32 + v_xor_b32 per lane, a[j] = 16 * lane + j, a[j] <- (a[j] + b) ^ b with
- * b = 0x9E3779B9 ^ workgroup, and sink[lane] = the xor of the 16 chains.  mix 1: the band test
- * of the nested-loop join, v_sub_u32 t = b - a[j], v_cmp_le_u32 t <= 2^20 into VCC and s_or_b64
- * of VCC into a 64-bit wave mask, and sink[lane] = the mask's two halves xored.  sink: device
+/* Run `blocks` workgroups of 256 lanes; every lane issues 32 * iters (mix 0, 1) or 48 * iters
+ * (mix 2) int32 VALU instructions, so the launch performs blocks * 256 * that many
+ * lane-operations.  mix 0: 16 independent chains of v_add_u32 + v_xor_b32 per lane,
+ * a[j] = 16 * lane + j, a[j] <- (a[j] + b) ^ b with b = 0x9E3779B9 ^ workgroup, and
+ * sink[lane] = the xor of the 16 chains.  mix 1: a band test, v_sub_u32 t = b - a[j],
+ * v_cmp_le_u32 t <= 2^20 into VCC and s_or_b64 of VCC into a 64-bit wave mask, and
+ * sink[lane] = the mask's two halves xored.  mix 2: the nested-loop join's group filter, for
+ * every pair (a[j], a[j+1]) two v_sub_u32 from b and a v_min3_u32 into one of two running
+ * minima, twice per iteration, and sink[lane] = the smaller minimum (all ones when iters == 0).  sink: device
  * array of blocks * 256 uint32; clk: device array of 2 uint64 that receives the shader clock
  * cycles and the real-time counter ticks workgroup 0 spent in its loop (the real-time counter's
  * rate comes from join_prof_wall_clock_khz).  JOIN_E_INVAL for blocks outside [1, 2^22], another

@@ -29,11 +29,13 @@ __global__ __launch_bounds__(kCopyBlock) void copy_k(const i32x4* __restrict__ s
     for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
-// Each iteration issues exactly 2 * kSpinChains VALU instructions per lane, written as assembly
-// so that the compiler can neither fuse nor drop them.  MIX 0: kSpinChains independent chains of
-// v_add_u32 + v_xor_b32.  MIX 1: the band test of the nested-loop join, v_sub_u32 of a lane value
-// from a scalar, v_cmp_le_u32 into VCC and s_or_b64 of VCC into a scalar mask (on the scalar
-// unit).  Workgroup 0 reads the shader clock counter and the constant-rate real-time counter
+// The VALU instructions are written as assembly so that the compiler can neither fuse nor drop
+// them; an iteration issues 2 * kSpinChains of them per lane (MIX 0, 1) or 3 * kSpinChains
+// (MIX 2).  MIX 0: kSpinChains independent chains of v_add_u32 + v_xor_b32.  MIX 1: the old band
+// test of the nested-loop join, v_sub_u32 of a lane value from a scalar, v_cmp_le_u32 into VCC
+// and s_or_b64 of VCC into a scalar mask (on the scalar unit).  MIX 2: the nested-loop join's
+// group filter, two v_sub_u32 from a scalar and a v_min3_u32 into one of two running minima, for
+// every pair of lane values, twice.  Workgroup 0 reads the shader clock counter and the constant-rate real-time counter
 // around its loop.
 // One step of the band spin: subtract the next lane value, or the previous mask into %0, compare.
 #define SPIN_BAND_STEP(A) "v_sub_u32 %1, %2, " A "\n\ts_or_b64 %0, %0, vcc\n\tv_cmp_le_u32 vcc, %1, %3\n\t"
@@ -49,6 +51,7 @@ __global__ __launch_bounds__(kSpinBlock) void spin_k(uint32_t seed, uint32_t ite
 #pragma unroll
     for (int j = 0; j < kSpinChains; ++j) a[j] = gid * kSpinChains + j;
     uint64_t acc = 0;
+    uint32_t mn[2] = {~0u, ~0u};
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     uint64_t c0 = 0, r0 = 0;
     if (timer) {
@@ -60,6 +63,18 @@ __global__ __launch_bounds__(kSpinBlock) void spin_k(uint32_t seed, uint32_t ite
 #pragma unroll
             for (int j = 0; j < kSpinChains; ++j)
                 asm volatile("v_add_u32 %0, %0, %1\n\tv_xor_b32 %0, %0, %1" : "+v"(a[j]) : "v"(b));
+        } else if (MIX == 2) {
+            // twice over the 16 lane values: two subtracts from the scalar, one three-input min
+            // into one of two running minima
+#pragma unroll
+            for (int rep = 0; rep < 2; ++rep)
+#pragma unroll
+                for (int j = 0; j < kSpinChains; j += 2) {
+                    uint32_t t0, t1;
+                    asm volatile("v_sub_u32 %1, %3, %4\n\tv_sub_u32 %2, %3, %5\n\tv_min3_u32 %0, %0, %1, %2"
+                                 : "+v"(mn[(j >> 1) & 1]), "=&v"(t0), "=&v"(t1)
+                                 : "s"(b), "v"(a[j]), "v"(a[j + 1]));
+                }
         } else {
             // the nested-loop join's order: each subtract is issued before the previous compare's
             // mask is or-ed in, through one temporary and VCC
@@ -87,7 +102,7 @@ __global__ __launch_bounds__(kSpinBlock) void spin_k(uint32_t seed, uint32_t ite
     uint32_t f = 0;
 #pragma unroll
     for (int j = 0; j < kSpinChains; ++j) f ^= a[j];
-    sink[gid] = MIX == 0 ? f : (uint32_t)acc ^ (uint32_t)(acc >> 32);
+    sink[gid] = MIX == 0 ? f : MIX == 2 ? min(mn[0], mn[1]) : (uint32_t)acc ^ (uint32_t)(acc >> 32);
 }
 
 }  // namespace
@@ -121,12 +136,13 @@ int join_prof_valu(uint32_t blocks, uint32_t iters, int mix, uint32_t* sink, uin
                    void* stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (!blocks || blocks > (1u << 22) || !sink || !clk || (mix != 0 && mix != 1)) {
-        set_error("join_prof_valu: blocks must be in [1, 2^22], mix 0 or 1, sink and clk non-null");
+    if (!blocks || blocks > (1u << 22) || !sink || !clk || mix < 0 || mix > 2) {
+        set_error("join_prof_valu: blocks must be in [1, 2^22], mix 0, 1 or 2, sink and clk non-null");
         return JOIN_E_INVAL;
     }
-    prof::Scope ps(st, mix ? "ceiling.valu.band" : "ceiling.valu");
-    if (mix) spin_k<1><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
+    prof::Scope ps(st, mix == 2 ? "ceiling.valu.min" : mix ? "ceiling.valu.band" : "ceiling.valu");
+    if (mix == 2) spin_k<2><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
+    else if (mix) spin_k<1><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
     else spin_k<0><<<blocks, kSpinBlock, 0, st>>>(0x9e3779b9u, iters, sink, clk);
     JL_LAUNCH("spin_k");
     return JOIN_OK;

@@ -192,17 +192,17 @@ def prof_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
 
 def prof_valu(blocks: int, iters: int, sink: torch.Tensor, clk: torch.Tensor, stream=None,
               mix: int = 0) -> int:
-    """int32 VALU spin: blocks x 256 lanes x 32 x iters lane-operations (returned); mix 0 add/xor
-    chains, mix 1 the band test's subtract, compare and mask.  sink is an int32 tensor of
-    blocks * 256 elements, clk an int64 tensor of 2 (shader cycles, real-time ticks of
-    workgroup 0)."""
+    """int32 VALU spin: blocks x 256 lanes x (32, or 48 for mix 2) x iters lane-operations
+    (returned); mix 0 add/xor chains, mix 1 a band test's subtract, compare and mask, mix 2 the
+    nested-loop join's subtract and three-input min.  sink is an int32 tensor of blocks * 256
+    elements, clk an int64 tensor of 2 (shader cycles, real-time ticks of workgroup 0)."""
     if sink.dtype != torch.int32 or sink.numel() < blocks * 256:
         raise ValueError("prof_valu: sink must be int32 with blocks * 256 elements")
     if clk.dtype != torch.int64 or clk.numel() < 2:
         raise ValueError("prof_valu: clk must be int64 with 2 elements")
     _check(_native.lib.join_prof_valu(blocks, iters, mix, ctypes.c_void_p(sink.data_ptr()),
                                       ctypes.c_void_p(clk.data_ptr()), _stream(stream)))
-    return blocks * 256 * 32 * iters
+    return blocks * 256 * (48 if mix == 2 else 32) * iters
 
 
 def prof_wall_clock_hz() -> float:

@@ -184,5 +184,5 @@ def test_ceiling_calls_reject_bad_arguments():
     assert lib.join_prof_valu(0, 1, 0, sink, sink, None) == 1
     assert lib.join_prof_valu((1 << 22) + 1, 1, 0, sink, sink, None) == 1
     assert lib.join_prof_valu(1, 1, 0, None, sink, None) == 1
-    assert lib.join_prof_valu(1, 1, 2, sink, sink, None) == 1
+    assert lib.join_prof_valu(1, 1, 3, sink, sink, None) == 1
     assert "join_prof_valu" in n.last_error()

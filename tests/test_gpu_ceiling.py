@@ -23,7 +23,7 @@ def test_copy_moves_every_byte(nbytes):
 
 
 @gpu
-@pytest.mark.parametrize("mix", [0, 1])
+@pytest.mark.parametrize("mix", [0, 1, 2])
 @pytest.mark.parametrize("blocks,iters", [(1, 0), (3, 1), (5, 257)])
 def test_valu_spin_results_and_clock(blocks, iters, mix):
     need_gpu()
@@ -33,7 +33,7 @@ def test_valu_spin_results_and_clock(blocks, iters, mix):
     clk = torch.zeros(2, dtype=torch.int64, device="cuda")
     ops = J.prof_valu(blocks, iters, sink, clk, mix=mix)
     torch.cuda.synchronize()
-    assert ops == blocks * 256 * 32 * iters
+    assert ops == blocks * 256 * (48 if mix == 2 else 32) * iters
     # each lane: a_j = 16 * gid + j, b = 0x9E3779B9 ^ block
     m32 = np.uint64(0xFFFFFFFF)
     gid = np.arange(blocks * 256, dtype=np.uint64)
@@ -43,6 +43,9 @@ def test_valu_spin_results_and_clock(blocks, iters, mix):
         for _ in range(iters):
             a = ((a + b[:, None]) & m32) ^ b[:, None]
         want = np.bitwise_xor.reduce(a, axis=1).astype(np.uint32).view(np.int32)
+    elif mix == 2:  # min over the lane's 16 values of (b - a_j) mod 2^32; all ones if no pass
+        d = ((b[:, None] - a) & m32).min(axis=1)
+        want = (d if iters > 0 else np.full_like(d, 0xFFFFFFFF)).astype(np.uint32).view(np.int32)
     else:  # wave mask of lanes with some (b - a_j) mod 2^32 <= 2^20; halves xored
         hit = (((b[:, None] - a) & m32) <= np.uint64(1 << 20)).any(axis=1) & (iters > 0)
         w = hit.reshape(-1, 64)

@@ -179,6 +179,20 @@ def test_lds_overflow_chunked_build(monkeypatch):
 
 
 @gpu
+def test_many_units_scan_kernels(monkeypatch):
+    """Over 8192 work units (64-entry tables at fan-out 8: about 9400 R chunks): the unit counts
+    go through the separate scan kernels instead of the count kernel's last workgroup."""
+    need_gpu()
+    R, S = datagen.small_random(23, 600_000, 800_000, 0, 300_000, rid_mode="random")
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
+    monkeypatch.setenv("JOIN_HASH_CAP", "64")
+    monkeypatch.setenv("JOIN_HASH_BITS", "8")
+    log("hash many units cap=64 bits=8")
+    got = canon_gpu(_hash(R, S))
+    assert len(got) == n and np.array_equal(got, ref)
+
+
+@gpu
 def test_skewed_build_and_probe():
     """Zipf keys on both sides: hot partitions are split into many S slices."""
     need_gpu()
