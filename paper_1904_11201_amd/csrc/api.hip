@@ -222,6 +222,61 @@ hipError_t read_total(const void* src, hipStream_t st, uint64_t* count)
     return e;
 }
 
+// The hash paths skip that copy: the kernel that produces the total also stores it into the
+// pinned slot through the slot's device address (publish_total), and the host polls the slot.
+// The slot holds kUnpublished until then; if the stream goes idle (or fails) with the slot
+// unchanged, the wait ends with an error instead of spinning on.
+constexpr uint64_t kUnpublished = ~0ull;
+
+// Device address of this thread's pinned slot, NULL when the runtime gives none (then the copy
+// above is used).
+uint64_t* published_slot()
+{
+    static thread_local struct {
+        bool done = false;
+        uint64_t* dev = nullptr;
+    } m;
+    if (!m.done) {
+        m.done = true;
+        uint64_t* slot = pinned_slot();
+        void* d = nullptr;
+        if (slot && hipHostGetDevicePointer(&d, slot, 0) == hipSuccess) m.dev = static_cast<uint64_t*>(d);
+        else (void)hipGetLastError();
+    }
+    return m.dev;
+}
+
+hipError_t wait_published(hipStream_t st, uint64_t* count)
+{
+    volatile uint64_t* slot = pinned_slot();
+    uint64_t v;
+    uint32_t spins = 0;
+    while ((v = *slot) == kUnpublished) {
+        __builtin_ia32_pause();
+        if ((++spins & 4095u) != 0) continue;
+        const hipError_t q = hipStreamQuery(st);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return q;
+        if ((v = *slot) == kUnpublished) return hipErrorLaunchFailure;  // idle, nothing stored
+        break;
+    }
+    *count = v;
+    return hipSuccess;
+}
+
+// Count pass of the hash paths, with the total read from the slot the kernels store it into.
+hipError_t hash_count_total(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
+                            hipStream_t st, const RView* pre, uint64_t* count, const char** what)
+{
+    uint64_t* pub = published_slot();
+    if (pub) *pinned_slot() = kUnpublished;
+    *what = pre ? "probe count pass" : "hash count pass";
+    hipError_t e = hash_count(pl, R, S, ws, st, pre, pub);
+    if (e != hipSuccess) return e;
+    *what = "reading the exact total";
+    return pub ? wait_published(st, count) : read_total(ws, st, count);
+}
+
 int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
                hipStream_t st, uint64_t* count)
 {
@@ -230,11 +285,13 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         *count = 0;
     } else {
         char* w = static_cast<char*>(ws);
-        hipError_t e;
+        hipError_t e = hipSuccess;
         size_t total_at = 0;  // where the exact total lands in ws
         if (kind == JOIN_KIND_HASH) {
             const HashPlan pl = hash_plan(R->n, S->n, num_cus());
-            e = hash_count(pl, *R, *S, w, st);
+            const char* what = "";
+            e = hash_count_total(pl, *R, *S, w, st, nullptr, count, &what);
+            if (e != hipSuccess) return hip_fail(e, what);
         } else if (kind == JOIN_KIND_HASH_PREFILTER) {
             const PrefilterPlan pl = prefilter_plan(R->n, S->n, num_cus());
             e = prefilter_count(pl, *R, *S, w, st, num_cus());
@@ -245,9 +302,12 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
             const ThetaPlan pl = plan_theta(R->n, S->n, p);
             e = theta_count(pl, *R, *S, *p, w, st);
         }
-        if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
-        e = read_total(w + total_at, st, count);
-        if (e != hipSuccess) return hip_fail(e, "reading the exact total");
+        if (kind != JOIN_KIND_HASH) {  // the hash path has its total already
+            if (e != hipSuccess)
+                return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
+            e = read_total(w + total_at, st, count);
+            if (e != hipSuccess) return hip_fail(e, "reading the exact total");
+        }
     }
     g_last.valid = true;
     g_last.kind = kind;
@@ -568,10 +628,9 @@ int join_probe_count(const join_build_t* desc, const void* build, const join_rel
         join_rel_t R{};
         R.n = b.nR;
         const RView v = build_view(b, build);
-        const hipError_t e = hash_count(pl, R, *S, static_cast<char*>(ws), st, &v);
-        if (e != hipSuccess) return hip_fail(e, "probe count pass");
-        const hipError_t er = read_total(ws, st, count);
-        if (er != hipSuccess) return hip_fail(er, "reading the exact total");
+        const char* what = "";
+        const hipError_t e = hash_count_total(pl, R, *S, static_cast<char*>(ws), st, &v, count, &what);
+        if (e != hipSuccess) return hip_fail(e, what);
     }
     g_last_probe.valid = true;
     g_last_probe.build = build;

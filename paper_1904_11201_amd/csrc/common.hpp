@@ -68,6 +68,14 @@ __device__ __forceinline__ gptr<T> as_global(const T* p)
 using i32x4 = int32_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ i32x4 load4(gptr<int32_t> p) { return *(const __attribute__((address_space(1))) i32x4*)p; }
 
+// Store a join's exact total into the caller's pinned host slot (device-visible address of host
+// memory), after every earlier write of this thread: a system-scope release store, so the host
+// thread polling the slot can size the output without a copy or a stream synchronisation.
+__device__ __forceinline__ void publish_total(uint64_t* pub, uint64_t v)
+{
+    __hip_atomic_store(pub, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // DPP control codes (GFX9 encoding).
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowShr2 = 0x112;

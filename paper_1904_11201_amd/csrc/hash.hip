@@ -1056,7 +1056,7 @@ constexpr int64_t kFuseScanMax = (int64_t)kJoinBlock * kFuseScanPer;
 // thread; entries U..Umax-1 are set to the sum, and *total receives it.  wsum: kJoinBlock / 64
 // words of LDS.
 __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, uint64_t* total,
-                                  uint64_t* wsum)
+                                  uint64_t* pub, uint64_t* wsum)
 {
     const int64_t i0 = (int64_t)threadIdx.x * kFuseScanPer;
     uint64_t v[kFuseScanPer];
@@ -1082,14 +1082,19 @@ __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, ui
         if (i0 + k < Umax) counts[i0 + k] = run;
         run += v[k];
     }
-    if (threadIdx.x == 0) *total = sum;
+    if (threadIdx.x == 0) {
+        *total = sum;
+        if (pub) publish_total(pub, sum);
+    }
 }
 
 // done: NULL, or a zeroed arrival counter; then the last workgroup to arrive scans the counts
-// (Umax <= kFuseScanMax) and writes the sum to *total.
+// (Umax <= kFuseScanMax) and writes the sum to *total and, when pub is not NULL, to that pinned
+// host slot.
 template <bool AOS>
 __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
-                                           uint32_t* __restrict__ done, uint64_t* __restrict__ total)
+                                           uint32_t* __restrict__ done, uint64_t* __restrict__ total,
+                                           uint64_t* pub)
 {
     extern __shared__ uint4 tab[];
     __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
@@ -1141,7 +1146,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         __syncthreads();
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            scan_counts_block(counts, U, g.Umax, total, reinterpret_cast<uint64_t*>(tab));
+            scan_counts_block(counts, U, g.Umax, total, pub, reinterpret_cast<uint64_t*>(tab));
         }
         return;
     }
@@ -1585,7 +1590,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
 }
 
 hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      hipStream_t st, const RView* pre)
+                      hipStream_t st, const RView* pre, uint64_t* pub)
 {
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
@@ -1654,12 +1659,13 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         uint32_t* done = !pl.single && pl.Umax <= kFuseScanMax
                              ? reinterpret_cast<uint32_t*>(ws + pl.off_done) : nullptr;
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, nullptr, total);
-        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, done, total);
+        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, nullptr, total, nullptr);
+        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, done, total, pub);
         e = hipGetLastError();
         if (e != hipSuccess || done) return e;
     }
-    return exclusive_scan<uint64_t>(counts, counts, pl.Umax, total, reinterpret_cast<uint64_t*>(temp), st);
+    return exclusive_scan<uint64_t>(counts, counts, pl.Umax, total, reinterpret_cast<uint64_t*>(temp), st,
+                                    pub);
 }
 
 hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
@@ -1944,7 +1950,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
         prof::Scope pc(st, "hash.count");
-        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts, nullptr, nullptr);
+        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts, nullptr, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -81,9 +81,10 @@ hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipS
 RView build_view(const BuildPlan& b, const void* build);
 
 // Histogram, scatter, planning, count pass and the scan of counts.  Leaves the exact total at
-// ws[0..8) and the per-unit offsets in ws.
+// ws[0..8) and the per-unit offsets in ws; pub (may be NULL): a pinned host slot (its device
+// address) that the kernel producing the total also stores it into.
 hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                      hipStream_t st, const RView* pre = nullptr);
+                      hipStream_t st, const RView* pre = nullptr, uint64_t* pub = nullptr);
 
 // Write pass from the state hash_count left in ws.
 hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,

@@ -90,15 +90,17 @@ __device__ __forceinline__ T scan_tile(const T* __restrict__ in, T* __restrict__
 }
 
 // Single workgroup: exclusive scan of all n values in tiles, carrying the running sum.
+// pub: NULL, or a pinned host slot that also receives the total.
 template <typename T>
 __global__ __launch_bounds__(kScanBlock) void scan_single_k(const T* __restrict__ in,
                                                             T* __restrict__ out, int64_t n,
-                                                            T* __restrict__ total)
+                                                            T* __restrict__ total, uint64_t* pub)
 {
     __shared__ T lds[kScanBlock / kWave];
     T carry = 0;
     for (int64_t base = 0; base < n; base += kScanTile) carry = scan_tile<T>(in, out, n, base, carry, lds);
     if (threadIdx.x == 0 && total) *total = carry;
+    if (threadIdx.x == 0 && pub) publish_total(pub, (uint64_t)carry);
 }
 
 // Per-tile scan seeded with the scanned tile sums.
@@ -121,19 +123,20 @@ size_t scan_temp_elems(int64_t n)
 }
 
 template <typename T>
-hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* total, T* temp, hipStream_t st)
+hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* total, T* temp, hipStream_t st,
+                         uint64_t* pub)
 {
     if (n < 0) n = 0;
     prof::Scope ps(st, sizeof(T) == 8 ? "scan.u64" : "scan.u32");
     int64_t tiles = ceil_div(n, kScanTile);
     if (tiles <= kSingleTiles) {  // also n == 0: writes *total = 0 without a memset node
-        scan_single_k<T><<<1, kScanBlock, 0, st>>>(in, out, n, total);
+        scan_single_k<T><<<1, kScanBlock, 0, st>>>(in, out, n, total, pub);
         return hipGetLastError();
     }
     // Tile sums are computed from `in` before any output is written, so in == out is safe:
     // scan_apply reads a tile only in the workgroup that writes it.
     tile_sum_k<T><<<(unsigned)tiles, kScanBlock, 0, st>>>(in, n, temp);
-    scan_single_k<T><<<1, kScanBlock, 0, st>>>(temp, temp, tiles, total);
+    scan_single_k<T><<<1, kScanBlock, 0, st>>>(temp, temp, tiles, total, pub);
     scan_apply_k<T><<<(unsigned)tiles, kScanBlock, 0, st>>>(in, out, n, temp);
     return hipGetLastError();
 }
@@ -141,8 +144,8 @@ hipError_t exclusive_scan(const T* in, T* out, int64_t n, T* total, T* temp, hip
 template size_t scan_temp_elems<uint32_t>(int64_t);
 template size_t scan_temp_elems<uint64_t>(int64_t);
 template hipError_t exclusive_scan<uint32_t>(const uint32_t*, uint32_t*, int64_t, uint32_t*,
-                                             uint32_t*, hipStream_t);
+                                             uint32_t*, hipStream_t, uint64_t*);
 template hipError_t exclusive_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, uint64_t*,
-                                             uint64_t*, hipStream_t);
+                                             uint64_t*, hipStream_t, uint64_t*);
 
 }  // namespace jl
