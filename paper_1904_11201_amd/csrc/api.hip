@@ -222,8 +222,8 @@ hipError_t read_total(const void* src, hipStream_t st, uint64_t* count)
     return e;
 }
 
-// The hash paths skip that copy: the kernel that produces the total also stores it into the
-// pinned slot through the slot's device address (publish_total), and the host polls the slot.
+// Count passes skip that copy: the kernel that produces the total also stores it into the pinned
+// slot through the slot's device address (publish_total), and the host polls the slot.
 // The slot holds kUnpublished until then; if the stream goes idle (or fails) with the slot
 // unchanged, the wait ends with an error instead of spinning on.
 constexpr uint64_t kUnpublished = ~0ull;
@@ -264,17 +264,18 @@ hipError_t wait_published(hipStream_t st, uint64_t* count)
     return hipSuccess;
 }
 
-// Count pass of the hash paths, with the total read from the slot the kernels store it into.
-hipError_t hash_count_total(const HashPlan& pl, const join_rel_t& R, const join_rel_t& S, char* ws,
-                            hipStream_t st, const RView* pre, uint64_t* count, const char** what)
+// The slot the next count pass stores its total into (NULL: read it by copy), reset first.
+uint64_t* arm_published_slot()
 {
     uint64_t* pub = published_slot();
     if (pub) *pinned_slot() = kUnpublished;
-    *what = pre ? "probe count pass" : "hash count pass";
-    hipError_t e = hash_count(pl, R, S, ws, st, pre, pub);
-    if (e != hipSuccess) return e;
-    *what = "reading the exact total";
-    return pub ? wait_published(st, count) : read_total(ws, st, count);
+    return pub;
+}
+
+// The exact total of the count pass just enqueued: from the slot, or copied from `src`.
+hipError_t take_total(uint64_t* pub, const void* src, hipStream_t st, uint64_t* count)
+{
+    return pub ? wait_published(st, count) : read_total(src, st, count);
 }
 
 int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
@@ -285,29 +286,25 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         *count = 0;
     } else {
         char* w = static_cast<char*>(ws);
-        hipError_t e = hipSuccess;
+        hipError_t e;
         size_t total_at = 0;  // where the exact total lands in ws
+        uint64_t* pub = arm_published_slot();
         if (kind == JOIN_KIND_HASH) {
             const HashPlan pl = hash_plan(R->n, S->n, num_cus());
-            const char* what = "";
-            e = hash_count_total(pl, *R, *S, w, st, nullptr, count, &what);
-            if (e != hipSuccess) return hip_fail(e, what);
+            e = hash_count(pl, *R, *S, w, st, nullptr, pub);
         } else if (kind == JOIN_KIND_HASH_PREFILTER) {
             const PrefilterPlan pl = prefilter_plan(R->n, S->n, num_cus());
-            e = prefilter_count(pl, *R, *S, w, st, num_cus());
+            e = prefilter_count(pl, *R, *S, w, st, num_cus(), pub);
             total_at = prefilter_total_offset(pl);
         } else if (kind == JOIN_KIND_THETA_REGION) {
-            e = region_count(plan_region(R->n, S->n, p), *R, *S, *p, w, st);
+            e = region_count(plan_region(R->n, S->n, p), *R, *S, *p, w, st, pub);
         } else {
             const ThetaPlan pl = plan_theta(R->n, S->n, p);
-            e = theta_count(pl, *R, *S, *p, w, st);
+            e = theta_count(pl, *R, *S, *p, w, st, pub);
         }
-        if (kind != JOIN_KIND_HASH) {  // the hash path has its total already
-            if (e != hipSuccess)
-                return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
-            e = read_total(w + total_at, st, count);
-            if (e != hipSuccess) return hip_fail(e, "reading the exact total");
-        }
+        if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
+        e = take_total(pub, w + total_at, st, count);
+        if (e != hipSuccess) return hip_fail(e, "reading the exact total");
     }
     g_last.valid = true;
     g_last.kind = kind;
@@ -628,9 +625,11 @@ int join_probe_count(const join_build_t* desc, const void* build, const join_rel
         join_rel_t R{};
         R.n = b.nR;
         const RView v = build_view(b, build);
-        const char* what = "";
-        const hipError_t e = hash_count_total(pl, R, *S, static_cast<char*>(ws), st, &v, count, &what);
-        if (e != hipSuccess) return hip_fail(e, what);
+        uint64_t* pub = arm_published_slot();
+        const hipError_t e = hash_count(pl, R, *S, static_cast<char*>(ws), st, &v, pub);
+        if (e != hipSuccess) return hip_fail(e, "probe count pass");
+        const hipError_t er = take_total(pub, ws, st, count);
+        if (er != hipSuccess) return hip_fail(er, "reading the exact total");
     }
     g_last_probe.valid = true;
     g_last_probe.build = build;

@@ -180,7 +180,7 @@ static hipError_t read_sizes(const PrefilterPlan& pl, char* ws, hipStream_t st, 
 }
 
 hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                           char* ws, hipStream_t st, int num_cus)
+                           char* ws, hipStream_t st, int num_cus, uint64_t* pub)
 {
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + pl.off_cnt);
     uint32_t* fR = reinterpret_cast<uint32_t*>(ws + pl.off_fR);
@@ -225,11 +225,14 @@ hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const j
     if (R2.n == 0 || S2.n == 0) {
         // nothing survives on one side: the count is 0 (total and unit count cleared)
         zero_words_k<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(inner), 4);
-        return hipGetLastError();
+        e = hipGetLastError();
+        // a scan of nothing stores the zero total into the host slot
+        if (e == hipSuccess && pub) e = exclusive_scan<uint64_t>(nullptr, nullptr, 0, nullptr, nullptr, st, pub);
+        return e;
     }
     const HashPlan hp = hash_plan(R2.n, S2.n, num_cus);
     if (hp.bytes > pl.inner_bytes) return hipErrorInvalidValue;  // cannot happen: see the plan
-    return hash_count(hp, R2, S2, inner, st);
+    return hash_count(hp, R2, S2, inner, st, nullptr, pub);
 }
 
 hipError_t prefilter_write(const PrefilterPlan& pl, const join_rel_t& R, const join_rel_t& S,

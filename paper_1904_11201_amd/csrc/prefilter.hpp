@@ -22,7 +22,7 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus);
 // Filters and compaction (launches), then the surviving sizes are read to the host (one
 // 8-byte read) and the inner hash join's count pass runs on the survivors.
 hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                           char* ws, hipStream_t st, int num_cus);
+                           char* ws, hipStream_t st, int num_cus, uint64_t* pub = nullptr);
 
 // Reads the surviving sizes (one 8-byte read, none if neither side has a filter), then the
 // inner hash join's write pass.

@@ -711,7 +711,7 @@ static hipError_t part_side(const RegionPlan& pl, const join_rel_t& X, bool has_
 }
 
 hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                        const join_pred_t& p, char* ws, hipStream_t st)
+                        const join_pred_t& p, char* ws, hipStream_t st, uint64_t* pub)
 {
     hipError_t e = region_attrs();
     if (e != hipSuccess) return e;
@@ -777,7 +777,7 @@ hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_re
     e = theta_count_units(unit_args(pl, ws), p, counts, st);
     if (e != hipSuccess) return e;
     return exclusive_scan<uint64_t>(counts, counts, pl.nOff, &h->total,
-                                    reinterpret_cast<uint64_t*>(ws + pl.off_temp), st);
+                                    reinterpret_cast<uint64_t*>(ws + pl.off_temp), st, pub);
 }
 
 hipError_t region_write(const RegionPlan& pl, const join_rel_t& R, const join_rel_t& S,

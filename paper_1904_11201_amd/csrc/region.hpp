@@ -20,7 +20,7 @@ RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k);
 // Range, buckets, partition, classification, red-unit count pass and the scan of all counts.
 // Leaves the exact total at ws[0..8).
 hipError_t region_count(const RegionPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                        const join_pred_t& p, char* ws, hipStream_t st);
+                        const join_pred_t& p, char* ws, hipStream_t st, uint64_t* pub = nullptr);
 
 // Write pass: red units (stash copy or re-sweep) and green cross products.
 hipError_t region_write(const RegionPlan& pl, const join_rel_t& R, const join_rel_t& S,

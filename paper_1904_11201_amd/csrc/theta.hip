@@ -573,7 +573,7 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int
 }
 
 hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                       const join_pred_t& p, char* ws, hipStream_t st)
+                       const join_pred_t& p, char* ws, hipStream_t st, uint64_t* pub)
 {
     uint64_t* total = reinterpret_cast<uint64_t*>(ws);
     uint64_t* counts = reinterpret_cast<uint64_t*>(ws + pl.off_counts);
@@ -587,7 +587,7 @@ hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return exclusive_scan<uint64_t>(counts, counts, pl.U, total, temp, st);
+    return exclusive_scan<uint64_t>(counts, counts, pl.U, total, temp, st, pub);
 }
 
 hipError_t theta_write(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,

@@ -20,7 +20,7 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int
 
 // Count pass + device scan.  Leaves offsets in ws and the total at ws[0..8).
 hipError_t theta_count(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S,
-                       const join_pred_t& p, char* ws, hipStream_t st);
+                       const join_pred_t& p, char* ws, hipStream_t st, uint64_t* pub = nullptr);
 
 // Theta kernels over an explicit unit table (the red regions of the region-pruned join).
 struct ThetaUnitArgs {
