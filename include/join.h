@@ -23,8 +23,10 @@
  *     pointers.  The caller owns every buffer; the library never allocates device memory and
  *     keeps no pointer after a call returns.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All device work is
- *     enqueued on it in order.  The only host synchronisation is the 8-byte read of the exact
- *     count in join_count, join_hash and join_theta.
+ *     enqueued on it in order.  The only host synchronisation is the wait for the exact count
+ *     in join_count, join_hash, join_theta and join_probe_count: the kernel that produces it
+ *     stores it into a pinned host word the library keeps per host thread, and the calling
+ *     thread polls that word (until it changes, or the stream fails or goes idle without it).
  *   - Counts and offsets are uint64.  Output is int32 pairs, interleaved (rid_R, rid_S), i.e. a
  *     row-major [count][2] int32 array.  The order of pairs is unspecified; the multiset is
  *     exact (bag semantics: duplicate keys produce every matching pair).
