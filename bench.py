@@ -342,12 +342,19 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    _native.prof_enable(True)
+    # The timed steps run without the library's per-kernel events: a pair of events around every
+    # launch adds about 10 us at each boundary between dependent kernels on this GPU.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # Per-kernel launch durations: the same steps again, every launch bracketed by HIP events on
+    # its own stream.
+    _native.prof_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     prof = _native.prof_read()
     _native.prof_enable(False)
 
@@ -444,7 +451,7 @@ def main():
     batch = bench_batch(args, J, datagen, dev, stream) if args.batch_jobs > 0 else None
     serving = bench_serve(args, J) if args.serve_requests > 0 else None
 
-    # ---- per-kernel figures over the timed steps (HIP events on the launch stream) ----------
+    # ---- per-kernel figures over the profiled steps (HIP events on the launch stream) -------
     traffic = load_traffic()
     pairs_band = Rt.n * St.n
     alg = {

@@ -1048,7 +1048,7 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
 }
 
 // Up to kFuseScanMax units, the count kernel's last workgroup to finish also scans the counts,
-// which saves the launch of a separate scan (a launch boundary costs several microseconds).
+// instead of a separate scan kernel after the count kernel.
 constexpr int kFuseScanPer = 8;
 constexpr int64_t kFuseScanMax = (int64_t)kJoinBlock * kFuseScanPer;
 
@@ -1434,8 +1434,7 @@ static hipError_t hist_side(const SideItem* items, const SideItem& one, int64_t 
     return hipGetLastError();
 }
 
-// Both sides of a single join in one launch, R's chunks first: a launch boundary costs about as
-// much as a small kernel.
+// Both sides of a single join in one launch, R's chunks first.
 static hipError_t hist_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64_t gridR,
                             uint32_t* totR, uint32_t* grpR, const SideItem& oneS, int64_t chS,
                             int64_t nS, int64_t gridS, uint32_t* totS, uint32_t* grpS, int bits,
