@@ -228,22 +228,28 @@ hipError_t read_total(const void* src, hipStream_t st, uint64_t* count)
 // unchanged, the wait ends with an error instead of spinning on.
 constexpr uint64_t kUnpublished = ~0ull;
 
-// Device address of this thread's pinned slot, NULL when the runtime gives none (then the copy
-// above is used).
+// Device address of this thread's pinned slot for the current device, NULL when the runtime
+// gives none (then the copy above is used).  Looked up again when the thread's device changes.
 uint64_t* published_slot()
 {
     static thread_local struct {
-        bool done = false;
-        uint64_t* dev = nullptr;
+        int dev = -1;
+        uint64_t* addr = nullptr;
     } m;
-    if (!m.done) {
-        m.done = true;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (m.dev != dev) {
+        m.dev = dev;
+        m.addr = nullptr;
         uint64_t* slot = pinned_slot();
         void* d = nullptr;
-        if (slot && hipHostGetDevicePointer(&d, slot, 0) == hipSuccess) m.dev = static_cast<uint64_t*>(d);
+        if (slot && hipHostGetDevicePointer(&d, slot, 0) == hipSuccess) m.addr = static_cast<uint64_t*>(d);
         else (void)hipGetLastError();
     }
-    return m.dev;
+    return m.addr;
 }
 
 hipError_t wait_published(hipStream_t st, uint64_t* count)
