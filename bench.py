@@ -390,6 +390,21 @@ def main():
         if i >= args.warmup:
             lt_ms.append(a.elapsed_time(b))
 
+    # the same count by region pruning: green tiles are counted as products, white skipped, and
+    # only the diagonal (red) tiles evaluated
+    ws_lr = J.workspace(J.JOIN_KIND_THETA_REGION, Rl.n, Sl.n, lt_pred)
+    lt_reg_ms = []
+    for i in range(args.warmup + 20):
+        a, b = ev(), ev()
+        a.record(stream)
+        n_lt_reg = J.join_count(J.JOIN_KIND_THETA_REGION, dRl, dSl, lt_pred, ws_lr, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            lt_reg_ms.append(a.elapsed_time(b))
+    assert n_lt_reg == n_lt, (n_lt_reg, n_lt)
+    del ws_lr
+
     # the same band join by region pruning (shared value buckets; only red tiles evaluated)
     ws_r = J.workspace(J.JOIN_KIND_THETA_REGION, Rt.n, St.n, theta_pred)
     reg_ms = []
@@ -562,6 +577,7 @@ def main():
             "lt_count_64k_frac_of_valu_peak": round(
                 2 * Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
             "lt_count_64k_count": n_lt,
+            "lt_count_64k_region_ms": round(statistics.median(lt_reg_ms), 4),
             "region_ms": round(statistics.median(reg_ms), 4),
             "region_pairs_per_s": round(n_th / (statistics.median(reg_ms) * 1e-3), 1),
             "region_speedup_vs_nested_loop": round(th_mean / statistics.median(reg_ms), 1),
