@@ -716,10 +716,11 @@ __device__ __forceinline__ Table table_of(const Unit& un, uint4* lds)
 }
 
 // Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
-// HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.
+// HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.  pos[i]
+// receives the LDS word position of item i's slot.
 template <bool RIDS, bool HASHED>
 __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un, const Chunk<RIDS>& c,
-                                              uint4* lds)
+                                              uint4* lds, uint32_t (&pos)[kBuildItems])
 {
     const int tid = threadIdx.x;
     const uint32_t nb = table_buckets(un.rN);
@@ -760,6 +761,7 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
             }
             keys[b * kSlots + old] = c.k[i];
             if constexpr (RIDS) rids[b * kSlots + old] = c.r[i];
+            pos[i] = b * kSlots + old;
         }
     }
     __syncthreads();
@@ -824,10 +826,11 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 
 // Count the entries of N keys: read both candidate buckets of every key (all reads issued
 // together), count the matching slots with predicated arithmetic, and walk on only for keys
-// whose two buckets both overflowed.
+// whose two buckets both overflowed.  `multi` is set when a key has two or more entries (the
+// write pass then puts each key's entries in canonical order before it emits them).
 template <int N, bool HASHED, bool MARKED>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
-                                                const bool (&valid)[N])
+                                                const bool (&valid)[N], bool& multi)
 {
     uint32_t b1[N], b2[N], c1[N], c2[N];
     uint4 k1[N], k2[N];
@@ -840,13 +843,13 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
         k2[i] = t.keys[b2[i]];
         c2[i] = claims<MARKED>(t, b2[i]);
     }
-    uint32_t n = 0;
+    uint32_t n = 0, h[N];
     bool walk[N], any = false;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const uint32_t h = __builtin_popcount(hits<MARKED>(k1[i], c1[i], x[i])) +
-                           __builtin_popcount(hits<MARKED>(k2[i], c2[i], x[i]));
-        n += valid[i] ? h : 0u;
+        h[i] = valid[i] ? __builtin_popcount(hits<MARKED>(k1[i], c1[i], x[i])) +
+                              __builtin_popcount(hits<MARKED>(k2[i], c2[i], x[i]))
+                        : 0u;
         walk[i] = valid[i] && overflowed<MARKED>(k1[i], c1[i], x[i]) && overflowed<MARKED>(k2[i], c2[i], x[i]);
         any = any || walk[i];
     }
@@ -854,7 +857,12 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 #pragma unroll
         for (int i = 0; i < N; ++i)
             if (walk[i])
-                walk_on<MARKED>(t, x[i], b1[i], b2[i], [&](uint32_t, uint32_t hm) { n += __builtin_popcount(hm); });
+                walk_on<MARKED>(t, x[i], b1[i], b2[i], [&](uint32_t, uint32_t hm) { h[i] += __builtin_popcount(hm); });
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        n += h[i];
+        multi = multi || h[i] >= 2u;
     }
     return n;
 }
@@ -923,6 +931,48 @@ __device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_
     emit(b1, hits<MARKED>(k1, c1, x));
     emit(b2, hits<MARKED>(k2, c2, x));
     if (overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x)) walk_on<MARKED>(t, x, b1, b2, emit);
+}
+
+// Canonical order of a key's entries.  The inserts race for slots, so which slots a key's
+// entries take, and the order in which a probe meets them, can differ between runs.  The write
+// pass therefore moves the rids of every key with two or more entries so that the key's
+// visiting order (b1's slots, b2's, then the walk) meets them in ascending order (as signed
+// int32; equal rids give equal pairs, so their order does not matter).  Each entry finds its
+// rank among its key's entries and the slot of that rank in the visiting order; after a
+// barrier it stores its rid there.  Keys stay where they are.
+template <bool HASHED, bool MARKED>
+__device__ void canonicalize(const Table& t, int bits, const Unit& un, const Chunk<true>& c,
+                             const uint32_t (&pos)[kBuildItems], uint32_t* rids)
+{
+    uint32_t target[kBuildItems];
+#pragma unroll
+    for (int i = 0; i < kBuildItems; ++i) {
+        target[i] = ~0u;
+        const uint32_t e = (uint32_t)(i * kJoinBlock + threadIdx.x);
+        if (e < un.rN) {
+            const int32_t mine = (int32_t)c.r[i];
+            uint32_t m = 0, rank = 0;
+            bool self = false;
+            for_each_match<HASHED, MARKED>(t, bits, c.k[i], [&](uint32_t p) {
+                const int32_t r = (int32_t)rids[p];
+                if (p == pos[i]) self = true;
+                else if (r < mine || (r == mine && !self)) ++rank;
+                ++m;
+            });
+            if (m >= 2) {
+                uint32_t k = 0;
+                for_each_match<HASHED, MARKED>(t, bits, c.k[i], [&](uint32_t p) {
+                    if (k == rank) target[i] = p;
+                    ++k;
+                });
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kBuildItems; ++i)
+        if (target[i] != ~0u && target[i] != pos[i]) rids[target[i]] = c.r[i];
+    __syncthreads();
 }
 
 // Units of this join.  The device total never exceeds Umax (sum over partitions of
@@ -1028,9 +1078,11 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // Every half of the loop issues the same loads (a batch past the unit reloads a valid one), and
 // the buffers swap roles instead of being copied, so the wait before a probe is for that
 // batch's loads alone, never for the loads issued after them.
+// A batch's matches fit 32 bits (kCountBatch keys of at most kMaxCap entries each); the lane's
+// total over a unit is kept in 64 bits.
 template <bool AOS, bool MARKED>
 __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
-                                                const uint32_t (&xs)[kCountBatch])
+                                                const uint32_t (&xs)[kCountBatch], bool& multi)
 {
     uint32_t cnt = 0;
 #pragma unroll
@@ -1042,9 +1094,44 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
             x[i] = xs[h + i];
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
-        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok);
+        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok, multi);
     }
     return cnt;
+}
+
+// Each wave of the count and write passes takes the same probe tuples of a unit: those at
+// positions e with (e mod kJoinBlock) / 64 equal to its index.  The count pass records, per
+// unit and wave, where the wave's pairs start inside the unit's output range, so the write pass
+// needs no shared cursor and every pair lands at a position that depends on the input and the
+// plan alone.  Entry 0 of a unit (wave 0 starts at 0) instead holds 1 when some probe of the
+// unit has two or more entries in its table.
+constexpr int kJoinWaves = kJoinBlock / kWave;
+
+// End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u]
+// and the waves' starts in wave_off[u][1..]; sh: kJoinWaves + 1 words of LDS (64-bit).
+__device__ __forceinline__ void unit_totals(uint64_t lane_total, bool multi, uint32_t u,
+                                            uint64_t* __restrict__ counts,
+                                            uint64_t* __restrict__ wave_off, uint64_t* sh)
+{
+    const uint64_t wt = wave_sum64(lane_total);
+    const bool wm = ballot(multi) != 0;
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[wv] = wt | (wm ? (1ull << 63) : 0ull);
+    __syncthreads();
+    if (threadIdx.x < kJoinWaves) {
+        uint64_t before = 0, sum = 0, any = 0;
+#pragma unroll
+        for (int w = 0; w < kJoinWaves; ++w) {
+            const uint64_t v = sh[w];
+            const uint64_t c = v & ~(1ull << 63);
+            before += w < (int)threadIdx.x ? c : 0ull;
+            sum += c;
+            any |= v >> 63;
+        }
+        wave_off[(size_t)u * kJoinWaves + threadIdx.x] = threadIdx.x == 0 ? any : before;
+        if (threadIdx.x == 0) counts[u] = sum;
+    }
+    __syncthreads();
 }
 
 // Up to kFuseScanMax units, the count kernel's last workgroup to finish also scans the counts,
@@ -1093,11 +1180,12 @@ __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, ui
 // host slot.
 template <bool AOS>
 __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
+                                           uint64_t* __restrict__ wave_off,
                                            uint32_t* __restrict__ done, uint64_t* __restrict__ total,
                                            uint64_t* pub)
 {
     extern __shared__ uint4 tab[];
-    __shared__ uint32_t wsum[kJoinBlock / kWave + 1];
+    __shared__ uint64_t wsum[kJoinWaves + 1];
     constexpr uint32_t kB = kJoinBlock * kCountBatch;  // keys per batch
     const uint32_t U = unit_total(g);
     uint32_t xa[kCountBatch], xb[kCountBatch];
@@ -1109,29 +1197,28 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
         Chunk<false> ch;
         load_chunk<AOS, false>(g, un, ch);
-        const Table t = insert_chunk<false, AOS>(g, un, ch, tab);
+        uint32_t pos[kBuildItems];
+        const Table t = insert_chunk<false, AOS>(g, un, ch, tab, pos);
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
         const bool more = u + gridDim.x < U;
         const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
-        uint32_t cnt = 0;
+        uint64_t cnt = 0;
+        bool multi = false;
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
             for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
                 const uint32_t e1 = e0 + kB, e2 = e1 + kB;
                 load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
-                cnt += count_batch<AOS, M>(t, un, e0, xa);
+                cnt += count_batch<AOS, M>(t, un, e0, xa, multi);
                 const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
                 load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
-                cnt += count_batch<AOS, M>(t, un, e1, xb);  // every lane masked past the unit
+                cnt += count_batch<AOS, M>(t, un, e1, xb, multi);  // every lane masked past the unit
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
-        uint32_t tot;
-        block_excl_scan<kJoinBlock>(cnt, wsum, &tot);
-        if (threadIdx.x == 0) counts[u] = tot;
-        __syncthreads();
+        unit_totals(cnt, multi, u, counts, wave_off, wsum);
         un = nx;
     }
     if (done) {
@@ -1146,7 +1233,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         __syncthreads();
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            scan_counts_block(counts, U, g.Umax, total, pub, reinterpret_cast<uint64_t*>(tab));
+            scan_counts_block(counts, U, g.Umax, total, pub, wsum);
         }
         return;
     }
@@ -1156,20 +1243,37 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         counts[i] = 0;
 }
 
+// Whether any unit of [u, end) that shares unit u's R chunk had a probe with two or more
+// entries (entry 0 of its wave_off record): then the chunk's table is put in canonical order.
+__device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint64_t* wave_off, uint32_t u,
+                                                  uint32_t end, uint32_t step, const Unit& un)
+{
+    const cptr<uint64_t> wo = as_const(wave_off);
+    bool any = wo[(size_t)u * kJoinWaves] != 0;
+    if (step != 1) return any;  // round robin: every unit builds its own table
+    for (uint32_t v = u + 1; v < end && !any; ++v) {
+        const Unit n = decode_unit(g, v);
+        if (n.rBeg != un.rBeg || n.rN != un.rN) break;
+        any = wo[(size_t)v * kJoinWaves] != 0;
+    }
+    return any;
+}
+
+// Write pass.  Units are walked as in the count pass (contiguous runs per workgroup for one
+// join, round robin for batches); each wave writes the pairs of its probe tuples from the
+// start the count pass recorded for it, in (batch, tuple, lane) order, with one wave-wide scan
+// per round and no shared cursor: the output depends on the input and the plan only.
 template <bool AOS>
-__global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
-                                                           const uint64_t* __restrict__ offsets,
-                                                           const uint64_t* __restrict__ total,
-                                                           int2* __restrict__ out, uint64_t cap)
+__global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restrict__ offsets,
+                                           const uint64_t* __restrict__ wave_off,
+                                           const uint64_t* __restrict__ total,
+                                           int2* __restrict__ out, uint64_t cap)
 {
     extern __shared__ uint4 tab[];
-    // Output slots handed out so far.  Contiguous runs (g.contig): the run's pairs fill
-    // [offsets[u0], offsets[u1]) and one running cursor serves all its units.  Round robin: each
-    // unit fills [offsets[u], offsets[u + 1]) and the cursor restarts with the unit's build.
-    __shared__ uint32_t cursor;
     if (*total > cap) return;  // an output too small for the exact count receives nothing
     const uint32_t U = unit_total(g);
     const bool contig = g.contig != 0;  // uniform
+    const int wv = uniform((int32_t)(threadIdx.x / kWave));
     uint32_t u0, u1, step;
     if (contig) {
         unit_range(U, u0, u1);
@@ -1179,10 +1283,13 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
         u1 = U;
         step = gridDim.x;
     }
+    const cptr<uint64_t> offs = as_const(offsets);
+    const cptr<uint64_t> wo = as_const(wave_off);
     // The next unit's R chunk (when it needs a new table) is loaded into registers while the
     // current unit probes, and the next unit's first S batch while its last batch probes.
     Unit un{};
     Chunk<true> ch;
+    uint32_t pos[kBuildItems];
     uint32_t nx[kWriteLoad];
     int32_t nr[kWriteLoad];
     if (u0 < u1) {
@@ -1190,17 +1297,20 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
         load_chunk<AOS, true>(g, un, ch);
         load_tuples<AOS>(g, un, 0, nx, nr);
     }
-    if (threadIdx.x == 0) cursor = 0;  // published by the first build's barriers
-    const uint64_t base0 = contig && u0 < u1 ? offsets[u0] : 0;
     uint32_t tBeg = 0, tN = 0;  // R chunk in the table (tN == 0: none yet)
     for (uint32_t u = u0; u < u1; u += step) {
         if (!contig || un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
-            if (!contig && threadIdx.x == 0) cursor = 0;   // the build's barriers publish it
-            insert_chunk<true, AOS>(g, un, ch, tab);
+            const Table tb = insert_chunk<true, AOS>(g, un, ch, tab, pos);
+            if (chunk_needs_order(g, wave_off, u, u1, step, un)) {
+                uint32_t* rids = reinterpret_cast<uint32_t*>(tab + tb.nb);
+                if (AOS && tb.marked) canonicalize<AOS, true>(tb, un.bits, un, ch, pos, rids);
+                else canonicalize<AOS, false>(tb, un.bits, un, ch, pos, rids);
+            }
             tBeg = un.rBeg;
             tN = un.rN;
         }
-        const uint64_t base = contig ? base0 : offsets[u];
+        // this wave's first output slot in unit u
+        uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kJoinWaves + wv]) : 0ull);
         const Table t = table_of<true, AOS>(un, tab);
         const bool more = u + step < u1;
         const Unit nxt = more ? decode_unit(g, u + step) : Unit{};
@@ -1232,9 +1342,10 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                         ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
                     }
                     probe_write<kWriteBatch, AOS, M>(t, un.bits, x, ok, m, p1, p2);
-                    // Slots inside the workgroup's range: waves take theirs from an LDS cursor (no
-                    // block-wide barrier); within a wave, the pairs of the i-th tuple of every lane
-                    // are contiguous, so each store instruction writes one coalesced run.
+                    // Slots: the wave's cursor plus an exclusive scan over (tuple i, lane); the
+                    // pairs of the i-th tuple of every lane are contiguous, so each store
+                    // instruction writes one coalesced run.  A round's pairs fit 32 bits
+                    // (kWriteBatch tuples x 64 lanes x at most kMaxCap entries).
                     uint32_t excl[kWriteBatch], wtot = 0;
 #pragma unroll
                     for (int i = 0; i < kWriteBatch; ++i) {
@@ -1242,12 +1353,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                         excl[i] = wtot + inc - m[i];
                         wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
                     }
-                    uint32_t wb = 0;
-                    if (lane_id() == 0 && wtot) wb = atomicAdd(&cursor, wtot);
-                    wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 0);
 #pragma unroll
                     for (int i = 0; i < kWriteBatch; ++i) {
-                        const uint64_t slot = base + wb + excl[i];
+                        const uint64_t slot = cursor + excl[i];
                         if (m[i] >= 1 && slot < cap) put_pair(&out[slot], make_int2((int32_t)rw[p1[i]], srid[i]));
                         if (m[i] >= 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2((int32_t)rw[p2[i]], srid[i]));
                         if (m[i] > 2) {  // more than two build matches: visit the buckets again
@@ -1258,6 +1366,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g,
                             });
                         }
                     }
+                    cursor += wtot;
                 }
             }
         };
@@ -1373,6 +1482,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     }
     pl.off_counts = off;
     off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
+    pl.off_wave = off;
+    off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * kJoinWaves * 8);
     size_t temp = scan_temp_elems<uint64_t>(pl.Umax) * 8;
     if (!pl.single) {
         const size_t t1 = scan_temp_elems<uint32_t>(pl.P + 1) * 4;
@@ -1657,9 +1768,10 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         // the partitioned path cleared the arrival counter with the partition sizes
         uint32_t* done = !pl.single && pl.Umax <= kFuseScanMax
                              ? reinterpret_cast<uint32_t*>(ws + pl.off_done) : nullptr;
+        uint64_t* wave_off = reinterpret_cast<uint64_t*>(ws + pl.off_wave);
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, nullptr, total, nullptr);
-        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, done, total, pub);
+        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, nullptr, total, nullptr);
+        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
         e = hipGetLastError();
         if (e != hipSuccess || done) return e;
     }
@@ -1674,14 +1786,15 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
     const uint64_t* offsets = reinterpret_cast<const uint64_t*>(ws + pl.off_counts);
+    const uint64_t* wave_off = reinterpret_cast<const uint64_t*>(ws + pl.off_wave);
     const uint64_t* total = reinterpret_cast<const uint64_t*>(ws);
     const JoinGeom g = make_geom(pl, R, S, ws, pre);
     const unsigned grid = (unsigned)(pl.single ? pl.Umax : pl.gridWrite);
     const size_t lds = table_lds((uint32_t)pl.cap, true);
     int2* out = reinterpret_cast<int2*>(pairs);
     prof::Scope pw(st, "hash.write");
-    if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
-    else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, total, out, cap);
+    if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
     return hipGetLastError();
 }
 
@@ -1812,6 +1925,7 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.off_units = take(off, (size_t)(bp.nParts + 1) * 4);
     bp.off_umap = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 4);
     bp.off_counts = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 8);
+    bp.off_wave = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * kJoinWaves * 8);
     size_t temp = scan_temp_elems<uint64_t>(bp.Umax) * 8;
     const size_t t1 = scan_temp_elems<uint32_t>(bp.nParts + 1) * 4;
     temp = temp > t1 ? temp : t1;
@@ -1949,7 +2063,8 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
         prof::Scope pc(st, "hash.count");
-        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(g, counts, nullptr, nullptr, nullptr);
+        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(
+            g, counts, reinterpret_cast<uint64_t*>(ws + bp.off_wave), nullptr, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1971,7 +2086,8 @@ hipError_t hash_batch_write(const BatchPlan& bp, char* ws, int32_t* pairs, uint6
     const JoinGeom g = batch_geom(bp, ws);
     prof::Scope pw(st, "hash.write");
     join_write_k<true><<<(unsigned)bp.gridWrite, kJoinBlock, table_lds((uint32_t)bp.cap, true), st>>>(
-        g, reinterpret_cast<const uint64_t*>(ws + bp.off_counts), reinterpret_cast<const uint64_t*>(ws),
+        g, reinterpret_cast<const uint64_t*>(ws + bp.off_counts),
+        reinterpret_cast<const uint64_t*>(ws + bp.off_wave), reinterpret_cast<const uint64_t*>(ws),
         reinterpret_cast<int2*>(pairs), cap);
     return hipGetLastError();
 }

@@ -54,7 +54,7 @@ struct HashPlan {
     int gridCount, gridWrite;  // persistent grids of the count and write kernels
     size_t off_tot, off_grpR, off_grpS, off_done, off_baseR, off_baseS, off_tupR, off_tupS;
     size_t off_info, off_units, off_umap;
-    size_t off_counts, off_temp, bytes;
+    size_t off_counts, off_wave, off_temp, bytes;
 };
 
 // prebuilt_bits >= 0: R is a resident build partitioned with that fan-out (no single path, no
@@ -97,7 +97,7 @@ struct BatchPlan {
     int64_t nParts, nItemsR, nItemsS, sumR, sumS, Umax;
     uint64_t off_jpart0, off_jbits, off_itemsR, off_itemsS, off_tot, off_baseR, off_baseS;
     uint64_t off_tupR, off_tupS, off_info, off_units, off_umap;
-    uint64_t off_counts, off_temp, bytes;
+    uint64_t off_counts, off_wave, off_temp, bytes;
     int32_t gridCount, gridWrite;
 };
 
