@@ -6,9 +6,13 @@
  * project's autotuner sets from its measured cache.
  *
  * Every knob is read when a call plans its work, so a workspace sized under one setting must
- * be counted and materialized under the same setting.  A value set here wins over the
- * environment variable of the same knob, which wins over the built-in default.  Setting is
- * atomic per knob; concurrent calls that plan while a knob changes may see either value.
+ * be counted and materialized under the same setting.  The count pass records a signature of
+ * its plan in the workspace; a write pass whose plan differs writes nothing (and
+ * join_materialize returns JOIN_E_INVAL when the count ran on the same thread).  A value set for
+ * the calling thread (join_tune_set_local) wins over a process-wide one (join_tune_set), which
+ * wins over the environment variable of the same knob, which wins over the built-in default.
+ * Process-wide setting is atomic per knob; concurrent calls that plan while a knob changes may
+ * see either value, so a caller that tunes one call should use the thread's own setting.
  *
  * Knobs (name, environment variable, meaning):
  *   "hash.cap"               JOIN_HASH_CAP                R entries per LDS table, 64..10240
@@ -34,7 +38,12 @@ extern "C" {
  * Returns 0 or JOIN_TUNE_UNKNOWN. */
 int join_tune_set(const char* name, int64_t value, int clear);
 
-/* Current value of knob `name` (set value, else environment, else `dflt`) into *value.
+/* Sets knob `name` for the calling thread only (or clears that setting if clear != 0): calls
+ * made by other threads do not see it.  Returns 0 or JOIN_TUNE_UNKNOWN. */
+int join_tune_set_local(const char* name, int64_t value, int clear);
+
+/* Current value of knob `name` as the calling thread sees it (its own setting, else the
+ * process-wide one, else environment, else `dflt`) into *value.
  * Returns 0 or JOIN_TUNE_UNKNOWN. */
 int join_tune_get(const char* name, int64_t dflt, int64_t* value);
 

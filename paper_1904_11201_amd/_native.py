@@ -35,7 +35,7 @@ EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash"
            "join_batch_materialize", "join_last_error", "join_scan_workspace_bytes",
            "join_scan_u64", "join_prof_enable", "join_prof_collect", "join_prof_count",
            "join_prof_entry", "join_prof_copy", "join_prof_valu", "join_prof_wall_clock_khz",
-           "join_tune_set", "join_tune_get")
+           "join_tune_set", "join_tune_set_local", "join_tune_get")
 
 
 class JoinRel(ctypes.Structure):
@@ -119,6 +119,8 @@ def _load():
     lib.join_batch_materialize.argtypes = [Bp, vp, sz, vp, u64, vp]
     lib.join_tune_set.restype = ctypes.c_int
     lib.join_tune_set.argtypes = [ctypes.c_char_p, i64, ctypes.c_int]
+    lib.join_tune_set_local.restype = ctypes.c_int
+    lib.join_tune_set_local.argtypes = [ctypes.c_char_p, i64, ctypes.c_int]
     lib.join_tune_get.restype = ctypes.c_int
     lib.join_tune_get.argtypes = [ctypes.c_char_p, i64, ctypes.POINTER(i64)]
     lib.join_last_error.restype = ctypes.c_char_p
@@ -170,9 +172,11 @@ def prof_read() -> dict:
     return out
 
 
-def tune_set(name: str, value: int | None) -> None:
-    """Set tuning knob `name` (see include/join_tune.h); None restores environment/default."""
-    rc = lib.join_tune_set(name.encode(), 0 if value is None else int(value), 1 if value is None else 0)
+def tune_set(name: str, value: int | None, local: bool = False) -> None:
+    """Set tuning knob `name` (see include/join_tune.h); None restores environment/default.
+    local=True sets it for the calling thread only (join_tune_set_local)."""
+    fn = lib.join_tune_set_local if local else lib.join_tune_set
+    rc = fn(name.encode(), 0 if value is None else int(value), 1 if value is None else 0)
     if rc != 0:
         raise KeyError(name)
 

@@ -133,6 +133,16 @@ RegionPlan plan_region(int64_t nR, int64_t nS, const join_pred_t* p)
     return region_plan(nR, nS, p ? p->op_a : JOIN_OP_NONE, theta_stash_k());
 }
 
+// Signature of the plan a call of this kind makes for these sizes under the current knobs
+// (the same value the count pass records in the workspace header).
+uint64_t plan_stamp_of(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
+{
+    if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).stamp;
+    if (kind == JOIN_KIND_HASH_PREFILTER) return prefilter_plan(nR, nS, num_cus()).stamp;
+    if (kind == JOIN_KIND_THETA_REGION) return plan_region(nR, nS, p).stamp;
+    return plan_theta(nR, nS, p).stamp;
+}
+
 size_t ws_needed(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
 {
     if (kind == JOIN_KIND_HASH) return hash_plan(nR, nS, num_cus()).bytes;
@@ -162,6 +172,7 @@ struct LastCount {
     join_pred_t p;
     void* ws;
     uint64_t count;
+    uint64_t stamp;  // plan stamp of that count pass
 };
 thread_local LastCount g_last{};
 
@@ -319,6 +330,7 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     if (p) g_last.p = *p;
     g_last.ws = ws;
     g_last.count = *count;
+    g_last.stamp = plan_stamp_of(kind, R->n, S->n, p);
     return JOIN_OK;
 }
 
@@ -379,10 +391,17 @@ int join_materialize(int kind, const join_rel_t* R, const join_rel_t* S, const j
     int rc = check_args(kind, R, S, pred);
     if (rc != JOIN_OK) return rc;
     if ((rc = check_ws(kind, R, S, pred, ws, ws_bytes)) != JOIN_OK) return rc;
-    if (matches_last(kind, R, S, pred, ws) && g_last.count > capacity) {
-        set_error("capacity %llu is below the exact count %llu", (unsigned long long)capacity,
-                  (unsigned long long)g_last.count);
-        return JOIN_E_CAPACITY;
+    if (matches_last(kind, R, S, pred, ws)) {
+        if (g_last.stamp != plan_stamp_of(kind, R->n, S->n, pred)) {
+            set_error("the plan differs from the one join_count ran on this workspace (a tuning "
+                      "knob changed in between); count again");
+            return JOIN_E_INVAL;
+        }
+        if (g_last.count > capacity) {
+            set_error("capacity %llu is below the exact count %llu", (unsigned long long)capacity,
+                      (unsigned long long)g_last.count);
+            return JOIN_E_CAPACITY;
+        }
     }
     return write_impl(kind, R, S, pred, ws, pairs, capacity, static_cast<hipStream_t>(stream));
 }
@@ -553,6 +572,7 @@ static thread_local struct {
     join_rel_t S;
     void* ws;
     uint64_t count;
+    uint64_t stamp;
 } g_last_probe{};
 
 size_t join_build_bytes(int64_t nR)
@@ -642,6 +662,7 @@ int join_probe_count(const join_build_t* desc, const void* build, const join_rel
     g_last_probe.S = *S;
     g_last_probe.ws = ws;
     g_last_probe.count = *count;
+    g_last_probe.stamp = pl.stamp;
     return JOIN_OK;
 }
 
@@ -661,10 +682,17 @@ int join_probe_materialize(const join_build_t* desc, const void* build, const jo
         return JOIN_E_INVAL;
     }
     if (g_last_probe.valid && g_last_probe.build == build && g_last_probe.ws == ws &&
-        same_rel(g_last_probe.S, *S) && g_last_probe.count > capacity) {
-        set_error("capacity %llu < exact count %llu", (unsigned long long)capacity,
-                  (unsigned long long)g_last_probe.count);
-        return JOIN_E_CAPACITY;
+        same_rel(g_last_probe.S, *S)) {
+        if (g_last_probe.stamp != pl.stamp) {
+            set_error("the plan differs from the one join_probe_count ran on this workspace (a "
+                      "tuning knob changed in between); count again");
+            return JOIN_E_INVAL;
+        }
+        if (g_last_probe.count > capacity) {
+            set_error("capacity %llu < exact count %llu", (unsigned long long)capacity,
+                      (unsigned long long)g_last_probe.count);
+            return JOIN_E_CAPACITY;
+        }
     }
     if (b.nR == 0 || S->n == 0) return JOIN_OK;
     join_rel_t R{};

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <initializer_list>
+
 #include "join.h"
 
 namespace jl {
@@ -67,6 +69,25 @@ __device__ __forceinline__ gptr<T> as_global(const T* p)
 // 16-byte load of four int32 through a global pointer (p 16-byte aligned).
 using i32x4 = int32_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ i32x4 load4(gptr<int32_t> p) { return *(const __attribute__((address_space(1))) i32x4*)p; }
+
+// Plan stamps.  Every workspace starts with a 256-byte header.  The count pass records at
+// kStampOffset a signature of the plan it ran (sizes, fan-out, capacities, tiles: how the work
+// was cut up), and the write pass, which plans again from its own arguments and the tuning
+// knobs, writes nothing unless its plan's signature is the one recorded.  A knob changed
+// between the two calls therefore cannot make the write pass read a layout the count pass did
+// not leave.
+constexpr size_t kStampOffset = 64;
+
+inline uint64_t plan_stamp(std::initializer_list<int64_t> fields)
+{
+    uint64_t h = 0xcbf29ce484222325ull;  // FNV-1a over the fields' bytes
+    for (int64_t f : fields)
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((f >> (8 * b)) & 0xff);
+            h *= 0x100000001b3ull;
+        }
+    return h | 1ull;  // never 0 (a cleared header)
+}
 
 // Store a join's exact total into the caller's pinned host slot (device-visible address of host
 // memory), after every earlier write of this thread: a system-scope release store, so the host

@@ -620,6 +620,7 @@ constexpr int kSlots = 4;
 #define JL_HASH_PROBE 2
 #endif
 constexpr int kProbe = JL_HASH_PROBE;  // keys probed together per thread
+constexpr int kEmitSort = 8;  // a probe with at most this many matches orders them in registers
 
 __host__ __device__ __forceinline__ uint32_t table_buckets(uint32_t rN)
 {
@@ -826,8 +827,9 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 
 // Count the entries of N keys: read both candidate buckets of every key (all reads issued
 // together), count the matching slots with predicated arithmetic, and walk on only for keys
-// whose two buckets both overflowed.  `multi` is set when a key has two or more entries (the
-// write pass then puts each key's entries in canonical order before it emits them).
+// whose two buckets both overflowed.  `multi` is set when a key has more than kEmitSort
+// entries (the write pass then puts the table's entries in canonical order before it emits
+// them; keys with fewer entries are ordered as they are emitted).
 template <int N, bool HASHED, bool MARKED>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
                                                 const bool (&valid)[N], bool& multi)
@@ -862,7 +864,7 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         n += h[i];
-        multi = multi || h[i] >= 2u;
+        multi = multi || h[i] > (uint32_t)kEmitSort;
     }
     return n;
 }
@@ -933,13 +935,52 @@ __device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_
     if (overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x)) walk_on<MARKED>(t, x, b1, b2, emit);
 }
 
+// The pairs of a probe with more than two matches, at slot .. slot + m - 1, in ascending rid
+// order.  Up to kEmitSort matches are gathered in registers and each goes to its rank (rids
+// below it, plus equal rids met before it); a probe with more meets them in order already (its
+// table was put in canonical order).
+template <bool HASHED, bool MARKED>
+__device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, uint32_t m,
+                                       const uint32_t* rw, int32_t srid, uint64_t slot,
+                                       int2* __restrict__ out, uint64_t cap)
+{
+    if (m > (uint32_t)kEmitSort) {
+        uint32_t seen = 0;
+        for_each_match<HASHED, MARKED>(t, bits, x, [&](uint32_t p) {
+            if (slot + seen < cap) put_pair(&out[slot + seen], make_int2((int32_t)rw[p], srid));
+            ++seen;
+        });
+        return;
+    }
+    int32_t r[kEmitSort];
+    uint32_t seen = 0;
+#pragma unroll
+    for (int j = 0; j < kEmitSort; ++j) r[j] = 0;
+    for_each_match<HASHED, MARKED>(t, bits, x, [&](uint32_t p) {
+        const int32_t v = (int32_t)rw[p];
+#pragma unroll
+        for (int j = 0; j < kEmitSort; ++j) r[j] = seen == (uint32_t)j ? v : r[j];
+        ++seen;
+    });
+#pragma unroll
+    for (int k = 0; k < kEmitSort; ++k) {
+        uint32_t rank = 0;
+#pragma unroll
+        for (int j = 0; j < kEmitSort; ++j)
+            rank += ((uint32_t)j < m && (r[j] < r[k] || (r[j] == r[k] && j < k))) ? 1u : 0u;
+        if ((uint32_t)k < m && slot + rank < cap) put_pair(&out[slot + rank], make_int2(r[k], srid));
+    }
+}
+
 // Canonical order of a key's entries.  The inserts race for slots, so which slots a key's
-// entries take, and the order in which a probe meets them, can differ between runs.  The write
-// pass therefore moves the rids of every key with two or more entries so that the key's
-// visiting order (b1's slots, b2's, then the walk) meets them in ascending order (as signed
-// int32; equal rids give equal pairs, so their order does not matter).  Each entry finds its
-// rank among its key's entries and the slot of that rank in the visiting order; after a
-// barrier it stores its rid there.  Keys stay where they are.
+// entries take, and the order in which a probe meets them, can differ between runs; the write
+// pass emits the matches of every probe in ascending rid order (as signed int32; equal rids give
+// equal pairs, so their order does not matter).  A probe with at most kEmitSort matches sorts
+// them in registers as it writes them.  For a table in which some probe has more (the count
+// pass records it per unit), the write pass first moves the rids of every key with two or more
+// entries so that the key's visiting order (b1's slots, b2's, then the walk) meets them in
+// ascending order: each entry finds its rank among its key's entries and the slot of that rank
+// in the visiting order, and after a barrier stores its rid there.  Keys stay where they are.
 template <bool HASHED, bool MARKED>
 __device__ void canonicalize(const Table& t, int bits, const Unit& un, const Chunk<true>& c,
                              const uint32_t (&pos)[kBuildItems], uint32_t* rids)
@@ -1104,7 +1145,7 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
 // unit and wave, where the wave's pairs start inside the unit's output range, so the write pass
 // needs no shared cursor and every pair lands at a position that depends on the input and the
 // plan alone.  Entry 0 of a unit (wave 0 starts at 0) instead holds 1 when some probe of the
-// unit has two or more entries in its table.
+// unit has more than kEmitSort entries in its table.
 constexpr int kJoinWaves = kJoinBlock / kWave;
 
 // End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u]
@@ -1188,6 +1229,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     __shared__ uint64_t wsum[kJoinWaves + 1];
     constexpr uint32_t kB = kJoinBlock * kCountBatch;  // keys per batch
     const uint32_t U = unit_total(g);
+    if (g.stamp_at && blockIdx.x == 0 && threadIdx.x == 0) *g.stamp_at = g.stamp;  // for the write pass
     uint32_t xa[kCountBatch], xb[kCountBatch];
     Unit un{};
     if (blockIdx.x < U) {
@@ -1243,8 +1285,9 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         counts[i] = 0;
 }
 
-// Whether any unit of [u, end) that shares unit u's R chunk had a probe with two or more
-// entries (entry 0 of its wave_off record): then the chunk's table is put in canonical order.
+// Whether any unit of [u, end) that shares unit u's R chunk had a probe with more than
+// kEmitSort matches (entry 0 of its wave_off record): then the chunk's table is put in
+// canonical order.
 __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint64_t* wave_off, uint32_t u,
                                                   uint32_t end, uint32_t step, const Unit& un)
 {
@@ -1270,7 +1313,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                                            int2* __restrict__ out, uint64_t cap)
 {
     extern __shared__ uint4 tab[];
-    if (*total > cap) return;  // an output too small for the exact count receives nothing
+    // an output too small for the exact count, or a plan other than the count pass's, receives
+    // nothing
+    if (*total > cap || (g.stamp_at && *g.stamp_at != g.stamp)) return;
     const uint32_t U = unit_total(g);
     const bool contig = g.contig != 0;  // uniform
     const int wv = uniform((int32_t)(threadIdx.x / kWave));
@@ -1300,8 +1345,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     uint32_t tBeg = 0, tN = 0;  // R chunk in the table (tN == 0: none yet)
     for (uint32_t u = u0; u < u1; u += step) {
         if (!contig || un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
+            const bool order = chunk_needs_order(g, wave_off, u, u1, step, un);
             const Table tb = insert_chunk<true, AOS>(g, un, ch, tab, pos);
-            if (chunk_needs_order(g, wave_off, u, u1, step, un)) {
+            if (order) {
                 uint32_t* rids = reinterpret_cast<uint32_t*>(tab + tb.nb);
                 if (AOS && tb.marked) canonicalize<AOS, true>(tb, un.bits, un, ch, pos, rids);
                 else canonicalize<AOS, false>(tb, un.bits, un, ch, pos, rids);
@@ -1356,15 +1402,12 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
 #pragma unroll
                     for (int i = 0; i < kWriteBatch; ++i) {
                         const uint64_t slot = cursor + excl[i];
-                        if (m[i] >= 1 && slot < cap) put_pair(&out[slot], make_int2((int32_t)rw[p1[i]], srid[i]));
-                        if (m[i] >= 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2((int32_t)rw[p2[i]], srid[i]));
-                        if (m[i] > 2) {  // more than two build matches: visit the buckets again
-                            uint32_t seen = 0;
-                            for_each_match<AOS, M>(t, un.bits, x[i], [&](uint32_t p) {
-                                if (seen >= 2 && slot + seen < cap) out[slot + seen] = make_int2((int32_t)rw[p], srid[i]);
-                                ++seen;
-                            });
-                        }
+                        // two matches leave in ascending rid order
+                        const int32_t ra = (int32_t)rw[p1[i]], rb = (int32_t)rw[p2[i]];
+                        const bool sw = m[i] == 2 && rb < ra;
+                        if (m[i] >= 1 && m[i] <= 2 && slot < cap) put_pair(&out[slot], make_int2(sw ? rb : ra, srid[i]));
+                        if (m[i] == 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2(sw ? ra : rb, srid[i]));
+                        if (m[i] > 2) emit_many<AOS, M>(t, un.bits, x[i], m[i], rw, srid[i], slot, out, cap);
                     }
                     cursor += wtot;
                 }
@@ -1501,6 +1544,9 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     };
     pl.gridCount = grid_for(false);
     pl.gridWrite = grid_for(true);
+    pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.bits, pl.P, pl.cap,
+                           pl.slice, pl.nSs, pl.chR, pl.chS, pl.Umax, pl.gridCount, pl.gridWrite,
+                           (int64_t)pl.bytes});
     return pl;
 }
 
@@ -1671,6 +1717,8 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
     g.bits = pl.bits;
     g.cap = (uint32_t)pl.cap;
     g.Umax = pl.Umax;
+    g.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
+    g.stamp = pl.stamp;
     if (pl.single) {
         g.single = 1;
         g.rk = R.key;

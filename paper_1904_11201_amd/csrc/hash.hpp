@@ -40,6 +40,8 @@ struct JoinGeom {
     int P;
     int single;
     int contig;  // write pass: contiguous runs of units per workgroup (else round robin)
+    uint64_t* stamp_at;  // plan stamp in the workspace header (NULL for batches: no re-planning)
+    uint64_t stamp;      // this plan's stamp: the count pass records it, the write pass checks it
 };
 
 struct HashPlan {
@@ -55,6 +57,7 @@ struct HashPlan {
     size_t off_tot, off_grpR, off_grpS, off_done, off_baseR, off_baseS, off_tupR, off_tupS;
     size_t off_info, off_units, off_umap;
     size_t off_counts, off_wave, off_temp, bytes;
+    uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
 // prebuilt_bits >= 0: R is a resident build partitioned with that fan-out (no single path, no

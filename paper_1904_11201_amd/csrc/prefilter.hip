@@ -150,6 +150,8 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
     pl.inner_bytes = hash_plan(nR, nS, num_cus).bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 + 4096;
     pl.off_inner = take(pl.inner_bytes);
     pl.bytes = off;
+    pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.logR, pl.logS, (int64_t)pl.inner_bytes,
+                           (int64_t)hash_plan(nR, nS, num_cus).stamp, (int64_t)pl.bytes});
     return pl;
 }
 

@@ -15,6 +15,7 @@ struct PrefilterPlan {
     uint64_t off_inner;      // the inner hash join's workspace, sized for the unfiltered sizes
     uint64_t inner_bytes;
     uint64_t bytes;
+    uint64_t stamp;          // signature of the fields above and of the full-size inner plan
 };
 
 PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus);

@@ -550,10 +550,11 @@ __global__ void fill_u64_k(uint64_t* p, int64_t n, uint64_t v)
 __global__ __launch_bounds__(kCrossWaves * kWave) void cross_k(
     const BucketInfo* __restrict__ info, int B, uint32_t nR, const int32_t* __restrict__ rrid,
     const int32_t* __restrict__ srid, const uint64_t* __restrict__ goff,
-    const uint64_t* __restrict__ total, int2* __restrict__ out, uint64_t cap)
+    const uint64_t* __restrict__ total, int2* __restrict__ out, uint64_t cap,
+    const uint64_t* __restrict__ stamp_at, uint64_t stamp)
 {
     (void)nR;
-    if (*total > cap) return;
+    if (*total > cap || *stamp_at != stamp) return;  // see theta_write_k
     const int lane = (int)lane_id();
     const int wv = uniform((int32_t)(threadIdx.x >> 6));
     // one workgroup per (R bucket, side) item; its waves take the bucket's rows in turn, and a
@@ -569,7 +570,8 @@ __global__ __launch_bounds__(kCrossWaves * kWave) void cross_k(
         for (uint32_t r = (uint32_t)wv; r < bi.nR; r += kCrossWaves) {
             const int32_t rr = rrid[bi.rStart + r];
             const uint64_t base = base0 + (uint64_t)r * len;
-            for (uint64_t s2 = lane; s2 < len; s2 += kWave) out[base + s2] = make_int2(rr, srid[g0 + s2]);
+            for (uint64_t s2 = lane; s2 < len; s2 += kWave)
+                if (base + s2 < cap) out[base + s2] = make_int2(rr, srid[g0 + s2]);
         }
     }
 }
@@ -639,6 +641,8 @@ RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k)
     temp = temp > t3 ? temp : t3;
     pl.off_temp = take(temp + 8);
     pl.bytes = off;
+    pl.stamp = plan_stamp({JOIN_KIND_THETA_REGION, nR, nS, op_a, pl.bits, pl.B, pl.chR, pl.chS, pl.Umax,
+                           pl.K, pl.nOff, (int64_t)pl.bytes});
     return pl;
 }
 
@@ -676,6 +680,8 @@ static ThetaUnitArgs unit_args(const RegionPlan& pl, char* ws)
     a.stash = pl.K > 0 ? reinterpret_cast<int2*>(ws + pl.off_stash) : nullptr;
     a.K = pl.K;
     a.nOff = pl.nOff;
+    a.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
+    a.stamp = pl.stamp;
     return a;
 }
 
@@ -795,7 +801,8 @@ hipError_t region_write(const RegionPlan& pl, const join_rel_t& R, const join_re
             reinterpret_cast<const BucketInfo*>(ws + pl.off_info), pl.B, (uint32_t)R.n,
             reinterpret_cast<const int32_t*>(ws + pl.off_Rr),
             reinterpret_cast<const int32_t*>(ws + pl.off_Sr), offsets + pl.Umax, total,
-            reinterpret_cast<int2*>(pairs), cap);
+            reinterpret_cast<int2*>(pairs), cap, reinterpret_cast<const uint64_t*>(ws + kStampOffset),
+            pl.stamp);
         e = hipGetLastError();
     }
     return e;

@@ -13,6 +13,7 @@ struct RegionPlan {
     size_t off_hist2, off_lut, off_vlo, off_vhi, off_hR, off_hS;
     size_t off_Ra, off_Rc, off_Rr, off_Sa, off_Sc, off_Sr;
     size_t off_info, off_split, off_units, off_table, off_counts, off_stash, off_temp, bytes;
+    uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
 RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k);

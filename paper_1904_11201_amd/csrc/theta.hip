@@ -49,6 +49,8 @@ struct ThetaGeom {
     const uint4* units;
     const uint32_t* Uptr;  // device unit count when units != NULL (clamped to U)
     int64_t nOff;          // entries of the offsets array the write pass reads
+    uint64_t* stamp_at;    // plan stamp in the workspace header: recorded by the count pass,
+    uint64_t stamp;        // checked by the write pass
 };
 
 // Per-R-row constants of op_a.  BAND keeps [lo, lo + wid] with lo = max(a - w, INT32_MIN),
@@ -260,6 +262,7 @@ __global__ __launch_bounds__(kThetaBlock) void theta_count_k(ThetaGeom g,
                                                              uint64_t* __restrict__ counts)
 {
     const int lane = (int)lane_id();
+    if (g.stamp_at && blockIdx.x == 0 && threadIdx.x == 0) *g.stamp_at = g.stamp;  // for the write pass
     const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
     if (u >= unit_count(g)) return;
     {
@@ -363,7 +366,9 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
                                                              int2* __restrict__ out, uint64_t cap)
 {
     const uint64_t tot = *total;
-    if (tot > cap) return;  // an output too small for the exact count receives nothing
+    // an output too small for the exact count, or a plan other than the count pass's, receives
+    // nothing
+    if (tot > cap || (g.stamp_at && *g.stamp_at != g.stamp)) return;
     const int lane = (int)lane_id();
     const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + uniform((int32_t)(threadIdx.x >> 6));
     if (u >= unit_count(g)) return;
@@ -373,7 +378,8 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
         if (cnt == 0) return;
         if (g.stash && cnt <= (uint64_t)g.K) {  // the count pass kept every match of this unit
             const int2* st = g.stash + u * g.K;
-            for (uint64_t i = lane; i < cnt; i += kWave) out[off + i] = st[i];
+            for (uint64_t i = lane; i < cnt; i += kWave)
+                if (off + i < cap) out[off + i] = st[i];
             return;
         }
         int64_t r0, rEnd, s0, s1;
@@ -485,6 +491,8 @@ ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, co
     g.units = nullptr;
     g.Uptr = nullptr;
     g.nOff = pl.U;
+    g.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
+    g.stamp = pl.stamp;
     return g;
 }
 
@@ -506,6 +514,8 @@ ThetaGeom unit_geom(const ThetaUnitArgs& a, const join_pred_t& p)
     g.units = a.units;
     g.Uptr = a.Uptr;
     g.nOff = a.nOff;
+    g.stamp_at = a.stamp_at;
+    g.stamp = a.stamp;
     return g;
 }
 
@@ -569,6 +579,7 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int
     pl.off_stash = off;
     off = align_up(off + (size_t)pl.U * (size_t)pl.K * sizeof(int2));
     pl.bytes = off;
+    pl.stamp = plan_stamp({JOIN_KIND_THETA, nR, nS, op_a, pl.TS, pl.nSt, pl.U, pl.K, (int64_t)pl.bytes});
     return pl;
 }
 

@@ -10,6 +10,7 @@ struct ThetaPlan {
     int64_t U;    // work units (one wave each)
     int64_t K;    // per-unit match stash of the count pass (0: none)
     size_t off_counts, off_temp, off_stash, bytes;
+    uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
 // Plan for |R| = nR, |S| = nS and operator op_a (JOIN_OP_NONE: unknown, sized for the largest
@@ -32,6 +33,8 @@ struct ThetaUnitArgs {
     int2* stash;                    // [Umax][K] or NULL
     int64_t K;
     int64_t nOff;                   // entries of the offsets array
+    uint64_t* stamp_at;             // plan stamp in the workspace header (see ThetaPlan)
+    uint64_t stamp;
 };
 
 hipError_t theta_count_units(const ThetaUnitArgs& a, const join_pred_t& p, uint64_t* counts,

@@ -50,10 +50,22 @@ int find(const char* name)
     return -1;
 }
 
+// Values set for the calling thread only (join_tune_set_local); they win over the process-wide
+// ones.
+struct LocalOverrides {
+    int64_t v[TUNE_COUNT];
+    LocalOverrides()
+    {
+        for (auto& x : v) x = kUnset;
+    }
+};
+thread_local LocalOverrides g_local;
+
 }  // namespace
 
 int64_t tune_get(TuneKnob k, int64_t dflt)
 {
+    if (g_local.v[k] != kUnset) return g_local.v[k];
     const int64_t v = overrides().v[k].load(std::memory_order_relaxed);
     if (v != kUnset) return v;
     const char* s = getenv(kKnobs[k].env);
@@ -70,6 +82,14 @@ int join_tune_set(const char* name, int64_t value, int clear)
     const int i = jl::find(name);
     if (i < 0) return JOIN_TUNE_UNKNOWN;
     jl::overrides().v[i].store(clear ? jl::kUnset : value, std::memory_order_relaxed);
+    return 0;
+}
+
+int join_tune_set_local(const char* name, int64_t value, int clear)
+{
+    const int i = jl::find(name);
+    if (i < 0) return JOIN_TUNE_UNKNOWN;
+    jl::g_local.v[i] = clear ? jl::kUnset : value;
     return 0;
 }
 

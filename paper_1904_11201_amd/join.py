@@ -233,8 +233,8 @@ def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = N
                region: bool = False, tuned: bool = False):
     """Theta join op_a(R.key, S.key) [and op_c(R.key2, S.key2)]; exact-size [count, 2] output.
     region=True uses the region-pruned algorithm (JOIN_KIND_THETA_REGION); same result.
-    tuned=True applies the autotuner's S tile for these sizes (process-wide knob, set for the
-    duration of the call)."""
+    tuned=True applies the autotuner's S tile for these sizes (set for the calling thread only,
+    for the duration of the call)."""
     kind = JOIN_KIND_THETA_REGION if region else JOIN_KIND_THETA
     if not tuned:
         return _exact(kind, R, S, pred, ws, stream)
@@ -242,11 +242,11 @@ def theta_join(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor | None = N
     ts = tune.theta_ts_for(R.n, S.n)
     if ts <= 0:
         return _exact(kind, R, S, pred, ws, stream)
-    _native.tune_set("theta.ts", ts)
+    _native.tune_set("theta.ts", ts, local=True)
     try:
         return _exact(kind, R, S, pred, None, stream)  # the workspace size depends on the tile
     finally:
-        _native.tune_set("theta.ts", None)
+        _native.tune_set("theta.ts", None, local=True)
 
 
 # ---- batched equi joins ------------------------------------------------------------------------

@@ -155,6 +155,27 @@ def test_tuning_knobs_override_environment(monkeypatch):
         n.tune_set("no.such.knob", 1)
 
 
+def test_thread_local_knobs_win_and_stay_on_their_thread():
+    """join_tune_set_local: the calling thread sees its own value over the process-wide one;
+    other threads do not see it."""
+    import threading
+    n.tune_set("theta.ts", 4096)
+    try:
+        n.tune_set("theta.ts", 512, local=True)
+        seen = {}
+        t = threading.Thread(target=lambda: seen.setdefault("other", n.tune_get("theta.ts", 0)))
+        t.start()
+        t.join()
+        assert n.tune_get("theta.ts", 0) == 512
+        assert seen["other"] == 4096
+        n.tune_set("theta.ts", None, local=True)
+        assert n.tune_get("theta.ts", 0) == 4096
+    finally:
+        n.tune_set("theta.ts", None, local=True)
+        n.tune_set("theta.ts", None)
+    assert n.tune_get("theta.ts", 0) == 0
+
+
 def test_build_sizes_and_argument_errors():
     assert n.lib.join_build_bytes(-1) == 0
     assert n.lib.join_build_bytes(1 << 31) == 0

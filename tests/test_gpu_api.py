@@ -75,3 +75,64 @@ def test_streams_are_respected():
     s.synchronize()
     n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
     assert np.array_equal(canon_gpu(out), ref)
+
+
+@gpu
+@pytest.mark.parametrize("kind", ["hash", "theta", "region"])
+def test_plan_changed_between_count_and_materialize(kind):
+    """The count pass records its plan's signature in the workspace.  A tuning knob changed
+    before the write pass: on the same thread join_materialize refuses (JOIN_E_INVAL); from
+    another thread, where the host cannot tell, the write kernels refuse and write nothing.
+    Counting again under the new plan then works."""
+    need_gpu()
+    import threading
+    from paper_1904_11201_amd import _native
+    from paper_1904_11201_amd import join as J
+    R, S = datagen.band_theta(seed=31, n=20_000, hi=1 << 14)
+    if kind == "hash":
+        k, pred, knob, vals = J.JOIN_KIND_HASH, None, "hash.cap", (4096, 2048)
+    elif kind == "theta":
+        k, pred, knob, vals = J.JOIN_KIND_THETA, J.Pred("band", 8, "lt"), "theta.ts", (512, 1024)
+    else:
+        k, pred, knob, vals = J.JOIN_KIND_THETA_REGION, J.Pred("band", 8, "lt"), "theta.stash", (64, 32)
+    dR, dS = dev_rel(R), dev_rel(S)
+    if kind == "hash":
+        n_exact, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
+    else:
+        n_exact, ref = oracle.theta_nlj(R.key, S.key, "band", w=8, Rc=R.key2, Sc=S.key2,
+                                        op_c="lt", Rrid=R.rid, Srid=S.rid)
+    sizes = []
+    for v in vals:
+        _native.tune_set(knob, v, local=True)
+        sizes.append(J.join_workspace_bytes(k, R.n, S.n, pred))
+    ws = torch.empty(max(sizes), dtype=torch.uint8, device="cuda")
+    try:
+        _native.tune_set(knob, vals[0], local=True)
+        log(f"plan stamp {kind}: count under {knob}={vals[0]}")
+        assert J.join_count(k, dR, dS, pred, ws) == n_exact
+        _native.tune_set(knob, vals[1], local=True)
+        out = torch.full((n_exact, 2), -7, dtype=torch.int32, device="cuda")
+        with pytest.raises(J.JoinError) as ei:
+            J.join_materialize(k, dR, dS, pred, ws, out)
+        assert ei.value.status == _native.JOIN_E_INVAL
+        # another thread (the host keeps no record there): the device refuses
+        errs = []
+
+        def other():
+            try:
+                _native.tune_set(knob, vals[1], local=True)
+                J.join_materialize(k, dR, dS, pred, ws, out)
+                torch.cuda.synchronize()
+            except Exception as e:  # noqa: BLE001
+                errs.append(e)
+        t = threading.Thread(target=other)
+        t.start()
+        t.join()
+        assert not errs, errs
+        assert bool((out == -7).all()), "a write pass under another plan must write nothing"
+        # count again under the new plan, then the write goes through
+        assert J.join_count(k, dR, dS, pred, ws) == n_exact
+        J.join_materialize(k, dR, dS, pred, ws, out)
+        assert np.array_equal(canon_gpu(out), ref)
+    finally:
+        _native.tune_set(knob, None, local=True)

@@ -1,11 +1,11 @@
 """Output order is unspecified but fixed for a given input and plan: the same join run twice
 gives the same pairs in the same positions, byte for byte (the unsorted output is compared).
 
-Every source of run-to-run variation in the hash path is removed by construction: partition
-positions come from per-tile histogram prefixes, each wave of the write pass writes from a
-start recorded by the count pass, and the entries of a duplicated build key are put in
-canonical (ascending rid) order before they are emitted."""
+In the write pass each wave writes from a start recorded by the count pass (no shared cursor),
+and the matches of one probe leave in ascending rid order: sorted in registers when there are at
+most 8, else met in that order in a table whose duplicated keys were put in canonical order."""
 import numpy as np
+import pytest
 import torch
 
 from paper_1904_11201_amd import datagen
@@ -45,3 +45,47 @@ def test_duplicate_heavy_build_is_deterministic():
     log("determinism hash duplicate-heavy build")
     a, b = _twice(lambda: hash_join(dR, dS))
     assert a.shape == b.shape and torch.equal(a, b)
+
+
+def _probe_runs_ascending(pairs: np.ndarray) -> bool:
+    """With unique probe rids: every probe's pairs form one contiguous run, ascending in rid_R."""
+    if len(pairs) == 0:
+        return True
+    s = pairs[:, 1]
+    brk = np.flatnonzero(s[1:] != s[:-1]) + 1
+    starts = np.concatenate([[0], brk])
+    if len(np.unique(s[starts])) != len(starts):  # a probe's pairs split into several runs
+        return False
+    same = s[1:] == s[:-1]
+    return bool(np.all(pairs[1:, 0][same] >= pairs[:-1, 0][same]))
+
+
+@gpu
+@pytest.mark.parametrize("bits", ["-1", "0", "3", "9"])
+def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits):
+    """Build keys with 1 to 12 entries each (random rids, some repeated), through the single
+    path (bits -1) and partitioned plans: probes with up to 8 matches order them as they are
+    written, probes with more meet them in a table put in canonical order.  Either way each
+    probe's pairs are contiguous and ascending in rid_R, and the multiset equals the oracle's."""
+    need_gpu()
+    import oracle
+    from tests.gpu_util import canon_gpu
+    from paper_1904_11201_amd.join import hash_join
+    g = datagen.rng_for(47)
+    nkeys = 6000
+    keys = g.permutation(1 << 20)[:nkeys].astype(np.int32) - (1 << 19)
+    mult = g.integers(1, 13, nkeys)
+    rk = np.repeat(keys, mult)
+    perm = g.permutation(len(rk))
+    R = datagen.Rel(key=rk[perm], rid=g.integers(0, 3 * len(rk), len(rk)).astype(np.int32))
+    S = datagen.Rel(key=keys[g.integers(0, nkeys, 50_000)], rid=np.arange(50_000, dtype=np.int32))
+    n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
+    monkeypatch.setenv("JOIN_HASH_BITS", bits)
+    dR, dS = dev_rel(R), dev_rel(S)
+    log(f"probe match order, bits={bits}")
+    a = hash_join(dR, dS)
+    torch.cuda.synchronize()
+    host = a.cpu().numpy()
+    assert _probe_runs_ascending(host)
+    got = canon_gpu(a)
+    assert len(got) == n and np.array_equal(got, ref)
