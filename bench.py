@@ -232,7 +232,10 @@ def measure_ceilings(J, _native, dev, stream, reps=5):
     blocks, iters = props.multi_processor_count * 8, 1 << 14
     sink = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
     clk = torch.zeros(2, dtype=torch.int64, device=dev)
+    rsink = torch.empty(4 * 1024 * props.multi_processor_count, dtype=torch.int32, device=dev)
     J.prof_copy(src, dst, stream)
+    J.prof_stream("read", src, rsink, stream)
+    J.prof_stream("write", dst, None, stream)
     ops = J.prof_valu(blocks, iters, sink, clk, stream, mix=0)
     J.prof_valu(blocks, iters, sink, clk, stream, mix=1)
     ops_min = J.prof_valu(blocks, iters, sink, clk, stream, mix=2)
@@ -240,6 +243,8 @@ def measure_ceilings(J, _native, dev, stream, reps=5):
     _native.prof_enable(True)
     for _ in range(reps):
         J.prof_copy(src, dst, stream)
+        J.prof_stream("read", src, rsink, stream)
+        J.prof_stream("write", dst, None, stream)
     for mix in (0, 1, 2):
         for _ in range(reps):
             J.prof_valu(blocks, iters, sink, clk, stream, mix=mix)
@@ -247,9 +252,11 @@ def measure_ceilings(J, _native, dev, stream, reps=5):
     p = _native.prof_read()
     _native.prof_enable(False)
     cyc, ticks = (int(v) for v in clk.cpu().tolist())
-    del src, dst, sink, clk
+    del src, dst, sink, clk, rsink
     torch.cuda.empty_cache()
     copy_ms = p["ceiling.copy"][1] / p["ceiling.copy"][0]
+    read_ms = p["ceiling.read"][1] / p["ceiling.read"][0]
+    write_ms = p["ceiling.write"][1] / p["ceiling.write"][0]
     valu_ms = p["ceiling.valu"][1] / p["ceiling.valu"][0]
     band_ms = p["ceiling.valu.band"][1] / p["ceiling.valu.band"][0]
     min_ms = p["ceiling.valu.min"][1] / p["ceiling.valu.min"][0]
@@ -259,6 +266,10 @@ def measure_ceilings(J, _native, dev, stream, reps=5):
         "copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
         "copy_workload": "1 GiB device-to-device copy, 16-byte non-temporal loads and stores "
                          f"(2 GiB of HBM traffic per launch, mean of {reps})",
+        "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1),
+        "write_GBps": round(nb / (write_ms * 1e-3) / 1e9, 1),
+        "stream_workload": "1 GiB read-only and write-only streams, 16-byte non-temporal "
+                           f"accesses, 8 in flight per lane (mean of {reps})",
         "valu_Tops": round(ops / (valu_ms * 1e-3) / 1e12, 2),
         "valu_workload": f"{blocks} workgroups x 256 lanes x {32 * iters} v_add_u32/v_xor_b32 "
                          f"(mean of {reps})",

@@ -31,16 +31,24 @@ int join_prof_count(void);
 int join_prof_entry(int i, const char** name, uint64_t* launches, double* total_ms);
 
 /* ---- measured ceilings ----------------------------------------------------------------------
- * Two plain kernels whose rates are what the chip sustains, so that roofline fractions can be
+ * Plain kernels whose rates are what the chip sustains, so that roofline fractions can be
  * given against measured ceilings beside the published ones.  Both are stream-ordered on `stream`
  * (a hipStream_t passed as void*, NULL = the null stream),
- * allocate nothing, and are timed as "ceiling.copy", "ceiling.valu" (mix 0), "ceiling.valu.band" (mix 1) and
+ * allocate nothing, and are timed as "ceiling.copy", "ceiling.read", "ceiling.write", "ceiling.valu" (mix 0), "ceiling.valu.band" (mix 1) and
  * "ceiling.valu.min" (mix 2) while profiling is on. */
 
 /* Copy `bytes` from device buffer src to device buffer dst (both 16-byte aligned, bytes a
  * multiple of 16, not overlapping) with a grid-stride kernel of 16-byte non-temporal loads and
  * stores.  HBM traffic is 2 * bytes.  JOIN_E_INVAL for a misaligned or null argument. */
 int join_prof_copy(const void* src, void* dst, uint64_t bytes, void* stream);
+
+/* One streaming pass over `bytes` of device memory (16-byte aligned, a multiple of 16), 16-byte
+ * non-temporal accesses, each lane keeping 8 in flight, at most 4 workgroups of 1024 lanes per
+ * compute unit.  mode 1 reads src and stores one word per lane of the grid into dst (dst holds
+ * at least 4 * 1024 * 4 * compute units bytes); mode 2 writes dst (src unused).  HBM traffic is
+ * `bytes`.  Timed as "ceiling.read" / "ceiling.write".  JOIN_E_INVAL for another mode, a
+ * misaligned size or pointer, or a needed pointer that is null. */
+int join_prof_stream(int mode, const void* src, void* dst, uint64_t bytes, void* stream);
 
 /* Run `blocks` workgroups of 256 lanes; every lane issues 32 * iters (mix 0, 1) or 48 * iters
  * (mix 2) int32 VALU instructions, so the launch performs blocks * 256 * that many

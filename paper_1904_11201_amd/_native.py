@@ -34,7 +34,8 @@ EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash"
            "join_batch_workspace_bytes", "join_batch_prepare", "join_batch_count",
            "join_batch_materialize", "join_last_error", "join_scan_workspace_bytes",
            "join_scan_u64", "join_prof_enable", "join_prof_collect", "join_prof_count",
-           "join_prof_entry", "join_prof_copy", "join_prof_valu", "join_prof_wall_clock_khz",
+           "join_prof_entry", "join_prof_copy", "join_prof_stream", "join_prof_valu",
+           "join_prof_wall_clock_khz",
            "join_tune_set", "join_tune_set_local", "join_tune_get")
 
 
@@ -140,6 +141,8 @@ def _load():
                                     ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
     lib.join_prof_copy.restype = ctypes.c_int
     lib.join_prof_copy.argtypes = [vp, vp, u64, vp]
+    lib.join_prof_stream.restype = ctypes.c_int
+    lib.join_prof_stream.argtypes = [ctypes.c_int, vp, vp, u64, vp]
     lib.join_prof_valu.restype = ctypes.c_int
     lib.join_prof_valu.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, vp, vp, vp]
     lib.join_prof_wall_clock_khz.restype = ctypes.c_int

@@ -1,5 +1,6 @@
 // ceiling.hip -- what the chip sustains, for roofline fractions against measured rather than
-// published peaks (include/join_prof.h): a streaming copy and an int32 VALU spin.
+// published peaks (include/join_prof.h): streaming copy, read and write kernels, and int32
+// VALU spins.
 #include "common.hpp"
 #include "join_prof.h"
 #include "prof.hpp"
@@ -27,6 +28,44 @@ __global__ __launch_bounds__(kCopyBlock) void copy_k(const i32x4* __restrict__ s
         for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
     }
     for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// Read-only and write-only streams.  Each workgroup takes a contiguous range of kStreamPer
+// 16-byte vectors per lane round (the workgroup's rounds are consecutive 16 KB spans), every
+// lane keeping kStreamUnroll loads in flight.  The read stream folds what it reads into one
+// word per lane (stored, so nothing is dropped); the write stream stores a lane-dependent
+// pattern.
+constexpr int kStreamBlock = 1024;
+constexpr int kStreamUnroll = 8;
+
+__global__ __launch_bounds__(kStreamBlock) void read_k(const i32x4* __restrict__ src, uint64_t n,
+                                                       int32_t* __restrict__ sink)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kStreamBlock;
+    uint64_t i = (uint64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+    i32x4 acc = {0, 0, 0, 0};
+    for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
+        i32x4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) acc ^= v[u];
+    }
+    for (; i < n; i += stride) acc ^= __builtin_nontemporal_load(src + i);
+    sink[(uint64_t)blockIdx.x * kStreamBlock + threadIdx.x] = acc.x ^ acc.y ^ acc.z ^ acc.w;
+}
+
+__global__ __launch_bounds__(kStreamBlock) void write_k(i32x4* __restrict__ dst, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kStreamBlock;
+    uint64_t i = (uint64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+    const int32_t t = (int32_t)threadIdx.x;
+    const i32x4 v = {t, t + 1, t + 2, t + 3};
+    for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) __builtin_nontemporal_store(v, dst + i + u * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(v, dst + i);
 }
 
 // The VALU instructions are written as assembly so that the compiler can neither fuse nor drop
@@ -129,6 +168,34 @@ int join_prof_copy(const void* src, void* dst, uint64_t bytes, void* stream)
     prof::Scope ps(st, "ceiling.copy");
     copy_k<<<grid, kCopyBlock, 0, st>>>((const i32x4*)src, (i32x4*)dst, n);
     JL_LAUNCH("copy_k");
+    return JOIN_OK;
+}
+
+int join_prof_stream(int mode, const void* src, void* dst, uint64_t bytes, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (mode < 1 || mode > 2 || (bytes && !(mode == 1 ? src : dst)) || bytes % 16 ||
+        ((uintptr_t)src | (uintptr_t)dst) % 16 || (mode == 1 && bytes && !dst)) {
+        set_error("join_prof_stream: mode 1 (read) or 2 (write), bytes a multiple of 16, pointers "
+                  "16-byte aligned and non-null");
+        return JOIN_E_INVAL;
+    }
+    if (!bytes) return JOIN_OK;
+    int dev = 0, cus = 0;
+    JL_HIP(hipGetDevice(&dev));
+    JL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint64_t n = bytes / 16;
+    const uint64_t want = ceil_div((int64_t)n, (int64_t)kStreamBlock * kStreamUnroll);
+    const uint32_t grid = (uint32_t)(want < (uint64_t)cus * 4 ? want : (uint64_t)cus * 4);
+    if (mode == 1) {
+        prof::Scope ps(st, "ceiling.read");
+        read_k<<<grid, kStreamBlock, 0, st>>>((const i32x4*)src, n, (int32_t*)dst);
+        JL_LAUNCH("read_k");
+    } else {
+        prof::Scope ps(st, "ceiling.write");
+        write_k<<<grid, kStreamBlock, 0, st>>>((i32x4*)dst, n);
+        JL_LAUNCH("write_k");
+    }
     return JOIN_OK;
 }
 

@@ -190,6 +190,22 @@ def prof_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
                                       ctypes.c_void_p(dst.data_ptr()), nb, _stream(stream)))
 
 
+def prof_stream(mode: str, buf: torch.Tensor, sink: torch.Tensor | None = None, stream=None) -> None:
+    """One streaming pass over buf: mode 'read' (folds into sink, an int32 tensor of at least
+    4 * 1024 * compute units elements) or 'write'.  HBM traffic: buf's byte size."""
+    nb = buf.numel() * buf.element_size()
+    if mode == "read":
+        if sink is None or sink.dtype != torch.int32:
+            raise ValueError("prof_stream('read'): sink must be an int32 tensor")
+        _check(_native.lib.join_prof_stream(1, ctypes.c_void_p(buf.data_ptr()),
+                                            ctypes.c_void_p(sink.data_ptr()), nb, _stream(stream)))
+    elif mode == "write":
+        _check(_native.lib.join_prof_stream(2, None, ctypes.c_void_p(buf.data_ptr()), nb,
+                                            _stream(stream)))
+    else:
+        raise ValueError("prof_stream: mode is 'read' or 'write'")
+
+
 def prof_valu(blocks: int, iters: int, sink: torch.Tensor, clk: torch.Tensor, stream=None,
               mix: int = 0) -> int:
     """int32 VALU spin: blocks x 256 lanes x (32, or 48 for mix 2) x iters lane-operations
