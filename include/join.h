@@ -20,8 +20,11 @@
  * Conventions for every call below
  *   - Pointers inside join_rel_t, the workspace and the output are DEVICE pointers on the
  *     current HIP device.  join_rel_t / join_pred_t structs themselves and `count` are HOST
- *     pointers.  The caller owns every buffer; the library never allocates device memory and
- *     keeps no pointer after a call returns.
+ *     pointers (except join_hash_noalloc's `count`, a device pointer).  The caller owns every
+ *     buffer; the library never allocates device memory and keeps no pointer after a call
+ *     returns.  The one piece of device memory the library holds is the static 64 MiB array that
+ *     join_hash_noalloc works in, which exists once per GPU from the loading of the library's
+ *     GPU code until the process ends.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All device work is
  *     enqueued on it in order.  The only host synchronisation is the wait for the exact count
  *     in join_count, join_hash, join_theta and join_probe_count: the kernel that produces it
@@ -139,6 +142,23 @@ int join_hash(const join_rel_t* R, const join_rel_t* S, void* ws, size_t ws_byte
 int join_theta(const join_rel_t* R, const join_rel_t* S, const join_pred_t* pred, void* ws,
                size_t ws_bytes, int32_t* pairs, uint64_t capacity, uint64_t* count,
                void* stream);
+
+/* ---- the hash join without a workspace argument -------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): join_hash with its workspace taken from a static
+ * device array of 64 MiB that the library holds on every GPU it runs on until the process ends,
+ * instead of a caller buffer.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine) and does not synchronise: the exact count is written to `count`, a DEVICE
+ * pointer to one uint64, and the pairs are written to `pairs` (device, `capacity` pairs) only if
+ * the count fits (device-side snprintf semantics: count always set, pairs written only when
+ * count <= capacity).  Same inputs and result as join_hash.
+ * Every call on one GPU uses that GPU's array, which keeps the last call's contents; each call
+ * clears what it accumulates into before use.  Calls that overlap in time on one GPU (other
+ * streams, other host threads) race on the array and must be serialised by the caller.
+ * Errors: JOIN_E_INVAL, JOIN_E_UNSUPPORTED, JOIN_E_WORKSPACE (the join's workspace, the size
+ * join_workspace_bytes(JOIN_KIND_HASH, ...) reports, exceeds 64 MiB), JOIN_E_HIP. */
+int join_hash_noalloc(const join_rel_t* R, const join_rel_t* S, int32_t* pairs, uint64_t capacity,
+                      uint64_t* count, void* stream);
 
 /* ---- resident builds ---------------------------------------------------------------------
  * The partitioned form of a build relation R, kept in caller-owned device memory and probed by

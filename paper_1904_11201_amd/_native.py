@@ -29,6 +29,7 @@ OPS = {"none": 0, "eq": 1, "ne": 2, "lt": 3, "le": 4, "gt": 5, "ge": 6, "band": 
 
 # Every symbol include/*.h declares.
 EXPORTS = ("join_workspace_bytes", "join_count", "join_materialize", "join_hash", "join_theta",
+           "join_hash_noalloc",
            "join_build_bytes", "join_build", "join_probe_workspace_bytes", "join_probe_count",
            "join_probe_materialize",
            "join_batch_workspace_bytes", "join_batch_prepare", "join_batch_count",
@@ -118,6 +119,8 @@ def _load():
     lib.join_batch_count.argtypes = [Bp, vp, sz, vp, vp]
     lib.join_batch_materialize.restype = ctypes.c_int
     lib.join_batch_materialize.argtypes = [Bp, vp, sz, vp, u64, vp]
+    lib.join_hash_noalloc.restype = ctypes.c_int
+    lib.join_hash_noalloc.argtypes = [ctypes.POINTER(JoinRel), ctypes.POINTER(JoinRel), vp, u64, vp, vp]
     lib.join_tune_set.restype = ctypes.c_int
     lib.join_tune_set.argtypes = [ctypes.c_char_p, i64, ctypes.c_int]
     lib.join_tune_set_local.restype = ctypes.c_int

@@ -31,6 +31,7 @@ __all__ = [
     "JOIN_KIND_HASH_PREFILTER",
     "join_workspace_bytes",
     "workspace", "join_count", "join_materialize", "join_hash", "join_theta", "join_scan_u64",
+    "join_hash_noalloc",
     "hash_join", "theta_join", "Job", "Batch", "hash_join_batch", "ResidentBuild",
 ]
 
@@ -145,6 +146,20 @@ def join_hash(R: Relation, S: Relation, ws: torch.Tensor, pairs: torch.Tensor | 
         raise err
     _check(rc)
     return int(cnt.value)
+
+
+def join_hash_noalloc(R: Relation, S: Relation, pairs: torch.Tensor | None, count: torch.Tensor,
+                      stream=None) -> None:
+    """join_hash with the library's static scratch array instead of a workspace: allocates
+    nothing and does not synchronise.  count: a one-element int64 device tensor that receives
+    the exact count; pairs ([capacity, 2] int32) is written only if the count fits."""
+    if count.dtype != torch.int64 or count.numel() < 1 or count.device.type != "cuda":
+        raise ValueError("count must be an int64 cuda tensor of at least one element")
+    rr, sr = R.c(), S.c()
+    cap = 0 if pairs is None else pairs.numel() // 2
+    _check(_native.lib.join_hash_noalloc(ctypes.byref(rr), ctypes.byref(sr),
+                                         ctypes.c_void_p(pairs.data_ptr()) if cap else None, cap,
+                                         ctypes.c_void_p(count.data_ptr()), _stream(stream)))
 
 
 def join_theta(R: Relation, S: Relation, pred: Pred, ws: torch.Tensor,
