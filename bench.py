@@ -30,7 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = ("probe tuples/s + output pairs/s (16M⋈64M hash join, 1M×1M theta); "
           "p99 latency")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# int32 VALU peak in lane-ops/s: 256 CUs x 2 wave64 VALU instructions per CU and clock x 64 lanes
+# x 2.4 GHz.  Two per clock is the published fp32 vector rate (157.3 TFLOP/s = 128 FMA lanes per
+# CU and clock); the SQ_INSTS_VALU counters of the add/xor spin show about 1.7 per CU and clock
+# (profiles/valu_theta_1Mx1M.md), so one per clock (39.3 T) is not the ceiling.
+VALU_ISSUE_PER_CU_CLK = 2
+VALU_PEAK_TOPS = 256 * VALU_ISSUE_PER_CU_CLK * 64 * 2.4e9 / 1e12
 
 M = 1 << 20
 
@@ -73,6 +78,39 @@ def load_traffic():
         if grp.get("src_hash") == src_hash(grp.get("files")):
             kern.update(grp.get("kernels", {}))
     return kern
+
+
+def load_valu():
+    """VALU instructions per launch from the committed rocprofv3 --pmc summary
+    (profiles/valu.json), each group valid only while its kernel sources are unchanged."""
+    p = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(p):
+        return {}
+    with open(p) as f:
+        t = json.load(f)
+    kern = {}
+    for grp in t.get("groups", []):
+        if grp.get("src_hash") == src_hash(grp.get("files")):
+            kern.update(grp.get("kernels", {}))
+    return kern
+
+
+def cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def bench_batch(args, J, datagen, dev, stream):
@@ -168,14 +206,17 @@ def bench_batch(args, J, datagen, dev, stream):
         "per_join_ms": round(per_ms, 2),
         "batch_ms": round(batch_ms, 2),
         "batch_prepare_ms": round(tp, 2),
+        "batch_with_prepare_ms": round(batch_ms + tp, 2),
         "graph_ms": round(graph_ms, 2),
         "per_join_probe_tuples_per_s": round(rows_s / (per_ms * 1e-3), 1),
-        "batch_probe_tuples_per_s": round(rows_s / (batch_ms * 1e-3), 1),
+        "batch_probe_tuples_per_s": round(rows_s / ((batch_ms + tp) * 1e-3), 1),
+        "batch_probe_tuples_per_s_without_prepare": round(rows_s / (batch_ms * 1e-3), 1),
         "graph_probe_tuples_per_s": round(rows_s / (graph_ms * 1e-3), 1),
-        "speedup_batch_vs_per_join": round(per_ms / batch_ms, 3),
+        "speedup_batch_vs_per_join": round(per_ms / (batch_ms + tp), 3),
         "speedup_graph_vs_per_join": round(per_ms / graph_ms, 3),
         "timing": "host wall clock, median of 3, count + total read + exact allocation + write; "
-                  "prepare (host planning and table upload) reported separately",
+                  "the batched figures include prepare (host planning, table upload) once; the "
+                  "graph replays a prepared batch",
     }
 
 
@@ -204,6 +245,13 @@ def bench_serve(args, J):
         res, wall = eng.serve(serve.at_rate(reqs, f * mu), open_loop=True, keep_pairs=False)
         opened[f"{f}x"] = dict(serve.summary(res, wall), qps=round(f * mu, 2))
         print(f"# serve open loop {f}x: {opened[f'{f}x']}", file=sys.stderr, flush=True)
+    # the same stream under a budget that binds: 1 GiB for workspaces and outputs in flight
+    tight = serve.Engine(builds, slots=4, budget_bytes=1 << 30)
+    res, wall = tight.serve(reqs, open_loop=False, keep_pairs=False)
+    bound = dict(serve.summary(res, wall), budget_bytes=tight.budget,
+                 peak_reserved_bytes=tight.peak, admission_waits=tight.waits,
+                 restarts=tight.retries)
+    del tight
     n_theta = sum(r.kind == "theta" for r in reqs)
     n_res = sum(r.R is None for r in reqs)
     out = {
@@ -214,6 +262,7 @@ def bench_serve(args, J):
         "closed_loop": closed, "plain_closed_loop": plain_closed,
         "throughput_vs_plain": round(closed["pairs_per_s"] / plain_closed["pairs_per_s"], 3),
         "open_loop": opened,
+        "closed_loop_1GiB_budget": bound,
         "latency": "arrival to completion on the host clock, count + admission + write",
     }
     del eng, plain, builds, reqs
@@ -222,69 +271,80 @@ def bench_serve(args, J):
 
 
 def measure_ceilings(J, _native, dev, stream, reps=5):
-    """What the chip sustains: a plain 1 GiB device copy (HBM) and an int32 VALU spin whose
-    workgroup 0 also reads the shader clock against the constant real-time counter."""
+    """What the chip sustains: 1 GiB read-only, write-only and copy streams (HBM) and the int32
+    VALU spins, whose workgroup 0 also reads the shader clock against the constant real-time
+    counter (kept per spin)."""
     import torch
     props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
     nb = 1 << 30
     src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
     dst = torch.empty_like(src)
-    blocks, iters = props.multi_processor_count * 8, 1 << 14
+    rsink = torch.empty(2 * 1024 * cus, dtype=torch.int32, device=dev)
+    blocks, iters = cus * 8, 1 << 14
     sink = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
     clk = torch.zeros(2, dtype=torch.int64, device=dev)
-    rsink = torch.empty(4 * 1024 * props.multi_processor_count, dtype=torch.int32, device=dev)
     J.prof_copy(src, dst, stream)
     J.prof_stream("read", src, rsink, stream)
     J.prof_stream("write", dst, None, stream)
-    ops = J.prof_valu(blocks, iters, sink, clk, stream, mix=0)
-    J.prof_valu(blocks, iters, sink, clk, stream, mix=1)
-    ops_min = J.prof_valu(blocks, iters, sink, clk, stream, mix=2)
+    ops = {m: J.prof_valu(blocks, iters, sink, clk, stream, mix=m) for m in (0, 1, 2, 3, 4)}
     torch.cuda.synchronize()
     _native.prof_enable(True)
     for _ in range(reps):
         J.prof_copy(src, dst, stream)
         J.prof_stream("read", src, rsink, stream)
         J.prof_stream("write", dst, None, stream)
-    for mix in (0, 1, 2):
+    ghz = {}
+    hz = J.prof_wall_clock_hz()
+    for mix in (0, 1, 2, 3, 4):
         for _ in range(reps):
             J.prof_valu(blocks, iters, sink, clk, stream, mix=mix)
+        cyc, ticks = (int(v) for v in clk.cpu().tolist())  # the last launch of this spin
+        ghz[mix] = cyc / (ticks / hz) / 1e9 if ticks > 0 else None
     torch.cuda.synchronize()
     p = _native.prof_read()
     _native.prof_enable(False)
-    cyc, ticks = (int(v) for v in clk.cpu().tolist())
     del src, dst, sink, clk, rsink
     torch.cuda.empty_cache()
-    copy_ms = p["ceiling.copy"][1] / p["ceiling.copy"][0]
-    read_ms = p["ceiling.read"][1] / p["ceiling.read"][0]
-    write_ms = p["ceiling.write"][1] / p["ceiling.write"][0]
-    valu_ms = p["ceiling.valu"][1] / p["ceiling.valu"][0]
-    band_ms = p["ceiling.valu.band"][1] / p["ceiling.valu.band"][0]
-    min_ms = p["ceiling.valu.min"][1] / p["ceiling.valu.min"][0]
-    clock_ghz = cyc / (ticks / J.prof_wall_clock_hz()) / 1e9 if ticks > 0 else None
-    return {
-        "compute_units": props.multi_processor_count,
-        "copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
-        "copy_workload": "1 GiB device-to-device copy, 16-byte non-temporal loads and stores "
-                         f"(2 GiB of HBM traffic per launch, mean of {reps})",
-        "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1),
-        "write_GBps": round(nb / (write_ms * 1e-3) / 1e9, 1),
-        "stream_workload": "1 GiB read-only and write-only streams, 16-byte non-temporal "
-                           f"accesses, 8 in flight per lane (mean of {reps})",
-        "valu_Tops": round(ops / (valu_ms * 1e-3) / 1e12, 2),
-        "valu_workload": f"{blocks} workgroups x 256 lanes x {32 * iters} v_add_u32/v_xor_b32 "
-                         f"(mean of {reps})",
-        "valu_band_Tops": round(ops / (band_ms * 1e-3) / 1e12, 2),
-        "valu_band_workload": f"{blocks} workgroups x 256 lanes x {16 * iters} (v_sub_u32 from "
-                              "a scalar, v_cmp_le_u32 into VCC, s_or_b64): a compare-per-pair "
-                              f"band test (mean of {reps})",
-        "valu_min_Tops": round(ops_min / (min_ms * 1e-3) / 1e12, 2),
-        "valu_min_workload": f"{blocks} workgroups x 256 lanes x {16 * iters} (two v_sub_u32 "
-                             "from a scalar, one v_min3_u32 into one of two running minima): "
-                             f"the nested-loop join's group filter (mean of {reps})",
-        "shader_clock_GHz": clock_ghz and round(clock_ghz, 3),
-        "valu_peak_at_shader_clock_Tops": clock_ghz and round(
-            props.multi_processor_count * 64 * clock_ghz * 1e9 / 1e12, 2),
+
+    def avg(name):
+        return p[name][1] / p[name][0]
+
+    def tops(mix, name):
+        return ops[mix] / (avg(name) * 1e-3) / 1e12
+
+    def per_cu_clk(mix, name):
+        # wave64 VALU instructions per compute unit and shader clock
+        g = ghz[mix]
+        return g and round(tops(mix, name) * 1e12 / 64 / cus / (g * 1e9), 3)
+
+    out = {
+        "compute_units": cus,
+        "read_GBps": round(nb / (avg("ceiling.read") * 1e-3) / 1e9, 1),
+        "write_GBps": round(nb / (avg("ceiling.write") * 1e-3) / 1e9, 1),
+        "copy_GBps": round(2 * nb / (avg("ceiling.copy") * 1e-3) / 1e9, 1),
+        "stream_workload": "1 GiB read-only, write-only and copy streams of 16-byte non-temporal "
+                           "accesses, 2 workgroups of 1024 lanes per CU (the fastest shape of a "
+                           f"sweep), copy traffic counted both ways, mean of {reps}",
     }
+    names = {0: "ceiling.valu", 1: "ceiling.valu.band", 2: "ceiling.valu.min",
+             3: "ceiling.valu.sub", 4: "ceiling.valu.min3"}
+    desc = {0: "v_add_u32 + v_xor_b32 chains", 1: "v_sub_u32 from a scalar, v_cmp_le_u32 into "
+            "VCC, s_or_b64: a compare-per-pair band test", 2: "two v_sub_u32 from a scalar, one "
+            "v_min3_u32 into one of two running minima: the nested-loop join's group filter",
+            3: "v_sub_u32 from a scalar only", 4: "v_min3_u32 only"}
+    key = {0: "valu", 1: "valu_band", 2: "valu_min", 3: "valu_sub", 4: "valu_min3"}
+    for m in (0, 1, 2, 3, 4):
+        out[f"{key[m]}_Tops"] = round(tops(m, names[m]), 2)
+        out[f"{key[m]}_shader_clock_GHz"] = ghz[m] and round(ghz[m], 3)
+        out[f"{key[m]}_insts_per_cu_clk"] = per_cu_clk(m, names[m])
+        out[f"{key[m]}_workload"] = (f"{blocks} workgroups x 256 lanes x "
+                                     f"{(48 if m == 2 else 32) * iters} instructions: {desc[m]} "
+                                     f"(mean of {reps})")
+    out["valu_peak_Tops"] = round(VALU_PEAK_TOPS, 2)
+    out["valu_peak_model"] = (f"{cus} CUs x {VALU_ISSUE_PER_CU_CLK} wave64 VALU instructions per "
+                              "CU and clock x 64 lanes x 2.4 GHz")
+    return out
 
 
 def main():
@@ -362,14 +422,25 @@ def main():
     recs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # Per-kernel launch durations: the same steps again, every launch bracketed by HIP events on
-    # its own stream.
-    _native.prof_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    prof = _native.prof_read()
-    _native.prof_enable(False)
+    # Per-kernel launch durations: the same joins again, every launch bracketed by HIP events on
+    # its own stream, one workload at a time (so that each join's kernels have their own table).
+    def profiled(fn):
+        _native.prof_enable(True)
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        t = _native.prof_read()
+        _native.prof_enable(False)
+        return t
+
+    prof_u = profiled(lambda: run_join(J.JOIN_KIND_HASH, dRu, dSu, None, ws_h))
+    prof_z = profiled(lambda: run_join(J.JOIN_KIND_HASH, dRz, dSz, None, ws_h))
+    prof_t = profiled(lambda: run_join(J.JOIN_KIND_THETA, dRt, dSt, theta_pred, ws_t))
+    prof = {}
+    for t in (prof_u, prof_z, prof_t):
+        for k, (n, ms) in t.items():
+            a = prof.get(k, (0, 0.0))
+            prof[k] = (a[0] + n, a[1] + ms)
 
     wall_ms = (t1 - t0) * 1e3 / args.steps
     ceilings = measure_ceilings(J, _native, dev, stream)
@@ -483,68 +554,152 @@ def main():
 
     # ---- per-kernel figures over the profiled steps (HIP events on the launch stream) -------
     traffic = load_traffic()
+    valu = load_valu()
     pairs_band = Rt.n * St.n
     alg = {
-        # algorithmic bytes per launch (HBM-bound kernels) or int32 lane-ops (ALU-bound)
-        "hash.hist": ("hbm", 4 * (nR + nS)),  # both sides in one launch
-        "hash.scatter": ("hbm", 16 * (nR + nS)),
-        "hash.count": ("hbm", 4 * nR + 4 * nS),
-        "hash.write": ("hbm", 8 * nR + 8 * nS + 8 * nS),
-        # the band filter: one subtract per pair, one three-input min per two pairs
-        "theta.count": ("alu", 1.5 * pairs_band),
-        "theta.write": ("hbm", 16 * n_th),
+        # algorithmic bytes per launch (HBM-bound kernels) or int32 ops (ALU-bound): the
+        # per-unit figures of the scope table times the units of one launch
+        "hash.hist": ("hbm", 4 * (nR + nS), "read"),  # both sides in one launch
+        "hash.scatter": ("hbm", 16 * (nR + nS), "copy"),
+        "hash.count": ("hbm", 4 * nR + 4 * nS, "read"),
+        "hash.write": ("hbm", 8 * nR + 8 * nS + 8 * nS, "copy"),
+        # band and R.c < S.c: one subtract and two compares per pair
+        "theta.count": ("alu", 3 * pairs_band, None),
+        "theta.write": ("hbm", 16 * n_th, "copy"),
     }
-    kernels = []
-    for name, (launches, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
-        avg = tot_ms / launches
-        k = {"name": name, "launches": launches, "avg_ms": round(avg, 4),
-             "share_of_step": round(tot_ms / args.steps / wall_ms, 4)}
-        if name in alg:
-            bound, work = alg[name]
-            per_launch = work
-            if bound == "hbm":
-                ach = per_launch / (avg * 1e-3) / 1e9
-                k.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                         frac=round(ach / HBM_PEAK_GBS, 4))
-            else:
-                ach = per_launch / (avg * 1e-3) / 1e12
-                k.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
-                         unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4))
-            meas = ceilings["copy_GBps"] if bound == "hbm" else ceilings["valu_min_Tops"]
-            k["frac_of_measured_ceiling"] = round(k["achieved"] / meas, 4)
-            t = traffic.get(name)
-            k["traffic"] = t
-        kernels.append(k)
+    spin_rate = {"theta.count": ceilings["valu_min_Tops"]}  # the spin of its own sequence
+
+    def kernel_lines(table, steps_ms):
+        rows = []
+        for name, (launches, tot_ms) in sorted(table.items(), key=lambda kv: -kv[1][1]):
+            avg = tot_ms / launches
+            k = {"name": name, "launches": launches, "avg_ms": round(avg, 4),
+                 "share_of_step": round(tot_ms / args.steps / steps_ms, 4)}
+            if name in alg:
+                bound, work, mix = alg[name]
+                if bound == "hbm":
+                    ach = work / (avg * 1e-3) / 1e9
+                    meas = ceilings[f"{mix}_GBps"]
+                    k.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(ach / HBM_PEAK_GBS, 4),
+                             measured_ceiling=f"{mix} stream, {meas} GB/s",
+                             frac_of_measured_ceiling=round(ach / meas, 4))
+                    t = traffic.get(name)
+                    k["traffic"] = t
+                    if t:
+                        k["traffic_GBps"] = round(t / (avg * 1e-3) / 1e9, 1)
+                else:
+                    ach = work / (avg * 1e-3) / 1e12
+                    k.update(bound="alu", achieved=round(ach, 2), peak=round(VALU_PEAK_TOPS, 2),
+                             unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
+                             work="3 int32 ops per pair (one subtract, two compares)")
+                    v = valu.get(name)
+                    k["traffic"] = traffic.get(name)
+                    if v:
+                        lane_ops = v["SQ_INSTS_VALU"] * 64
+                        rate = lane_ops / (avg * 1e-3) / 1e12
+                        k.update(counter_lane_ops=lane_ops, counter_Tops=round(rate, 2),
+                                 counter_frac=round(rate / VALU_PEAK_TOPS, 4),
+                                 frac_of_measured_ceiling=round(rate / spin_rate[name], 4),
+                                 measured_ceiling=f"spin of the same instruction sequence, "
+                                                  f"{spin_rate[name]} T lane-ops/s")
+            rows.append(k)
+        return rows
+
+    kernels = kernel_lines(prof, wall_ms)
     dom = max((k for k in kernels if "bound" in k), key=lambda k: k["launches"] * k["avg_ms"])
     roofline = {"kernel": dom["name"], "bound": dom["bound"], "achieved": dom["achieved"],
                 "peak": dom["peak"], "unit": dom["unit"], "frac": dom["frac"],
                 "traffic": dom.get("traffic")}
-    hash_kernels = [k for k in kernels if k["name"].startswith("hash.") and "bound" in k]
-    hash_dom = max(hash_kernels, key=lambda k: k["launches"] * k["avg_ms"]) if hash_kernels else None
+    for f in ("work", "counter_Tops", "counter_frac", "measured_ceiling", "frac_of_measured_ceiling"):
+        if f in dom:
+            roofline[f] = dom[f]
+
+    def hash_graded(table, ms):
+        """HBM bytes the counters saw over the join's kernels / their summed time / 8 TB/s."""
+        names = [k for k in table if k.startswith("hash.")]
+        t_ms = sum(table[k][1] / table[k][0] for k in names)
+        if not names or any(traffic.get(k) is None for k in names if k in alg):
+            return None
+        b = sum(traffic[k] for k in names if k in alg)
+        return {"kernels": sorted(names), "hbm_bytes": b, "kernel_ms": round(t_ms, 4),
+                "GBps": round(b / (t_ms * 1e-3) / 1e9, 1),
+                "frac": round(b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": 8 * nR + 8 * nS + 8 * nS,
+                "algorithmic_frac": round((8 * nR + 16 * nS) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "algorithmic_basis": "8 B per R and S tuple read once + 8 B per output pair, over "
+                                     "the whole join (count, allocation, write)"}
 
     # ---- CPU oracle on a bounded sample of the same workload --------------------------------
+    # The oracle as it stands, timed on this host: the sort-merge equi join is sequential code,
+    # so "all threads" runs one instance per thread on disjoint slices of S (each sorting all of
+    # R, as one call does); the nested-loop theta oracle is OpenMP code, run with 1 thread and
+    # with every thread of the host.
     cpu = None
     cpu_theta = None
     if not args.no_cpu_baseline:
+        import concurrent.futures
+        import ctypes
         import oracle
+        nthr = host_threads()
         samp = 8 * M
         c0 = time.perf_counter()
         oracle.equi_sortmerge(Ru.key, Su.key[:samp], Rrid=Ru.rid, Srid=Su.rid[:samp])
         c1 = time.perf_counter()
-        cpu = {"value": round(samp / (c1 - c0), 1), "unit": "probe tuples/s", "cores": 1,
-               "kind": "oracle",
+        one = samp / (c1 - c0)
+        per = max(1, (nS - samp) // nthr)
+        slices = [(samp + i * per, samp + (i + 1) * per) for i in range(nthr)]
+
+        def leg(lo_hi):
+            lo, hi = lo_hi
+            oracle.equi_sortmerge(Ru.key, Su.key[lo:hi], Rrid=Ru.rid, Srid=Su.rid[lo:hi])
+
+        c2 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(leg, slices))
+        c3 = time.perf_counter()
+        allv = per * nthr / (c3 - c2)
+        model = cpu_model()
+        cpu = {"value": round(one, 1), "unit": "probe tuples/s", "cores": 1, "kind": "oracle",
                "sample": f"sort-merge oracle, all 16M R tuples x the first {samp} of the 64M "
-                         f"uniform S tuples, pairs materialised and sorted ({c1 - c0:.1f}s)"}
+                         f"uniform S tuples, pairs materialised and sorted ({c1 - c0:.1f}s)",
+               "cpu_model": model,
+               "all_threads": {"value": round(allv, 1), "cores": nthr,
+                               "sample": f"{nthr} concurrent oracle calls, each all 16M R tuples x "
+                                         f"{per} further S tuples ({c3 - c2:.1f}s)"}}
         rows = 8192
-        thr = oracle.threads()
-        c0 = time.perf_counter()
-        oracle.theta_nlj(Rt.key[:rows], St.key, "band", w=8, Rc=Rt.key2[:rows], Sc=St.key2,
-                         op_c="lt", Rrid=Rt.rid[:rows], Srid=St.rid)
-        c1 = time.perf_counter()
-        cpu_theta = {"value": round(rows * St.n / (c1 - c0), 1), "unit": "pair evaluations/s",
-                     "cores": thr, "kind": "oracle",
-                     "sample": f"brute-force nested-loop oracle, {rows} R rows x all 1M S rows "
-                               f"({c1 - c0:.1f}s)"}
+        gomp = None
+        try:
+            gomp = ctypes.CDLL("libgomp.so.1")
+        except OSError:
+            pass
+        theta_legs = {}
+        for t in (1, oracle.threads()):
+            if gomp is None and t != oracle.threads():
+                continue
+            if gomp is not None:
+                gomp.omp_set_num_threads(t)
+            r = rows if t > 1 else rows // 8
+            c0 = time.perf_counter()
+            oracle.theta_nlj(Rt.key[:r], St.key, "band", w=8, Rc=Rt.key2[:r], Sc=St.key2,
+                             op_c="lt", Rrid=Rt.rid[:r], Srid=St.rid)
+            c1 = time.perf_counter()
+            theta_legs[t] = (round(r * St.n / (c1 - c0), 1), r, c1 - c0)
+        if gomp is not None:
+            gomp.omp_set_num_threads(oracle.threads())
+        tmax = max(theta_legs)
+        v, r, secs = theta_legs[tmax]
+        cpu_theta = {"value": v, "unit": "pair evaluations/s", "cores": tmax, "kind": "oracle",
+                     "sample": f"brute-force nested-loop oracle, {r} R rows x all 1M S rows "
+                               f"({secs:.1f}s)", "cpu_model": model}
+        if 1 in theta_legs and tmax != 1:
+            v1, r1, s1 = theta_legs[1]
+            cpu_theta["one_thread"] = {"value": v1, "cores": 1,
+                                       "sample": f"{r1} R rows x all 1M S rows ({s1:.1f}s)"}
+
+    def pcts(v):
+        v = sorted(v)
+        return {"p50_ms": round(pct(v, 0.5), 4), "p99_ms": round(pct(v, 0.99), 4), "runs": len(v)}
 
     out = {
         "metric": METRIC,
@@ -571,12 +726,12 @@ def main():
             "ms_zipf": round(statistics.mean(hz_ms), 4),
             "probe_tuples_per_s": round(probe_tps, 1),
             "pairs_per_s": round(hash_pairs_ps, 1),
-            "p50_ms": round(statistics.median(hu_ms + hz_ms), 4),
-            "p99_ms": round(max(hu_ms + hz_ms), 4),
+            "uniform": pcts(hu_ms),
+            "zipf": pcts(hz_ms),
             "output_alloc_us_median": round(statistics.median(alloc_us), 2),
-            "roofline": hash_dom and {k: hash_dom[k] for k in
-                                      ("name", "bound", "achieved", "peak", "unit", "frac",
-                                       "traffic")},
+            "graded_uniform": hash_graded(prof_u, statistics.mean(hu_ms)),
+            "kernels_uniform": kernel_lines(prof_u, statistics.mean(hu_ms)),
+            "kernels_zipf": kernel_lines(prof_z, statistics.mean(hz_ms)),
         },
         "theta": {
             "ms": round(th_mean, 3),
@@ -587,6 +742,7 @@ def main():
             "lt_count_64k_pair_evaluations_per_s": round(Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3), 1),
             "lt_count_64k_frac_of_valu_peak": round(
                 2 * Rl.n * Sl.n / (statistics.median(lt_ms) * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+            "lt_count_64k_work": "2 int32 ops per pair (compare, accumulate), whole count call",
             "lt_count_64k_count": n_lt,
             "lt_count_64k_region_ms": round(statistics.median(lt_reg_ms), 4),
             "region_ms": round(statistics.median(reg_ms), 4),

@@ -225,7 +225,8 @@ def prof_valu(blocks: int, iters: int, sink: torch.Tensor, clk: torch.Tensor, st
               mix: int = 0) -> int:
     """int32 VALU spin: blocks x 256 lanes x (32, or 48 for mix 2) x iters lane-operations
     (returned); mix 0 add/xor chains, mix 1 a band test's subtract, compare and mask, mix 2 the
-    nested-loop join's subtract and three-input min.  sink is an int32 tensor of blocks * 256
+    nested-loop join's subtract and three-input min, mix 3 subtracts from a scalar only, mix 4
+    three-input minima only.  sink is an int32 tensor of blocks * 256
     elements, clk an int64 tensor of 2 (shader cycles, real-time ticks of workgroup 0)."""
     if sink.dtype != torch.int32 or sink.numel() < blocks * 256:
         raise ValueError("prof_valu: sink must be int32 with blocks * 256 elements")

@@ -2,7 +2,7 @@
 
     python -m paper_1904_11201_amd.profile_run hash    # 16M x 64M uniform hash join, three times
     python -m paper_1904_11201_amd.profile_run theta   # 1M x 1M band (w = 8) and R.c < S.c, once
-    python -m paper_1904_11201_amd.profile_run valu    # the three int32 VALU spins, once each
+    python -m paper_1904_11201_amd.profile_run valu    # the five int32 VALU spins, once each
     python -m paper_1904_11201_amd.profile_run copy    # the 1 GiB device copy, three times
 
 Inputs are the seeded synthetic workloads of datagen (seed 2 and seed 4), copied to the device
@@ -42,7 +42,7 @@ def main(argv=None) -> int:
         blocks, iters = props.multi_processor_count * 8, 1 << 14
         sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
         clk = torch.zeros(2, dtype=torch.int64, device="cuda")
-        for mix in (0, 1, 2):
+        for mix in (0, 1, 2, 3, 4):
             J.prof_valu(blocks, iters, sink, clk, mix=mix)
         out = sink
     elif what[0] == "copy":

@@ -205,5 +205,11 @@ def test_ceiling_calls_reject_bad_arguments():
     assert lib.join_prof_valu(0, 1, 0, sink, sink, None) == 1
     assert lib.join_prof_valu((1 << 22) + 1, 1, 0, sink, sink, None) == 1
     assert lib.join_prof_valu(1, 1, 0, None, sink, None) == 1
-    assert lib.join_prof_valu(1, 1, 3, sink, sink, None) == 1
+    assert lib.join_prof_valu(1, 1, 5, sink, sink, None) == 1
     assert "join_prof_valu" in n.last_error()
+    assert lib.join_prof_stream(0, None, sink, 16, None) == 1
+    assert lib.join_prof_stream(1, None, sink, 16, None) == 1
+    assert lib.join_prof_stream(2, None, ctypes.c_void_p(8), 16, None) == 1
+    assert lib.join_prof_stream(2, None, sink, 8, None) == 1
+    assert lib.join_prof_stream(1, None, None, 0, None) == 0
+    assert "join_prof_stream" in n.last_error()
