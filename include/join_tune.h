@@ -1,9 +1,10 @@
 /* join_tune.h -- process-wide tuning knobs of libjoin.
  *
- * The knobs change only how the work is cut up (table capacity, fan-out, tile shapes), never the
- * result.  The paper tunes its own cut of the work, the reducer count alpha, by measurement
- * (Section 3.3.4, equation "hier"; Sections 5.1.4 and 5.2.4); these knobs are what the
- * project's autotuner sets from its measured cache.
+ * The knobs change only how the work is cut up (table capacity, fan-out, tile shapes) and, for
+ * "hash.deterministic", the order of the output pairs, never the multiset of pairs.  The paper
+ * tunes its own cut of the work, the reducer count alpha, by measurement (Section 3.3.4,
+ * equation "hier"; Sections 5.1.4 and 5.2.4); these knobs are what the project's autotuner sets
+ * from its measured cache.
  *
  * Every knob is read when a call plans its work, so a workspace sized under one setting must
  * be counted and materialized under the same setting.  The count pass records a signature of
@@ -22,6 +23,12 @@
  *   "theta.ts"               JOIN_THETA_TS                S rows per theta tile, 0 automatic
  *   "theta.waves"            JOIN_THETA_WAVES             waves a theta grid aims for, 0 automatic
  *   "theta.stash"            JOIN_THETA_STASH             matches stashed per theta work unit
+ *   "hash.deterministic"     JOIN_HASH_DETERMINISTIC      1: partitioned hash joins (single and
+ *                                                         batched) place tuples in an order fixed by
+ *                                                         the input, so their output order is the
+ *                                                         same on every run; 0 (default): arrival
+ *                                                         order, faster.  Joins on the unpartitioned
+ *                                                         path are deterministic either way.
  */
 #ifndef JOIN_TUNE_H
 #define JOIN_TUNE_H

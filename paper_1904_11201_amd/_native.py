@@ -9,7 +9,11 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libjoin.so")
+# JOIN_LIBRARY selects another build of the same library: a file name next to this file (the
+# checking build libjoin_debug.so) or an absolute path (a sanitizer build of the host code); the
+# default is libjoin.so next to this file.
+_LIB = os.environ.get("JOIN_LIBRARY") or "libjoin.so"
+LIB_PATH = _LIB if os.path.isabs(_LIB) else os.path.join(HERE, os.path.basename(_LIB))
 
 JOIN_OK = 0
 JOIN_E_INVAL = 1

@@ -1,6 +1,6 @@
 """Build libjoin.so (gfx950) in-tree from csrc/*.hip with hipcc.
 
-Usage: python -m paper_1904_11201_amd.build   (or build() from Python)
+Usage: python -m paper_1904_11201_amd.build [--debug]   (or build() from Python)
 """
 from __future__ import annotations
 
@@ -29,32 +29,41 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *CFLAGS, "-c", src, "-o", obj]
+LIB_DEBUG = os.path.join(HERE, "libjoin_debug.so")
+
+
+def _compile(src: str, objdir: str = OBJDIR, extra=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *CFLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every csrc/*.hip for gfx950 and link libjoin.so next to this file."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, debug: bool = False) -> str:
+    """Compile every csrc/*.hip for gfx950 and link libjoin.so next to this file.  debug=True
+    builds libjoin_debug.so instead, with JL_DEBUG: the write passes count what they write per
+    work unit and compare it with the count pass, and join_materialize checks that the inputs
+    and the workspace did not change since join_count (both checks synchronise the stream)."""
+    objdir = os.path.join(OBJDIR, "debug") if debug else OBJDIR
+    lib = LIB_DEBUG if debug else LIB
+    extra = ("-DJL_DEBUG=1",) if debug else ()
+    os.makedirs(objdir, exist_ok=True)
     srcs = sources()
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, objdir, extra), srcs))
+    tmp = lib + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, debug="--debug" in sys.argv[1:])
     sys.exit(0)

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "debug.hpp"
 #include "hash.hpp"
 #include "prefilter.hpp"
 #include "region.hpp"
@@ -295,6 +296,57 @@ hipError_t take_total(uint64_t* pub, const void* src, hipStream_t st, uint64_t* 
     return pub ? wait_published(st, count) : read_total(src, st, count);
 }
 
+#if JL_DEBUG
+// The checking build's view of a workspace: where its per-unit written counts are, how many units
+// to check against which offsets, and how much of it the fingerprint covers (the header and the
+// written counts excluded; the pre-filter's inner workspace is not checked).
+struct DebugView {
+    size_t fp_end;    // fingerprint covers [256, fp_end)
+    size_t off_dbg;   // per-unit written counts
+    size_t off_offs;  // per-unit offsets left by the count pass
+    int64_t units, nOff;
+};
+
+DebugView debug_view(int kind, int64_t nR, int64_t nS, const join_pred_t* p)
+{
+    DebugView v{};
+    if (kind == JOIN_KIND_HASH) {
+        const HashPlan pl = hash_plan(nR, nS, num_cus());
+        v = DebugView{pl.off_dbg, pl.off_dbg, pl.off_counts, pl.Umax, pl.Umax};
+    } else if (kind == JOIN_KIND_THETA) {
+        const ThetaPlan pl = plan_theta(nR, nS, p);
+        v = DebugView{pl.off_dbg, pl.off_dbg, pl.off_counts, pl.U, pl.U};
+    } else if (kind == JOIN_KIND_THETA_REGION) {
+        const RegionPlan pl = plan_region(nR, nS, p);
+        v = DebugView{pl.off_dbg, pl.off_dbg, pl.off_counts, pl.Umax, pl.nOff};
+    }
+    return v;
+}
+
+// Fingerprint of the relations' columns and the workspace into the header word at `slot`.
+hipError_t debug_fingerprint(int kind, const join_rel_t* R, const join_rel_t* S,
+                             const join_pred_t* p, char* ws, size_t slot, hipStream_t st)
+{
+    uint64_t* out = reinterpret_cast<uint64_t*>(ws + slot);
+    hipError_t e = dbg_zero(out, 1, st);
+    const join_rel_t* X[2] = {R, S};
+    for (int side = 0; side < 2 && e == hipSuccess; ++side) {
+        const int32_t* cols[3] = {X[side]->key, X[side]->key2, X[side]->rid};
+        for (int c = 0; c < 3 && e == hipSuccess; ++c)
+            e = dbg_fingerprint(cols[c], (uint64_t)X[side]->n * 4, (uint64_t)(side * 3 + c) << 40, out, st);
+    }
+    const DebugView v = debug_view(kind, R->n, S->n, p);
+    if (e == hipSuccess && v.fp_end > 256) e = dbg_fingerprint(ws + 256, v.fp_end - 256, 7ull << 40, out, st);
+    return e;
+}
+
+hipError_t read_word(const void* src, uint64_t* v, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(v, src, 8, hipMemcpyDeviceToHost, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+}
+#endif
+
 int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pred_t* p, void* ws,
                hipStream_t st, uint64_t* count)
 {
@@ -322,6 +374,10 @@ int count_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta count pass" : "hash count pass");
         e = take_total(pub, w + total_at, st, count);
         if (e != hipSuccess) return hip_fail(e, "reading the exact total");
+#if JL_DEBUG
+        e = debug_fingerprint(kind, R, S, p, w, kDebugFpOffset, st);
+        if (e != hipSuccess) return hip_fail(e, "checking build: fingerprint");
+#endif
     }
     g_last.valid = true;
     g_last.kind = kind;
@@ -344,6 +400,24 @@ int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
     }
     char* w = static_cast<char*>(ws);
     hipError_t e;
+#if JL_DEBUG
+    // the inputs and the workspace must be as join_count left them
+    e = debug_fingerprint(kind, R, S, p, w, kDebugFp2Offset, st);
+    uint64_t fp1 = 0, fp2 = 1;
+    if (e == hipSuccess) e = read_word(w + kDebugFpOffset, &fp1, st);
+    if (e == hipSuccess) e = read_word(w + kDebugFp2Offset, &fp2, st);
+    if (e != hipSuccess) return hip_fail(e, "checking build: fingerprint");
+    if (fp1 != fp2) {
+        set_error("checking build: R, S or the workspace changed between join_count and join_materialize");
+        return JOIN_E_INVAL;
+    }
+    const DebugView dv = debug_view(kind, R->n, S->n, p);
+    if (dv.units > 0) {
+        e = dbg_zero(reinterpret_cast<uint64_t*>(w + dv.off_dbg), dv.units, st);
+        if (e == hipSuccess) e = dbg_zero(reinterpret_cast<uint64_t*>(w + kDebugBadOffset), 1, st);
+        if (e != hipSuccess) return hip_fail(e, "checking build: clearing the written counts");
+    }
+#endif
     if (kind == JOIN_KIND_HASH) {
         const HashPlan pl = hash_plan(R->n, S->n, num_cus());
         e = hash_write(pl, *R, *S, w, pairs, capacity, st);
@@ -356,6 +430,24 @@ int write_impl(int kind, const join_rel_t* R, const join_rel_t* S, const join_pr
         e = theta_write(pl, *R, *S, *p, w, pairs, capacity, st);
     }
     if (e != hipSuccess) return hip_fail(e, is_theta(kind) ? "theta write pass" : "hash write pass");
+#if JL_DEBUG
+    if (dv.units > 0) {
+        uint64_t total = 0, bad = 0;
+        e = read_word(w, &total, st);
+        if (e == hipSuccess && total <= capacity)  // an output too small receives nothing
+            e = dbg_check_units(reinterpret_cast<const uint64_t*>(w + dv.off_offs),
+                                reinterpret_cast<const uint64_t*>(w),
+                                reinterpret_cast<const uint64_t*>(w + dv.off_dbg), dv.units, dv.nOff,
+                                reinterpret_cast<uint32_t*>(w + kDebugBadOffset), st);
+        if (e == hipSuccess && total <= capacity) e = read_word(w + kDebugBadOffset, &bad, st);
+        if (e != hipSuccess) return hip_fail(e, "checking build: written counts");
+        if ((uint32_t)bad != 0) {
+            set_error("checking build: %u work units wrote a number of pairs other than they counted",
+                      (unsigned)(uint32_t)bad);
+            return JOIN_E_INVAL;
+        }
+    }
+#endif
     return JOIN_OK;
 }
 

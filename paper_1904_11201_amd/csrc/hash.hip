@@ -20,6 +20,7 @@
 // The LDS table is 4-slot buckets with two candidate buckets per key; a lookup reads both with
 // predicated compares, so a wave issues its LDS reads together and does not branch per key.
 #include "hash.hpp"
+#include "debug.hpp"
 
 #include <type_traits>
 #include <vector>
@@ -41,6 +42,7 @@ constexpr int kScatIt = JL_SCAT_IT;              // tuples per thread per scatte
 constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile (sorted in LDS)
 constexpr int kChunkAlign = 4 * kScatBlock;      // scatter chunks: whole 16-byte loads per thread
 constexpr int kGroups = 8;                       // chunk groups (XCDs) writing through shared cursors
+constexpr int64_t kBatchChunk = 65536;           // rows per histogram / scatter item of a batch
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
 constexpr int kMaxBits = 11;     // scatter: two partitions per thread; 2^11 x 8 B of LDS state
@@ -84,8 +86,13 @@ struct SideTwo {
     uint32_t* tot;  // histogram: its partition sizes
     uint32_t* grp;  // histogram: its group shares; scatter: its group cursors
     int2* out;      // scatter: its partitioned tuples
+    uint32_t* cnt;  // its per-tile counts (histogram), then its run offsets (scatter)
     uint32_t split;
 };
+
+// Tiles of a chunk of `len` rows (the scatter sorts one tile at a time; the histogram counts
+// each tile separately, so that every run of a tile gets a position of its own).
+__host__ __device__ __forceinline__ int64_t tiles_of(int64_t len) { return (len + kScatTile - 1) / kScatTile; }
 
 __device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items, const SideItem& one,
                                               int64_t chunk, int64_t n, uint32_t blk)
@@ -100,12 +107,14 @@ __device__ __forceinline__ SideItem side_item(const SideItem* __restrict__ items
         it.len = p->len;
         it.bits = p->bits;
         it.part0 = p->part0;
+        it.cnt0 = p->cnt0;
         return it;
     }
     SideItem it = one;
     it.beg = (int64_t)blk * chunk;
     const int64_t left = n - it.beg;
     it.len = (uint32_t)(left < chunk ? left : chunk);
+    it.cnt0 = ((uint64_t)blk * (uint64_t)tiles_of(chunk)) << it.bits;
     return it;
 }
 
@@ -118,33 +127,57 @@ __device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p 
 // partition's size) and grp[g * stride + part0 + p] (its group's share of the partition).
 __device__ __forceinline__ uint32_t group_of_block() { return blockIdx.x % kGroups; }
 
+// Per tile of kScatTile rows of the chunk (the scatter's tiles), the count of every partition
+// goes to the tile's row of the side's count array; the chunk's totals then go to the partition
+// sizes and to the chunk group's shares with one global atomic each.
 __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict__ items, SideItem one,
                                                      int64_t chunk, int64_t n, uint32_t* tot,
-                                                     uint32_t* grp, uint32_t stride, SideTwo two)
+                                                     uint32_t* grp, uint32_t stride, uint32_t* cnt,
+                                                     SideTwo two)
 {
     extern __shared__ uint32_t h[];
-    constexpr int V = 4;  // 16-byte loads in flight per thread
+    constexpr int V = 4;  // 16-byte loads in flight per thread: one full tile
+    static_assert(V * 4 * kHistBlock == kScatTile, "a full tile is one round of loads");
     const bool second = blockIdx.x >= two.split;
     const SideItem it = second ? side_item(nullptr, two.one, two.chunk, two.n, blockIdx.x - two.split)
                                : side_item(items, one, chunk, n, blockIdx.x);
     if (second) {
         tot = two.tot;
         grp = two.grp;
+        cnt = two.cnt;
     }
     const int P = 1 << it.bits;
     const int sh = 32 - it.bits;
     for (int i = threadIdx.x; i < P; i += kHistBlock) h[i] = 0;
+    uint32_t own[2] = {0u, 0u};  // chunk totals of partitions tid and tid + kHistBlock
     __syncthreads();
     const gptr<int32_t> key = as_global(it.key + it.beg);
+    const bool vec = aligned16(it.key + it.beg);
     const int64_t end = it.len;
-    int64_t i = 0;
-    if (aligned16(it.key + it.beg)) {
-        const int64_t step = 4 * kHistBlock;
-        for (; i + V * step <= end; i += V * step) {
+    // ordered scatter (cnt != NULL): one row per tile; else the chunk is counted as one span
+    const int64_t span = cnt ? (int64_t)kScatTile : (end > 0 ? end : 1);
+    uint32_t* __restrict__ row = cnt ? cnt + it.cnt0 : nullptr;
+    for (int64_t t0 = 0; t0 < end; t0 += span) {
+        const int64_t tn = end - t0 < span ? end - t0 : span;
+        if (!cnt && vec) {
+            int64_t i = 0;
+            for (; i + kScatTile <= tn; i += kScatTile) {
+                i32x4 k4[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) k4[v] = load4(key + t0 + i + v * 4 * kHistBlock + 4 * threadIdx.x);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    atomicAdd(&h[pid_of(k4[v].x, sh)], 1u);
+                    atomicAdd(&h[pid_of(k4[v].y, sh)], 1u);
+                    atomicAdd(&h[pid_of(k4[v].z, sh)], 1u);
+                    atomicAdd(&h[pid_of(k4[v].w, sh)], 1u);
+                }
+            }
+            for (i += threadIdx.x; i < tn; i += kHistBlock) atomicAdd(&h[pid_of(key[t0 + i], sh)], 1u);
+        } else if (vec && tn == kScatTile) {
             i32x4 k4[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                k4[v] = load4(key + i + v * step + 4 * threadIdx.x);
+            for (int v = 0; v < V; ++v) k4[v] = load4(key + t0 + v * 4 * kHistBlock + 4 * threadIdx.x);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 atomicAdd(&h[pid_of(k4[v].x, sh)], 1u);
@@ -152,18 +185,124 @@ __global__ __launch_bounds__(kHistBlock) void hist_k(const SideItem* __restrict_
                 atomicAdd(&h[pid_of(k4[v].z, sh)], 1u);
                 atomicAdd(&h[pid_of(k4[v].w, sh)], 1u);
             }
+        } else {
+            for (int64_t i = threadIdx.x; i < tn; i += kHistBlock) atomicAdd(&h[pid_of(key[t0 + i], sh)], 1u);
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int p = (int)threadIdx.x + j * kHistBlock;
+            if (p < P) {
+                const uint32_t v = h[p];
+                if (row) row[p] = v;
+                own[j] += v;
+                h[p] = 0;
+            }
+        }
+        __syncthreads();
+        if (row) row += P;
     }
-    for (i += threadIdx.x; i < end; i += kHistBlock) atomicAdd(&h[pid_of(key[i], sh)], 1u);
-    __syncthreads();
     uint32_t* __restrict__ gs = grp + (size_t)group_of_block() * stride + it.part0;
-    for (int p = threadIdx.x; p < P; p += kHistBlock) {
-        const uint32_t v = h[p];
-        if (v) {
-            atomicAdd(&tot[it.part0 + p], v);
-            atomicAdd(&gs[p], v);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int p = (int)threadIdx.x + j * kHistBlock;
+        if (p < P && own[j]) {
+            atomicAdd(&tot[it.part0 + p], own[j]);
+            atomicAdd(&gs[p], own[j]);
         }
     }
+}
+
+// Run offsets.  The runs a group's chunks write into partition p follow each other by tile
+// index, then by chunk index: tile t of every chunk of the group, then tile t + 1, and so on.
+// The group's workgroups work on about the same tile at the same time, so the runs written at
+// about the same time lie next to each other and the 64-byte granules they share are completed
+// in that XCD's L2 soon after; and the layout depends on the input alone.  In place, every
+// per-tile count becomes the offset of its run from the group's start in the partition.
+// Single join: one workgroup per (group, block of 64 partitions) of a side; thread (tl, q) takes
+// tiles t = tl, tl + 16, ... of partition p0 + q over the group's chunks c = g0, g0 + 8, ...
+// (g0 = the first chunk whose workgroup index falls in group g).  Chunk c has tiles_of(len_c)
+// tiles; rows past a chunk's last tile hold nothing.
+struct BandSide {
+    uint32_t* cnt;
+    int64_t chunk, n, nCh;
+    int bits;
+    uint32_t blockBase;  // workgroup index of chunk 0 in the histogram and scatter launches
+};
+
+constexpr int kBandBlock = 1024;
+constexpr int kBandQ = 64;                      // partitions per workgroup
+constexpr int kBandT = kBandBlock / kBandQ;     // tiles per pass
+
+__device__ void band_side(const BandSide& b, int g, int p0, uint32_t* lds)
+{
+    const int P = 1 << b.bits;
+    const int q = (int)threadIdx.x % kBandQ, tl = (int)threadIdx.x / kBandQ;
+    const int p = p0 + q;
+    const int64_t T = tiles_of(b.chunk);
+    const int64_t c0 = ((int64_t)g - (int64_t)(b.blockBase % kGroups) + kGroups) % kGroups;
+    uint32_t carry = 0;  // runs of partition p in earlier tile passes (same in every tile lane)
+    for (int64_t tb = 0; tb < T; tb += kBandT) {
+        const int64_t t = tb + tl;
+        uint32_t sum = 0;
+        if (p < P && t < T)
+            for (int64_t c = c0; c < b.nCh; c += kGroups) {
+                const int64_t len = b.n - c * b.chunk < b.chunk ? b.n - c * b.chunk : b.chunk;
+                if (t < tiles_of(len)) sum += b.cnt[((uint64_t)(c * T + t) << b.bits) + p];
+            }
+        lds[tl * kBandQ + q] = sum;
+        __syncthreads();
+        uint32_t run = carry, all = 0;
+        for (int j = 0; j < kBandT; ++j) {
+            const uint32_t v = lds[j * kBandQ + q];
+            run += j < tl ? v : 0u;
+            all += v;
+        }
+        __syncthreads();
+        if (p < P && t < T)
+            for (int64_t c = c0; c < b.nCh; c += kGroups) {
+                const int64_t len = b.n - c * b.chunk < b.chunk ? b.n - c * b.chunk : b.chunk;
+                if (t < tiles_of(len)) {
+                    uint32_t* x = &b.cnt[((uint64_t)(c * T + t) << b.bits) + p];
+                    const uint32_t v = *x;
+                    *x = run;
+                    run += v;
+                }
+            }
+        carry += all;
+    }
+}
+
+// Batch: one thread per (partition of any join, group) of a side.  A join's chunks are the items
+// [item0[j], item0[j + 1]) of the side; item i runs in workgroup i, so its group is i mod 8.
+__global__ void band_batch_k(const SideItem* __restrict__ items, const uint32_t* __restrict__ item0,
+                             const uint32_t* __restrict__ jpart0, int nJobs, uint32_t nParts,
+                             uint32_t* __restrict__ cnt)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint64_t)nParts * kGroups) return;
+    const uint32_t gp = (uint32_t)(x / kGroups);
+    const int g = (int)(x % kGroups);
+    int lo = 0, hi = nJobs - 1;  // last job whose first partition is <= gp
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jpart0[mid] <= gp) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t p = gp - jpart0[lo];
+    const uint32_t i0 = item0[lo], i1 = item0[lo + 1];
+    const uint32_t f = i0 + (uint32_t)((g - (int)(i0 % kGroups) + kGroups) % kGroups);
+    uint32_t run = 0;
+    for (int64_t t = 0; t < tiles_of(kBatchChunk); ++t)
+        for (uint32_t i = f; i < i1; i += kGroups) {
+            const SideItem& it = items[i];
+            if (t < tiles_of(it.len)) {
+                uint32_t* c = &cnt[it.cnt0 + ((uint64_t)t << it.bits) + p];
+                const uint32_t v = *c;
+                *c = run;
+                run += v;
+            }
+        }
 }
 
 // Group shares -> group cursors: the groups' ranges follow each other inside every partition,
@@ -188,18 +327,17 @@ __global__ void group_cursors_k(uint32_t* __restrict__ grp, const uint32_t* __re
 // write 64 partitions makes 64 of them), and 64-byte granules written in part (each is a
 // read-modify-write in HBM unless the rest of the granule reaches the L2 while the line is
 // still there).  Per tile of kScatTile tuples:
-//   1. each partition's share of the tile is counted (LDS atomics);
-//   2. the chunk's group takes that many output positions from its cursor for the partition
-//      (one global atomic per partition and tile), and an exclusive scan of the shares gives
-//      each partition's start in the sorted tile;
-//   3. each tuple takes the next slot of its partition in LDS (an LDS atomic on a cursor that
-//      starts at the partition's start) and is placed there: the tile is sorted by partition;
-//   4. the sorted tile is written out by consecutive lanes taking consecutive positions, so a
-//      store instruction covers runs of about kScatTile / 2^bits tuples and touches a few
-//      granules instead of 64.
-// A partition's runs from the chunks of one group follow each other at its group cursor, so the
-// granule a run leaves incomplete is completed by the next run of the same group soon after,
-// in the same XCD's L2.  Tuples of a partition keep no order, which does not matter to the join.
+//   1. each wave counts its tuples per partition (LDS atomics on the wave's own counters);
+//   2. per partition: the tile's share, its start in the sorted tile (block scan) and each
+//      wave's start inside it, and the shift from sorted to output position: the run's output
+//      start is the group's start in the partition plus the run offset the band scan computed;
+//   3. each tuple takes the next position of its wave in its partition (an LDS atomic on the
+//      wave's own counter, so positions follow the waves in order, and inside a wave the lanes
+//      of one instruction in order, then the instructions in order): the tile is sorted by
+//      partition, and the order depends on the input alone;
+//   4. the sorted tile goes through LDS in two halves and is written by consecutive lanes taking
+//      consecutive positions, so a store instruction covers runs of about kScatTile / 2^bits
+//      tuples and touches a few granules instead of 64.
 // Thread t handles partitions 2t and 2t + 1 in the per-partition steps.
 // Element of thread tid, item 4v + c: tile position 4 * (v * kScatBlock + tid) + c, so every
 // 16-byte load instruction of a wave reads 1 KB of consecutive input.
@@ -225,7 +363,13 @@ __device__ __forceinline__ void scat_load(gptr<int32_t> col, int t0, int tn, int
     }
 }
 
-struct ScatLds {
+// ---- the arrival-order scatter (default) ----
+// Each tile's runs go to its chunk group's cursor in every partition (one global atomic per
+// partition and tile): consecutive runs of a partition come from the group's chunks in the order
+// they arrive, so the granule a run leaves incomplete is completed by the next run of the same
+// group soon after, in the same XCD's L2.  The order of a partition's tuples depends on that
+// arrival order (and, inside a tile, on the order of the LDS atomics of different waves).
+struct ScatLdsA {
     int2* stg;      // [kScatTile] the tile sorted by partition
     uint32_t* cnt;  // [P] tile shares, then sorted starts
     uint32_t* dlt;  // [P] output position - sorted position
@@ -235,8 +379,8 @@ struct ScatLds {
 // One tile: k holds raw keys (hashed here), r the row ids (RIDS) or nothing (row id = pos0 + tile
 // position).  cur: this group's cursors of the join's partitions.
 template <bool RIDS, bool FULL>
-__device__ __forceinline__ void scat_tile(int32_t (&k)[kScatIt], const int32_t (&r)[kScatIt], int tn,
-                                          int64_t pos0, int P, int sh, const ScatLds& L,
+__device__ __forceinline__ void scat_tile_a(int32_t (&k)[kScatIt], const int32_t (&r)[kScatIt], int tn,
+                                          int64_t pos0, int P, int sh, const ScatLdsA& L,
                                           uint32_t* __restrict__ cur, int2* __restrict__ out)
 {
     const int tid = threadIdx.x;
@@ -306,9 +450,9 @@ __device__ __forceinline__ void scat_tile(int32_t (&k)[kScatIt], const int32_t (
 // worked on, before this tile's stores, so that waiting for them does not wait for the stores
 // (the vector memory counter counts loads and stores in one queue).
 template <bool RIDS>
-__device__ __forceinline__ void scat_full_tile(int t, int nfull, gptr<int32_t> key, gptr<int32_t> rid,
+__device__ __forceinline__ void scat_full_tile_a(int t, int nfull, gptr<int32_t> key, gptr<int32_t> rid,
                                                int32_t (&nk)[kScatIt], int32_t (&nr)[kScatIt],
-                                               int64_t beg, int P, int sh, const ScatLds& L,
+                                               int64_t beg, int P, int sh, const ScatLdsA& L,
                                                uint32_t* __restrict__ cur, int2* __restrict__ out)
 {
     int32_t k[kScatIt], r[kScatIt];
@@ -321,7 +465,187 @@ __device__ __forceinline__ void scat_full_tile(int t, int nfull, gptr<int32_t> k
         scat_load<true>(key, (t + 1) * kScatTile, kScatTile, nk);
         if (RIDS) scat_load<true>(rid, (t + 1) * kScatTile, kScatTile, nr);
     }
-    scat_tile<RIDS, true>(k, r, kScatTile, beg + (int64_t)t * kScatTile, P, sh, L, cur, out);
+    scat_tile_a<RIDS, true>(k, r, kScatTile, beg + (int64_t)t * kScatTile, P, sh, L, cur, out);
+}
+
+// A chunk: its full tiles, then the partial rest.  The first full tile is peeled off the loop,
+// so that every pass through the loop starts in the same state (the loads it needs issued before
+// the previous tile's stores) and waiting for those loads does not wait for the stores.
+template <bool RIDS>
+__device__ __forceinline__ void scat_chunk_a(gptr<int32_t> key, gptr<int32_t> rid, bool vec, int end,
+                                           int64_t beg, int P, int sh, const ScatLdsA& L,
+                                           uint32_t* __restrict__ cur, int2* __restrict__ out)
+{
+    const int nfull = vec ? end / kScatTile : 0;
+    int32_t nk[kScatIt], nr[kScatIt];
+    if (nfull > 0) {
+        scat_load<true>(key, 0, kScatTile, nk);
+        if (RIDS) scat_load<true>(rid, 0, kScatTile, nr);
+        scat_full_tile_a<RIDS>(0, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+    }
+    for (int t = 1; t < nfull; ++t)
+        scat_full_tile_a<RIDS>(t, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+    for (int t0 = nfull * kScatTile; t0 < end; t0 += kScatTile) {
+        const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
+        int32_t k[kScatIt], r[kScatIt];
+        scat_load<false>(key, t0, tn, k, vec);
+        if (RIDS) scat_load<false>(rid, t0, tn, r, vec);
+        scat_tile_a<RIDS, false>(k, r, tn, beg + t0, P, sh, L, cur, out);
+    }
+}
+
+// ---- the ordered scatter (plan option hash.deterministic) ----
+constexpr int kScatWaves = kScatBlock / kWave;
+constexpr int kScatHalf = kScatTile / 2;  // tuples of one half of the sorted tile
+static_assert(kScatTile <= 65536, "per-wave positions are 16-bit");
+
+struct ScatLds {
+    int2* stg;      // [kScatHalf] one half of the tile, sorted by partition
+    uint32_t* wc;   // [kScatWaves / 2][P] per-wave counters: wave w in half (w & 1) of row w / 2
+    uint32_t* dlt;  // [P] output position - sorted position
+    uint32_t* tmp;  // scan scratch
+};
+
+// Where the runs of a chunk's tiles go: the group's start in each of the thread's two
+// partitions, and the band scan's run offsets of the current tile.
+struct ScatDest {
+    uint32_t ga, gb;  // group starts of partitions 2t, 2t + 1
+    uint32_t oa, ob;  // run offsets in them of the tile being worked on
+};
+
+// One tile: k holds raw keys (hashed here), r the row ids (RIDS) or nothing (row id = pos0 + tile
+// position).
+template <bool RIDS, bool FULL>
+__device__ __forceinline__ void scat_tile(int32_t (&k)[kScatIt], const int32_t (&r)[kScatIt], int tn,
+                                          int64_t pos0, int P, int sh, const ScatLds& L,
+                                          const ScatDest& d, int2* __restrict__ out)
+{
+    const int tid = threadIdx.x;
+    const int pa = 2 * tid, pb = 2 * tid + 1;
+    const int wv = tid / kWave;
+    const uint32_t wsh = 16u * (uint32_t)(wv & 1);
+    uint32_t* __restrict__ wrow = L.wc + (size_t)(wv >> 1) * P;
+    // 1. the wave's shares.  Tuples are written as (hmix(key), rid): the hash is a bijection of
+    // the key, so the join kernels compare hashes and never hash again.
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        const uint32_t h = hmix((uint32_t)k[q]);
+        k[q] = (int32_t)h;
+        if (FULL || scat_pos(q) < tn) atomicAdd(&wrow[sh >= 32 ? 0u : h >> sh], 1u << wsh);
+    }
+    __syncthreads();
+    // 2. tile shares, sorted starts, per-wave starts, shifts
+    uint32_t wa[kScatWaves / 2], wb[kScatWaves / 2], ca = 0, cb = 0;
+#pragma unroll
+    for (int j = 0; j < kScatWaves / 2; ++j) {
+        wa[j] = pa < P ? L.wc[(size_t)j * P + pa] : 0u;
+        wb[j] = pb < P ? L.wc[(size_t)j * P + pb] : 0u;
+        ca += (wa[j] & 0xFFFFu) + (wa[j] >> 16);
+        cb += (wb[j] & 0xFFFFu) + (wb[j] >> 16);
+    }
+    uint32_t tot;
+    const uint32_t sa = block_excl_scan<kScatBlock>(ca + cb, L.tmp, &tot);
+    uint32_t run = sa;
+#pragma unroll
+    for (int j = 0; j < kScatWaves / 2; ++j) {
+        const uint32_t lo = wa[j] & 0xFFFFu;
+        if (pa < P) L.wc[(size_t)j * P + pa] = run | ((run + lo) << 16);
+        run += lo + (wa[j] >> 16);
+    }
+#pragma unroll
+    for (int j = 0; j < kScatWaves / 2; ++j) {
+        const uint32_t lo = wb[j] & 0xFFFFu;
+        if (pb < P) L.wc[(size_t)j * P + pb] = run | ((run + lo) << 16);
+        run += lo + (wb[j] >> 16);
+    }
+    if (pa < P) L.dlt[pa] = d.ga + d.oa - sa;
+    if (pb < P) L.dlt[pb] = d.gb + d.ob - (sa + ca);
+    __syncthreads();
+    // 3. positions in the sorted tile
+    uint32_t at[kScatIt];
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        at[q] = ~0u;
+        if (FULL || scat_pos(q) < tn) {
+            const uint32_t h = (uint32_t)k[q];
+            const uint32_t old = atomicAdd(&wrow[sh >= 32 ? 0u : h >> sh], 1u << wsh);
+            at[q] = (old >> wsh) & 0xFFFFu;
+        }
+    }
+    // 4. the sorted tile, half by half: placed in LDS, then written by consecutive lanes, eight
+    // LDS reads in flight at a time
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int q = 0; q < kScatIt; ++q)
+            if (at[q] - (uint32_t)(half * kScatHalf) < (uint32_t)kScatHalf)
+                L.stg[at[q] - half * kScatHalf] = make_int2(k[q], RIDS ? r[q] : (int32_t)(pos0 + scat_pos(q)));
+        __syncthreads();
+        if (half == 0) {  // every position is taken: the next tile's counters start from zero
+#pragma unroll
+            for (int j = 0; j < kScatWaves / 2; ++j) {
+                if (pa < P) L.wc[(size_t)j * P + pa] = 0;
+                if (pb < P) L.wc[(size_t)j * P + pb] = 0;
+            }
+        }
+        constexpr int G = 8;
+#pragma unroll
+        for (int g = 0; g < kScatIt / 2; g += G) {
+            int2 v[G];
+            uint32_t o[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int i = (g + u) * kScatBlock + tid;
+                v[u] = (FULL || half * kScatHalf + i < tn) ? L.stg[i] : make_int2(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const uint32_t h = (uint32_t)v[u].x;
+                o[u] = L.dlt[sh >= 32 ? 0u : h >> sh];
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int i = (g + u) * kScatBlock + tid;
+                if (FULL || half * kScatHalf + i < tn) put(&out[o[u] + (uint32_t)(half * kScatHalf + i)], v[u]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The run offsets of tile t of the chunk in the thread's two partitions.
+__device__ __forceinline__ void scat_offsets(const uint32_t* __restrict__ cnt0, int t, int P,
+                                             uint32_t& oa, uint32_t& ob)
+{
+    const int pa = 2 * (int)threadIdx.x, pb = pa + 1;
+    const uint32_t* row = cnt0 + (size_t)t * P;
+    oa = pa < P ? row[pa] : 0u;
+    ob = pb < P ? row[pb] : 0u;
+}
+
+// Full tile t of a chunk: the next tile's keys, rids and run offsets are loaded into nk, nr, nd
+// while this one is worked on, before this tile's stores, so that waiting for them does not wait
+// for the stores (the vector memory counter counts loads and stores in one queue).
+template <bool RIDS>
+__device__ __forceinline__ void scat_full_tile(int t, int nfull, gptr<int32_t> key, gptr<int32_t> rid,
+                                               int32_t (&nk)[kScatIt], int32_t (&nr)[kScatIt],
+                                               ScatDest& nd, const uint32_t* __restrict__ cnt0,
+                                               int64_t beg, int P, int sh, const ScatLds& L,
+                                               int2* __restrict__ out)
+{
+    int32_t k[kScatIt], r[kScatIt];
+#pragma unroll
+    for (int q = 0; q < kScatIt; ++q) {
+        k[q] = nk[q];
+        if (RIDS) r[q] = nr[q];
+    }
+    const ScatDest d = nd;
+    if (t + 1 < nfull) {
+        scat_offsets(cnt0, t + 1, P, nd.oa, nd.ob);
+        scat_load<true>(key, (t + 1) * kScatTile, kScatTile, nk);
+        if (RIDS) scat_load<true>(rid, (t + 1) * kScatTile, kScatTile, nr);
+    }
+    scat_tile<RIDS, true>(k, r, kScatTile, beg + (int64_t)t * kScatTile, P, sh, L, d, out);
 }
 
 // A chunk: its full tiles, then the partial rest.  The first full tile is peeled off the loop,
@@ -330,23 +654,26 @@ __device__ __forceinline__ void scat_full_tile(int t, int nfull, gptr<int32_t> k
 template <bool RIDS>
 __device__ __forceinline__ void scat_chunk(gptr<int32_t> key, gptr<int32_t> rid, bool vec, int end,
                                            int64_t beg, int P, int sh, const ScatLds& L,
-                                           uint32_t* __restrict__ cur, int2* __restrict__ out)
+                                           ScatDest d, const uint32_t* __restrict__ cnt0,
+                                           int2* __restrict__ out)
 {
     const int nfull = vec ? end / kScatTile : 0;
     int32_t nk[kScatIt], nr[kScatIt];
     if (nfull > 0) {
+        scat_offsets(cnt0, 0, P, d.oa, d.ob);
         scat_load<true>(key, 0, kScatTile, nk);
         if (RIDS) scat_load<true>(rid, 0, kScatTile, nr);
-        scat_full_tile<RIDS>(0, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+        scat_full_tile<RIDS>(0, nfull, key, rid, nk, nr, d, cnt0, beg, P, sh, L, out);
     }
     for (int t = 1; t < nfull; ++t)
-        scat_full_tile<RIDS>(t, nfull, key, rid, nk, nr, beg, P, sh, L, cur, out);
+        scat_full_tile<RIDS>(t, nfull, key, rid, nk, nr, d, cnt0, beg, P, sh, L, out);
     for (int t0 = nfull * kScatTile; t0 < end; t0 += kScatTile) {
         const int tn = end - t0 < kScatTile ? end - t0 : kScatTile;
         int32_t k[kScatIt], r[kScatIt];
+        scat_offsets(cnt0, t0 / kScatTile, P, d.oa, d.ob);
         scat_load<false>(key, t0, tn, k, vec);
         if (RIDS) scat_load<false>(rid, t0, tn, r, vec);
-        scat_tile<RIDS, false>(k, r, tn, beg + t0, P, sh, L, cur, out);
+        scat_tile<RIDS, false>(k, r, tn, beg + t0, P, sh, L, d, out);
     }
 }
 
@@ -441,15 +768,35 @@ __device__ __forceinline__ void group_cursors(uint32_t* __restrict__ grp, uint32
     }
 }
 
+// Band work of a single join: 8 groups x ceil(P / kBandQ) partition blocks per side with counts
+// (cnt != NULL).
+__host__ __device__ __forceinline__ int64_t band_blocks(const BandSide& b)
+{
+    return b.cnt ? (int64_t)kGroups * (((1 << b.bits) + kBandQ - 1) / kBandQ) : 0;
+}
+
+// Workgroups 0 and 1: each side's partition starts and group starts (a NULL tot skips that
+// side).  Workgroups from 2 on: the run offsets of R's tiles, then of S's (band_side).
 __global__ __launch_bounds__(kFuseBlock) void part_starts_k(const uint32_t* __restrict__ totR,
                                                             uint32_t* __restrict__ baseR,
                                                             uint32_t* __restrict__ grpR,
                                                             const uint32_t* __restrict__ totS,
                                                             uint32_t* __restrict__ baseS,
                                                             uint32_t* __restrict__ grpS,
-                                                            uint32_t stride, int n)
+                                                            uint32_t stride, int n, BandSide bR,
+                                                            BandSide bS)
 {
-    __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
+    static_assert(kFuseBlock == kBandBlock, "one launch shape for both kinds of workgroup");
+    __shared__ uint32_t tmp[kBandBlock];
+    if (blockIdx.x >= 2) {
+        int64_t k = blockIdx.x - 2;
+        const bool s = k >= band_blocks(bR);
+        if (s) k -= band_blocks(bR);
+        const BandSide& b = s ? bS : bR;
+        const int64_t nq = ((1 << b.bits) + kBandQ - 1) / kBandQ;
+        band_side(b, (int)(k / nq), (int)(k % nq) * kBandQ, tmp);
+        return;
+    }
     {
         const int side = blockIdx.x;  // workgroup 0: R, workgroup 1: S
         const uint32_t* tot = side ? totS : totR;
@@ -530,12 +877,15 @@ struct PlanArgs {
 };
 
 // RIDS: the side has a rid column (a batch passes RIDS and may still leave it NULL per item;
-// without rids the row ids are positions).  cur: group cursors, [kGroups][stride].
-template <bool RIDS>
+// without rids the row ids are positions).  cur: the groups' starts in every partition,
+// [kGroups][stride]; cnt: the side's run offsets (band scan).
+// ORDERED: the ordered scatter (runs at the band scan's offsets, ranks from per-wave counters),
+// else the arrival-order one (runs at the group cursors).
+template <bool RIDS, bool ORDERED>
 __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restrict__ items, SideItem one,
                                                         int64_t chunk, int64_t n, uint32_t* cur,
-                                                        uint32_t stride, int2* out, SideTwo two,
-                                                        PlanArgs pa)
+                                                        uint32_t stride, int2* out,
+                                                        const uint32_t* cnt, SideTwo two, PlanArgs pa)
 {
     extern __shared__ uint32_t lds[];
     // The chunk of workgroup b is the one the histogram counted in workgroup b: its group shares
@@ -551,26 +901,50 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
     if (second) {
         cur = two.grp;
         out = two.out;
+        cnt = two.cnt;
     }
     const int P = 1 << it.bits;
     const int sh = 32 - it.bits;
+    const int tid = threadIdx.x;
+    if constexpr (!ORDERED) {
+        ScatLdsA L;
+        L.stg = reinterpret_cast<int2*>(lds);
+        L.cnt = lds + 2 * kScatTile;
+        L.dlt = L.cnt + P;
+        L.tmp = L.dlt + P;
+        if (2 * tid < P) L.cnt[2 * tid] = 0;
+        if (2 * tid + 1 < P) L.cnt[2 * tid + 1] = 0;
+        __syncthreads();
+        uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
+        const gptr<int32_t> key = as_global(it.key + it.beg);
+        const bool kvec = aligned16(it.key + it.beg);
+        if (!RIDS || it.rid == nullptr) {
+            scat_chunk_a<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, gc, out);
+        } else {
+            const bool vec = kvec && aligned16(it.rid + it.beg);
+            scat_chunk_a<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, gc, out);
+        }
+        return;
+    }
     ScatLds L;
     L.stg = reinterpret_cast<int2*>(lds);
-    L.cnt = lds + 2 * kScatTile;
-    L.dlt = L.cnt + P;
+    L.wc = lds + 2 * kScatHalf;
+    L.dlt = L.wc + (size_t)(kScatWaves / 2) * P;
     L.tmp = L.dlt + P;
-    const int tid = threadIdx.x;
-    if (2 * tid < P) L.cnt[2 * tid] = 0;
-    if (2 * tid + 1 < P) L.cnt[2 * tid + 1] = 0;
+    for (int i = tid; i < (kScatWaves / 2) * P; i += kScatBlock) L.wc[i] = 0;
     __syncthreads();
-    uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
+    const uint32_t* __restrict__ gc = cur + (size_t)group_of_block() * stride + it.part0;
+    ScatDest d{};
+    d.ga = 2 * tid < P ? gc[2 * tid] : 0u;
+    d.gb = 2 * tid + 1 < P ? gc[2 * tid + 1] : 0u;
+    const uint32_t* __restrict__ c0 = cnt + it.cnt0;
     const gptr<int32_t> key = as_global(it.key + it.beg);
     const bool kvec = aligned16(it.key + it.beg);
     if (!RIDS || it.rid == nullptr) {
-        scat_chunk<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, gc, out);
+        scat_chunk<false>(key, nullptr, kvec, (int)it.len, it.beg, P, sh, L, d, c0, out);
     } else {
         const bool vec = kvec && aligned16(it.rid + it.beg);
-        scat_chunk<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, gc, out);
+        scat_chunk<true>(key, as_global(it.rid + it.beg), vec, (int)it.len, it.beg, P, sh, L, d, c0, out);
     }
 }
 
@@ -935,14 +1309,33 @@ __device__ __forceinline__ void for_each_match(const Table& t, int bits, uint32_
     if (overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x)) walk_on<MARKED>(t, x, b1, b2, emit);
 }
 
+// Sorts 8 values ascending with the 19 compare-exchanges of Batcher's odd-even merge network.
+__device__ __forceinline__ void sort8(uint32_t (&v)[8])
+{
+    constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2},
+                                 {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4},
+                                 {5, 6}};
+#pragma unroll
+    for (int c = 0; c < 19; ++c) {
+        const uint32_t a = v[kNet[c][0]], b = v[kNet[c][1]];
+        v[kNet[c][0]] = min(a, b);
+        v[kNet[c][1]] = max(a, b);
+    }
+}
+
 // The pairs of a probe with more than two matches, at slot .. slot + m - 1, in ascending rid
-// order.  Up to kEmitSort matches are gathered in registers and each goes to its rank (rids
-// below it, plus equal rids met before it); a probe with more meets them in order already (its
-// table was put in canonical order).
+// order (as signed int32).
+//  * Up to kEmitSort matches, all in the two candidate buckets (neither walks on): the 8 slots'
+//    rids are read at once and sorted by a network, as unsigned keys rid ^ 2^31, the slots that
+//    do not match set to all ones; the first m are written.  A matching rid of INT32_MAX has the
+//    same key as a slot that does not match, and both turn back into INT32_MAX, so the first m
+//    values are the matches in order either way.
+//  * Up to kEmitSort matches with a walk (rare): gathered in registers, each written at its rank.
+//  * More: the table was put in canonical order, so the visiting order is ascending.
 template <bool HASHED, bool MARKED>
 __device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, uint32_t m,
-                                       const uint32_t* rw, int32_t srid, uint64_t slot,
-                                       int2* __restrict__ out, uint64_t cap)
+                                          const uint32_t* rw, int32_t srid, uint64_t slot,
+                                          int2* __restrict__ out, uint64_t cap)
 {
     if (m > (uint32_t)kEmitSort) {
         uint32_t seen = 0;
@@ -950,6 +1343,23 @@ __device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, 
             if (slot + seen < cap) put_pair(&out[slot + seen], make_int2((int32_t)rw[p], srid));
             ++seen;
         });
+        return;
+    }
+    uint32_t b1, b2;
+    choices(HASHED ? x : hmix(x), bits, t.nb, b1, b2);
+    const uint4 k1 = t.keys[b1], k2 = t.keys[b2];
+    const uint32_t c1 = claims<MARKED>(t, b1), c2 = claims<MARKED>(t, b2);
+    if (!(overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x))) {
+        const uint32_t hm = hits<MARKED>(k1, c1, x) | (hits<MARKED>(k2, c2, x) << 4);
+        const uint4 r1 = t.rids[b1], r2 = t.rids[b2];
+        uint32_t v[8] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = ((hm >> j) & 1u) ? v[j] ^ 0x80000000u : ~0u;
+        sort8(v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((uint32_t)k < m && slot + k < cap)
+                put_pair(&out[slot + k], make_int2((int32_t)(v[k] ^ 0x80000000u), srid));
         return;
     }
     int32_t r[kEmitSort];
@@ -1357,6 +1767,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         }
         // this wave's first output slot in unit u
         uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kJoinWaves + wv]) : 0ull);
+#if JL_DEBUG
+        const uint64_t cursor0 = cursor;
+#endif
         const Table t = table_of<true, AOS>(un, tab);
         const bool more = u + step < u1;
         const Unit nxt = more ? decode_unit(g, u + step) : Unit{};
@@ -1415,6 +1828,10 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
+#if JL_DEBUG
+        if (g.dbg && lane_id() == 0 && cursor > cursor0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&g.dbg[u]), (unsigned long long)(cursor - cursor0));
+#endif
         if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
         __syncthreads();
         un = nxt;
@@ -1426,11 +1843,16 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 
-// sorted tile, shares/starts and shifts per partition, scan scratch
-static size_t scatter_lds(int P)
+// Arrival order: the sorted tile, shares/starts and shifts per partition, scan scratch.
+// Ordered: half of the sorted tile, per-wave counters and shifts per partition, scan scratch.
+static size_t scatter_lds(int P, bool ordered)
 {
-    return (size_t)kScatTile * sizeof(int2) + (size_t)P * 8 + (kScatBlock / kWave + 1) * 4;
+    if (!ordered) return (size_t)kScatTile * sizeof(int2) + (size_t)P * 8 + (kScatBlock / kWave + 1) * 4;
+    return (size_t)kScatHalf * sizeof(int2) + (size_t)(kScatWaves / 2) * P * 4 + (size_t)P * 4 +
+           (kScatWaves + 1) * 4;
 }
+
+static bool ordered_knob() { return tune_get(TUNE_HASH_DETERMINISTIC, 0) != 0; }
 
 // Default fan-out: mean partition size <= 0.9 * cap keeps the largest partitions (mean + 6 sigma
 // for hashed unique keys) under cap; past 2^kMaxBits partitions R chunks repeat per S slice.
@@ -1461,6 +1883,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     if (pl.slice < 1024) pl.slice = 1024;
     const int64_t single_max = tune_get(TUNE_HASH_SINGLE_MAX, 16) * cap;
     pl.prebuilt = prebuilt_bits >= 0;
+    pl.ordered = ordered_knob();
     const int forced_bits = pl.prebuilt ? prebuilt_bits : (int)tune_get(TUNE_HASH_BITS, -1);
     pl.single = !pl.prebuilt && (forced_bits == 0 || (forced_bits < 0 && nR <= single_max));
     size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
@@ -1487,7 +1910,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         pl.P = 1 << bits;
         // scatter chunks: one per resident scatter workgroup (the sorted tile decides how many
         // fit a CU), each a multiple of kChunkAlign rows
-        int per_cu = (int)((160 * 1024) / scatter_lds(pl.P));
+        int per_cu = (int)((160 * 1024) / scatter_lds(pl.P, pl.ordered));
         if (per_cu < 1) per_cu = 1;
         if (per_cu > 2) per_cu = 2;
         auto chunk_for = [&](int64_t n) {
@@ -1522,6 +1945,13 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         off = align_up(off + (size_t)(pl.P + 1) * 4);
         pl.off_umap = off;
         off = align_up(off + (size_t)pl.Umax * 4);
+        // ordered scatter: per-tile counts, then run offsets, of each side (chunks x tiles per
+        // chunk x P)
+        const size_t on = pl.ordered ? 1 : 0;
+        pl.off_cntR = off;
+        off = align_up(off + ((on * (size_t)pl.nChR * (size_t)tiles_of(pl.chR) * 4) << pl.bits));
+        pl.off_cntS = off;
+        off = align_up(off + ((on * (size_t)pl.nChS * (size_t)tiles_of(pl.chS) * 4) << pl.bits));
     }
     pl.off_counts = off;
     off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
@@ -1534,6 +1964,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     }
     pl.off_temp = off;
     off = align_up(off + temp + 8);
+    pl.off_dbg = off;  // last: the checking build's per-unit written counts
+    off = align_up(off + (JL_DEBUG ? (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8 : 0));
     pl.bytes = off;
     // persistent grids of the join kernels: as many workgroups per CU as the LDS table allows
     auto grid_for = [&](bool rids) {
@@ -1544,7 +1976,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     };
     pl.gridCount = grid_for(false);
     pl.gridWrite = grid_for(true);
-    pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.bits, pl.P, pl.cap,
+    pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.ordered, pl.bits, pl.P, pl.cap,
                            pl.slice, pl.nSs, pl.chR, pl.chS, pl.Umax, pl.gridCount, pl.gridWrite,
                            (int64_t)pl.bytes});
     return pl;
@@ -1557,7 +1989,8 @@ static hipError_t set_attrs()
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
     const void* fns[] = {
-        (const void*)scatter_k<true>, (const void*)scatter_k<false>, (const void*)hist_k,
+        (const void*)scatter_k<true, false>, (const void*)scatter_k<false, false>,
+        (const void*)scatter_k<true, true>, (const void*)scatter_k<false, true>, (const void*)hist_k,
         (const void*)join_count_k<true>, (const void*)join_count_k<false>,
         (const void*)join_write_k<true>, (const void*)join_write_k<false>,
     };
@@ -1580,22 +2013,22 @@ static SideItem whole_side(const join_rel_t& X, int bits)
 
 static hipError_t hist_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
                             int64_t grid, int maxBits, uint32_t* tot, uint32_t* grp, int64_t stride,
-                            hipStream_t st, bool is_r)
+                            uint32_t* cnt, hipStream_t st, bool is_r)
 {
     if (grid <= 0) return hipSuccess;
     const size_t hl = (size_t)4 << maxBits;
     SideTwo none{};
     none.split = (uint32_t)grid;
     prof::Scope ph(st, is_r ? "hash.hist.R" : "hash.hist.S");
-    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, grp, (uint32_t)stride, none);
+    hist_k<<<(unsigned)grid, kHistBlock, hl, st>>>(items, one, ch, n, tot, grp, (uint32_t)stride, cnt, none);
     return hipGetLastError();
 }
 
 // Both sides of a single join in one launch, R's chunks first.
 static hipError_t hist_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64_t gridR,
-                            uint32_t* totR, uint32_t* grpR, const SideItem& oneS, int64_t chS,
-                            int64_t nS, int64_t gridS, uint32_t* totS, uint32_t* grpS, int bits,
-                            int64_t stride, hipStream_t st)
+                            uint32_t* totR, uint32_t* grpR, uint32_t* cntR, const SideItem& oneS,
+                            int64_t chS, int64_t nS, int64_t gridS, uint32_t* totS, uint32_t* grpS,
+                            uint32_t* cntS, int bits, int64_t stride, hipStream_t st)
 {
     if (gridR + gridS <= 0) return hipSuccess;
     SideTwo two{};
@@ -1604,10 +2037,11 @@ static hipError_t hist_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64
     two.n = nS;
     two.tot = totS;
     two.grp = grpS;
+    two.cnt = cntS;
     two.split = (uint32_t)gridR;
     prof::Scope ph(st, "hash.hist");
     hist_k<<<(unsigned)(gridR + gridS), kHistBlock, (size_t)4 << bits, st>>>(
-        nullptr, oneR, chR, nR, totR, grpR, (uint32_t)stride, two);
+        nullptr, oneR, chR, nR, totR, grpR, (uint32_t)stride, cntR, two);
     return hipGetLastError();
 }
 
@@ -1620,17 +2054,23 @@ static hipError_t cursors_side(uint32_t* grp, const uint32_t* base, int64_t stri
     return hipGetLastError();
 }
 
-// Partition starts and group cursors of both sides (a NULL totR or totS skips that side): one
-// launch up to kFuseParts partitions, else a scan and a cursor kernel per side.
+// Partition starts and group starts of both sides (a NULL totR or totS skips that side), and
+// the run offsets of the sides' tiles given by bR and bS (cnt NULL: none): one launch up to
+// kFuseParts partitions, else a scan and a cursor kernel per side (then no run offsets: batches
+// compute theirs with band_batch_k).
 static hipError_t starts_sides(const uint32_t* totR, uint32_t* baseR, uint32_t* grpR,
                                const uint32_t* totS, uint32_t* baseS, uint32_t* grpS, int64_t n,
-                               uint32_t* temp, hipStream_t st)
+                               uint32_t* temp, hipStream_t st, const BandSide& bR = BandSide{},
+                               const BandSide& bS = BandSide{})
 {
     if (n <= kFuseParts) {
         prof::Scope pc(st, "hash.plan");
-        part_starts_k<<<2, kFuseBlock, 0, st>>>(totR, baseR, grpR, totS, baseS, grpS, (uint32_t)n, (int)n);
+        const int64_t blocks = 2 + band_blocks(bR) + band_blocks(bS);
+        part_starts_k<<<(unsigned)blocks, kFuseBlock, 0, st>>>(totR, baseR, grpR, totS, baseS, grpS,
+                                                               (uint32_t)n, (int)n, bR, bS);
         return hipGetLastError();
     }
+    if (bR.cnt || bS.cnt) return hipErrorInvalidValue;  // band work rides only on the fused launch
     hipError_t e = hipSuccess;
     if (totR) {
         e = exclusive_scan<uint32_t>(totR, baseR, n, nullptr, temp, st);
@@ -1641,6 +2081,21 @@ static hipError_t starts_sides(const uint32_t* totR, uint32_t* baseR, uint32_t* 
         if (e == hipSuccess) e = cursors_side(grpS, baseS, n, st);
     }
     return e;
+}
+
+// The band work of one side of a single join: its chunks start at workgroup `base` of the
+// histogram and scatter launches.
+static BandSide band_of(uint32_t* cnt, int64_t chunk, int64_t n, int64_t nCh, int bits, int64_t base)
+{
+    BandSide b{};
+    if (nCh <= 0 || !cnt) return b;
+    b.cnt = cnt;
+    b.chunk = chunk;
+    b.n = n;
+    b.nCh = nCh;
+    b.bits = bits;
+    b.blockBase = (uint32_t)base;
+    return b;
 }
 
 // Per-partition plans, unit starts (total at *Utotal) and the unit -> partition map.
@@ -1668,27 +2123,33 @@ static hipError_t plan_parts(const PartPlan& q, int64_t nParts, PartInfo* info, 
 }
 
 static hipError_t scatter_side(const SideItem* items, const SideItem& one, int64_t ch, int64_t n,
-                               int64_t grid, int maxBits, uint32_t* cur, int64_t stride, int2* out,
-                               hipStream_t st, bool is_r, const PlanArgs* plan = nullptr)
+                               int64_t grid, int maxBits, uint32_t* cur, int64_t stride,
+                               int2* out, const uint32_t* cnt, hipStream_t st, bool is_r,
+                               const PlanArgs* plan = nullptr)
 {
     const PlanArgs pa = plan ? *plan : PlanArgs{};
     const int64_t all = grid + (plan ? 1 : 0);
     if (all <= 0) return hipSuccess;
-    const size_t sl = scatter_lds(1 << maxBits);
+    const size_t sl = scatter_lds(1 << maxBits, cnt != nullptr);
     SideTwo none{};
     none.split = (uint32_t)grid;
     prof::Scope ps(st, is_r ? "hash.scatter.R" : "hash.scatter.S");
-    if (items != nullptr || one.rid != nullptr)
-        scatter_k<true><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, none, pa);
-    else
-        scatter_k<false><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, none, pa);
+    const bool rids = items != nullptr || one.rid != nullptr;
+    if (cnt) {
+        if (rids) scatter_k<true, true><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, cnt, none, pa);
+        else scatter_k<false, true><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, cnt, none, pa);
+    } else {
+        if (rids) scatter_k<true, false><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, cnt, none, pa);
+        else scatter_k<false, false><<<(unsigned)all, kScatBlock, sl, st>>>(items, one, ch, n, cur, (uint32_t)stride, out, cnt, none, pa);
+    }
     return hipGetLastError();
 }
 
 // Both sides of a single join in one launch, R's chunks first (the plan's workgroup last).
 static hipError_t scatter_pair(const SideItem& oneR, int64_t chR, int64_t nR, int64_t gridR,
-                               uint32_t* curR, int2* outR, const SideItem& oneS, int64_t chS,
-                               int64_t nS, int64_t gridS, uint32_t* curS, int2* outS, int bits,
+                               uint32_t* curR, int2* outR, const uint32_t* cntR,
+                               const SideItem& oneS, int64_t chS, int64_t nS, int64_t gridS,
+                               uint32_t* curS, int2* outS, uint32_t* cntS, int bits,
                                int64_t stride, hipStream_t st, const PlanArgs* plan)
 {
     const PlanArgs pa = plan ? *plan : PlanArgs{};
@@ -1700,13 +2161,19 @@ static hipError_t scatter_pair(const SideItem& oneR, int64_t chR, int64_t nR, in
     two.n = nS;
     two.grp = curS;
     two.out = outS;
+    two.cnt = cntS;
     two.split = (uint32_t)gridR;
-    const size_t sl = scatter_lds(1 << bits);
+    const bool ordered = cntR != nullptr || cntS != nullptr;
+    const size_t sl = scatter_lds(1 << bits, ordered);
     prof::Scope ps(st, "hash.scatter");
-    if (oneR.rid != nullptr || oneS.rid != nullptr)
-        scatter_k<true><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, two, pa);
-    else
-        scatter_k<false><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, two, pa);
+    const bool rids = oneR.rid != nullptr || oneS.rid != nullptr;
+    if (ordered) {
+        if (rids) scatter_k<true, true><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, cntR, two, pa);
+        else scatter_k<false, true><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, cntR, two, pa);
+    } else {
+        if (rids) scatter_k<true, false><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, cntR, two, pa);
+        else scatter_k<false, false><<<(unsigned)all, kScatBlock, sl, st>>>(nullptr, oneR, chR, nR, curR, (uint32_t)stride, outR, cntR, two, pa);
+    }
     return hipGetLastError();
 }
 
@@ -1719,6 +2186,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
     g.Umax = pl.Umax;
     g.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
     g.stamp = pl.stamp;
+    g.dbg = JL_DEBUG ? reinterpret_cast<uint64_t*>(ws + pl.off_dbg) : nullptr;
     if (pl.single) {
         g.single = 1;
         g.rk = R.key;
@@ -1774,14 +2242,20 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         const SideItem oneR = whole_side(R, pl.bits), oneS = whole_side(S, pl.bits);
+        uint32_t* cntR = pl.ordered ? reinterpret_cast<uint32_t*>(ws + pl.off_cntR) : nullptr;
+        uint32_t* cntS = pl.ordered ? reinterpret_cast<uint32_t*>(ws + pl.off_cntS) : nullptr;
         if (pre)
-            e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, st, false);
+            e = hist_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, totS, grpS, pl.P, cntS, st, false);
         else
-            e = hist_pair(oneR, pl.chR, R.n, pl.nChR, totR, grpR, oneS, pl.chS, S.n, pl.nChS, totS,
-                          grpS, pl.bits, pl.P, st);
+            e = hist_pair(oneR, pl.chR, R.n, pl.nChR, totR, grpR, cntR, oneS, pl.chS, S.n, pl.nChS,
+                          totS, grpS, cntS, pl.bits, pl.P, st);
         if (e != hipSuccess) return e;
+        // the scatter launch puts R's chunks first (none for a prebuilt R)
+        const int64_t sBase = pre ? 0 : pl.nChR;
         e = starts_sides(pre ? nullptr : totR, baseR, grpR, totS, baseS, grpS, pl.P,
-                         reinterpret_cast<uint32_t*>(temp), st);
+                         reinterpret_cast<uint32_t*>(temp), st,
+                         pre ? BandSide{} : band_of(cntR, pl.chR, R.n, pl.nChR, pl.bits, 0),
+                         band_of(cntS, pl.chS, S.n, pl.nChS, pl.bits, sBase));
         if (e != hipSuccess) return e;
         const uint32_t* pbaseR = pre ? pre->base : baseR;
         const uint32_t* ptotR = pre ? pre->tot : totR;
@@ -1797,11 +2271,11 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         // up to kFuseParts partitions the plan is one workgroup of the scatter launch
         const PlanArgs* fused = pl.P <= kFuseParts ? &pa : nullptr;
         if (pre)
-            e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, grpS, pl.P, tupS, st, false,
-                             fused);
+            e = scatter_side(nullptr, oneS, pl.chS, S.n, pl.nChS, pl.bits, grpS, pl.P, tupS, cntS, st,
+                             false, fused);
         else
-            e = scatter_pair(oneR, pl.chR, R.n, pl.nChR, grpR, tupR, oneS, pl.chS, S.n, pl.nChS, grpS,
-                             tupS, pl.bits, pl.P, st, fused);
+            e = scatter_pair(oneR, pl.chR, R.n, pl.nChR, grpR, tupR, cntR, oneS, pl.chS, S.n, pl.nChS,
+                             grpS, tupS, cntS, pl.bits, pl.P, st, fused);
         if (e != hipSuccess) return e;
         if (!fused) {
             e = plan_parts(pa.q, pl.P, pa.info, pa.units, pa.Utotal, pl.Umax, pa.umap,
@@ -1867,7 +2341,8 @@ BuildPlan hash_build_plan(int64_t nR, int num_cus)
     if (bits > kMaxBits) bits = kMaxBits;
     b.bits = bits;
     b.P = 1 << bits;
-    int per_cu = (int)((160 * 1024) / scatter_lds(b.P));
+    b.ordered = ordered_knob();
+    int per_cu = (int)((160 * 1024) / scatter_lds(b.P, b.ordered));
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 2) per_cu = 2;
     int64_t c = ceil_div(nR > 0 ? nR : 1, (int64_t)num_cus * per_cu);
@@ -1879,6 +2354,7 @@ BuildPlan hash_build_plan(int64_t nR, int num_cus)
     b.off_base = take(off, (size_t)(b.P + 1) * 4);
     b.off_tup = take(off, (size_t)nR * 8);
     b.off_temp = take(off, scan_temp_elems<uint32_t>(b.P + 1) * 4 + 8);
+    b.off_cnt = take(off, ((b.ordered ? (size_t)b.nChR * (size_t)tiles_of(b.chR) * 4 : 0)) << b.bits);
     b.bytes = off;
     return b;
 }
@@ -1899,12 +2375,14 @@ hipError_t hash_build(const BuildPlan& b, const join_rel_t& R, char* build, hipS
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const SideItem one = whole_side(R, b.bits);
-    e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, grp, b.P, st, true);
+    uint32_t* cnt = b.ordered ? reinterpret_cast<uint32_t*>(build + b.off_cnt) : nullptr;
+    e = hist_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, tot, grp, b.P, cnt, st, true);
     if (e != hipSuccess) return e;
     e = starts_sides(tot, base, grp, nullptr, nullptr, nullptr, b.P,
-                     reinterpret_cast<uint32_t*>(build + b.off_temp), st);
+                     reinterpret_cast<uint32_t*>(build + b.off_temp), st,
+                     band_of(cnt, b.chR, R.n, b.nChR, b.bits, 0));
     if (e != hipSuccess) return e;
-    return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, grp, b.P, tup, st, true);
+    return scatter_side(nullptr, one, b.chR, R.n, b.nChR, b.bits, grp, b.P, tup, cnt, st, true);
 }
 
 RView build_view(const BuildPlan& b, const void* build)
@@ -1924,7 +2402,6 @@ RView build_view(const BuildPlan& b, const void* build)
 // of unit counts and the write pass are one launch each, and join j's pairs land contiguously,
 // in join order, in one output array.
 
-constexpr int64_t kBatchChunk = 65536;  // rows per histogram / scatter item
 
 static int job_bits(const join_job_t& j, int cap)
 {
@@ -1934,6 +2411,14 @@ static int job_bits(const join_job_t& j, int cap)
 
 static int64_t side_items(int64_t n) { return n > 0 ? ceil_div(n, kBatchChunk) : 0; }
 
+// Tiles of all items of a side of n rows (every item but the last is kBatchChunk rows).
+static int64_t side_tiles(int64_t n)
+{
+    if (n <= 0) return 0;
+    const int64_t full = n / kBatchChunk, rest = n - full * kBatchChunk;
+    return full * tiles_of(kBatchChunk) + tiles_of(rest);
+}
+
 int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* out)
 {
     BatchPlan bp{};
@@ -1941,7 +2426,9 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.cap = env_cap();
     bp.slice = (int)tune_get(TUNE_HASH_SLICE, 32768);
     if (bp.slice < 1024) bp.slice = 1024;
+    bp.ordered = ordered_knob();
     int64_t umax = 0;
+    uint64_t cntR = 0, cntS = 0;  // per-tile count entries of each side
     for (int j = 0; j < njobs; ++j) {
         const int b = job_bits(jobs[j], bp.cap);
         if (b > bp.maxBits) bp.maxBits = b;
@@ -1949,6 +2436,8 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
         bp.nParts += P;
         bp.nItemsR += side_items(jobs[j].R.n);
         bp.nItemsS += side_items(jobs[j].S.n);
+        cntR += (uint64_t)side_tiles(jobs[j].R.n) << b;
+        cntS += (uint64_t)side_tiles(jobs[j].S.n) << b;
         bp.sumR += jobs[j].R.n;
         bp.sumS += jobs[j].S.n;
         umax += P + ceil_div(jobs[j].R.n, bp.cap) + ceil_div(jobs[j].S.n, bp.slice) + 1;
@@ -1974,6 +2463,10 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.off_umap = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 4);
     bp.off_counts = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 8);
     bp.off_wave = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * kJoinWaves * 8);
+    bp.off_item0R = take(off, (size_t)(njobs + 1) * 4);
+    bp.off_item0S = take(off, (size_t)(njobs + 1) * 4);
+    bp.off_cntR = take(off, bp.ordered ? (size_t)cntR * 4 : 0);
+    bp.off_cntS = take(off, bp.ordered ? (size_t)cntS * 4 : 0);
     size_t temp = scan_temp_elems<uint64_t>(bp.Umax) * 8;
     const size_t t1 = scan_temp_elems<uint32_t>(bp.nParts + 1) * 4;
     temp = temp > t1 ? temp : t1;
@@ -1993,16 +2486,19 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
 
 hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* ws, hipStream_t st)
 {
-    std::vector<uint32_t> jpart0((size_t)bp.njobs + 1);
+    std::vector<uint32_t> jpart0((size_t)bp.njobs + 1), item0R((size_t)bp.njobs + 1), item0S((size_t)bp.njobs + 1);
     std::vector<int32_t> jbits((size_t)bp.njobs);
     std::vector<SideItem> itemsR((size_t)bp.nItemsR), itemsS((size_t)bp.nItemsS);
     uint32_t part0 = 0;
     size_t iR = 0, iS = 0;
+    uint64_t cR = 0, cS = 0;
     for (int j = 0; j < bp.njobs; ++j) {
         const int b = job_bits(jobs[j], bp.cap);
         jpart0[j] = part0;
         jbits[j] = b;
-        auto add = [&](const join_rel_t& X, std::vector<SideItem>& items, size_t& i) {
+        item0R[j] = (uint32_t)iR;
+        item0S[j] = (uint32_t)iS;
+        auto add = [&](const join_rel_t& X, std::vector<SideItem>& items, size_t& i, uint64_t& c) {
             for (int64_t beg = 0; beg < X.n; beg += kBatchChunk) {
                 SideItem it{};
                 it.key = X.key;
@@ -2011,18 +2507,26 @@ hipError_t hash_batch_upload(const BatchPlan& bp, const join_job_t* jobs, char* 
                 it.len = (uint32_t)(X.n - beg < kBatchChunk ? X.n - beg : kBatchChunk);
                 it.bits = b;
                 it.part0 = part0;
+                it.cnt0 = c;
+                c += (uint64_t)tiles_of(it.len) << b;
                 items[i++] = it;
             }
         };
-        add(jobs[j].R, itemsR, iR);
-        add(jobs[j].S, itemsS, iS);
+        add(jobs[j].R, itemsR, iR, cR);
+        add(jobs[j].S, itemsS, iS, cS);
         part0 += 1u << b;
     }
     jpart0[bp.njobs] = part0;
+    item0R[bp.njobs] = (uint32_t)iR;
+    item0S[bp.njobs] = (uint32_t)iS;
     hipError_t e;
     e = hipMemcpyAsync(ws + bp.off_jpart0, jpart0.data(), jpart0.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && bp.njobs > 0)
         e = hipMemcpyAsync(ws + bp.off_jbits, jbits.data(), jbits.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + bp.off_item0R, item0R.data(), item0R.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + bp.off_item0S, item0S.data(), item0S.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !itemsR.empty())
         e = hipMemcpyAsync(ws + bp.off_itemsR, itemsR.data(), itemsR.size() * sizeof(SideItem), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !itemsS.empty())
@@ -2093,15 +2597,27 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hist_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, totR, grpR, bp.nParts, st, true);
+    uint32_t* cntR = bp.ordered ? reinterpret_cast<uint32_t*>(ws + bp.off_cntR) : nullptr;
+    uint32_t* cntS = bp.ordered ? reinterpret_cast<uint32_t*>(ws + bp.off_cntS) : nullptr;
+    e = hist_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, totR, grpR, bp.nParts, cntR, st, true);
     if (e != hipSuccess) return e;
-    e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, grpS, bp.nParts, st, false);
+    e = hist_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, totS, grpS, bp.nParts, cntS, st, false);
     if (e != hipSuccess) return e;
     e = starts_sides(totR, baseR, grpR, totS, baseS, grpS, bp.nParts, reinterpret_cast<uint32_t*>(temp), st);
     if (e != hipSuccess) return e;
-    e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, grpR, bp.nParts, tupR, st, true);
+    if (bp.ordered && bp.nParts > 0) {
+        prof::Scope pb(st, "hash.plan");
+        const unsigned grid = (unsigned)ceil_div(bp.nParts * kGroups, 256);
+        band_batch_k<<<grid, 256, 0, st>>>(itemsR, reinterpret_cast<const uint32_t*>(ws + bp.off_item0R),
+                                           jpart0, bp.njobs, (uint32_t)bp.nParts, cntR);
+        band_batch_k<<<grid, 256, 0, st>>>(itemsS, reinterpret_cast<const uint32_t*>(ws + bp.off_item0S),
+                                           jpart0, bp.njobs, (uint32_t)bp.nParts, cntS);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    e = scatter_side(itemsR, none, 0, 0, bp.nItemsR, bp.maxBits, grpR, bp.nParts, tupR, cntR, st, true);
     if (e != hipSuccess) return e;
-    e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, grpS, bp.nParts, tupS, st, false);
+    e = scatter_side(itemsS, none, 0, 0, bp.nItemsS, bp.maxBits, grpS, bp.nParts, tupS, cntS, st, false);
     if (e != hipSuccess) return e;
     PartPlan q{baseR, totR, baseS, totS, jpart0, jbits, bp.njobs, 0, (uint32_t)bp.cap, (uint32_t)bp.slice};
     e = plan_parts(q, bp.nParts, reinterpret_cast<PartInfo*>(ws + bp.off_info), units,

@@ -18,6 +18,8 @@ struct SideItem {
     uint32_t len;        // rows in the chunk
     int32_t bits;        // the join's fan-out
     uint32_t part0;      // the join's first partition in the partition arrays
+    uint64_t cnt0;       // first per-tile count row of the chunk: tile t's row of 2^bits
+                         // counts starts at element cnt0 + t * 2^bits of the side's count array
 };
 
 // Everything the count and write kernels need to walk the work units.
@@ -42,12 +44,14 @@ struct JoinGeom {
     int contig;  // write pass: contiguous runs of units per workgroup (else round robin)
     uint64_t* stamp_at;  // plan stamp in the workspace header (NULL for batches: no re-planning)
     uint64_t stamp;      // this plan's stamp: the count pass records it, the write pass checks it
+    uint64_t* dbg;       // checking build: pairs written per unit (NULL: not counted)
 };
 
 struct HashPlan {
     int64_t nR, nS;
     int single;    // 1: no partitioning, units = R chunks x S slices of the inputs themselves
     int prebuilt;  // 1: R comes partitioned from a resident build (RView)
+    int ordered;   // 1: the ordered scatter (output order fixed by the input), else arrival order
     int bits, P;
     int cap, slice;
     int64_t nSs;  // S slices (single)
@@ -55,8 +59,8 @@ struct HashPlan {
     int64_t Umax;
     int gridCount, gridWrite;  // persistent grids of the count and write kernels
     size_t off_tot, off_grpR, off_grpS, off_done, off_baseR, off_baseS, off_tupR, off_tupS;
-    size_t off_info, off_units, off_umap;
-    size_t off_counts, off_wave, off_temp, bytes;
+    size_t off_info, off_units, off_umap, off_cntR, off_cntS;
+    size_t off_counts, off_wave, off_temp, off_dbg, bytes;
     uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
@@ -75,8 +79,9 @@ struct RView {
 struct BuildPlan {
     int64_t nR;
     int32_t bits, P;
+    int32_t ordered, pad;
     int64_t chR, nChR;
-    uint64_t off_tot, off_base, off_tup, off_temp, bytes;
+    uint64_t off_tot, off_base, off_tup, off_temp, off_cnt, bytes;
 };
 
 BuildPlan hash_build_plan(int64_t nR, int num_cus);
@@ -97,9 +102,11 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
 // by the caller as an opaque join_batch_plan_t between the prepare, count and write calls.
 struct BatchPlan {
     int32_t njobs, maxBits, cap, slice;
+    int32_t ordered, pad;
     int64_t nParts, nItemsR, nItemsS, sumR, sumS, Umax;
     uint64_t off_jpart0, off_jbits, off_itemsR, off_itemsS, off_tot, off_baseR, off_baseS;
     uint64_t off_tupR, off_tupS, off_info, off_units, off_umap;
+    uint64_t off_item0R, off_item0S, off_cntR, off_cntS;  // per-join first items, per-tile counts
     uint64_t off_counts, off_wave, off_temp, bytes;
     int32_t gridCount, gridWrite;
 };

@@ -145,9 +145,10 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
     pl.off_kS = take(pl.logR ? (size_t)nS * 4 : 0);
     pl.off_rS = take(pl.logR ? (size_t)nS * 4 : 0);
     // The inner join sees at most nR x nS rows.  Its layout grows with the sizes except the
-    // chunk offset arrays, which a smaller fan-out may lay out for twice the chunks: bounded by
-    // 2^11 partitions x 2 chunks per CU x 2 sides.
-    pl.inner_bytes = hash_plan(nR, nS, num_cus).bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 + 4096;
+    // chunk arrays (group shares, and the per-tile counts' last partial tile of every chunk),
+    // which a smaller fan-out may lay out for twice the chunks: bounded by 2^11 partitions x 2
+    // chunks per CU x 2 sides, twice.
+    pl.inner_bytes = hash_plan(nR, nS, num_cus).bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 * 2 + 4096;
     pl.off_inner = take(pl.inner_bytes);
     pl.bytes = off;
     pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.logR, pl.logS, (int64_t)pl.inner_bytes,

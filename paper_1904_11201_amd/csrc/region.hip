@@ -19,6 +19,7 @@
 // The result is exactly the nested-loop result: every pair is either in a red unit (evaluated),
 // in a green span (holds by the range argument) or in a white span (cannot hold).
 #include "region.hpp"
+#include "debug.hpp"
 
 #include "prof.hpp"
 #include "scan.hpp"
@@ -640,6 +641,7 @@ RegionPlan region_plan(int64_t nR, int64_t nS, int op_a, int64_t stash_k)
     temp = temp > t2 ? temp : t2;
     temp = temp > t3 ? temp : t3;
     pl.off_temp = take(temp + 8);
+    pl.off_dbg = take(JL_DEBUG ? (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8 : 0);  // last (checking build)
     pl.bytes = off;
     pl.stamp = plan_stamp({JOIN_KIND_THETA_REGION, nR, nS, op_a, pl.bits, pl.B, pl.chR, pl.chS, pl.Umax,
                            pl.K, pl.nOff, (int64_t)pl.bytes});
@@ -682,6 +684,7 @@ static ThetaUnitArgs unit_args(const RegionPlan& pl, char* ws)
     a.nOff = pl.nOff;
     a.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
     a.stamp = pl.stamp;
+    a.dbg = JL_DEBUG ? reinterpret_cast<uint64_t*>(ws + pl.off_dbg) : nullptr;
     return a;
 }
 

@@ -12,7 +12,7 @@ struct RegionPlan {
     int64_t nOff;                // Umax red counts + 2 green counts per bucket
     size_t off_hist2, off_lut, off_vlo, off_vhi, off_hR, off_hS;
     size_t off_Ra, off_Rc, off_Rr, off_Sa, off_Sc, off_Sr;
-    size_t off_info, off_split, off_units, off_table, off_counts, off_stash, off_temp, bytes;
+    size_t off_info, off_split, off_units, off_table, off_counts, off_stash, off_temp, off_dbg, bytes;
     uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 

@@ -15,6 +15,7 @@
 // [offset[u], offset[u] + count[u]) for each unit: the exact result size of Section 3.3.3
 // with no over-allocation.
 #include "theta.hpp"
+#include "debug.hpp"
 
 #include "prof.hpp"
 #include "scan.hpp"
@@ -51,6 +52,7 @@ struct ThetaGeom {
     int64_t nOff;          // entries of the offsets array the write pass reads
     uint64_t* stamp_at;    // plan stamp in the workspace header: recorded by the count pass,
     uint64_t stamp;        // checked by the write pass
+    uint64_t* dbg;         // checking build: pairs written per unit (NULL: not counted)
 };
 
 // Per-R-row constants of op_a.  BAND keeps [lo, lo + wid] with lo = max(a - w, INT32_MIN),
@@ -227,8 +229,8 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
     // A pair can hold only if s - x0 <= x1 for its R row (equality: s - x0 == 0), and x1 <= wmax
     // for every row (rows clamped at the ends of the int32 range have narrower bands), so a
     // group with min(s - x0) over its 64 pairs above wmax holds no pair.  The running minimum
-    // costs one subtract per pair and one three-input min per two pairs, with one compare per
-    // group; two minima alternate so consecutive mins do not wait on each other.
+    // costs one subtract per pair, one three-input min per two pairs and one move per S row, with
+    // one compare per group; two minima alternate so consecutive mins do not wait on each other.
     const uint32_t wmax = OPA == JOIN_OP_BAND ? (uint32_t)(2 * (int64_t)g.w) : 0u;
     int64_t j = s0;
     for (; j + kSGroup <= s1; j += kSGroup) {
@@ -237,14 +239,19 @@ __device__ __forceinline__ void sweep_selective(const ThetaGeom& g, const RRows&
         for (int k = 0; k < kSGroup; ++k) sa[k] = Sa[j + k];
         uint32_t m0 = ~0u, m1 = ~0u;
 #pragma unroll
-        for (int k = 0; k < kSGroup; ++k)
+        for (int k = 0; k < kSGroup; ++k) {
+            // the S value is moved into a vector register once for its 8 subtracts: a subtract
+            // of two vector registers issues faster than one that reads a scalar register
+            int32_t sv;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(sv) : "s"(sa[k]));
 #pragma unroll
             for (int r = 0; r < kRB; r += 2) {
-                const uint32_t d0 = (uint32_t)(sa[k] - rr.x0[r]);
-                const uint32_t d1 = (uint32_t)(sa[k] - rr.x0[r + 1]);
+                const uint32_t d0 = (uint32_t)(sv - rr.x0[r]);
+                const uint32_t d1 = (uint32_t)(sv - rr.x0[r + 1]);
                 if (k & 1) m1 = min(min(m1, d0), d1);
                 else m0 = min(min(m0, d0), d1);
             }
+        }
         if (ballot(min(m0, m1) <= wmax)) exact(j, j + kSGroup);
     }
     if (j < s1) exact(j, s1);
@@ -380,6 +387,9 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
             const int2* st = g.stash + u * g.K;
             for (uint64_t i = lane; i < cnt; i += kWave)
                 if (off + i < cap) out[off + i] = st[i];
+#if JL_DEBUG
+            if (g.dbg && lane == 0) g.dbg[u] = cnt;
+#endif
             return;
         }
         int64_t r0, rEnd, s0, s1;
@@ -404,6 +414,9 @@ __global__ __launch_bounds__(kThetaBlock) void theta_write_k(ThetaGeom g,
                 emit_row<OPA, OPC>(rr, rid, vm, Sa[j], sc, srid, base, out, cap, lane);
             }
         }
+#if JL_DEBUG
+        if (g.dbg && lane == 0) g.dbg[u] = base - off;
+#endif
     }
 }
 
@@ -493,6 +506,7 @@ ThetaGeom geom(const ThetaPlan& pl, const join_rel_t& R, const join_rel_t& S, co
     g.nOff = pl.U;
     g.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
     g.stamp = pl.stamp;
+    g.dbg = JL_DEBUG ? reinterpret_cast<uint64_t*>(ws + pl.off_dbg) : nullptr;
     return g;
 }
 
@@ -516,6 +530,7 @@ ThetaGeom unit_geom(const ThetaUnitArgs& a, const join_pred_t& p)
     g.nOff = a.nOff;
     g.stamp_at = a.stamp_at;
     g.stamp = a.stamp;
+    g.dbg = a.dbg;
     return g;
 }
 
@@ -578,6 +593,8 @@ ThetaPlan theta_plan(int64_t nR, int64_t nS, int op_a, int64_t target_waves, int
     pl.K = sel && stash_k > 0 ? stash_k : 0;
     pl.off_stash = off;
     off = align_up(off + (size_t)pl.U * (size_t)pl.K * sizeof(int2));
+    pl.off_dbg = off;  // last: the checking build's per-unit written counts
+    off = align_up(off + (JL_DEBUG ? (size_t)(pl.U > 0 ? pl.U : 1) * 8 : 0));
     pl.bytes = off;
     pl.stamp = plan_stamp({JOIN_KIND_THETA, nR, nS, op_a, pl.TS, pl.nSt, pl.U, pl.K, (int64_t)pl.bytes});
     return pl;

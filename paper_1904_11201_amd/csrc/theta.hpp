@@ -9,7 +9,7 @@ struct ThetaPlan {
     int64_t nSt;  // S tiles
     int64_t U;    // work units (one wave each)
     int64_t K;    // per-unit match stash of the count pass (0: none)
-    size_t off_counts, off_temp, off_stash, bytes;
+    size_t off_counts, off_temp, off_stash, off_dbg, bytes;
     uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
@@ -35,6 +35,7 @@ struct ThetaUnitArgs {
     int64_t nOff;                   // entries of the offsets array
     uint64_t* stamp_at;             // plan stamp in the workspace header (see ThetaPlan)
     uint64_t stamp;
+    uint64_t* dbg;                  // checking build: pairs written per unit, or NULL
 };
 
 hipError_t theta_count_units(const ThetaUnitArgs& a, const join_pred_t& p, uint64_t* counts,

@@ -24,6 +24,7 @@ const KnobDesc kKnobs[TUNE_COUNT] = {
     {"theta.ts", "JOIN_THETA_TS"},
     {"theta.waves", "JOIN_THETA_WAVES"},
     {"theta.stash", "JOIN_THETA_STASH"},
+    {"hash.deterministic", "JOIN_HASH_DETERMINISTIC"},
 };
 
 constexpr int64_t kUnset = INT64_MIN;

@@ -13,6 +13,7 @@ enum TuneKnob {
     TUNE_THETA_TS,         // S rows per theta tile, 0 = automatic ("theta.ts", JOIN_THETA_TS)
     TUNE_THETA_WAVES,      // waves the theta grid aims for, 0 = automatic ("theta.waves")
     TUNE_THETA_STASH,      // matches stashed per theta unit ("theta.stash", JOIN_THETA_STASH)
+    TUNE_HASH_DETERMINISTIC,  // 1: ordered scatter, output order fixed ("hash.deterministic")
     TUNE_COUNT
 };
 

@@ -1,8 +1,13 @@
 """Output order is unspecified but fixed for a given input and plan: the same join run twice
 gives the same pairs in the same positions, byte for byte (the unsorted output is compared).
 
-In the write pass each wave writes from a start recorded by the count pass (no shared cursor),
-and the matches of one probe leave in ascending rid order: sorted in registers when there are at
+Joins on the unpartitioned path are deterministic in every plan.  Partitioned joins (single and
+batched) are deterministic in plans with the option hash.deterministic (JOIN_HASH_DETERMINISTIC
+= 1): partitioned tuples then land at positions computed from per-tile counts (runs ordered by
+tile, then chunk, inside each chunk group's range of a partition; inside a tile each wave places
+its tuples from its own counters); by default they land in arrival order, which is faster.  In
+the write pass each wave writes from a start recorded by the count pass (no shared cursor), and
+the matches of one probe leave in ascending rid order: sorted in registers when there are at
 most 8, else met in that order in a table whose duplicated keys were put in canonical order."""
 import numpy as np
 import pytest
@@ -57,8 +62,8 @@ def _probe_runs_ascending(pairs: np.ndarray) -> bool:
 
 
 @gpu
-@pytest.mark.parametrize("bits", ["-1", "0", "3", "9"])
-def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits):
+@pytest.mark.parametrize("bits,det", [("-1", "0"), ("0", "0"), ("3", "0"), ("3", "1"), ("9", "1")])
+def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits, det):
     """Build keys with 1 to 12 entries each (random rids, some repeated), through the single
     path (bits -1) and partitioned plans: probes with up to 8 matches order them as they are
     written, probes with more meet them in a table put in canonical order.  Either way the
@@ -78,11 +83,50 @@ def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits):
     S = datagen.Rel(key=keys[g.integers(0, nkeys, 50_000)], rid=np.arange(50_000, dtype=np.int32))
     n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
     monkeypatch.setenv("JOIN_HASH_BITS", bits)
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", det)
     dR, dS = dev_rel(R), dev_rel(S)
-    log(f"probe match order, bits={bits}")
-    a = hash_join(dR, dS)
-    torch.cuda.synchronize()
+    log(f"probe match order, bits={bits} deterministic={det}")
+    a, b = _twice(lambda: hash_join(dR, dS))
+    if det == "1" or bits in ("-1", "0"):  # the unpartitioned path is deterministic in any plan
+        assert torch.equal(a, b)
     host = a.cpu().numpy()
     assert _probe_runs_ascending(host)
     got = canon_gpu(a)
     assert len(got) == n and np.array_equal(got, ref)
+
+
+@gpu
+@pytest.mark.parametrize("zipf", [False, True])
+def test_large_partitioned_join_is_deterministic(monkeypatch, zipf):
+    """The 16M x 64M join (2048 partitions), uniform and Zipf probe keys, run twice in a
+    deterministic plan."""
+    need_gpu()
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
+    from paper_1904_11201_amd.join import JOIN_KIND_HASH, hash_join, workspace
+    R, S, _ = datagen.large_equi(seed=3 if zipf else 2, zipf=zipf)
+    dR, dS = dev_rel(R), dev_rel(S)
+    ws = workspace(JOIN_KIND_HASH, R.n, S.n)
+    log(f"determinism hash 16M x 64M zipf={zipf}")
+    a, b = _twice(lambda: hash_join(dR, dS, ws=ws))
+    assert a.shape[0] == S.n and torch.equal(a, b)
+
+
+@gpu
+def test_batch_is_deterministic(monkeypatch):
+    """A batch of uneven joins (fan-outs 0 to 11), run twice in a deterministic plan: the same
+    output array."""
+    need_gpu()
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
+    from paper_1904_11201_amd.join import Job, hash_join_batch
+    g = datagen.rng_for(49)
+    jobs = []
+    for j in range(24):
+        nr, ns = (int(x) for x in datagen.log_uniform_sizes(g, 2, 1, 400_000))
+        rk = datagen.uniform_keys(g, nr, 0, max(nr, 1))
+        sk = datagen.uniform_keys(g, ns, 0, max(nr, 1))
+        jobs.append(Job(dev_rel(datagen.Rel(key=rk, rid=np.arange(nr, dtype=np.int32))),
+                        dev_rel(datagen.Rel(key=sk, rid=np.arange(ns, dtype=np.int32))),
+                        -1 if j % 3 else j % 12))
+    log("determinism batch of 24 joins")
+    (a, oa), (b, ob) = _twice(lambda: hash_join_batch(jobs))
+    assert oa == ob and torch.equal(a, b)
