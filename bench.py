@@ -235,8 +235,8 @@ def bench_serve(args, J):
     eng = serve.Engine(builds, slots=4, budget_bytes=64 << 30)
     plain = serve.Engine(builds, slots=1, budget_bytes=64 << 30, resident=False)
     eng.serve(reqs[:16], open_loop=False, keep_pairs=False)  # warm-up
-    res, wall = eng.serve(reqs, open_loop=False, keep_pairs=False)
-    closed = serve.summary(res, wall)
+    res_c, wall = eng.serve(reqs, open_loop=False, keep_pairs=False)
+    closed = serve.summary(res_c, wall)
     mu = closed["requests_per_s"]
     res, wall = plain.serve(reqs, open_loop=False, keep_pairs=False)
     plain_closed = serve.summary(res, wall)
@@ -245,12 +245,17 @@ def bench_serve(args, J):
         res, wall = eng.serve(serve.at_rate(reqs, f * mu), open_loop=True, keep_pairs=False)
         opened[f"{f}x"] = dict(serve.summary(res, wall), qps=round(f * mu, 2))
         print(f"# serve open loop {f}x: {opened[f'{f}x']}", file=sys.stderr, flush=True)
-    # the same stream under a budget that binds: 1 GiB for workspaces and outputs in flight
-    tight = serve.Engine(builds, slots=4, budget_bytes=1 << 30)
-    res, wall = tight.serve(reqs, open_loop=False, keep_pairs=False)
-    bound = dict(serve.summary(res, wall), budget_bytes=tight.budget,
+    # the same stream under a budget that binds: 5% above the largest single request's
+    # workspace + output, so that a large request in flight holds the others back
+    budget = int(1.05 * eng.max_request)
+    tight = serve.Engine(builds, slots=4, budget_bytes=budget)
+    res_t, wall = tight.serve(reqs, open_loop=False, keep_pairs=False)
+    same = all(a.count == b.count for a, b in zip(res_c, res_t))
+    bound = dict(serve.summary(res_t, wall), budget_bytes=tight.budget,
+                 largest_request_bytes=eng.max_request,
                  peak_reserved_bytes=tight.peak, admission_waits=tight.waits,
-                 restarts=tight.retries)
+                 restarts=tight.retries, counts_equal_unbounded=same)
+    assert same, "a request's count differs under the binding budget"
     del tight
     n_theta = sum(r.kind == "theta" for r in reqs)
     n_res = sum(r.R is None for r in reqs)
@@ -262,7 +267,7 @@ def bench_serve(args, J):
         "closed_loop": closed, "plain_closed_loop": plain_closed,
         "throughput_vs_plain": round(closed["pairs_per_s"] / plain_closed["pairs_per_s"], 3),
         "open_loop": opened,
-        "closed_loop_1GiB_budget": bound,
+        "closed_loop_binding_budget": bound,
         "latency": "arrival to completion on the host clock, count + admission + write",
     }
     del eng, plain, builds, reqs

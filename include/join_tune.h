@@ -16,7 +16,7 @@
  * see either value, so a caller that tunes one call should use the thread's own setting.
  *
  * Knobs (name, environment variable, meaning):
- *   "hash.cap"               JOIN_HASH_CAP                R entries per LDS table, 64..10240
+ *   "hash.cap"               JOIN_HASH_CAP                R entries per LDS table, 64..9728
  *   "hash.slice"             JOIN_HASH_SLICE              S rows per work unit, >= 1024
  *   "hash.bits"              JOIN_HASH_BITS               single-join fan-out log2, -1 automatic
  *   "hash.single_max_chunks" JOIN_HASH_SINGLE_MAX_CHUNKS  R up to this many tables: no partitioning

@@ -46,7 +46,7 @@ constexpr int64_t kBatchChunk = 65536;           // rows per histogram / scatter
 constexpr int kJoinBlock = 1024;
 constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
 constexpr int kMaxBits = 11;     // scatter: two partitions per thread; 2^11 x 8 B of LDS state
-constexpr int kMaxCap = 10240;   // R chunk entries: 15 B of LDS table per entry fits 160 KB
+constexpr int kMaxCap = 9728;    // R chunk entries: the write pass's table (15 B an entry) and queue fit 160 KB
 
 // Stores of the join's output pairs, which nothing here reads again: optionally non-temporal.
 #ifndef JL_NT_PAIRS
@@ -726,6 +726,20 @@ __device__ __forceinline__ uint32_t plan_part(const PartPlan& q, int p, PartInfo
     return nrc * nss;
 }
 
+// Work unit `local` of a partition (R chunk local / nSs, S slice local % nSs) as one record:
+// {first R tuple, R tuples | fan-out << 24, first S tuple, S tuples}.  The planning kernels
+// write every unit's record, so the join kernels read a unit with one 16-byte load.
+constexpr int kRecBitsShift = 24;
+__host__ __device__ __forceinline__ uint4 unit_rec(const PartInfo& pi, uint32_t local, uint32_t cap)
+{
+    const uint32_t rc = local / pi.nSs;
+    const uint32_t sc = local - rc * pi.nSs;
+    const uint32_t slen = (pi.nS + pi.nSs - 1) / pi.nSs;
+    const uint32_t rN = min(cap, pi.nR - rc * cap);
+    const uint32_t sN = sc * slen < pi.nS ? min(slen, pi.nS - sc * slen) : 0u;
+    return make_uint4(pi.rStart + rc * cap, rN | (pi.bits << kRecBitsShift), pi.sStart + sc * slen, sN);
+}
+
 __global__ void plan_units_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
                              uint32_t* __restrict__ units)
 {
@@ -741,13 +755,14 @@ __global__ void plan_units_k(PartPlan q, int nParts, PartInfo* __restrict__ info
 }
 
 // Unit -> partition map: partition p owns units [unitStart[p], unitStart[p + 1]).
-__global__ void expand_units_k(const uint32_t* __restrict__ unitStart, int P, int64_t Umax,
-                               uint32_t* __restrict__ umap)
+__global__ void expand_units_k(const uint32_t* __restrict__ unitStart, const PartInfo* __restrict__ info,
+                               int P, uint32_t cap, int64_t Umax, uint4* __restrict__ urec)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    const PartInfo pi = info[p];
     for (uint32_t u = unitStart[p]; u < unitStart[p + 1] && (int64_t)u < Umax; ++u)
-        umap[u] = (uint32_t)p;
+        urec[u] = unit_rec(pi, u - unitStart[p], cap);
 }
 
 // One workgroup for up to kFuseParts partitions, in place of several launches of a few
@@ -827,7 +842,7 @@ __global__ __launch_bounds__(kFuseBlock) void part_starts_k(const uint32_t* __re
 template <int BLOCK>
 __device__ void plan_block(const PartPlan& q, int nParts, PartInfo* __restrict__ info,
                            uint32_t* __restrict__ unitStart, uint32_t* __restrict__ Utotal,
-                           int64_t Umax, uint32_t* __restrict__ umap, uint32_t* tmp)
+                           int64_t Umax, uint4* __restrict__ urec, uint32_t* tmp)
 {
     uint32_t carry = 0;
     for (int b0 = 0; b0 < nParts; b0 += 2 * BLOCK) {
@@ -840,12 +855,13 @@ __device__ void plan_block(const PartPlan& q, int nParts, PartInfo* __restrict__
         if (pa < nParts) {
             info[pa] = ia;
             unitStart[pa] = sa;
-            for (uint32_t u = sa; u < sa + ua && (int64_t)u < Umax; ++u) umap[u] = (uint32_t)pa;
+            for (uint32_t u = sa; u < sa + ua && (int64_t)u < Umax; ++u) urec[u] = unit_rec(ia, u - sa, q.cap);
         }
         if (pb < nParts) {
             info[pb] = ib;
             unitStart[pb] = sa + ua;
-            for (uint32_t u = sa + ua; u < sa + ua + ub && (int64_t)u < Umax; ++u) umap[u] = (uint32_t)pb;
+            for (uint32_t u = sa + ua; u < sa + ua + ub && (int64_t)u < Umax; ++u)
+                urec[u] = unit_rec(ib, u - sa - ua, q.cap);
         }
         carry += t;
     }
@@ -858,10 +874,10 @@ __device__ void plan_block(const PartPlan& q, int nParts, PartInfo* __restrict__
 __global__ __launch_bounds__(kFuseBlock) void plan_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
                                                      uint32_t* __restrict__ unitStart,
                                                      uint32_t* __restrict__ Utotal, int64_t Umax,
-                                                     uint32_t* __restrict__ umap)
+                                                     uint4* __restrict__ urec)
 {
     __shared__ uint32_t tmp[kFuseBlock / kWave + 1];
-    plan_block<kFuseBlock>(q, nParts, info, unitStart, Utotal, Umax, umap, tmp);
+    plan_block<kFuseBlock>(q, nParts, info, unitStart, Utotal, Umax, urec, tmp);
 }
 
 // The per-partition plan can ride along with the scatter of a single join: with pa.info set, the
@@ -873,7 +889,7 @@ struct PlanArgs {
     uint32_t* units;
     uint32_t* Utotal;
     int64_t Umax;
-    uint32_t* umap;
+    uint4* urec;
 };
 
 // RIDS: the side has a rid column (a batch passes RIDS and may still leave it NULL per item;
@@ -892,7 +908,7 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
     // were counted under the same group, so the plan's workgroup comes after every chunk.
     const uint32_t blk = blockIdx.x;
     if (pa.info && blk == gridDim.x - 1) {
-        plan_block<kScatBlock>(pa.q, pa.nParts, pa.info, pa.units, pa.Utotal, pa.Umax, pa.umap, lds);
+        plan_block<kScatBlock>(pa.q, pa.nParts, pa.info, pa.units, pa.Utotal, pa.Umax, pa.urec, lds);
         return;
     }
     const bool second = blk >= two.split;
@@ -954,28 +970,30 @@ struct Unit {
     int bits;  // fan-out of the unit's join: the table position uses the hash bits below it
 };
 
+__device__ __forceinline__ Unit unit_of(uint4 r)
+{
+    Unit o;
+    o.rBeg = r.x;
+    o.rN = r.y & ((1u << kRecBitsShift) - 1);
+    o.sBeg = r.z;
+    o.sN = r.w;
+    o.bits = (int)(r.y >> kRecBitsShift);
+    return o;
+}
+
+// Unit u.  PART: a partitioned join (the kernels' AOS instances), whose plan wrote every unit's
+// record; otherwise the single partition's units are computed.
+template <bool PART>
 __device__ __forceinline__ Unit decode_unit(const JoinGeom& g, uint32_t u)
 {
-    PartInfo pi;
-    uint32_t local;
-    if (g.single) {
-        pi = g.one;
-        local = u;
-    } else {
-        const uint32_t p = g.umap[u];
-        pi = g.part[p];
-        local = u - g.unitStart[p];
-    }
-    const uint32_t rc = local / pi.nSs;
-    const uint32_t sc = local - rc * pi.nSs;
-    const uint32_t slen = (pi.nS + pi.nSs - 1) / pi.nSs;
-    Unit o;
-    o.rBeg = pi.rStart + rc * g.cap;
-    o.rN = min(g.cap, pi.nR - rc * g.cap);
-    o.sBeg = pi.sStart + sc * slen;
-    o.sN = sc * slen < pi.nS ? min(slen, pi.nS - sc * slen) : 0u;
-    o.bits = (int)pi.bits;
-    return o;
+    if constexpr (PART) return unit_of(g.urec[u]);
+    else return unit_of(unit_rec(g.one, u, g.cap));
+}
+
+// Whether two units hash the same chunk (the write pass keeps a table across such units).
+__device__ __forceinline__ bool same_chunk(const Unit& a, const Unit& b)
+{
+    return a.rBeg == b.rBeg && a.rN == b.rN;
 }
 
 // ------------------------------------------------------------------------ the LDS table --
@@ -996,7 +1014,7 @@ constexpr int kSlots = 4;
 constexpr int kProbe = JL_HASH_PROBE;  // keys probed together per thread
 constexpr int kEmitSort = 8;  // a probe with at most this many matches orders them in registers
 
-__host__ __device__ __forceinline__ uint32_t table_buckets(uint32_t rN)
+__host__ __device__ constexpr uint32_t table_buckets(uint32_t rN)
 {
     const uint32_t nb = (rN * 5 + 11) / 12;  // 4 * nb * 0.6 >= rN
     return nb < 2 ? 2u : nb;                 // two distinct candidates need two buckets
@@ -1031,7 +1049,7 @@ struct Table {
 
 // LDS bytes of a table for chunks of up to `cap` entries: 16 bytes of keys per bucket, 16 of
 // rids when the table keeps them (the count pass does not), and a 4-byte claim counter.
-__host__ __device__ __forceinline__ size_t table_lds(uint32_t cap, bool rids)
+__host__ __device__ constexpr size_t table_lds(uint32_t cap, bool rids)
 {
     return (size_t)table_buckets(cap) * (rids ? 36 : 20) + 64;
 }
@@ -1203,10 +1221,11 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 // together), count the matching slots with predicated arithmetic, and walk on only for keys
 // whose two buckets both overflowed.  `multi` is set when a key has more than kEmitSort
 // entries (the write pass then puts the table's entries in canonical order before it emits
-// them; keys with fewer entries are ordered as they are emitted).
+// them; keys with fewer entries are ordered as they are emitted); `many` adds up the entries
+// of keys with more than two (the write pass places their pairs apart).
 template <int N, bool HASHED, bool MARKED>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
-                                                const bool (&valid)[N], bool& multi)
+                                                const bool (&valid)[N], bool& multi, uint32_t& many)
 {
     uint32_t b1[N], b2[N], c1[N], c2[N];
     uint4 k1[N], k2[N];
@@ -1238,6 +1257,7 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         n += h[i];
+        many += h[i] > 2 ? h[i] : 0u;
         multi = multi || h[i] > (uint32_t)kEmitSort;
     }
     return n;
@@ -1323,34 +1343,27 @@ __device__ __forceinline__ void sort8(uint32_t (&v)[8])
     }
 }
 
-// The pairs of a probe with more than two matches, at slot .. slot + m - 1, in ascending rid
+// The m pairs of probe x (m counted here), at slot .. slot + m - 1, in ascending build rid
 // order (as signed int32).
-//  * Up to kEmitSort matches, all in the two candidate buckets (neither walks on): the 8 slots'
-//    rids are read at once and sorted by a network, as unsigned keys rid ^ 2^31, the slots that
-//    do not match set to all ones; the first m are written.  A matching rid of INT32_MAX has the
-//    same key as a slot that does not match, and both turn back into INT32_MAX, so the first m
+//  * No walk (the two candidate buckets hold every match, so m <= 8): the 8 slots' rids are
+//    read at once and sorted by a network, as unsigned keys rid ^ 2^31, the slots that do not
+//    match set to all ones; the first m are written.  A matching rid of INT32_MAX has the same
+//    key as a slot that does not match, and both turn back into INT32_MAX, so the first m
 //    values are the matches in order either way.
-//  * Up to kEmitSort matches with a walk (rare): gathered in registers, each written at its rank.
+//  * A walk with up to kEmitSort matches (rare): gathered in registers, each written at its rank.
 //  * More: the table was put in canonical order, so the visiting order is ascending.
 template <bool HASHED, bool MARKED>
-__device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, uint32_t m,
-                                          const uint32_t* rw, int32_t srid, uint64_t slot,
+__device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, int32_t srid,
+                                          uint64_t slot, const uint32_t* rw,
                                           int2* __restrict__ out, uint64_t cap)
 {
-    if (m > (uint32_t)kEmitSort) {
-        uint32_t seen = 0;
-        for_each_match<HASHED, MARKED>(t, bits, x, [&](uint32_t p) {
-            if (slot + seen < cap) put_pair(&out[slot + seen], make_int2((int32_t)rw[p], srid));
-            ++seen;
-        });
-        return;
-    }
     uint32_t b1, b2;
     choices(HASHED ? x : hmix(x), bits, t.nb, b1, b2);
     const uint4 k1 = t.keys[b1], k2 = t.keys[b2];
     const uint32_t c1 = claims<MARKED>(t, b1), c2 = claims<MARKED>(t, b2);
     if (!(overflowed<MARKED>(k1, c1, x) && overflowed<MARKED>(k2, c2, x))) {
         const uint32_t hm = hits<MARKED>(k1, c1, x) | (hits<MARKED>(k2, c2, x) << 4);
+        const uint32_t m = __builtin_popcount(hm);
         const uint4 r1 = t.rids[b1], r2 = t.rids[b2];
         uint32_t v[8] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
 #pragma unroll
@@ -1360,6 +1373,16 @@ __device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, 
         for (int k = 0; k < 8; ++k)
             if ((uint32_t)k < m && slot + k < cap)
                 put_pair(&out[slot + k], make_int2((int32_t)(v[k] ^ 0x80000000u), srid));
+        return;
+    }
+    uint32_t m = 0;
+    for_each_match<HASHED, MARKED>(t, bits, x, [&](uint32_t) { ++m; });
+    if (m > (uint32_t)kEmitSort) {
+        uint32_t seen = 0;
+        for_each_match<HASHED, MARKED>(t, bits, x, [&](uint32_t p) {
+            if (slot + seen < cap) put_pair(&out[slot + seen], make_int2((int32_t)rw[p], srid));
+            ++seen;
+        });
         return;
     }
     int32_t r[kEmitSort];
@@ -1380,6 +1403,51 @@ __device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, 
             rank += ((uint32_t)j < m && (r[j] < r[k] || (r[j] == r[k] && j < k))) ? 1u : 0u;
         if ((uint32_t)k < m && slot + rank < cap) put_pair(&out[slot + rank], make_int2(r[k], srid));
     }
+}
+
+// Probes with more than two matches are rare (and scattered over the lanes): each wave queues
+// them in LDS, {key, probe rid, matches}, and emits the queue with one probe per lane when the
+// next tuple's probes would not fit (and at the end of the unit), instead of running emit_many
+// with a few lanes active after every round.  Their pairs form one contiguous block per wave
+// and unit, after the wave's other pairs, so each emission writes a contiguous run.  The
+// emitting function is not inlined: its registers are needed only while it runs, not across
+// the probe loop.
+constexpr int kManyQ = 64;  // a whole wave's worth: one tuple index of a round always fits
+
+// The write pass's LDS: its dynamic table, and the queues at file scope, so that the emitting
+// function below, which is not inlined, still addresses them as LDS.
+extern __shared__ uint4 write_lds[];
+__shared__ uint4 write_manyq[kJoinBlock / kWave * kManyQ];
+
+// Emits the qn queued probes of wave wv (one per lane) against the table of a unit whose chunk
+// has nb buckets (rids after the keys, claim counters after the rids): their pairs go, in queue
+// order, to the contiguous block at `at`.  Returns the end of that block.
+template <bool HASHED, bool MARKED>
+__device__ __attribute__((noinline)) uint64_t flush_many(uint32_t nb, int bits, int wv, uint32_t qn,
+                                                         uint64_t at, int2* __restrict__ out, uint64_t cap)
+{
+    Table t;
+    t.keys = write_lds;
+    t.rids = write_lds + nb;
+    t.cnt = reinterpret_cast<const uint32_t*>(write_lds + 2 * nb);
+    t.nb = nb;
+    t.marked = MARKED;
+    const uint4* q = write_manyq + wv * kManyQ;
+    // the queue was written by other lanes of this wave; LDS accesses of a wave complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool mine = lane_id() < qn;
+    const uint4 e = mine ? q[lane_id()] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t inc = wave_incl_scan(e.z);  // e.z: the probe's matches (0 for no entry)
+    const uint64_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+    if (mine)
+        emit_many<HASHED, MARKED>(t, bits, e.x, (int32_t)e.y, at + (inc - e.z),
+                                  reinterpret_cast<const uint32_t*>(t.rids), out, cap);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return at + total;
 }
 
 // Canonical order of a key's entries.  The inserts race for slots, so which slots a key's
@@ -1478,7 +1546,10 @@ __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, u
     for (int i = 0; i < kWriteLoad; ++i) {
         const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
         const bool ok = full || e < un.sN;
-        const uint32_t idx = un.sBeg + (ok ? e : 0u);
+        uint32_t idx = un.sBeg + (ok ? e : 0u);
+        // computed where the load is issued: hoisted out of the probe loop, the addresses of the
+        // next unit's first loads would occupy registers through it
+        asm volatile("" : "+v"(idx));
         // no select on the loaded values: the probe masks the out-of-range lanes, and a select
         // here would wait for the loads
         if constexpr (AOS) {
@@ -1533,7 +1604,8 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // total over a unit is kept in 64 bits.
 template <bool AOS, bool MARKED>
 __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
-                                                const uint32_t (&xs)[kCountBatch], bool& multi)
+                                                const uint32_t (&xs)[kCountBatch], bool& multi,
+                                                uint32_t& many)
 {
     uint32_t cnt = 0;
 #pragma unroll
@@ -1545,7 +1617,7 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
             x[i] = xs[h + i];
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
-        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok, multi);
+        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok, multi, many);
     }
     return cnt;
 }
@@ -1555,19 +1627,31 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
 // unit and wave, where the wave's pairs start inside the unit's output range, so the write pass
 // needs no shared cursor and every pair lands at a position that depends on the input and the
 // plan alone.  Entry 0 of a unit (wave 0 starts at 0) instead holds 1 when some probe of the
-// unit has more than kEmitSort entries in its table.
+// unit has more than kEmitSort entries in its table.  Inside a wave's range the pairs of probes
+// with at most two matches come first, in (batch, tuple, lane) order, then those of probes with
+// more, in the order the wave queued them; the second half of the unit's record holds, per wave,
+// where that second block starts inside the wave's range.
 constexpr int kJoinWaves = kJoinBlock / kWave;
+constexpr int kWaveRec = 2 * kJoinWaves;  // uint64 entries per unit in the wave record
+// the write pass's queues of probes with many matches, beside its dynamic table
+constexpr size_t kWriteStaticLds = (size_t)kJoinWaves * kManyQ * 16;
+static_assert(table_lds(kMaxCap, true) + kWriteStaticLds <= 160 * 1024, "write pass LDS");
 
-// End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u]
-// and the waves' starts in wave_off[u][1..]; sh: kJoinWaves + 1 words of LDS (64-bit).
-__device__ __forceinline__ void unit_totals(uint64_t lane_total, bool multi, uint32_t u,
+// End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u],
+// the waves' starts in wave_off[u][1..kJoinWaves) and each wave's count of pairs before its
+// block of many-match pairs in wave_off[u][kJoinWaves + w]; sh: kJoinWaves + 1 words of LDS.
+__device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi, uint32_t u,
                                             uint64_t* __restrict__ counts,
                                             uint64_t* __restrict__ wave_off, uint64_t* sh)
 {
     const uint64_t wt = wave_sum64(lane_total);
+    const uint64_t wmany = wave_sum64(lane_many);
     const bool wm = ballot(multi) != 0;
     const int wv = threadIdx.x / kWave;
-    if (lane_id() == 0) sh[wv] = wt | (wm ? (1ull << 63) : 0ull);
+    if (lane_id() == 0) {
+        sh[wv] = wt | (wm ? (1ull << 63) : 0ull);
+        wave_off[(size_t)u * kWaveRec + kJoinWaves + wv] = wt - wmany;
+    }
     __syncthreads();
     if (threadIdx.x < kJoinWaves) {
         uint64_t before = 0, sum = 0, any = 0;
@@ -1579,7 +1663,7 @@ __device__ __forceinline__ void unit_totals(uint64_t lane_total, bool multi, uin
             sum += c;
             any |= v >> 63;
         }
-        wave_off[(size_t)u * kJoinWaves + threadIdx.x] = threadIdx.x == 0 ? any : before;
+        wave_off[(size_t)u * kWaveRec + threadIdx.x] = threadIdx.x == 0 ? any : before;
         if (threadIdx.x == 0) counts[u] = sum;
     }
     __syncthreads();
@@ -1643,7 +1727,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     uint32_t xa[kCountBatch], xb[kCountBatch];
     Unit un{};
     if (blockIdx.x < U) {
-        un = decode_unit(g, blockIdx.x);
+        un = decode_unit<AOS>(g, blockIdx.x);
         load_keys<AOS>(g, un, 0, xa);
     }
     for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
@@ -1653,24 +1737,26 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         const Table t = insert_chunk<false, AOS>(g, un, ch, tab, pos);
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
         const bool more = u + gridDim.x < U;
-        const Unit nx = more ? decode_unit(g, u + gridDim.x) : Unit{};
-        uint64_t cnt = 0;
+        const Unit nx = more ? decode_unit<AOS>(g, u + gridDim.x) : Unit{};
+        uint64_t cnt = 0, many = 0;
         bool multi = false;
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
             for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
                 const uint32_t e1 = e0 + kB, e2 = e1 + kB;
+                uint32_t ma = 0, mb = 0;
                 load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
-                cnt += count_batch<AOS, M>(t, un, e0, xa, multi);
+                cnt += count_batch<AOS, M>(t, un, e0, xa, multi, ma);
                 const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
                 load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
-                cnt += count_batch<AOS, M>(t, un, e1, xb, multi);  // every lane masked past the unit
+                cnt += count_batch<AOS, M>(t, un, e1, xb, multi, mb);  // every lane masked past the unit
+                many += (uint64_t)ma + mb;
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
-        unit_totals(cnt, multi, u, counts, wave_off, wsum);
+        unit_totals(cnt, many, multi, u, counts, wave_off, wsum);
         un = nx;
     }
     if (done) {
@@ -1698,16 +1784,17 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
 // Whether any unit of [u, end) that shares unit u's R chunk had a probe with more than
 // kEmitSort matches (entry 0 of its wave_off record): then the chunk's table is put in
 // canonical order.
+template <bool PART>
 __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint64_t* wave_off, uint32_t u,
                                                   uint32_t end, uint32_t step, const Unit& un)
 {
     const cptr<uint64_t> wo = as_const(wave_off);
-    bool any = wo[(size_t)u * kJoinWaves] != 0;
+    bool any = wo[(size_t)u * kWaveRec] != 0;
     if (step != 1) return any;  // round robin: every unit builds its own table
     for (uint32_t v = u + 1; v < end && !any; ++v) {
-        const Unit n = decode_unit(g, v);
-        if (n.rBeg != un.rBeg || n.rN != un.rN) break;
-        any = wo[(size_t)v * kJoinWaves] != 0;
+        const Unit n = decode_unit<PART>(g, v);
+        if (!same_chunk(n, un)) break;
+        any = wo[(size_t)v * kWaveRec] != 0;
     }
     return any;
 }
@@ -1722,13 +1809,15 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                                            const uint64_t* __restrict__ total,
                                            int2* __restrict__ out, uint64_t cap)
 {
-    extern __shared__ uint4 tab[];
+    uint4* const tab = write_lds;
     // an output too small for the exact count, or a plan other than the count pass's, receives
     // nothing
     if (*total > cap || (g.stamp_at && *g.stamp_at != g.stamp)) return;
     const uint32_t U = unit_total(g);
     const bool contig = g.contig != 0;  // uniform
     const int wv = uniform((int32_t)(threadIdx.x / kWave));
+    uint4* q = write_manyq + wv * kManyQ;  // this wave's queue of probes with many matches
+    uint32_t qn = 0;                 // uniform: its length
     uint32_t u0, u1, step;
     if (contig) {
         unit_range(U, u0, u1);
@@ -1738,8 +1827,6 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         u1 = U;
         step = gridDim.x;
     }
-    const cptr<uint64_t> offs = as_const(offsets);
-    const cptr<uint64_t> wo = as_const(wave_off);
     // The next unit's R chunk (when it needs a new table) is loaded into registers while the
     // current unit probes, and the next unit's first S batch while its last batch probes.
     Unit un{};
@@ -1748,32 +1835,34 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     uint32_t nx[kWriteLoad];
     int32_t nr[kWriteLoad];
     if (u0 < u1) {
-        un = decode_unit(g, u0);
+        un = decode_unit<AOS>(g, u0);
         load_chunk<AOS, true>(g, un, ch);
         load_tuples<AOS>(g, un, 0, nx, nr);
     }
-    uint32_t tBeg = 0, tN = 0;  // R chunk in the table (tN == 0: none yet)
+    Unit tu{};  // the unit whose chunk is in the table (rN == 0: none yet)
+    const cptr<uint64_t> offs = as_const(offsets);
+    const cptr<uint64_t> wo = as_const(wave_off);
     for (uint32_t u = u0; u < u1; u += step) {
-        if (!contig || un.rBeg != tBeg || un.rN != tN) {  // uniform: a new R chunk (loaded in ch)
-            const bool order = chunk_needs_order(g, wave_off, u, u1, step, un);
+        const bool more = u + step < u1;
+        if (!contig || tu.rN == 0 || !same_chunk(un, tu)) {  // uniform: a new chunk (loaded in ch)
+            const bool order = chunk_needs_order<AOS>(g, wave_off, u, u1, step, un);
             const Table tb = insert_chunk<true, AOS>(g, un, ch, tab, pos);
             if (order) {
                 uint32_t* rids = reinterpret_cast<uint32_t*>(tab + tb.nb);
                 if (AOS && tb.marked) canonicalize<AOS, true>(tb, un.bits, un, ch, pos, rids);
                 else canonicalize<AOS, false>(tb, un.bits, un, ch, pos, rids);
             }
-            tBeg = un.rBeg;
-            tN = un.rN;
+            tu = un;
         }
-        // this wave's first output slot in unit u
-        uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kJoinWaves + wv]) : 0ull);
+        // this wave's first output slot in unit u, and the start of its block of many-match pairs
+        uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kWaveRec + wv]) : 0ull);
+        uint64_t cmany = cursor + uniform(wo[(size_t)u * kWaveRec + kJoinWaves + wv]);
 #if JL_DEBUG
-        const uint64_t cursor0 = cursor;
+        const uint64_t cursor0 = cursor, cmany0 = cmany;
 #endif
         const Table t = table_of<true, AOS>(un, tab);
-        const bool more = u + step < u1;
-        const Unit nxt = more ? decode_unit(g, u + step) : Unit{};
-        if (more && (!contig || nxt.rBeg != un.rBeg || nxt.rN != un.rN)) load_chunk<AOS, true>(g, nxt, ch);
+        const Unit nxt = more ? decode_unit<AOS>(g, u + step) : Unit{};
+        if (more && (!contig || !same_chunk(nxt, un))) load_chunk<AOS, true>(g, nxt, ch);
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
@@ -1801,15 +1890,15 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                         ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
                     }
                     probe_write<kWriteBatch, AOS, M>(t, un.bits, x, ok, m, p1, p2);
-                    // Slots: the wave's cursor plus an exclusive scan over (tuple i, lane); the
-                    // pairs of the i-th tuple of every lane are contiguous, so each store
-                    // instruction writes one coalesced run.  A round's pairs fit 32 bits
-                    // (kWriteBatch tuples x 64 lanes x at most kMaxCap entries).
+                    // Slots of probes with one or two matches: the wave's cursor plus an
+                    // exclusive scan over (tuple i, lane); the pairs of the i-th tuple of every
+                    // lane are contiguous, so each store instruction writes one coalesced run.
                     uint32_t excl[kWriteBatch], wtot = 0;
 #pragma unroll
                     for (int i = 0; i < kWriteBatch; ++i) {
-                        const uint32_t inc = wave_incl_scan(m[i]);
-                        excl[i] = wtot + inc - m[i];
+                        const uint32_t ms = m[i] <= 2 ? m[i] : 0u;
+                        const uint32_t inc = wave_incl_scan(ms);
+                        excl[i] = wtot + inc - ms;
                         wtot += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
                     }
 #pragma unroll
@@ -1818,9 +1907,21 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                         // two matches leave in ascending rid order
                         const int32_t ra = (int32_t)rw[p1[i]], rb = (int32_t)rw[p2[i]];
                         const bool sw = m[i] == 2 && rb < ra;
-                        if (m[i] >= 1 && m[i] <= 2 && slot < cap) put_pair(&out[slot], make_int2(sw ? rb : ra, srid[i]));
-                        if (m[i] == 2 && slot + 1 < cap) put_pair(&out[slot + 1], make_int2(sw ? ra : rb, srid[i]));
-                        if (m[i] > 2) emit_many<AOS, M>(t, un.bits, x[i], m[i], rw, srid[i], slot, out, cap);
+                        if (m[i] >= 1 && m[i] <= 2 && slot < cap)
+                            put_pair(&out[slot], make_int2(sw ? rb : ra, srid[i]));
+                        if (m[i] == 2 && slot + 1 < cap)
+                            put_pair(&out[slot + 1], make_int2(sw ? ra : rb, srid[i]));
+                        const bool many = m[i] > 2;
+                        const uint64_t bm = ballot(many);
+                        if (bm) {  // uniform
+                            const uint32_t c = (uint32_t)__builtin_popcountll(bm);
+                            if (qn + c > (uint32_t)kManyQ) {
+                                cmany = flush_many<AOS, M>(t.nb, un.bits, wv, qn, cmany, out, cap);
+                                qn = 0;
+                            }
+                            if (many) q[qn + mask_rank(bm)] = make_uint4(x[i], (uint32_t)srid[i], m[i], 0u);
+                            qn += c;
+                        }
                     }
                     cursor += wtot;
                 }
@@ -1828,9 +1929,15 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
+        if (qn) {  // uniform: the queue must be empty before the table changes
+            if (AOS && t.marked) cmany = flush_many<AOS, true>(t.nb, un.bits, wv, qn, cmany, out, cap);
+            else cmany = flush_many<AOS, false>(t.nb, un.bits, wv, qn, cmany, out, cap);
+            qn = 0;
+        }
 #if JL_DEBUG
-        if (g.dbg && lane_id() == 0 && cursor > cursor0)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&g.dbg[u]), (unsigned long long)(cursor - cursor0));
+        const uint64_t wrote = (cursor - cursor0) + (cmany - cmany0);
+        if (g.dbg && lane_id() == 0 && wrote > 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&g.dbg[u]), (unsigned long long)wrote);
 #endif
         if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
         __syncthreads();
@@ -1943,8 +2050,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
         off = align_up(off + (size_t)pl.P * sizeof(PartInfo));
         pl.off_units = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
-        pl.off_umap = off;
-        off = align_up(off + (size_t)pl.Umax * 4);
+        pl.off_umap = off;  // the unit records
+        off = align_up(off + (size_t)pl.Umax * 16);
         // ordered scatter: per-tile counts, then run offsets, of each side (chunks x tiles per
         // chunk x P)
         const size_t on = pl.ordered ? 1 : 0;
@@ -1956,7 +2063,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     pl.off_counts = off;
     off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8);
     pl.off_wave = off;
-    off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * kJoinWaves * 8);
+    off = align_up(off + (size_t)(pl.Umax > 0 ? pl.Umax : 1) * kWaveRec * 8);
     size_t temp = scan_temp_elems<uint64_t>(pl.Umax) * 8;
     if (!pl.single) {
         const size_t t1 = scan_temp_elems<uint32_t>(pl.P + 1) * 4;
@@ -1988,14 +2095,18 @@ static hipError_t set_attrs()
 {
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
+    const int write_max = (int)(160 * 1024 - kWriteStaticLds - 256);  // beside its static queue
     const void* fns[] = {
         (const void*)scatter_k<true, false>, (const void*)scatter_k<false, false>,
         (const void*)scatter_k<true, true>, (const void*)scatter_k<false, true>, (const void*)hist_k,
         (const void*)join_count_k<true>, (const void*)join_count_k<false>,
-        (const void*)join_write_k<true>, (const void*)join_write_k<false>,
     };
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        if (e != hipSuccess) return e;
+    }
+    for (const void* f : {(const void*)join_write_k<true>, (const void*)join_write_k<false>}) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, write_max);
         if (e != hipSuccess) return e;
     }
     g_attr_done = true;
@@ -2100,12 +2211,12 @@ static BandSide band_of(uint32_t* cnt, int64_t chunk, int64_t n, int64_t nCh, in
 
 // Per-partition plans, unit starts (total at *Utotal) and the unit -> partition map.
 static hipError_t plan_parts(const PartPlan& q, int64_t nParts, PartInfo* info, uint32_t* units,
-                             uint32_t* Utotal, int64_t Umax, uint32_t* umap, uint32_t* temp,
+                             uint32_t* Utotal, int64_t Umax, uint4* urec, uint32_t* temp,
                              hipStream_t st)
 {
     if (nParts <= kFuseParts) {
         prof::Scope pp(st, "hash.plan");
-        plan_k<<<1, kFuseBlock, 0, st>>>(q, (int)nParts, info, units, Utotal, Umax, umap);
+        plan_k<<<1, kFuseBlock, 0, st>>>(q, (int)nParts, info, units, Utotal, Umax, urec);
         return hipGetLastError();
     }
     {
@@ -2117,7 +2228,7 @@ static hipError_t plan_parts(const PartPlan& q, int64_t nParts, PartInfo* info, 
     if (e != hipSuccess) return e;
     {
         prof::Scope pe(st, "hash.plan");
-        expand_units_k<<<(unsigned)ceil_div(nParts, 256), 256, 0, st>>>(units, (int)nParts, Umax, umap);
+        expand_units_k<<<(unsigned)ceil_div(nParts, 256), 256, 0, st>>>(units, info, (int)nParts, q.cap, Umax, urec);
     }
     return hipGetLastError();
 }
@@ -2208,7 +2319,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.st = reinterpret_cast<const int2*>(ws + pl.off_tupS);
         g.part = reinterpret_cast<const PartInfo*>(ws + pl.off_info);
         g.unitStart = reinterpret_cast<const uint32_t*>(ws + pl.off_units);
-        g.umap = reinterpret_cast<const uint32_t*>(ws + pl.off_umap);
+        g.urec = reinterpret_cast<const uint4*>(ws + pl.off_umap);
         g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
         g.P = pl.P;
     }
@@ -2267,7 +2378,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
         pa.units = reinterpret_cast<uint32_t*>(ws + pl.off_units);
         pa.Utotal = reinterpret_cast<uint32_t*>(ws + 8);
         pa.Umax = pl.Umax;
-        pa.umap = reinterpret_cast<uint32_t*>(ws + pl.off_umap);
+        pa.urec = reinterpret_cast<uint4*>(ws + pl.off_umap);
         // up to kFuseParts partitions the plan is one workgroup of the scatter launch
         const PlanArgs* fused = pl.P <= kFuseParts ? &pa : nullptr;
         if (pre)
@@ -2278,7 +2389,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
                              grpS, tupS, cntS, pl.bits, pl.P, st, fused);
         if (e != hipSuccess) return e;
         if (!fused) {
-            e = plan_parts(pa.q, pl.P, pa.info, pa.units, pa.Utotal, pl.Umax, pa.umap,
+            e = plan_parts(pa.q, pl.P, pa.info, pa.units, pa.Utotal, pl.Umax, pa.urec,
                            reinterpret_cast<uint32_t*>(temp), st);
             if (e != hipSuccess) return e;
         }
@@ -2460,9 +2571,9 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.off_tupS = take(off, (size_t)bp.sumS * 8);
     bp.off_info = take(off, (size_t)bp.nParts * sizeof(PartInfo));
     bp.off_units = take(off, (size_t)(bp.nParts + 1) * 4);
-    bp.off_umap = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 4);
+    bp.off_umap = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 16);
     bp.off_counts = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * 8);
-    bp.off_wave = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * kJoinWaves * 8);
+    bp.off_wave = take(off, (size_t)(bp.Umax > 0 ? bp.Umax : 1) * kWaveRec * 8);
     bp.off_item0R = take(off, (size_t)(njobs + 1) * 4);
     bp.off_item0S = take(off, (size_t)(njobs + 1) * 4);
     bp.off_cntR = take(off, bp.ordered ? (size_t)cntR * 4 : 0);
@@ -2545,7 +2656,7 @@ static JoinGeom batch_geom(const BatchPlan& bp, char* ws)
     g.st = reinterpret_cast<const int2*>(ws + bp.off_tupS);
     g.part = reinterpret_cast<const PartInfo*>(ws + bp.off_info);
     g.unitStart = reinterpret_cast<const uint32_t*>(ws + bp.off_units);
-    g.umap = reinterpret_cast<const uint32_t*>(ws + bp.off_umap);
+    g.urec = reinterpret_cast<const uint4*>(ws + bp.off_umap);
     g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
     g.P = (int)bp.nParts;
     return g;
@@ -2621,7 +2732,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (e != hipSuccess) return e;
     PartPlan q{baseR, totR, baseS, totS, jpart0, jbits, bp.njobs, 0, (uint32_t)bp.cap, (uint32_t)bp.slice};
     e = plan_parts(q, bp.nParts, reinterpret_cast<PartInfo*>(ws + bp.off_info), units,
-                   reinterpret_cast<uint32_t*>(ws + 8), bp.Umax, reinterpret_cast<uint32_t*>(ws + bp.off_umap),
+                   reinterpret_cast<uint32_t*>(ws + 8), bp.Umax, reinterpret_cast<uint4*>(ws + bp.off_umap),
                    reinterpret_cast<uint32_t*>(temp), st);
     if (e != hipSuccess) return e;
     if (bp.Umax > 0) {

@@ -32,7 +32,7 @@ struct JoinGeom {
     const int2* st;     // partitioned: (key, rid) probe tuples, partition-major
     const PartInfo* part;       // [P]
     const uint32_t* unitStart;  // [P + 1], exclusive scan of units per partition
-    const uint32_t* umap;       // [Umax], partition of each unit
+    const uint4* urec;          // [Umax], each unit's record (unit_rec)
     const uint32_t* Uptr;       // device total of units
     PartInfo one;               // the single partition when single != 0
     uint32_t Uhost;             // units when single != 0

@@ -19,6 +19,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 
+import numpy as np
 import torch
 
 from . import _native
@@ -291,17 +292,80 @@ class Job:
     bits: int = -1
 
 
+# join_job_t as a numpy record: R (key, key2, rid, n), S (key, key2, rid, n), bits, reserved
+_JOB_DTYPE = np.dtype([("Rk", "<u8"), ("R2", "<u8"), ("Rr", "<u8"), ("Rn", "<i8"),
+                       ("Sk", "<u8"), ("S2", "<u8"), ("Sr", "<u8"), ("Sn", "<i8"),
+                       ("bits", "<i4"), ("reserved", "<i4")])
+assert _JOB_DTYPE.itemsize == ctypes.sizeof(JoinJob)
+
+
+def _col(t, n: int) -> int:
+    """Device address of a join column of n rows (0 for None or an empty column)."""
+    if t is None:
+        return 0
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("join columns must be contiguous int32 cuda tensors")
+    if t.numel() != n:
+        raise ValueError("all columns of a relation need the same length")
+    return t.data_ptr() if n > 0 else 0
+
+
+def _jobs_array(jobs) -> np.ndarray:
+    """The join_job_t array of a batch, built as one numpy record array."""
+    rows = []
+    for j in jobs:
+        R, S = j.R, j.S
+        nr, ns = R.key.numel(), S.key.numel()
+        rows.append((_col(R.key, nr), _col(R.key2, nr), _col(R.rid, nr), nr,
+                     _col(S.key, ns), _col(S.key2, ns), _col(S.rid, ns), ns, int(j.bits), 0))
+    return np.array(rows if rows else [(0,) * 10], dtype=_JOB_DTYPE)
+
+
+def _packed_array(rkeys: torch.Tensor, roffs, skeys: torch.Tensor, soffs, bits=None,
+                  rrids: torch.Tensor | None = None, srids: torch.Tensor | None = None) -> np.ndarray:
+    """The join_job_t array of a packed batch: join j's R keys are rkeys[roffs[j]:roffs[j+1]]
+    (rids likewise, or row positions within the join when rrids is None), and the same for S."""
+    roffs = np.asarray(roffs, dtype=np.int64)
+    soffs = np.asarray(soffs, dtype=np.int64)
+    n = len(roffs) - 1
+    if n < 0 or len(soffs) != n + 1:
+        raise ValueError("offsets need njobs + 1 entries on both sides")
+    for offs, col in ((roffs, rkeys), (soffs, skeys)):
+        if offs[0] != 0 or offs[-1] != col.numel() or np.any(np.diff(offs) < 0):
+            raise ValueError("offsets must rise from 0 to the column length")
+    base = {}
+    for name, t, nn in (("rk", rkeys, int(roffs[-1])), ("rr", rrids, int(roffs[-1])),
+                        ("sk", skeys, int(soffs[-1])), ("sr", srids, int(soffs[-1]))):
+        base[name] = _col(t, nn)
+    arr = np.zeros(max(n, 1), dtype=_JOB_DTYPE)
+    if n == 0:
+        return arr
+    rn, sn = np.diff(roffs), np.diff(soffs)
+    a = arr[:n]
+    a["Rn"], a["Sn"] = rn, sn
+    a["Rk"] = np.where(rn > 0, base["rk"] + 4 * roffs[:-1], 0)
+    a["Sk"] = np.where(sn > 0, base["sk"] + 4 * soffs[:-1], 0)
+    if base["rr"]:
+        a["Rr"] = np.where(rn > 0, base["rr"] + 4 * roffs[:-1], 0)
+    if base["sr"]:
+        a["Sr"] = np.where(sn > 0, base["sr"] + 4 * soffs[:-1], 0)
+    a["bits"] = -1 if bits is None else np.asarray(bits, dtype=np.int32)
+    return arr
+
+
 class Batch:
     """A prepared batch of independent equi joins (join_batch_prepare).  count() and
     materialize() only launch kernels, so they can run inside a captured HIP graph.  The
     relations' tensors must stay alive and unchanged while the batch is in use."""
 
-    def __init__(self, jobs: list[Job], stream=None, device="cuda"):
+    def __init__(self, jobs: list[Job], stream=None, device="cuda", _arr: np.ndarray | None = None):
         self.jobs = list(jobs)
-        n = len(self.jobs)
-        self._c = (JoinJob * max(n, 1))()
-        for i, j in enumerate(self.jobs):
-            self._c[i] = JoinJob(j.R.c(), j.S.c(), int(j.bits), 0)
+        self._arr = _jobs_array(self.jobs) if _arr is None else _arr
+        n = len(self.jobs) if _arr is None else int(len(_arr) if _arr["Rn"].size > 1 or
+                                                     _arr["Rn"][0] or _arr["Sn"][0] else 0)
+        self._c = self._arr.ctypes.data_as(ctypes.POINTER(JoinJob))
         nbytes = int(_native.lib.join_batch_workspace_bytes(n, self._c))
         if nbytes == 0:
             raise JoinError(_native.JOIN_E_INVAL, _native.last_error() or "batch too large")

@@ -74,6 +74,7 @@ class Engine:
         self.peak = 0
         self.waits = 0
         self.retries = 0
+        self.max_request = 0  # largest workspace + output of one request served so far
         self.active = 0
         self._waiting: set = set()
         self._cv = threading.Condition()
@@ -150,6 +151,8 @@ class Engine:
         try:
             ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
             n = rb.count(req.S, ws, stream) if rb is not None else J.join_count(kind, R, req.S, pred, ws, stream)
+            with self._cv:
+                self.max_request = max(self.max_request, wsb + 8 * n)
             self._reserve_out(8 * n, key, wsb)
             try:
                 out = torch.empty((n, 2), dtype=torch.int32, device=dev)

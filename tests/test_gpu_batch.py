@@ -134,3 +134,40 @@ def test_count_pass_in_a_replayed_graph():
     out = torch.empty((total, 2), dtype=torch.int32, device="cuda")
     b.materialize(out)
     _check_batch(jobs, out, [int(v) for v in b.offsets.cpu().tolist()])
+
+
+def _side_jobs(seed: int):
+    """Joins that exercise the choice of the hashed table and probes with many matches: S smaller
+    than R (S hashed: pairs must still leave as (rid_R, rid_S)), with S keys from a handful of
+    values (a hashed side with long runs of one key: walks and tables in canonical order) or
+    uniform; R smaller with duplicate keys (3..8 matches per probe); equal sizes (R hashed);
+    fan-outs 0 and 1 (claim-counter tables) and larger (marked tables).  R rids are negative and
+    S rids positive, so a pair turned the wrong way round cannot match the oracle."""
+    g = datagen.rng_for(seed)
+    jobs = []
+    specs = [  # (nR, nS, S key domain or 0 for |R|, R key domain or 0 for |R|, bits)
+        (200_000, 3_000, 7, 0, -1), (150_000, 20_000, 0, 0, 0), (90_000, 40_000, 0, 0, 1),
+        (60_000, 59_999, 0, 0, 3), (5_000, 120_000, 0, 1_500, -1), (20_000, 300_000, 0, 4_000, 2),
+        (70_000, 70_000, 0, 0, -1), (300_000, 1_000, 3, 0, 4), (2_000, 2_000, 0, 200, 0),
+        (100_000, 50_000, 0, 25_000, 1),
+    ]
+    for nr, ns, sdom, rdom, bits in specs:
+        d = rdom or nr
+        rk = datagen.uniform_keys(g, nr, 0, d)
+        sk = datagen.uniform_keys(g, ns, 0, sdom) if sdom else datagen.uniform_keys(g, ns, 0, d)
+        R = datagen.Rel(key=rk, rid=-1 - g.permutation(nr).astype(np.int32))
+        S = datagen.Rel(key=sk, rid=g.permutation(ns).astype(np.int32))
+        jobs.append((R, S, bits))
+    return jobs
+
+
+@gpu
+@pytest.mark.parametrize("det", ["0", "1"])
+def test_smaller_side_hashed_and_many_matches(monkeypatch, det):
+    need_gpu()
+    from paper_1904_11201_amd.join import hash_join_batch
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", det)
+    jobs = _side_jobs(67)
+    log(f"batch of {len(jobs)} joins with S hashed where smaller, deterministic={det}")
+    pairs, offs = hash_join_batch(_to_jobs(jobs))
+    _check_batch(jobs, pairs, offs)

@@ -52,13 +52,14 @@ def test_duplicate_heavy_build_is_deterministic():
     assert a.shape == b.shape and torch.equal(a, b)
 
 
-def _probe_runs_ascending(pairs: np.ndarray) -> bool:
-    """With unique probe rids: inside every run of consecutive pairs of one probe (the matches
-    one work unit wrote for it), rid_R does not decrease."""
+def _probe_runs_ascending(pairs: np.ndarray, col: int = 1) -> bool:
+    """With unique probe rids in column `col`: inside every run of consecutive pairs of one probe
+    (the matches one work unit wrote for it), the other column does not decrease."""
     if len(pairs) == 0:
         return True
-    same = pairs[1:, 1] == pairs[:-1, 1]
-    return bool(np.all(pairs[1:, 0][same] >= pairs[:-1, 0][same]))
+    other = 1 - col
+    same = pairs[1:, col] == pairs[:-1, col]
+    return bool(np.all(pairs[1:, other][same] >= pairs[:-1, other][same]))
 
 
 @gpu
@@ -66,8 +67,8 @@ def _probe_runs_ascending(pairs: np.ndarray) -> bool:
 def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits, det):
     """Build keys with 1 to 12 entries each (random rids, some repeated), through the single
     path (bits -1) and partitioned plans: probes with up to 8 matches order them as they are
-    written, probes with more meet them in a table put in canonical order.  Either way the
-    pairs a work unit writes for one probe are ascending in rid_R, and the multiset equals the
+    written, probes with more meet them in a table put in canonical order.  Either way the pairs
+    a work unit writes for one probe are ascending in rid_R, and the multiset equals the
     oracle's."""
     need_gpu()
     import oracle
@@ -77,10 +78,10 @@ def test_matches_of_a_probe_leave_in_rid_order(monkeypatch, bits, det):
     nkeys = 6000
     keys = g.permutation(1 << 20)[:nkeys].astype(np.int32) - (1 << 19)
     mult = g.integers(1, 13, nkeys)
-    rk = np.repeat(keys, mult)
-    perm = g.permutation(len(rk))
-    R = datagen.Rel(key=rk[perm], rid=g.integers(0, 3 * len(rk), len(rk)).astype(np.int32))
-    S = datagen.Rel(key=keys[g.integers(0, nkeys, 50_000)], rid=np.arange(50_000, dtype=np.int32))
+    bk = np.repeat(keys, mult)
+    perm = g.permutation(len(bk))
+    R = datagen.Rel(key=bk[perm], rid=g.integers(0, 3 * len(bk), len(bk)).astype(np.int32))
+    S = datagen.Rel(key=keys[g.integers(0, nkeys, 200_000)], rid=np.arange(200_000, dtype=np.int32))
     n, ref = oracle.equi_sortmerge(R.key, S.key, Rrid=R.rid, Srid=S.rid)
     monkeypatch.setenv("JOIN_HASH_BITS", bits)
     monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", det)
