@@ -360,11 +360,28 @@ class Batch:
     materialize() only launch kernels, so they can run inside a captured HIP graph.  The
     relations' tensors must stay alive and unchanged while the batch is in use."""
 
-    def __init__(self, jobs: list[Job], stream=None, device="cuda", _arr: np.ndarray | None = None):
+    def __init__(self, jobs: list[Job], stream=None, device="cuda"):
         self.jobs = list(jobs)
-        self._arr = _jobs_array(self.jobs) if _arr is None else _arr
-        n = len(self.jobs) if _arr is None else int(len(_arr) if _arr["Rn"].size > 1 or
-                                                     _arr["Rn"][0] or _arr["Sn"][0] else 0)
+        self._prepare(_jobs_array(self.jobs), len(self.jobs), stream, device)
+
+    @classmethod
+    def packed(cls, rkeys: torch.Tensor, roffs, skeys: torch.Tensor, soffs, bits=None,
+               rrids: torch.Tensor | None = None, srids: torch.Tensor | None = None,
+               stream=None, device="cuda") -> "Batch":
+        """A batch whose joins are slices of packed columns: join j's R keys are
+        rkeys[roffs[j]:roffs[j+1]] (rids the same slice of rrids, or row positions within the
+        join when rrids is None), and likewise for S; bits: one fan-out per join or None (the
+        library's default).  The job table is built with vectorised arithmetic, not per join."""
+        b = cls.__new__(cls)
+        b.jobs = []
+        b._cols = (rkeys, skeys, rrids, srids)  # kept alive with the batch
+        b._prepare(_packed_array(rkeys, roffs, skeys, soffs, bits, rrids, srids), len(roffs) - 1,
+                   stream, device)
+        return b
+
+    def _prepare(self, arr: np.ndarray, n: int, stream, device):
+        self._arr = arr
+        self.njobs = n
         self._c = self._arr.ctypes.data_as(ctypes.POINTER(JoinJob))
         nbytes = int(_native.lib.join_batch_workspace_bytes(n, self._c))
         if nbytes == 0:

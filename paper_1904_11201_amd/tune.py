@@ -62,6 +62,16 @@ def hash_bits_for(nR: int, cache: dict | None = None) -> int:
     return -1 if v is None else int(v)
 
 
+def hash_bits_for_sizes(nR, cache: dict | None = None):
+    """hash_bits_for over an array of build sizes (numpy int array, -1 where nothing is tuned),
+    by one lookup table over the log2 buckets instead of a call per size."""
+    import numpy as np
+    n = np.maximum(np.asarray(nR, dtype=np.int64), 1)
+    b = np.floor(np.log2(n)).astype(np.int64)
+    table = np.array([hash_bits_for(1 << k, cache) for k in range(64)], dtype=np.int32)
+    return table[np.clip(b, 0, 63)]
+
+
 def theta_ts_for(nR: int, nS: int, cache: dict | None = None) -> int:
     """Tuned S rows per theta tile for an nR x nS join, or 0 (library default)."""
     c = load() if cache is None else cache

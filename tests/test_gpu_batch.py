@@ -171,3 +171,39 @@ def test_smaller_side_hashed_and_many_matches(monkeypatch, det):
     log(f"batch of {len(jobs)} joins with S hashed where smaller, deterministic={det}")
     pairs, offs = hash_join_batch(_to_jobs(jobs))
     _check_batch(jobs, pairs, offs)
+
+
+@gpu
+def test_packed_batch_equals_the_list_form(monkeypatch):
+    """Batch.packed over slices of one key tensor per side (with empty joins, rid columns and
+    per-join fan-outs) gives, in a deterministic plan, exactly the output array of the list form."""
+    need_gpu()
+    from paper_1904_11201_amd.join import Batch, Job, Relation
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
+    jobs = _mixed_jobs(71, 24, 150_000)
+    rk = np.concatenate([R.key for R, _, _ in jobs]).astype(np.int32)
+    sk = np.concatenate([S.key for _, S, _ in jobs]).astype(np.int32)
+    rr = np.concatenate([R.rid if R.rid is not None else np.arange(R.n, dtype=np.int32) for R, _, _ in jobs])
+    sr = np.concatenate([S.rid if S.rid is not None else np.arange(S.n, dtype=np.int32) for _, S, _ in jobs])
+    roffs = np.concatenate([[0], np.cumsum([R.n for R, _, _ in jobs])])
+    soffs = np.concatenate([[0], np.cumsum([S.n for _, S, _ in jobs])])
+    bits = [b for _, _, b in jobs]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    drk, dsk, drr, dsr = d(rk), d(sk), d(rr), d(sr)
+    log(f"packed batch of {len(jobs)} joins")
+    listed = [Job(Relation(drk[roffs[j]:roffs[j + 1]], rid=drr[roffs[j]:roffs[j + 1]]),
+                  Relation(dsk[soffs[j]:soffs[j + 1]], rid=dsr[soffs[j]:soffs[j + 1]]), bits[j])
+              for j in range(len(jobs))]
+
+    def run(b):
+        offs = b.count()
+        out = torch.empty((int(offs[-1].item()), 2), dtype=torch.int32, device="cuda")
+        b.materialize(out)
+        return out, offs.cpu()
+
+    a, oa = run(Batch(listed))
+    p, op = run(Batch.packed(drk, roffs, dsk, soffs, bits, rrids=drr, srids=dsr))
+    assert torch.equal(oa, op) and torch.equal(a, p)
+    full = [(R, S if S.rid is not None else datagen.Rel(key=S.key, rid=np.arange(S.n, dtype=np.int32)), b)
+            for R, S, b in jobs]
+    _check_batch(full, p, [int(v) for v in op.tolist()])

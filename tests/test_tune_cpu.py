@@ -29,3 +29,25 @@ def test_apply_bits_keeps_explicit_choices():
     jobs = [_J(1 << 14), _J(1 << 22, bits=3)]
     tune.apply_bits(jobs, CACHE)
     assert [j.bits for j in jobs] == [1, 3]
+
+
+def test_bits_for_sizes_matches_the_per_size_lookup():
+    import numpy as np
+    sizes = np.array([1, 100, 1 << 10, (1 << 14) + 3, 1 << 18, (1 << 20) + 5, 1 << 23, 3 << 21])
+    got = tune.hash_bits_for_sizes(sizes, CACHE)
+    assert got.tolist() == [tune.hash_bits_for(int(n), CACHE) for n in sizes]
+    assert tune.hash_bits_for_sizes(sizes, {}).tolist() == [-1] * len(sizes)
+
+
+def test_packed_job_table_checks_offsets():
+    import numpy as np
+    import pytest
+    import torch
+    from paper_1904_11201_amd import join as J
+    k = torch.zeros(10, dtype=torch.int32)
+    for roffs, soffs in (([0, 5, 4, 10], [0, 3, 6, 10]),   # falling
+                         ([0, 5, 9], [0, 5, 10]),          # does not end at the length
+                         ([1, 5, 10], [0, 5, 10]),         # does not start at 0
+                         ([0, 5, 10], [0, 10])):           # sides disagree on the join count
+        with pytest.raises(ValueError):
+            J._packed_array(k, np.array(roffs), k, np.array(soffs))
