@@ -1024,10 +1024,11 @@ __device__ __forceinline__ uint32_t next_bucket(uint32_t b, uint32_t nb) { retur
 
 // The two candidate buckets of hash h.  The partition id took the top `bits` bits of h, so b1
 // comes from the bits below it and b2 from a multiplicative remix of all of h.
+// (bits <= kMaxBits < 32.)
 __device__ __forceinline__ void choices(uint32_t h, int bits, uint32_t nb, uint32_t& b1, uint32_t& b2)
 {
-    b1 = (uint32_t)(((uint64_t)(bits >= 32 ? 0u : (h << bits)) * nb) >> 32);
-    b2 = (uint32_t)(((uint64_t)(h * 0x9E3779B1u) * nb) >> 32);
+    b1 = __umulhi(h << bits, nb);
+    b2 = __umulhi(h * 0x9E3779B1u, nb);
     b2 = b2 == b1 ? next_bucket(b1, nb) : b2;
 }
 
@@ -1193,6 +1194,18 @@ __device__ __forceinline__ uint32_t hits(const uint4& k, uint32_t c, uint32_t x)
     else return bucket_hits(k, c, x);
 }
 
+// The number of matches of x in a bucket (the popcount of hits), as a sum of comparisons.
+template <bool MARKED>
+__device__ __forceinline__ uint32_t hit_count(const uint4& k, uint32_t c, uint32_t x)
+{
+    if constexpr (MARKED)
+        return (uint32_t)(k.x == x) + (uint32_t)(k.y == x) + (uint32_t)(k.z == x) +
+               (uint32_t)(((k.w ^ x) & ~kOverflow) == 0u);
+    else
+        return (uint32_t)(k.x == x && c > 0) + (uint32_t)(k.y == x && c > 1) + (uint32_t)(k.z == x && c > 2) +
+               (uint32_t)(k.w == x && c > 3);
+}
+
 // Whether a bucket holds more than 4 claims, so that lookups go on past it.  In a marked table x
 // (a hash of the partition) tells the fourth key's true bit 30.
 template <bool MARKED>
@@ -1223,10 +1236,13 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 // entries (the write pass then puts the table's entries in canonical order before it emits
 // them; keys with fewer entries are ordered as they are emitted); `many` adds up the entries
 // of keys with more than two (the write pass places their pairs apart).
-template <int N, bool HASHED, bool MARKED>
+template <int N, bool HASHED, bool MARKED, bool FULL>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
-                                                const bool (&valid)[N], bool& multi, uint32_t& many)
+                                                const bool (&valid_in)[N], bool& multi, uint32_t& many)
 {
+    bool valid[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) valid[i] = FULL || valid_in[i];  // FULL: every key is in range
     uint32_t b1[N], b2[N], c1[N], c2[N];
     uint4 k1[N], k2[N];
 #pragma unroll
@@ -1242,9 +1258,8 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
     bool walk[N], any = false;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        h[i] = valid[i] ? __builtin_popcount(hits<MARKED>(k1[i], c1[i], x[i])) +
-                              __builtin_popcount(hits<MARKED>(k2[i], c2[i], x[i]))
-                        : 0u;
+        h[i] = hit_count<MARKED>(k1[i], c1[i], x[i]) + hit_count<MARKED>(k2[i], c2[i], x[i]);
+        if (!FULL) h[i] = valid[i] ? h[i] : 0u;
         walk[i] = valid[i] && overflowed<MARKED>(k1[i], c1[i], x[i]) && overflowed<MARKED>(k2[i], c2[i], x[i]);
         any = any || walk[i];
     }
@@ -1602,10 +1617,10 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // batch's loads alone, never for the loads issued after them.
 // A batch's matches fit 32 bits (kCountBatch keys of at most kMaxCap entries each); the lane's
 // total over a unit is kept in 64 bits.
-template <bool AOS, bool MARKED>
-__device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
-                                                const uint32_t (&xs)[kCountBatch], bool& multi,
-                                                uint32_t& many)
+template <bool AOS, bool MARKED, bool FULL>
+__device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& un, uint32_t e0,
+                                                   const uint32_t (&xs)[kCountBatch], bool& multi,
+                                                   uint32_t& many)
 {
     uint32_t cnt = 0;
 #pragma unroll
@@ -1617,9 +1632,20 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
             x[i] = xs[h + i];
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
-        cnt += probe_count<kProbe, AOS, MARKED>(t, un.bits, x, ok, multi, many);
+        cnt += probe_count<kProbe, AOS, MARKED, FULL>(t, un.bits, x, ok, multi, many);
     }
     return cnt;
+}
+
+// A batch wholly inside the unit (the common case) probes without per-key range checks.
+template <bool AOS, bool MARKED>
+__device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
+                                                const uint32_t (&xs)[kCountBatch], bool& multi,
+                                                uint32_t& many)
+{
+    if (e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN)  // uniform
+        return count_batch_of<AOS, MARKED, true>(t, un, e0, xs, multi, many);
+    return count_batch_of<AOS, MARKED, false>(t, un, e0, xs, multi, many);
 }
 
 // Each wave of the count and write passes takes the same probe tuples of a unit: those at
