@@ -18,6 +18,7 @@
 
 #include "prof.hpp"
 #include "scan.hpp"
+#include "tune.hpp"
 
 namespace jl {
 
@@ -25,9 +26,18 @@ namespace {
 
 constexpr int kBlock = 1024;
 
-__device__ __forceinline__ uint32_t filter_bit(int32_t key, int logm)
+// A blocked filter with two bits per key: both in one 32-bit word.  The word index takes the top
+// bits of the key hash, the two bit positions its lowest ten bits (independent of the top ones
+// while the filter has at most 2^24 bits).  At 16 bits per key this leaves about 1.4% false
+// positives, where one bit per key leaves about 6%, for the same one word read per lookup.
+struct FilterSlot {
+    uint32_t word, mask;
+};
+
+__device__ __forceinline__ FilterSlot filter_slot(int32_t key, int logm)
 {
-    return hmix((uint32_t)key) >> (32 - logm);
+    const uint32_t h = hmix((uint32_t)key);
+    return FilterSlot{h >> (32 - (logm - 5)), (1u << (h & 31)) | (1u << ((h >> 5) & 31))};
 }
 
 __global__ void zero_words_k(uint32_t* __restrict__ p, int64_t n)
@@ -40,16 +50,69 @@ __global__ __launch_bounds__(kBlock) void set_bits_k(const int32_t* __restrict__
                                                      uint32_t* __restrict__ filter, int logm)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const uint32_t b = filter_bit(key[i], logm);
-        atomicOr(&filter[b >> 5], 1u << (b & 31));
+        const FilterSlot f = filter_slot(key[i], logm);
+        atomicOr(&filter[f.word], f.mask);
     }
 }
 
-// Keeps the rows whose bit is set in the other relation's filter.  A workgroup takes kPer rows
-// per thread per round; waves count their survivors with ballots, one thread reserves the
-// workgroup's range of the output with one global atomic, and every wave writes its survivors
-// at its offset inside that range.
+// One round of a compaction: kPer rows per thread (all loads, then all filter reads, in flight
+// together) and the ballots of the rows that pass.
 constexpr int kPer = 8;
+
+struct Round {
+    int32_t k[kPer], r[kPer];
+    uint64_t m[kPer];
+    uint32_t count;  // wave-uniform: rows of this wave that pass
+};
+
+__device__ __forceinline__ void round_of(const int32_t* __restrict__ key, const int32_t* __restrict__ rid,
+                                         int64_t base, int64_t end, const uint32_t* __restrict__ filter,
+                                         int logm, Round& rd)
+{
+    uint32_t fw[kPer];
+    FilterSlot fs[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
+        rd.k[q] = i < end ? key[i] : 0;
+        rd.r[q] = i < end ? (rid ? rid[i] : (int32_t)i) : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        fs[q] = filter_slot(rd.k[q], logm);
+        fw[q] = filter[fs[q].word];
+    }
+    rd.count = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
+        rd.m[q] = ballot(i < end && (fw[q] & fs[q].mask) == fs[q].mask);
+        rd.count += (uint32_t)__builtin_popcountll(rd.m[q]);
+    }
+}
+
+// This wave's passing rows of a round, the first `skip` of them left out, the next `take` written
+// from out position at on (in (q, lane) order).
+__device__ __forceinline__ void put_round(const Round& rd, uint32_t skip, uint32_t take, uint32_t at,
+                                          int32_t* __restrict__ okey, int32_t* __restrict__ orid)
+{
+    uint32_t before = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t j = before + mask_rank(rd.m[q]);  // this lane's rank among the passing rows
+        if (((rd.m[q] >> lane_id()) & 1u) && j >= skip && j < skip + take) {
+            okey[at + j - skip] = rd.k[q];
+            orid[at + j - skip] = rd.r[q];
+        }
+        before += (uint32_t)__builtin_popcountll(rd.m[q]);
+    }
+}
+
+// Arrival-order compaction: waves append their passing rows to a workgroup stage in LDS (one LDS
+// atomic per wave and round, no barrier), and the workgroup writes the stage out in one
+// coalesced run at the end, reserved with one global atomic.  Rows that find the stage full go
+// straight out with a global atomic of their wave.
+constexpr int kStage = 8192;
 
 __global__ __launch_bounds__(kBlock) void compact_k(const int32_t* __restrict__ key,
                                                     const int32_t* __restrict__ rid, int64_t n,
@@ -57,56 +120,67 @@ __global__ __launch_bounds__(kBlock) void compact_k(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ okey, int32_t* __restrict__ orid,
                                                     uint32_t* __restrict__ counter)
 {
-    __shared__ uint32_t wtot[kBlock / kWave];
-    __shared__ uint32_t gbase;
-    const int wv = threadIdx.x / kWave;
+    __shared__ int32_t sk[kStage], sr[kStage];
+    __shared__ uint32_t sn, gbase;
+    if (threadIdx.x == 0) sn = 0;
+    __syncthreads();
     const int64_t step = (int64_t)kBlock * kPer;
     for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += (int64_t)gridDim.x * step) {
-        int32_t k[kPer], r[kPer];
-        uint32_t fw[kPer];
-        uint64_t m[kPer];
-        uint32_t mine = 0;
-        // all key and rid loads first, then all filter reads, then the ballots: every load of
-        // the round is in flight together
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
-            k[q] = i < n ? key[i] : 0;
-            r[q] = i < n ? (rid ? rid[i] : (int32_t)i) : 0;
+        Round rd;
+        round_of(key, rid, base, n, filter, logm, rd);
+        if (rd.count == 0) continue;  // uniform
+        uint32_t at = 0;
+        if (lane_id() == 0) at = atomicAdd(&sn, rd.count);
+        at = uniform(__shfl(at, 0));
+        const uint32_t staged = at >= (uint32_t)kStage ? 0u : min(rd.count, (uint32_t)kStage - at);
+        if (staged) put_round(rd, 0, staged, at, sk, sr);
+        if (staged < rd.count) {  // uniform: the stage is full
+            uint32_t g = 0;
+            if (lane_id() == 0) g = atomicAdd(counter, rd.count - staged);
+            put_round(rd, staged, rd.count - staged, uniform(__shfl(g, 0)), okey, orid);
         }
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) fw[q] = filter[filter_bit(k[q], logm) >> 5];
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
-            const bool keep = i < n && ((fw[q] >> (filter_bit(k[q], logm) & 31)) & 1u);
-            m[q] = ballot(keep);
-            mine += (uint32_t)__builtin_popcountll(m[q]);
-        }
-        if (lane_id() == 0) wtot[wv] = mine;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                const uint32_t c = wtot[w];
-                wtot[w] = t;
-                t += c;
-            }
-            gbase = t ? atomicAdd(counter, t) : 0u;
-        }
-        __syncthreads();
-        uint32_t at = gbase + wtot[wv];
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            if ((m[q] >> lane_id()) & 1u) {
-                const uint32_t pos = at + mask_rank(m[q]);
-                okey[pos] = k[q];
-                orid[pos] = r[q];
-            }
-            at += (uint32_t)__builtin_popcountll(m[q]);
-        }
-        __syncthreads();  // wtot and gbase are reused by the next round
     }
+    __syncthreads();
+    const uint32_t ns = min(sn, (uint32_t)kStage);
+    if (threadIdx.x == 0) gbase = ns ? atomicAdd(counter, ns) : 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ns; i += kBlock) {
+        okey[gbase + i] = sk[i];
+        orid[gbase + i] = sr[i];
+    }
+}
+
+// Ordered compaction (the deterministic option): workgroup b takes rows [b * per, (b + 1) * per)
+// and places its passing rows in (round, wave, q, lane) order.  WRITE = false counts them into
+// counts[b]; WRITE = true writes them from offsets[b] (the exclusive scan of the counts).
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void compact_ordered_k(const int32_t* __restrict__ key,
+                                                            const int32_t* __restrict__ rid, int64_t n,
+                                                            int64_t per, const uint32_t* __restrict__ filter,
+                                                            int logm, uint32_t* __restrict__ counts,
+                                                            int32_t* __restrict__ okey, int32_t* __restrict__ orid)
+{
+    __shared__ uint32_t wtot[kBlock / kWave];
+    const int wv = threadIdx.x / kWave;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    uint32_t run = WRITE ? counts[blockIdx.x] : 0u;
+    for (int64_t base = b0; base < b1; base += (int64_t)kBlock * kPer) {
+        Round rd;
+        round_of(key, rid, base, b1, filter, logm, rd);
+        if (lane_id() == 0) wtot[wv] = rd.count;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            const uint32_t c = wtot[w];
+            before += w < wv ? c : 0u;
+            tot += c;
+        }
+        if (WRITE && rd.count) put_round(rd, 0, rd.count, run + before, okey, orid);
+        run += tot;
+        __syncthreads();  // wtot is reused by the next round
+    }
+    if (!WRITE && threadIdx.x == 0) counts[blockIdx.x] = run;
 }
 
 constexpr int kMinLog = 16, kMaxLog = 24;
@@ -136,7 +210,12 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
         off = (off + b + 255) & ~(size_t)255;
         return at;
     };
+    pl.ordered = tune_get(TUNE_HASH_DETERMINISTIC, 0) != 0 ? 1 : 0;
+    pl.grid = num_cus * 8;
     pl.off_cnt = take(8);
+    // the ordered compaction's per-workgroup counts (then offsets) and its scan's storage
+    pl.off_wcnt = take(pl.ordered ? (size_t)pl.grid * 4 : 0);
+    pl.off_wtmp = take(pl.ordered ? scan_temp_elems<uint32_t>(pl.grid) * 4 : 0);
     pl.off_fR = take(pl.logR ? ((size_t)1 << pl.logR) / 8 : 0);
     pl.off_fS = take(pl.logS ? ((size_t)1 << pl.logS) / 8 : 0);
     // R is compacted when S has a filter, S when R has one
@@ -151,7 +230,7 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
     pl.inner_bytes = hash_plan(nR, nS, num_cus).bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 * 2 + 4096;
     pl.off_inner = take(pl.inner_bytes);
     pl.bytes = off;
-    pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.logR, pl.logS, (int64_t)pl.inner_bytes,
+    pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.logR, pl.logS, pl.ordered, pl.grid, (int64_t)pl.inner_bytes,
                            (int64_t)hash_plan(nR, nS, num_cus).stamp, (int64_t)pl.bytes});
     return pl;
 }
@@ -167,6 +246,16 @@ static void survivors(const PrefilterPlan& pl, char* ws, const uint32_t* n, cons
                                reinterpret_cast<const int32_t*>(ws + pl.off_rS), (int64_t)n[1]}
                   : S;
 }
+
+// The surviving sizes the last count pass on this thread read, with the workspace and plan they
+// belong to: the write pass that follows on the same thread plans from them without a second
+// host read (the caller keeps ws and the inputs unchanged between the two).
+struct SizesSeen {
+    const char* ws;
+    uint64_t stamp;
+    uint32_t n[2];
+};
+static thread_local SizesSeen g_seen{nullptr, 0, {0, 0}};
 
 static hipError_t read_sizes(const PrefilterPlan& pl, char* ws, hipStream_t st, uint32_t* n)
 {
@@ -206,22 +295,36 @@ hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const j
     if (e != hipSuccess) return e;
     {
         prof::Scope pc(st, "prefilter.compact");
-        if (pl.logS)
-            compact_k<<<grid, kBlock, 0, st>>>(R.key, R.rid, R.n, fS, pl.logS,
-                                               reinterpret_cast<int32_t*>(ws + pl.off_kR),
-                                               reinterpret_cast<int32_t*>(ws + pl.off_rR), cnt);
-        if (pl.logR)
-            compact_k<<<grid, kBlock, 0, st>>>(S.key, S.rid, S.n, fR, pl.logR,
-                                               reinterpret_cast<int32_t*>(ws + pl.off_kS),
-                                               reinterpret_cast<int32_t*>(ws + pl.off_rS), cnt + 1);
+        auto compact = [&](const join_rel_t& X, const uint32_t* f, int logm, size_t off_k, size_t off_r,
+                           uint32_t* total) -> hipError_t {
+            int32_t* ok = reinterpret_cast<int32_t*>(ws + off_k);
+            int32_t* orr = reinterpret_cast<int32_t*>(ws + off_r);
+            if (!pl.ordered) {
+                compact_k<<<(unsigned)pl.grid, kBlock, 0, st>>>(X.key, X.rid, X.n, f, logm, ok, orr, total);
+                return hipGetLastError();
+            }
+            uint32_t* wc = reinterpret_cast<uint32_t*>(ws + pl.off_wcnt);
+            const int64_t per = (X.n + pl.grid - 1) / pl.grid;
+            compact_ordered_k<false><<<(unsigned)pl.grid, kBlock, 0, st>>>(X.key, X.rid, X.n, per, f, logm, wc,
+                                                                          nullptr, nullptr);
+            hipError_t r = hipGetLastError();
+            if (r == hipSuccess)
+                r = exclusive_scan<uint32_t>(wc, wc, pl.grid, total, reinterpret_cast<uint32_t*>(ws + pl.off_wtmp), st);
+            if (r != hipSuccess) return r;
+            compact_ordered_k<true><<<(unsigned)pl.grid, kBlock, 0, st>>>(X.key, X.rid, X.n, per, f, logm, wc, ok, orr);
+            return hipGetLastError();
+        };
+        if (pl.logS) e = compact(R, fS, pl.logS, pl.off_kR, pl.off_rR, cnt);
+        if (e == hipSuccess && pl.logR) e = compact(S, fR, pl.logR, pl.off_kS, pl.off_rS, cnt + 1);
     }
-    e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t n[2] = {0, 0};
     if (pl.logR || pl.logS) {
         e = read_sizes(pl, ws, st, n);
         if (e != hipSuccess) return e;
     }
+    g_seen = SizesSeen{ws, pl.stamp, {n[0], n[1]}};
     join_rel_t R2, S2;
     survivors(pl, ws, n, R, S, &R2, &S2);
     char* inner = ws + pl.off_inner;
@@ -242,7 +345,10 @@ hipError_t prefilter_write(const PrefilterPlan& pl, const join_rel_t& R, const j
                            char* ws, int32_t* pairs, uint64_t cap, hipStream_t st, int num_cus)
 {
     uint32_t n[2] = {0, 0};
-    if (pl.logR || pl.logS) {
+    if (g_seen.ws == ws && g_seen.stamp == pl.stamp) {
+        n[0] = g_seen.n[0];
+        n[1] = g_seen.n[1];
+    } else if (pl.logR || pl.logS) {
         hipError_t e = read_sizes(pl, ws, st, n);
         if (e != hipSuccess) return e;
     }

@@ -9,6 +9,9 @@ namespace jl {
 struct PrefilterPlan {
     int64_t nR, nS;
     int logR, logS;          // log2 of the filter sizes in bits (of R, of S); 0 = no filter
+    int ordered;             // 1: compaction in input order (deterministic option), else arrival order
+    int grid;                // compaction workgroups
+    uint64_t off_wcnt, off_wtmp;  // ordered compaction: per-workgroup counts, scan storage
     uint64_t off_cnt;        // 2 uint32: surviving R rows, surviving S rows
     uint64_t off_fR, off_fS; // the two bit filters
     uint64_t off_kR, off_rR, off_kS, off_rS;  // compacted columns (key, rid)

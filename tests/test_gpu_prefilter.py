@@ -58,3 +58,28 @@ def test_duplicates_and_extreme_keys():
     R = datagen.Rel(key=rk.astype(np.int32), rid=g.integers(-2**31, 2**31 - 1, len(rk), dtype=np.int64).astype(np.int32))
     S = datagen.Rel(key=sk.astype(np.int32))
     _check(R, S, "duplicates and int32 extremes")
+
+
+@gpu
+def test_full_stages_and_the_ordered_compaction(monkeypatch):
+    """Every probe key passes (more passing rows per workgroup than its LDS stage holds, so
+    waves write straight out), then the same join and a 1%-match one with the deterministic
+    option: the ordered compaction gives the same output array on two runs, and the oracle's
+    pairs."""
+    need_gpu()
+    import torch
+    from paper_1904_11201_amd.join import hash_join
+    g = datagen.rng_for(83)
+    R = datagen.Rel(key=np.arange(100_000, dtype=np.int32), rid=g.permutation(100_000).astype(np.int32))
+    S = datagen.Rel(key=datagen.uniform_keys(g, 24_000_000, 0, 100_000), rid=None)
+    _check(R, S, "all of 24M probes pass")
+    R2 = datagen.Rel(key=np.arange(0, 10_000_000, 100, dtype=np.int32), rid=None)
+    S2 = datagen.Rel(key=datagen.uniform_keys(g, 5_000_000, 0, 10_000_000), rid=g.permutation(5_000_000).astype(np.int32))
+    monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
+    for X, Y, label in ((R, S, "all pass, ordered"), (R2, S2, "1% match, ordered")):
+        _check(X, Y, label)
+        dX, dY = dev_rel(X), dev_rel(Y)
+        a = hash_join(dX, dY, prefilter=True)
+        b = hash_join(dX, dY, prefilter=True)
+        torch.cuda.synchronize()
+        assert a.shape == b.shape and torch.equal(a, b), label
