@@ -1238,7 +1238,8 @@ __device__ __forceinline__ void walk_on(const Table& t, uint32_t x, uint32_t b1,
 // of keys with more than two (the write pass places their pairs apart).
 template <int N, bool HASHED, bool MARKED, bool FULL>
 __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const uint32_t (&x)[N],
-                                                const bool (&valid_in)[N], bool& multi, uint32_t& many)
+                                                const bool (&valid_in)[N], bool& multi, uint32_t& many,
+                                                uint32_t (&hout)[N])
 {
     bool valid[N];
 #pragma unroll
@@ -1274,6 +1275,7 @@ __device__ __forceinline__ uint32_t probe_count(const Table& t, int bits, const 
         n += h[i];
         many += h[i] > 2 ? h[i] : 0u;
         multi = multi || h[i] > (uint32_t)kEmitSort;
+        hout[i] = h[i];
     }
     return n;
 }
@@ -1617,35 +1619,61 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // batch's loads alone, never for the loads issued after them.
 // A batch's matches fit 32 bits (kCountBatch keys of at most kMaxCap entries each); the lane's
 // total over a unit is kept in 64 bits.
-template <bool AOS, bool MARKED, bool FULL>
+// The probe rows of a wave that have matches (the semi-join), recorded by the count pass when
+// the write pass is to visit only them: the k-th such row of wave wv in a unit is stored, as its
+// index in the partitioned probe tuples, at the place of the wave's k-th own row
+// (unit start + (k / 64) * kJoinBlock + wv * 64 + k % 64), which lies inside the unit because
+// the wave has at least k + 1 rows there.
+struct Semi {
+    uint32_t* rows;  // [probe rows]
+    uint32_t sBeg;   // the unit's first probe row
+    uint32_t k;      // uniform: matching rows of this wave in the unit so far
+};
+
+__device__ __forceinline__ uint32_t semi_slot(uint32_t sBeg, uint32_t k, int wv)
+{
+    return sBeg + (k / kWave) * kJoinBlock + (uint32_t)wv * kWave + (k % kWave);
+}
+
+template <bool AOS, bool MARKED, bool FULL, bool SEMI>
 __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& un, uint32_t e0,
                                                    const uint32_t (&xs)[kCountBatch], bool& multi,
-                                                   uint32_t& many)
+                                                   uint32_t& many, Semi& sm)
 {
     uint32_t cnt = 0;
 #pragma unroll
     for (int h = 0; h < kCountBatch; h += kProbe) {
-        uint32_t x[kProbe];
+        uint32_t x[kProbe], hv[kProbe];
         bool ok[kProbe];
 #pragma unroll
         for (int i = 0; i < kProbe; ++i) {
             x[i] = xs[h + i];
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
-        cnt += probe_count<kProbe, AOS, MARKED, FULL>(t, un.bits, x, ok, multi, many);
+        cnt += probe_count<kProbe, AOS, MARKED, FULL>(t, un.bits, x, ok, multi, many, hv);
+        if constexpr (SEMI) {
+            const int wv = (int)(threadIdx.x / kWave);
+#pragma unroll
+            for (int i = 0; i < kProbe; ++i) {
+                const bool hit = hv[i] > 0;  // zero for rows past the unit
+                const uint64_t bm = ballot(hit);
+                if (hit) sm.rows[semi_slot(sm.sBeg, sm.k + mask_rank(bm), wv)] = un.sBeg + e0 + (h + i) * kJoinBlock + threadIdx.x;
+                sm.k += (uint32_t)__builtin_popcountll(bm);
+            }
+        }
     }
     return cnt;
 }
 
 // A batch wholly inside the unit (the common case) probes without per-key range checks.
-template <bool AOS, bool MARKED>
+template <bool AOS, bool MARKED, bool SEMI>
 __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
                                                 const uint32_t (&xs)[kCountBatch], bool& multi,
-                                                uint32_t& many)
+                                                uint32_t& many, Semi& sm)
 {
     if (e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN)  // uniform
-        return count_batch_of<AOS, MARKED, true>(t, un, e0, xs, multi, many);
-    return count_batch_of<AOS, MARKED, false>(t, un, e0, xs, multi, many);
+        return count_batch_of<AOS, MARKED, true, SEMI>(t, un, e0, xs, multi, many, sm);
+    return count_batch_of<AOS, MARKED, false, SEMI>(t, un, e0, xs, multi, many, sm);
 }
 
 // Each wave of the count and write passes takes the same probe tuples of a unit: those at
@@ -1664,10 +1692,12 @@ constexpr size_t kWriteStaticLds = (size_t)kJoinWaves * kManyQ * 16;
 static_assert(table_lds(kMaxCap, true) + kWriteStaticLds <= 160 * 1024, "write pass LDS");
 
 // End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u],
-// the waves' starts in wave_off[u][1..kJoinWaves) and each wave's count of pairs before its
-// block of many-match pairs in wave_off[u][kJoinWaves + w]; sh: kJoinWaves + 1 words of LDS.
-__device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi, uint32_t u,
-                                            uint64_t* __restrict__ counts,
+// the waves' starts in wave_off[u][1..kJoinWaves) and, in wave_off[u][kJoinWaves + w], each
+// wave's count of pairs before its block of many-match pairs (low 32 bits: at most two pairs per
+// probe row of the wave) and its count of probe rows with matches when the semi-join is recorded
+// (high 32 bits, else 0); sh: kJoinWaves + 1 words of LDS.
+__device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi,
+                                            uint32_t semi_rows, uint32_t u, uint64_t* __restrict__ counts,
                                             uint64_t* __restrict__ wave_off, uint64_t* sh)
 {
     const uint64_t wt = wave_sum64(lane_total);
@@ -1676,7 +1706,7 @@ __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_m
     const int wv = threadIdx.x / kWave;
     if (lane_id() == 0) {
         sh[wv] = wt | (wm ? (1ull << 63) : 0ull);
-        wave_off[(size_t)u * kWaveRec + kJoinWaves + wv] = wt - wmany;
+        wave_off[(size_t)u * kWaveRec + kJoinWaves + wv] = (wt - wmany) | ((uint64_t)semi_rows << 32);
     }
     __syncthreads();
     if (threadIdx.x < kJoinWaves) {
@@ -1739,7 +1769,7 @@ __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, ui
 // done: NULL, or a zeroed arrival counter; then the last workgroup to arrive scans the counts
 // (Umax <= kFuseScanMax) and writes the sum to *total and, when pub is not NULL, to that pinned
 // host slot.
-template <bool AOS>
+template <bool AOS, bool SEMI>
 __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
                                            uint64_t* __restrict__ wave_off,
                                            uint32_t* __restrict__ done, uint64_t* __restrict__ total,
@@ -1766,23 +1796,24 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         const Unit nx = more ? decode_unit<AOS>(g, u + gridDim.x) : Unit{};
         uint64_t cnt = 0, many = 0;
         bool multi = false;
+        Semi sm{g.semi, un.sBeg, 0u};
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
             for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
                 const uint32_t e1 = e0 + kB, e2 = e1 + kB;
                 uint32_t ma = 0, mb = 0;
                 load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
-                cnt += count_batch<AOS, M>(t, un, e0, xa, multi, ma);
+                cnt += count_batch<AOS, M, SEMI>(t, un, e0, xa, multi, ma, sm);
                 const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
                 load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
-                cnt += count_batch<AOS, M>(t, un, e1, xb, multi, mb);  // every lane masked past the unit
+                cnt += count_batch<AOS, M, SEMI>(t, un, e1, xb, multi, mb, sm);  // every lane masked past the unit
                 many += (uint64_t)ma + mb;
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
-        unit_totals(cnt, many, multi, u, counts, wave_off, wsum);
+        unit_totals(cnt, many, multi, sm.k, u, counts, wave_off, wsum);
         un = nx;
     }
     if (done) {
@@ -1829,7 +1860,7 @@ __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint6
 // join, round robin for batches); each wave writes the pairs of its probe tuples from the
 // start the count pass recorded for it, in (batch, tuple, lane) order, with one wave-wide scan
 // per round and no shared cursor: the output depends on the input and the plan only.
-template <bool AOS>
+template <bool AOS, bool SEMI>
 __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restrict__ offsets,
                                            const uint64_t* __restrict__ wave_off,
                                            const uint64_t* __restrict__ total,
@@ -1863,7 +1894,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     if (u0 < u1) {
         un = decode_unit<AOS>(g, u0);
         load_chunk<AOS, true>(g, un, ch);
-        load_tuples<AOS>(g, un, 0, nx, nr);
+        if constexpr (!SEMI) load_tuples<AOS>(g, un, 0, nx, nr);
     }
     Unit tu{};  // the unit whose chunk is in the table (rN == 0: none yet)
     const cptr<uint64_t> offs = as_const(offsets);
@@ -1882,7 +1913,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         }
         // this wave's first output slot in unit u, and the start of its block of many-match pairs
         uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kWaveRec + wv]) : 0ull);
-        uint64_t cmany = cursor + uniform(wo[(size_t)u * kWaveRec + kJoinWaves + wv]);
+        const uint64_t wrec = uniform(wo[(size_t)u * kWaveRec + kJoinWaves + wv]);
+        uint64_t cmany = cursor + (uint32_t)wrec;
+        const uint32_t semi_rows = (uint32_t)(wrec >> 32);  // the semi-join's rows of this wave
 #if JL_DEBUG
         const uint64_t cursor0 = cursor, cmany0 = cmany;
 #endif
@@ -1892,18 +1925,9 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
-            for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
-                uint32_t cx[kWriteLoad];
-                int32_t cr[kWriteLoad];
-#pragma unroll
-                for (int i = 0; i < kWriteLoad; ++i) {
-                    cx[i] = nx[i];
-                    cr[i] = nr[i];
-                }
-                if (e0 + kJoinBlock * kWriteLoad < un.sN)
-                    load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
-                else if (more)
-                    load_tuples<AOS>(g, nxt, 0, nx, nr);
+            // kWriteLoad probe tuples per lane (lanes and tuples in range where ok_of(j) holds):
+            // probed kWriteBatch at a time, pairs written
+            auto round = [&](const uint32_t (&cx)[kWriteLoad], const int32_t (&cr)[kWriteLoad], auto ok_of) {
 #pragma unroll
                 for (int h = 0; h < kWriteLoad; h += kWriteBatch) {
                     uint32_t x[kWriteBatch], m[kWriteBatch], p1[kWriteBatch], p2[kWriteBatch];
@@ -1913,7 +1937,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                     for (int i = 0; i < kWriteBatch; ++i) {
                         x[i] = cx[h + i];
                         srid[i] = cr[h + i];
-                        ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+                        ok[i] = ok_of(h + i);
                     }
                     probe_write<kWriteBatch, AOS, M>(t, un.bits, x, ok, m, p1, p2);
                     // Slots of probes with one or two matches: the wave's cursor plus an
@@ -1951,6 +1975,37 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                     }
                     cursor += wtot;
                 }
+            };
+            if constexpr (SEMI) {
+                // only this wave's probe rows with matches, as the count pass recorded them
+                for (uint32_t k0 = 0; k0 < semi_rows; k0 += kWave * kWriteLoad) {  // wave-uniform
+                    uint32_t cx[kWriteLoad];
+                    int32_t cr[kWriteLoad];
+#pragma unroll
+                    for (int j = 0; j < kWriteLoad; ++j) {
+                        const uint32_t k = k0 + j * kWave + lane_id();
+                        const uint32_t row = g.semi[semi_slot(un.sBeg, k < semi_rows ? k : 0u, wv)];
+                        const int2 tp = g.st[row];
+                        cx[j] = (uint32_t)tp.x;
+                        cr[j] = tp.y;
+                    }
+                    round(cx, cr, [&](int j) { return k0 + j * kWave + lane_id() < semi_rows; });
+                }
+            } else {
+                for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
+                    uint32_t cx[kWriteLoad];
+                    int32_t cr[kWriteLoad];
+#pragma unroll
+                    for (int i = 0; i < kWriteLoad; ++i) {
+                        cx[i] = nx[i];
+                        cr[i] = nr[i];
+                    }
+                    if (e0 + kJoinBlock * kWriteLoad < un.sN)
+                        load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
+                    else if (more)
+                        load_tuples<AOS>(g, nxt, 0, nx, nr);
+                    round(cx, cr, [&](int j) { return e0 + j * kJoinBlock + threadIdx.x < un.sN; });
+                }
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
@@ -1965,7 +2020,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         if (g.dbg && lane_id() == 0 && wrote > 0)
             atomicAdd(reinterpret_cast<unsigned long long*>(&g.dbg[u]), (unsigned long long)wrote);
 #endif
-        if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
+        if constexpr (!SEMI)
+            if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
         __syncthreads();
         un = nxt;
     }
@@ -2005,7 +2061,7 @@ static int env_cap()
     return (int)cap;
 }
 
-HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool semi)
 {
     HashPlan pl{};
     pl.nR = nR;
@@ -2097,6 +2153,9 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     }
     pl.off_temp = off;
     off = align_up(off + temp + 8);
+    pl.semi = semi && !pl.single ? 1 : 0;
+    pl.off_semi = off;  // the semi-join's probe rows: one slot per probe row
+    off = align_up(off + (pl.semi ? (size_t)nS * 4 : 0));
     pl.off_dbg = off;  // last: the checking build's per-unit written counts
     off = align_up(off + (JL_DEBUG ? (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8 : 0));
     pl.bytes = off;
@@ -2109,7 +2168,7 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits)
     };
     pl.gridCount = grid_for(false);
     pl.gridWrite = grid_for(true);
-    pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.ordered, pl.bits, pl.P, pl.cap,
+    pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.ordered, pl.semi, pl.bits, pl.P, pl.cap,
                            pl.slice, pl.nSs, pl.chR, pl.chS, pl.Umax, pl.gridCount, pl.gridWrite,
                            (int64_t)pl.bytes});
     return pl;
@@ -2125,13 +2184,15 @@ static hipError_t set_attrs()
     const void* fns[] = {
         (const void*)scatter_k<true, false>, (const void*)scatter_k<false, false>,
         (const void*)scatter_k<true, true>, (const void*)scatter_k<false, true>, (const void*)hist_k,
-        (const void*)join_count_k<true>, (const void*)join_count_k<false>,
+        (const void*)join_count_k<true, false>, (const void*)join_count_k<false, false>,
+        (const void*)join_count_k<true, true>,
     };
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
         if (e != hipSuccess) return e;
     }
-    for (const void* f : {(const void*)join_write_k<true>, (const void*)join_write_k<false>}) {
+    for (const void* f : {(const void*)join_write_k<true, false>, (const void*)join_write_k<false, false>,
+                          (const void*)join_write_k<true, true>}) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, write_max);
         if (e != hipSuccess) return e;
     }
@@ -2324,6 +2385,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
     g.stamp_at = reinterpret_cast<uint64_t*>(ws + kStampOffset);
     g.stamp = pl.stamp;
     g.dbg = JL_DEBUG ? reinterpret_cast<uint64_t*>(ws + pl.off_dbg) : nullptr;
+    g.semi = pl.semi ? reinterpret_cast<uint32_t*>(ws + pl.off_semi) : nullptr;
     if (pl.single) {
         g.single = 1;
         g.rk = R.key;
@@ -2429,8 +2491,9 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
                              ? reinterpret_cast<uint32_t*>(ws + pl.off_done) : nullptr;
         uint64_t* wave_off = reinterpret_cast<uint64_t*>(ws + pl.off_wave);
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, nullptr, total, nullptr);
-        else join_count_k<true><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
+        if (pl.single) join_count_k<false, false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, nullptr, total, nullptr);
+        else if (pl.semi) join_count_k<true, true><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
+        else join_count_k<true, false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
         e = hipGetLastError();
         if (e != hipSuccess || done) return e;
     }
@@ -2452,8 +2515,9 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     const size_t lds = table_lds((uint32_t)pl.cap, true);
     int2* out = reinterpret_cast<int2*>(pairs);
     prof::Scope pw(st, "hash.write");
-    if (pl.single) join_write_k<false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
-    else join_write_k<true><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    if (pl.single) join_write_k<false, false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    else if (pl.semi) join_write_k<true, true><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    else join_write_k<true, false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
     return hipGetLastError();
 }
 
@@ -2764,7 +2828,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
         prof::Scope pc(st, "hash.count");
-        join_count_k<true><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(
+        join_count_k<true, false><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(
             g, counts, reinterpret_cast<uint64_t*>(ws + bp.off_wave), nullptr, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2786,7 +2850,7 @@ hipError_t hash_batch_write(const BatchPlan& bp, char* ws, int32_t* pairs, uint6
     if (e != hipSuccess) return e;
     const JoinGeom g = batch_geom(bp, ws);
     prof::Scope pw(st, "hash.write");
-    join_write_k<true><<<(unsigned)bp.gridWrite, kJoinBlock, table_lds((uint32_t)bp.cap, true), st>>>(
+    join_write_k<true, false><<<(unsigned)bp.gridWrite, kJoinBlock, table_lds((uint32_t)bp.cap, true), st>>>(
         g, reinterpret_cast<const uint64_t*>(ws + bp.off_counts),
         reinterpret_cast<const uint64_t*>(ws + bp.off_wave), reinterpret_cast<const uint64_t*>(ws),
         reinterpret_cast<int2*>(pairs), cap);

@@ -45,6 +45,7 @@ struct JoinGeom {
     uint64_t* stamp_at;  // plan stamp in the workspace header (NULL for batches: no re-planning)
     uint64_t stamp;      // this plan's stamp: the count pass records it, the write pass checks it
     uint64_t* dbg;       // checking build: pairs written per unit (NULL: not counted)
+    uint32_t* semi;      // the probe rows with matches, per unit and wave (NULL: not recorded)
 };
 
 struct HashPlan {
@@ -52,6 +53,8 @@ struct HashPlan {
     int single;    // 1: no partitioning, units = R chunks x S slices of the inputs themselves
     int prebuilt;  // 1: R comes partitioned from a resident build (RView)
     int ordered;   // 1: the ordered scatter (output order fixed by the input), else arrival order
+    int semi;      // 1: the count pass records the probe rows with matches and the write pass
+                   // visits only those (partitioned plans; asked for by the pre-filter)
     int bits, P;
     int cap, slice;
     int64_t nSs;  // S slices (single)
@@ -60,13 +63,14 @@ struct HashPlan {
     int gridCount, gridWrite;  // persistent grids of the count and write kernels
     size_t off_tot, off_grpR, off_grpS, off_done, off_baseR, off_baseS, off_tupR, off_tupS;
     size_t off_info, off_units, off_umap, off_cntR, off_cntS;
-    size_t off_counts, off_wave, off_temp, off_dbg, bytes;
+    size_t off_counts, off_wave, off_temp, off_dbg, off_semi, bytes;
     uint64_t stamp;  // signature of the fields above (plan_stamp)
 };
 
 // prebuilt_bits >= 0: R is a resident build partitioned with that fan-out (no single path, no
 // R arrays in the workspace).
-HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits = -1);
+// semi: record the semi-join in the count pass (ignored by the unpartitioned path).
+HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits = -1, bool semi = false);
 
 // A build relation already partitioned (resident build): its partition sizes, starts, tuples.
 struct RView {

@@ -202,8 +202,13 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
     PrefilterPlan pl{};
     pl.nR = nR;
     pl.nS = nS;
-    pl.logR = log_bits(nR);
-    pl.logS = log_bits(nS);
+    // A probe side too large for a filter of its own is also too large to check row by row
+    // against R's filter at the rate the caches serve random words: there the hash join's count
+    // pass is the filter (the semi-join, exact, from its LDS tables), and its write pass visits
+    // only the probe rows it recorded as matching.
+    pl.semi = nS > kMaxFilteredRows ? 1 : 0;
+    pl.logR = pl.semi ? 0 : log_bits(nR);
+    pl.logS = pl.semi ? 0 : log_bits(nS);
     size_t off = 0;
     auto take = [&](size_t b) {
         const size_t at = off;
@@ -227,11 +232,13 @@ PrefilterPlan prefilter_plan(int64_t nR, int64_t nS, int num_cus)
     // chunk arrays (group shares, and the per-tile counts' last partial tile of every chunk),
     // which a smaller fan-out may lay out for twice the chunks: bounded by 2^11 partitions x 2
     // chunks per CU x 2 sides, twice.
-    pl.inner_bytes = hash_plan(nR, nS, num_cus).bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 * 2 + 4096;
+    const HashPlan full = hash_plan(nR, nS, num_cus, -1, pl.semi != 0);
+    pl.inner_bytes = pl.semi ? full.bytes
+                             : full.bytes + ((size_t)1 << 11) * num_cus * 2 * 4 * 2 * 2 + 4096;
     pl.off_inner = take(pl.inner_bytes);
     pl.bytes = off;
-    pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.logR, pl.logS, pl.ordered, pl.grid, (int64_t)pl.inner_bytes,
-                           (int64_t)hash_plan(nR, nS, num_cus).stamp, (int64_t)pl.bytes});
+    pl.stamp = plan_stamp({JOIN_KIND_HASH_PREFILTER, nR, nS, pl.semi, pl.logR, pl.logS, pl.ordered, pl.grid,
+                           (int64_t)pl.inner_bytes, (int64_t)full.stamp, (int64_t)pl.bytes});
     return pl;
 }
 
@@ -274,6 +281,7 @@ static hipError_t read_sizes(const PrefilterPlan& pl, char* ws, hipStream_t st, 
 hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const join_rel_t& S,
                            char* ws, hipStream_t st, int num_cus, uint64_t* pub)
 {
+    if (pl.semi) return hash_count(hash_plan(pl.nR, pl.nS, num_cus, -1, true), R, S, ws + pl.off_inner, st, nullptr, pub);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + pl.off_cnt);
     uint32_t* fR = reinterpret_cast<uint32_t*>(ws + pl.off_fR);
     uint32_t* fS = reinterpret_cast<uint32_t*>(ws + pl.off_fS);
@@ -344,6 +352,8 @@ hipError_t prefilter_count(const PrefilterPlan& pl, const join_rel_t& R, const j
 hipError_t prefilter_write(const PrefilterPlan& pl, const join_rel_t& R, const join_rel_t& S,
                            char* ws, int32_t* pairs, uint64_t cap, hipStream_t st, int num_cus)
 {
+    if (pl.semi)
+        return hash_write(hash_plan(pl.nR, pl.nS, num_cus, -1, true), R, S, ws + pl.off_inner, pairs, cap, st);
     uint32_t n[2] = {0, 0};
     if (g_seen.ws == ws && g_seen.stamp == pl.stamp) {
         n[0] = g_seen.n[0];

@@ -9,6 +9,7 @@ namespace jl {
 struct PrefilterPlan {
     int64_t nR, nS;
     int logR, logS;          // log2 of the filter sizes in bits (of R, of S); 0 = no filter
+    int semi;                // 1: no filters; the inner join records its semi-join (probe side too large)
     int ordered;             // 1: compaction in input order (deterministic option), else arrival order
     int grid;                // compaction workgroups
     uint64_t off_wcnt, off_wtmp;  // ordered compaction: per-workgroup counts, scan storage

@@ -34,7 +34,7 @@ def test_few_and_all_keys_matching():
     _check(R, S, "every key shared")
     R = datagen.Rel(key=datagen.uniform_keys(g, 50_000, 0, 5_000_000))
     S = datagen.Rel(key=datagen.uniform_keys(g, 2_500_000, 0, 50_000_000))
-    _check(R, S, "large probe side: only the small side is filtered")
+    _check(R, S, "large probe side: the count pass records the semi-join")
 
 
 @gpu
@@ -61,22 +61,29 @@ def test_duplicates_and_extreme_keys():
 
 
 @gpu
-def test_full_stages_and_the_ordered_compaction(monkeypatch):
-    """Every probe key passes (more passing rows per workgroup than its LDS stage holds, so
-    waves write straight out), then the same join and a 1%-match one with the deterministic
-    option: the ordered compaction gives the same output array on two runs, and the oracle's
-    pairs."""
+def test_full_stages_semi_join_and_the_ordered_compaction(monkeypatch):
+    """Every build row passes S's filter (more passing rows per workgroup than its LDS stage
+    holds, so waves write straight out); a probe side too large for a filter (the count pass
+    records the semi-join, the write pass visits only matching rows), all and 1% matching; then,
+    with the deterministic option, the ordered compaction and the semi-join give the same output
+    array on two runs, and the oracle's pairs."""
     need_gpu()
     import torch
     from paper_1904_11201_amd.join import hash_join
-    g = datagen.rng_for(83)
-    R = datagen.Rel(key=np.arange(100_000, dtype=np.int32), rid=g.permutation(100_000).astype(np.int32))
-    S = datagen.Rel(key=datagen.uniform_keys(g, 24_000_000, 0, 100_000), rid=None)
-    _check(R, S, "all of 24M probes pass")
-    R2 = datagen.Rel(key=np.arange(0, 10_000_000, 100, dtype=np.int32), rid=None)
-    S2 = datagen.Rel(key=datagen.uniform_keys(g, 5_000_000, 0, 10_000_000), rid=g.permutation(5_000_000).astype(np.int32))
+    g = datagen.rng_for(84)
+    R1 = datagen.Rel(key=datagen.uniform_keys(g, 24_000_000, 0, 100_000), rid=None)
+    S1 = datagen.Rel(key=np.arange(100_000, dtype=np.int32), rid=g.permutation(100_000).astype(np.int32))
+    _check(R1, S1, "all of 24M build rows pass")
+    R2 = datagen.Rel(key=np.arange(100_000, dtype=np.int32), rid=g.permutation(100_000).astype(np.int32))
+    S2 = datagen.Rel(key=datagen.uniform_keys(g, 6_000_000, 0, 100_000), rid=None)
+    _check(R2, S2, "semi-join, every probe row matches")
+    R3 = datagen.Rel(key=np.arange(0, 10_000_000, 100, dtype=np.int32), rid=None)
+    S3 = datagen.Rel(key=datagen.uniform_keys(g, 5_000_000, 0, 10_000_000), rid=g.permutation(5_000_000).astype(np.int32))
+    _check(R3, S3, "semi-join, 1% of probe rows match")
+    S4 = datagen.Rel(key=datagen.uniform_keys(g, 1_500_000, 0, 10_000_000), rid=None)
     monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
-    for X, Y, label in ((R, S, "all pass, ordered"), (R2, S2, "1% match, ordered")):
+    for X, Y, label in ((R1, S1, "filtered build side, ordered"), (R3, S3, "semi-join, ordered"),
+                        (R3, S4, "filtered probe side, ordered")):
         _check(X, Y, label)
         dX, dY = dev_rel(X), dev_rel(Y)
         a = hash_join(dX, dY, prefilter=True)
