@@ -729,7 +729,10 @@ __device__ __forceinline__ uint32_t plan_part(const PartPlan& q, int p, PartInfo
 // Work unit `local` of a partition (R chunk local / nSs, S slice local % nSs) as one record:
 // {first R tuple, R tuples | fan-out << 24, first S tuple, S tuples}.  The planning kernels
 // write every unit's record, so the join kernels read a unit with one 16-byte load.
+// Bit kRecShared of the second word: the partition has several R chunks, so several units probe
+// the same S slice.
 constexpr int kRecBitsShift = 24;
+constexpr int kRecShared = 28;
 __host__ __device__ __forceinline__ uint4 unit_rec(const PartInfo& pi, uint32_t local, uint32_t cap)
 {
     const uint32_t rc = local / pi.nSs;
@@ -737,7 +740,9 @@ __host__ __device__ __forceinline__ uint4 unit_rec(const PartInfo& pi, uint32_t 
     const uint32_t slen = (pi.nS + pi.nSs - 1) / pi.nSs;
     const uint32_t rN = min(cap, pi.nR - rc * cap);
     const uint32_t sN = sc * slen < pi.nS ? min(slen, pi.nS - sc * slen) : 0u;
-    return make_uint4(pi.rStart + rc * cap, rN | (pi.bits << kRecBitsShift), pi.sStart + sc * slen, sN);
+    return make_uint4(pi.rStart + rc * cap,
+                      rN | (pi.bits << kRecBitsShift) | ((pi.nRc > 1 ? 1u : 0u) << kRecShared),
+                      pi.sStart + sc * slen, sN);
 }
 
 __global__ void plan_units_k(PartPlan q, int nParts, PartInfo* __restrict__ info,
@@ -967,7 +972,8 @@ __global__ __launch_bounds__(kScatBlock) void scatter_k(const SideItem* __restri
 // ------------------------------------------------------------------------- join work units --
 struct Unit {
     uint32_t rBeg, rN, sBeg, sN;
-    int bits;  // fan-out of the unit's join: the table position uses the hash bits below it
+    int bits;     // fan-out of the unit's join: the table position uses the hash bits below it
+    bool shared;  // other units (other R chunks) probe the same S slice
 };
 
 __device__ __forceinline__ Unit unit_of(uint4 r)
@@ -977,7 +983,8 @@ __device__ __forceinline__ Unit unit_of(uint4 r)
     o.rN = r.y & ((1u << kRecBitsShift) - 1);
     o.sBeg = r.z;
     o.sN = r.w;
-    o.bits = (int)(r.y >> kRecBitsShift);
+    o.bits = (int)((r.y >> kRecBitsShift) & ((1u << (kRecShared - kRecBitsShift)) - 1));
+    o.shared = ((r.y >> kRecShared) & 1u) != 0;
     return o;
 }
 
@@ -1623,7 +1630,8 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
 // the write pass is to visit only them: the k-th such row of wave wv in a unit is stored, as its
 // index in the partitioned probe tuples, at the place of the wave's k-th own row
 // (unit start + (k / 64) * kJoinBlock + wv * 64 + k % 64), which lies inside the unit because
-// the wave has at least k + 1 rows there.
+// the wave has at least k + 1 rows there.  A unit whose S slice other units also probe (its
+// partition has several R chunks) records nothing (rows == NULL) and is written in full.
 struct Semi {
     uint32_t* rows;  // [probe rows]
     uint32_t sBeg;   // the unit's first probe row
@@ -1651,7 +1659,7 @@ __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& u
             ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
         }
         cnt += probe_count<kProbe, AOS, MARKED, FULL>(t, un.bits, x, ok, multi, many, hv);
-        if constexpr (SEMI) {
+        if (SEMI && sm.rows) {  // uniform
             const int wv = (int)(threadIdx.x / kWave);
 #pragma unroll
             for (int i = 0; i < kProbe; ++i) {
@@ -1796,7 +1804,7 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         const Unit nx = more ? decode_unit<AOS>(g, u + gridDim.x) : Unit{};
         uint64_t cnt = 0, many = 0;
         bool multi = false;
-        Semi sm{g.semi, un.sBeg, 0u};
+        Semi sm{SEMI && !un.shared ? g.semi : nullptr, un.sBeg, 0u};
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
             for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
@@ -1976,7 +1984,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                     cursor += wtot;
                 }
             };
-            if constexpr (SEMI) {
+            if (SEMI && !un.shared) {  // uniform
                 // only this wave's probe rows with matches, as the count pass recorded them
                 for (uint32_t k0 = 0; k0 < semi_rows; k0 += kWave * kWriteLoad) {  // wave-uniform
                     uint32_t cx[kWriteLoad];
@@ -1992,6 +2000,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                     round(cx, cr, [&](int j) { return k0 + j * kWave + lane_id() < semi_rows; });
                 }
             } else {
+                if (SEMI) load_tuples<AOS>(g, un, 0, nx, nr);  // not loaded ahead in this mode
                 for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
                     uint32_t cx[kWriteLoad];
                     int32_t cr[kWriteLoad];

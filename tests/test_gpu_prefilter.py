@@ -80,6 +80,11 @@ def test_full_stages_semi_join_and_the_ordered_compaction(monkeypatch):
     R3 = datagen.Rel(key=np.arange(0, 10_000_000, 100, dtype=np.int32), rid=None)
     S3 = datagen.Rel(key=datagen.uniform_keys(g, 5_000_000, 0, 10_000_000), rid=g.permutation(5_000_000).astype(np.int32))
     _check(R3, S3, "semi-join, 1% of probe rows match")
+    hot = np.concatenate([np.full(40_000, 777, np.int32), datagen.uniform_keys(g, 200_000, 0, 10_000_000)])
+    R5 = datagen.Rel(key=g.permutation(hot).astype(np.int32), rid=g.permutation(len(hot)).astype(np.int32))
+    S5 = datagen.Rel(key=np.concatenate([np.full(50, 777, np.int32),
+                                         datagen.uniform_keys(g, 3_000_000, 0, 10_000_000)]).astype(np.int32), rid=None)
+    _check(R5, S5, "semi-join, a build partition of several chunks (its units share their S slice)")
     S4 = datagen.Rel(key=datagen.uniform_keys(g, 1_500_000, 0, 10_000_000), rid=None)
     monkeypatch.setenv("JOIN_HASH_DETERMINISTIC", "1")
     for X, Y, label in ((R1, S1, "filtered build side, ordered"), (R3, S3, "semi-join, ordered"),
