@@ -1538,7 +1538,7 @@ __device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u
 }
 
 #ifndef JL_HASH_COUNT_BATCH
-#define JL_HASH_COUNT_BATCH 4
+#define JL_HASH_COUNT_BATCH 2
 #endif
 // The count kernel's keys-only table lets two 1024-thread workgroups share a CU, so it is
 // compiled for 8 waves per SIMD (64 VGPRs); the write kernel runs one workgroup per CU.

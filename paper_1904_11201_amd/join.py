@@ -53,7 +53,7 @@ def _ptr(t):
         return None
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
-    if t.dtype != torch.int32 or not t.is_contiguous() or t.device.type != "cuda":
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
         raise ValueError("join columns must be contiguous int32 cuda tensors")
     return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
 
