@@ -16,7 +16,7 @@
 //   6. scan:        per-unit counts -> exact output offsets and the total (Section 3.3.3,
 //                   computed exactly instead of estimated);
 //   7. write pass:  same units, re-probe, each match written inside the unit's output range at
-//                   a slot taken from a per-unit LDS cursor (one atomic per wave and round).
+//                   a slot fixed by the count pass's per-wave totals and a wave-wide scan.
 // The LDS table is 4-slot buckets with two candidate buckets per key; a lookup reads both with
 // predicated compares, so a wave issues its LDS reads together and does not branch per key.
 #include "hash.hpp"
@@ -730,9 +730,11 @@ __device__ __forceinline__ uint32_t plan_part(const PartPlan& q, int p, PartInfo
 // {first R tuple, R tuples | fan-out << 24, first S tuple, S tuples}.  The planning kernels
 // write every unit's record, so the join kernels read a unit with one 16-byte load.
 // Bit kRecShared of the second word: the partition has several R chunks, so several units probe
-// the same S slice.
+// the same S slice.  Bit kRecOrder: set by the count pass when some probe of the unit has more
+// than kEmitSort matches (the write pass then puts the table in canonical order).
 constexpr int kRecBitsShift = 24;
 constexpr int kRecShared = 28;
+constexpr int kRecOrder = 29;
 __host__ __device__ __forceinline__ uint4 unit_rec(const PartInfo& pi, uint32_t local, uint32_t cap)
 {
     const uint32_t rc = local / pi.nSs;
@@ -974,6 +976,7 @@ struct Unit {
     uint32_t rBeg, rN, sBeg, sN;
     int bits;     // fan-out of the unit's join: the table position uses the hash bits below it
     bool shared;  // other units (other R chunks) probe the same S slice
+    bool order;   // partitioned joins, after the count pass: the table needs canonical order
 };
 
 __device__ __forceinline__ Unit unit_of(uint4 r)
@@ -985,6 +988,7 @@ __device__ __forceinline__ Unit unit_of(uint4 r)
     o.sN = r.w;
     o.bits = (int)((r.y >> kRecBitsShift) & ((1u << (kRecShared - kRecBitsShift)) - 1));
     o.shared = ((r.y >> kRecShared) & 1u) != 0;
+    o.order = ((r.y >> kRecOrder) & 1u) != 0;
     return o;
 }
 
@@ -1130,8 +1134,10 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
     uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
     const bool marked = HASHED && un.bits >= 2;
     if (marked) {
-        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed)
-        const uint32_t m = (((uint32_t)g.rt[un.rBeg].x) ^ 0x80000000u) & 0xC0000000u;
+        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed);
+        // every thread's first chunk entry is a hash of the partition (lanes past the chunk hold
+        // its last one)
+        const uint32_t m = (c.k[0] ^ 0x80000000u) & 0xC0000000u;
         for (uint32_t b = tid; b < nb; b += kJoinBlock) {
             cnt[b] = 0;
             lds[b] = make_uint4(m, m, m, m);
@@ -1526,8 +1532,8 @@ __device__ __forceinline__ uint32_t unit_total(const JoinGeom& g)
     return (int64_t)U < g.Umax ? U : (uint32_t)g.Umax;
 }
 
-// The write pass's units per workgroup of one join: a contiguous run [u0, u1) of the unit list.
-// Units of one partition follow each other R chunk by R chunk, S slice by S slice, so
+// A contiguous run [u0, u1) of the unit list per workgroup: the write pass's static share of one
+// join.  Units of one partition follow each other R chunk by R chunk, S slice by S slice, so
 // consecutive slices of one chunk keep its table (a skewed probe side cuts its hot partitions
 // into many slices).  Batches of joins, whose units differ widely in size, and the count pass
 // keep the round-robin order, which balances better.
@@ -1535,6 +1541,96 @@ __device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u
 {
     u0 = (uint32_t)(((uint64_t)U * blockIdx.x) / gridDim.x);
     u1 = (uint32_t)(((uint64_t)U * (blockIdx.x + 1)) / gridDim.x);
+}
+
+// The sequence of units a workgroup of the count or write pass takes.  A fixed share per
+// workgroup leaves CUs idle at the end of a pass: units differ in size (batches), CUs in speed,
+// and of two count workgroups on one CU the older one runs ahead.  With a ticket counter (two
+// words of the workspace, zero before the pass), each workgroup takes a static head, half of
+// its even share (a contiguous run for the write pass of one join, whose consecutive units of
+// one R chunk keep the table, else round robin), and then units handed out one at a time after
+// all static heads, so that faster workgroups take more.  Without one, the whole share is static
+// as before.  The unit two places ahead is fixed while a unit runs (its ticket taken at the
+// unit's start, read back after the unit's last barrier), so the loads the passes issue ahead
+// for the next unit never wait for a ticket.
+constexpr uint32_t kTicketed = 0xFFFFFFFFu;
+
+struct Sched {
+    uint32_t U;         // units
+    uint32_t head;      // static positions
+    uint32_t base;      // contig: first unit of the static run
+    uint32_t dyn0;      // the first unit handed out by ticket
+    uint32_t pos;       // uniform: position of the current unit in this workgroup's sequence
+    bool contig;
+    uint32_t* ticket;   // NULL: static only
+
+    // Unit at position k: a static one (U or more once the static share is used up and there
+    // is no ticket), or kTicketed.
+    __device__ __forceinline__ uint32_t at(uint32_t k) const
+    {
+        if (k >= head) return ticket ? kTicketed : U;
+        return contig ? base + k : blockIdx.x + k * gridDim.x;
+    }
+};
+
+__device__ __forceinline__ Sched make_sched(uint32_t U, bool contig, uint32_t* ticket)
+{
+    Sched s{};
+    s.U = U;
+    s.contig = contig;
+    s.ticket = ticket;
+    if (ticket) {
+        const uint32_t h = U / gridDim.x / 2;
+        s.head = h;
+        s.base = blockIdx.x * h;
+        s.dyn0 = gridDim.x * h;
+    } else if (contig) {
+        uint32_t u0, u1;
+        unit_range(U, u0, u1);
+        s.head = u1 - u0;
+        s.base = u0;
+    } else {
+        s.head = 0xFFFFFFFFu;  // u = blockIdx.x + k * gridDim.x < U + 2 * gridDim.x: no wrap
+    }
+    return s;
+}
+
+// The first two units of the sequence (U or more: none).  slot: two words of LDS.
+__device__ __forceinline__ void sched_start(const Sched& s, uint32_t& u, uint32_t& nxi, uint32_t* slot)
+{
+    u = s.at(0);
+    nxi = s.at(1);
+    if (u == kTicketed || nxi == kTicketed) {  // uniform
+        if (threadIdx.x == 0) {
+            if (u == kTicketed) slot[0] = s.dyn0 + atomicAdd(s.ticket, 1u);
+            if (nxi == kTicketed) slot[1] = s.dyn0 + atomicAdd(s.ticket, 1u);
+        }
+        __syncthreads();
+        if (u == kTicketed) u = uniform(slot[0]);
+        if (nxi == kTicketed) nxi = uniform(slot[1]);
+        __syncthreads();
+    }
+}
+
+// At the start of the unit at s.pos, with the next one nxi: whether the unit after nxi comes
+// from a ticket (then thread 0 takes it now).
+__device__ __forceinline__ bool sched_need(const Sched& s, uint32_t nxi)
+{
+    return nxi < s.U && s.at(s.pos + 2) == kTicketed;
+}
+
+// Thread 0 publishes the ticket before the unit's last barrier; every thread reads the unit
+// after nxi once past it.  The two LDS slots alternate by position, so a slot is written again
+// only after a barrier that every reader of its previous value has passed.
+__device__ __forceinline__ void sched_put(const Sched& s, bool need, uint32_t tk, uint32_t* slot)
+{
+    if (need && threadIdx.x == 0) slot[s.pos & 1] = s.dyn0 + tk;
+}
+
+__device__ __forceinline__ uint32_t sched_after(const Sched& s, bool need, uint32_t nxi, const uint32_t* slot)
+{
+    if (need) return uniform(slot[s.pos & 1]);
+    return nxi < s.U ? s.at(s.pos + 2) : s.U;
 }
 
 #ifndef JL_HASH_COUNT_BATCH
@@ -1618,7 +1714,7 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
     load_keys_of<AOS>(g, un, e0, xs);
 }
 
-// Count pass.  A workgroup walks units u = blockIdx.x, + gridDim.x, ...  The S keys come in
+// Count pass.  A workgroup walks the units of its sequence (Sched).  The S keys come in
 // batches of kCountBatch per thread through two register buffers used in turn: while one batch
 // is probed the next is in flight, and the next unit's first batch while the last one probes.
 // Every half of the loop issues the same loads (a batch past the unit reloads a valid one), and
@@ -1703,10 +1799,11 @@ static_assert(table_lds(kMaxCap, true) + kWriteStaticLds <= 160 * 1024, "write p
 // the waves' starts in wave_off[u][1..kJoinWaves) and, in wave_off[u][kJoinWaves + w], each
 // wave's count of pairs before its block of many-match pairs (low 32 bits: at most two pairs per
 // probe row of the wave) and its count of probe rows with matches when the semi-join is recorded
-// (high 32 bits, else 0); sh: kJoinWaves + 1 words of LDS.
+// (high 32 bits, else 0); sh: kJoinWaves + 1 words of LDS.  rec_word (partitioned joins): the
+// second word of the unit's record, which receives the canonical-order flag as well.
 __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi,
                                             uint32_t semi_rows, uint32_t u, uint64_t* __restrict__ counts,
-                                            uint64_t* __restrict__ wave_off, uint64_t* sh)
+                                            uint64_t* __restrict__ wave_off, uint64_t* sh, uint32_t* rec_word)
 {
     const uint64_t wt = wave_sum64(lane_total);
     const uint64_t wmany = wave_sum64(lane_many);
@@ -1728,7 +1825,10 @@ __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_m
             any |= v >> 63;
         }
         wave_off[(size_t)u * kWaveRec + threadIdx.x] = threadIdx.x == 0 ? any : before;
-        if (threadIdx.x == 0) counts[u] = sum;
+        if (threadIdx.x == 0) {
+            counts[u] = sum;
+            if (any && rec_word) atomicOr(rec_word, 1u << kRecOrder);
+        }
     }
     __syncthreads();
 }
@@ -1788,20 +1888,27 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     constexpr uint32_t kB = kJoinBlock * kCountBatch;  // keys per batch
     const uint32_t U = unit_total(g);
     if (g.stamp_at && blockIdx.x == 0 && threadIdx.x == 0) *g.stamp_at = g.stamp;  // for the write pass
+    __shared__ uint32_t slot[2];
+    Sched sc = make_sched(U, false, g.sched);
+    uint32_t u, nxi;
+    sched_start(sc, u, nxi, slot);
     uint32_t xa[kCountBatch], xb[kCountBatch];
     Unit un{};
-    if (blockIdx.x < U) {
-        un = decode_unit<AOS>(g, blockIdx.x);
+    if (u < U) {
+        un = decode_unit<AOS>(g, u);
         load_keys<AOS>(g, un, 0, xa);
     }
-    for (uint32_t u = blockIdx.x; u < U; u += gridDim.x) {
+    while (u < U) {
+        const bool need = sched_need(sc, nxi);
+        uint32_t tk = 0;
+        if (need && threadIdx.x == 0) tk = atomicAdd(sc.ticket, 1u);
         Chunk<false> ch;
         load_chunk<AOS, false>(g, un, ch);
         uint32_t pos[kBuildItems];
         const Table t = insert_chunk<false, AOS>(g, un, ch, tab, pos);
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
-        const bool more = u + gridDim.x < U;
-        const Unit nx = more ? decode_unit<AOS>(g, u + gridDim.x) : Unit{};
+        const bool more = nxi < U;
+        const Unit nx = more ? decode_unit<AOS>(g, nxi) : Unit{};
         uint64_t cnt = 0, many = 0;
         bool multi = false;
         Semi sm{SEMI && !un.shared ? g.semi : nullptr, un.sBeg, 0u};
@@ -1821,7 +1928,15 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
         if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
-        unit_totals(cnt, many, multi, sm.k, u, counts, wave_off, wsum);
+        sched_put(sc, need, tk, slot);
+        // a partitioned join's record is read only by this workgroup in this pass (it decoded it
+        // before), so the flag can go into it
+        uint32_t* rec_word = AOS ? const_cast<uint32_t*>(&g.urec[u].y) : nullptr;
+        unit_totals(cnt, many, multi, sm.k, u, counts, wave_off, wsum, rec_word);  // ends with a barrier
+        const uint32_t nn = sched_after(sc, need, nxi, slot);
+        u = nxi;
+        nxi = nn;
+        ++sc.pos;
         un = nx;
     }
     if (done) {
@@ -1846,28 +1961,36 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         counts[i] = 0;
 }
 
+// Whether unit v (record n) had a probe with more than kEmitSort matches: the flag the count pass
+// put into a partitioned join's record, else entry 0 of the unit's wave_off record.
+template <bool PART>
+__device__ __forceinline__ bool unit_order(const uint64_t* wave_off, uint32_t v, const Unit& n)
+{
+    if constexpr (PART) return n.order;
+    else return as_const(wave_off)[(size_t)v * kWaveRec] != 0;
+}
+
 // Whether any unit of [u, end) that shares unit u's R chunk had a probe with more than
-// kEmitSort matches (entry 0 of its wave_off record): then the chunk's table is put in
-// canonical order.
+// kEmitSort matches: then the chunk's table is put in canonical order.  end: the end of the
+// contiguous run u is in, 0 for a unit outside a run (which builds its own table).
 template <bool PART>
 __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint64_t* wave_off, uint32_t u,
-                                                  uint32_t end, uint32_t step, const Unit& un)
+                                                  uint32_t end, const Unit& un)
 {
-    const cptr<uint64_t> wo = as_const(wave_off);
-    bool any = wo[(size_t)u * kWaveRec] != 0;
-    if (step != 1) return any;  // round robin: every unit builds its own table
+    bool any = unit_order<PART>(wave_off, u, un);
     for (uint32_t v = u + 1; v < end && !any; ++v) {
         const Unit n = decode_unit<PART>(g, v);
         if (!same_chunk(n, un)) break;
-        any = wo[(size_t)v * kWaveRec] != 0;
+        any = unit_order<PART>(wave_off, v, n);
     }
     return any;
 }
 
-// Write pass.  Units are walked as in the count pass (contiguous runs per workgroup for one
-// join, round robin for batches); each wave writes the pairs of its probe tuples from the
-// start the count pass recorded for it, in (batch, tuple, lane) order, with one wave-wide scan
-// per round and no shared cursor: the output depends on the input and the plan only.
+// Write pass.  Units are walked in a Sched sequence (its static head a contiguous run per
+// workgroup for one join, round robin for batches); each wave writes the pairs of its probe
+// tuples from the start the count pass recorded for it, in (batch, tuple, lane) order, with one
+// wave-wide scan per round and no shared cursor: the output depends on the input and the plan
+// only, not on which workgroup takes a unit.
 template <bool AOS, bool SEMI>
 __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restrict__ offsets,
                                            const uint64_t* __restrict__ wave_off,
@@ -1883,15 +2006,13 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     const int wv = uniform((int32_t)(threadIdx.x / kWave));
     uint4* q = write_manyq + wv * kManyQ;  // this wave's queue of probes with many matches
     uint32_t qn = 0;                 // uniform: its length
-    uint32_t u0, u1, step;
-    if (contig) {
-        unit_range(U, u0, u1);
-        step = 1;
-    } else {
-        u0 = blockIdx.x;
-        u1 = U;
-        step = gridDim.x;
-    }
+    __shared__ uint32_t slot[2];
+    Sched sc = make_sched(U, contig, g.sched ? g.sched + 1 : nullptr);
+    uint32_t u, nxi;
+    sched_start(sc, u, nxi, slot);
+    // Units of the static run of one join follow each other, so a unit whose R chunk is the
+    // previous unit's keeps the table; other units build their own.
+    const uint32_t run_end = contig ? sc.base + sc.head : 0u;
     // The next unit's R chunk (when it needs a new table) is loaded into registers while the
     // current unit probes, and the next unit's first S batch while its last batch probes.
     Unit un{};
@@ -1899,18 +2020,23 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     uint32_t pos[kBuildItems];
     uint32_t nx[kWriteLoad];
     int32_t nr[kWriteLoad];
-    if (u0 < u1) {
-        un = decode_unit<AOS>(g, u0);
+    if (u < U) {
+        un = decode_unit<AOS>(g, u);
         load_chunk<AOS, true>(g, un, ch);
         if constexpr (!SEMI) load_tuples<AOS>(g, un, 0, nx, nr);
     }
     Unit tu{};  // the unit whose chunk is in the table (rN == 0: none yet)
     const cptr<uint64_t> offs = as_const(offsets);
     const cptr<uint64_t> wo = as_const(wave_off);
-    for (uint32_t u = u0; u < u1; u += step) {
-        const bool more = u + step < u1;
-        if (!contig || tu.rN == 0 || !same_chunk(un, tu)) {  // uniform: a new chunk (loaded in ch)
-            const bool order = chunk_needs_order<AOS>(g, wave_off, u, u1, step, un);
+    while (u < U) {
+        const bool need = sched_need(sc, nxi);
+        uint32_t tk = 0;
+        if (need && threadIdx.x == 0) tk = atomicAdd(sc.ticket, 1u);
+        const bool more = nxi < U;
+        const bool in_run = contig && sc.pos < sc.head;            // uniform
+        const bool next_in_run = contig && sc.pos + 1 < sc.head;  // uniform
+        if (!in_run || tu.rN == 0 || !same_chunk(un, tu)) {  // uniform: a new chunk (loaded in ch)
+            const bool order = chunk_needs_order<AOS>(g, wave_off, u, in_run ? run_end : 0u, un);
             const Table tb = insert_chunk<true, AOS>(g, un, ch, tab, pos);
             if (order) {
                 uint32_t* rids = reinterpret_cast<uint32_t*>(tab + tb.nb);
@@ -1928,8 +2054,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         const uint64_t cursor0 = cursor, cmany0 = cmany;
 #endif
         const Table t = table_of<true, AOS>(un, tab);
-        const Unit nxt = more ? decode_unit<AOS>(g, u + step) : Unit{};
-        if (more && (!contig || !same_chunk(nxt, un))) load_chunk<AOS, true>(g, nxt, ch);
+        const Unit nxt = more ? decode_unit<AOS>(g, nxi) : Unit{};
+        if (more && (!next_in_run || !same_chunk(nxt, un))) load_chunk<AOS, true>(g, nxt, ch);
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
@@ -2031,8 +2157,19 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
 #endif
         if constexpr (!SEMI)
             if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
+        sched_put(sc, need, tk, slot);
         __syncthreads();
+        const uint32_t nn = sched_after(sc, need, nxi, slot);
+        u = nxi;
+        nxi = nn;
+        ++sc.pos;
         un = nxt;
+    }
+    // The last workgroup to finish resets the ticket counter for the next write from this
+    // workspace (every workgroup took its last ticket before it arrives here).
+    if (sc.ticket && threadIdx.x == 0 && atomicAdd(g.sched + 2, 1u) == gridDim.x - 1) {
+        atomicExch(g.sched + 1, 0u);
+        atomicExch(g.sched + 2, 0u);
     }
 }
 
@@ -2127,8 +2264,10 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool 
         pl.off_tot = off;
         pl.off_grpS = off + (size_t)2 * pl.P * 4;
         pl.off_grpR = pl.off_grpS + (size_t)kGroups * pl.P * 4;
-        pl.off_done = pl.off_grpR + (size_t)kGroups * pl.P * 4;  // cleared with the sizes and shares
-        off = align_up(pl.off_done + 4);
+        // the count kernel's arrival counter and the passes' unit tickets (Sched): cleared with
+        // the sizes and shares
+        pl.off_done = pl.off_grpR + (size_t)kGroups * pl.P * 4;
+        off = align_up(pl.off_done + 16);
         pl.off_baseR = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
         pl.off_baseS = off;
@@ -2419,6 +2558,7 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.urec = reinterpret_cast<const uint4*>(ws + pl.off_umap);
         g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
         g.P = pl.P;
+        g.sched = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 1;
     }
     return g;
 }
@@ -2444,7 +2584,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
             // a prebuilt R keeps its sizes: only the S sizes and shares are cleared
             prof::Scope pz(st, "hash.plan");
             uint32_t* z = pre ? totS : totR;
-            const int64_t nz = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 1 - z;
+            const int64_t nz = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 4 - z;
             zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(z, nz);
         }
         e = hipGetLastError();
@@ -2663,7 +2803,8 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     bp.off_itemsR = take(off, (size_t)bp.nItemsR * sizeof(SideItem));
     bp.off_itemsS = take(off, (size_t)bp.nItemsS * sizeof(SideItem));
     // totR, totS, then the group shares of R and S: cleared together
-    bp.off_tot = take(off, (size_t)(2 + 2 * kGroups) * bp.nParts * 4);
+    // sizes, group shares, then the count and write passes' unit tickets (Sched), cleared together
+    bp.off_tot = take(off, ((size_t)(2 + 2 * kGroups) * bp.nParts + 4) * 4);
     bp.off_baseR = take(off, (size_t)(bp.nParts + 1) * 4);
     bp.off_baseS = take(off, (size_t)(bp.nParts + 1) * 4);
     bp.off_tupR = take(off, (size_t)bp.sumR * 8);
@@ -2758,6 +2899,7 @@ static JoinGeom batch_geom(const BatchPlan& bp, char* ws)
     g.urec = reinterpret_cast<const uint4*>(ws + bp.off_umap);
     g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
     g.P = (int)bp.nParts;
+    g.sched = reinterpret_cast<uint32_t*>(ws + bp.off_tot) + (2 + 2 * kGroups) * bp.nParts;
     return g;
 }
 
@@ -2802,7 +2944,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     const SideItem none{};
     if (bp.nParts > 0) {
         prof::Scope pz(st, "hash.plan");
-        const int64_t nz = (2 + 2 * kGroups) * bp.nParts;
+        const int64_t nz = (2 + 2 * kGroups) * bp.nParts + 4;
         zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(totR, nz);
     }
     e = hipGetLastError();

@@ -46,6 +46,7 @@ struct JoinGeom {
     uint64_t stamp;      // this plan's stamp: the count pass records it, the write pass checks it
     uint64_t* dbg;       // checking build: pairs written per unit (NULL: not counted)
     uint32_t* semi;      // the probe rows with matches, per unit and wave (NULL: not recorded)
+    uint32_t* sched;     // [3]: count ticket, write ticket, write arrivals (NULL: static shares)
 };
 
 struct HashPlan {

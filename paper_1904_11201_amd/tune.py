@@ -55,21 +55,40 @@ def _nearest(table: dict, n: int):
     return table[str(below[-1] if below else keys[0])]
 
 
-def hash_bits_for(nR: int, cache: dict | None = None) -> int:
-    """Tuned fan-out (log2) for a build side of nR rows, or -1 (library default)."""
+HASH_CAP = 9216     # the library's default R chunk capacity (entries of one LDS table)
+HASH_MAX_BITS = 11  # the library's largest fan-out
+
+
+def hash_min_bits(nR: int, cap: int = HASH_CAP) -> int:
+    """Fewest bits whose mean partition holds at most 0.9 * cap build rows (the library's
+    default rule): with fewer, partitions split into several R chunks and each of them probes
+    the partition's S slice again."""
+    if nR <= 0.9 * cap:
+        return 0
+    return min(HASH_MAX_BITS, int(math.ceil(math.log2(nR / (0.9 * cap)))))
+
+
+def hash_bits_for(nR: int, cache: dict | None = None, cap: int = HASH_CAP) -> int:
+    """Tuned fan-out (log2) for a build side of nR rows, or -1 (library default).  The table is
+    tuned at powers of two and looked up by the largest bucket <= log2(nR); a size up to twice its
+    bucket's would overflow the partitions at the bucket's fan-out, so the result is at least
+    hash_min_bits(nR)."""
     c = load() if cache is None else cache
     v = _nearest(c.get("hash_bits", {}), nR)
-    return -1 if v is None else int(v)
+    return -1 if v is None else max(int(v), hash_min_bits(nR, cap))
 
 
-def hash_bits_for_sizes(nR, cache: dict | None = None):
+def hash_bits_for_sizes(nR, cache: dict | None = None, cap: int = HASH_CAP):
     """hash_bits_for over an array of build sizes (numpy int array, -1 where nothing is tuned),
     by one lookup table over the log2 buckets instead of a call per size."""
     import numpy as np
     n = np.maximum(np.asarray(nR, dtype=np.int64), 1)
     b = np.floor(np.log2(n)).astype(np.int64)
-    table = np.array([hash_bits_for(1 << k, cache) for k in range(64)], dtype=np.int32)
-    return table[np.clip(b, 0, 63)]
+    table = np.array([hash_bits_for(1 << k, cache, cap) for k in range(64)], dtype=np.int32)
+    tuned = table[np.clip(b, 0, 63)]
+    lo = np.where(n <= 0.9 * cap, 0,
+                  np.minimum(HASH_MAX_BITS, np.ceil(np.log2(n / (0.9 * cap))))).astype(np.int32)
+    return np.where(tuned < 0, tuned, np.maximum(tuned, lo)).astype(np.int32)
 
 
 def theta_ts_for(nR: int, nS: int, cache: dict | None = None) -> int:

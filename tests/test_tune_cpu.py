@@ -13,10 +13,27 @@ CACHE = {"hash_bits": {"10": 0, "14": 1, "18": 6, "22": 10}, "theta_ts": {"12": 
 
 def test_nearest_bucket_at_or_below():
     assert tune.hash_bits_for(1 << 18, CACHE) == 6
-    assert tune.hash_bits_for((1 << 20) + 5, CACHE) == 6      # bucket 20 -> tuned 18
+    # bucket 20 -> tuned 18's 6 bits, raised to the 7 that 2^20 rows need (16K-row partitions
+    # would not fit one table)
+    assert tune.hash_bits_for((1 << 20) + 5, CACHE) == 7
     assert tune.hash_bits_for(1 << 23, CACHE) == 10
     assert tune.hash_bits_for(100, CACHE) == 0                # below every bucket: the smallest
     assert tune.hash_bits_for(1 << 18, {}) == -1              # nothing tuned: library default
+
+
+def test_fan_out_keeps_partitions_inside_one_table():
+    """The lookup never picks fewer bits than the size needs for a mean partition of at most
+    0.9 of the table capacity: fewer would split partitions into several R chunks."""
+    import numpy as np
+    cap = tune.HASH_CAP
+    assert tune.hash_min_bits(int(0.9 * cap), cap) == 0
+    assert tune.hash_min_bits(int(0.9 * cap) + 1, cap) == 1
+    assert tune.hash_min_bits(3_000_000, cap) == 9          # 3M / 2^9 = 5859 <= 8294 < 11719
+    assert tune.hash_min_bits(1 << 40, cap) == tune.HASH_MAX_BITS
+    sizes = np.unique(np.logspace(10, 22, 200, base=2).astype(np.int64))
+    got = tune.hash_bits_for_sizes(sizes, CACHE)
+    assert (sizes / (1 << got.astype(np.int64)) <= 0.9 * cap).all()
+    assert (got >= np.array([tune.hash_bits_for(1 << int(np.log2(n)), CACHE) for n in sizes])).all()
 
 
 def test_theta_tile_clamped_to_probe_side():
