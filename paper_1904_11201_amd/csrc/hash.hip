@@ -43,10 +43,15 @@ constexpr int kScatTile = kScatBlock * kScatIt;  // tuples per scatter tile (sor
 constexpr int kChunkAlign = 4 * kScatBlock;      // scatter chunks: whole 16-byte loads per thread
 constexpr int kGroups = 8;                       // chunk groups (XCDs) writing through shared cursors
 constexpr int64_t kBatchChunk = 65536;           // rows per histogram / scatter item of a batch
-constexpr int kJoinBlock = 1024;
-constexpr int kBuildItems = 10;  // R chunk entries per thread: cap <= kJoinBlock * kBuildItems
+constexpr int kJoinBlock = 1024;  // threads of a count or write workgroup of one join
+constexpr int kBatchBlock = 512;  // ... of a batch of joins, with tables of at most kBatchCap
+constexpr int kBuildItems = 10;   // R chunk entries per thread: cap <= block * kBuildItems
 constexpr int kMaxBits = 11;     // scatter: two partitions per thread; 2^11 x 8 B of LDS state
 constexpr int kMaxCap = 9728;    // R chunk entries: the write pass's table (15 B an entry) and queue fit 160 KB
+// Batches: 512-thread workgroups with tables of up to 4608 entries, so that two write workgroups
+// (four count workgroups) share a CU and one's table build overlaps another's probes.
+constexpr int kBatchCap = 4608;
+static_assert(kBatchCap <= kBatchBlock * kBuildItems, "a batch chunk fits its workgroup's registers");
 
 // Stores of the join's output pairs, which nothing here reads again: optionally non-temporal.
 #ifndef JL_NT_PAIRS
@@ -1076,11 +1081,11 @@ struct Chunk {
 // Issue every load of a chunk before any use (uniform guards only), so the chunk arrives in one
 // memory round trip.  AOS: the chunk is partitioned (key, rid) tuples; otherwise it is a range
 // of the input columns.
-template <bool AOS, bool RIDS>
+template <bool AOS, bool RIDS, int B>
 __device__ __forceinline__ void load_chunk(const JoinGeom& g, const Unit& un, Chunk<RIDS>& c)
 {
     const int tid = threadIdx.x;
-    const uint32_t nIt = (un.rN + kJoinBlock - 1) / kJoinBlock;
+    const uint32_t nIt = (un.rN + B - 1) / B;
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
         c.k[i] = 0u;
@@ -1089,7 +1094,7 @@ __device__ __forceinline__ void load_chunk(const JoinGeom& g, const Unit& un, Ch
     if (un.rN > 0) {  // every unit has rN >= 1; the guard keeps the clamped index in bounds
 #pragma unroll
         for (int i = 0; i < kBuildItems; ++i) {
-            const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+            const uint32_t e = (uint32_t)(i * B + tid);
             const uint32_t idx = un.rBeg + (e < un.rN ? e : un.rN - 1);
             if ((uint32_t)i < nIt) {
                 if constexpr (AOS) {
@@ -1123,7 +1128,7 @@ __device__ __forceinline__ Table table_of(const Unit& un, uint4* lds)
 // Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
 // HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.  pos[i]
 // receives the LDS word position of item i's slot.
-template <bool RIDS, bool HASHED>
+template <bool RIDS, bool HASHED, int B>
 __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un, const Chunk<RIDS>& c,
                                               uint4* lds, uint32_t (&pos)[kBuildItems])
 {
@@ -1138,17 +1143,17 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
         // every thread's first chunk entry is a hash of the partition (lanes past the chunk hold
         // its last one)
         const uint32_t m = (c.k[0] ^ 0x80000000u) & 0xC0000000u;
-        for (uint32_t b = tid; b < nb; b += kJoinBlock) {
+        for (uint32_t b = tid; b < nb; b += B) {
             cnt[b] = 0;
             lds[b] = make_uint4(m, m, m, m);
         }
     } else {
-        for (uint32_t b = tid; b < nb; b += kJoinBlock) cnt[b] = 0;
+        for (uint32_t b = tid; b < nb; b += B) cnt[b] = 0;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
-        const uint32_t e = (uint32_t)(i * kJoinBlock + tid);
+        const uint32_t e = (uint32_t)(i * B + tid);
         if (e < un.rN) {
             uint32_t b1, b2;
             choices(HASHED ? c.k[i] : hmix(c.k[i]), un.bits, nb, b1, b2);
@@ -1173,7 +1178,7 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
     }
     __syncthreads();
     if (marked) {  // flag the overflowed buckets, now that every slot is written
-        for (uint32_t b = tid; b < nb; b += kJoinBlock)
+        for (uint32_t b = tid; b < nb; b += B)
             if (cnt[b] > (uint32_t)kSlots) keys[b * kSlots + 3] ^= kOverflow;
         __syncthreads();
     }
@@ -1447,12 +1452,23 @@ constexpr int kManyQ = 64;  // a whole wave's worth: one tuple index of a round 
 // The write pass's LDS: its dynamic table, and the queues at file scope, so that the emitting
 // function below, which is not inlined, still addresses them as LDS.
 extern __shared__ uint4 write_lds[];
-__shared__ uint4 write_manyq[kJoinBlock / kWave * kManyQ];
+__shared__ uint4 write_manyq[kJoinBlock / kWave * kManyQ];       // 1024-thread workgroups
+__shared__ uint4 write_manyq_b[kBatchBlock / kWave * kManyQ];    // 512-thread workgroups
+
+// The queues of a B-thread workgroup (each kernel instance references one of the arrays only,
+// so its static LDS holds that one).
+template <int B>
+__device__ __forceinline__ uint4* manyq()
+{
+    static_assert(B == kJoinBlock || B == kBatchBlock, "two workgroup sizes");
+    if constexpr (B == kJoinBlock) return write_manyq;
+    else return write_manyq_b;
+}
 
 // Emits the qn queued probes of wave wv (one per lane) against the table of a unit whose chunk
 // has nb buckets (rids after the keys, claim counters after the rids): their pairs go, in queue
 // order, to the contiguous block at `at`.  Returns the end of that block.
-template <bool HASHED, bool MARKED>
+template <bool HASHED, bool MARKED, int B>
 __device__ __attribute__((noinline)) uint64_t flush_many(uint32_t nb, int bits, int wv, uint32_t qn,
                                                          uint64_t at, int2* __restrict__ out, uint64_t cap)
 {
@@ -1462,7 +1478,7 @@ __device__ __attribute__((noinline)) uint64_t flush_many(uint32_t nb, int bits, 
     t.cnt = reinterpret_cast<const uint32_t*>(write_lds + 2 * nb);
     t.nb = nb;
     t.marked = MARKED;
-    const uint4* q = write_manyq + wv * kManyQ;
+    const uint4* q = manyq<B>() + wv * kManyQ;
     // the queue was written by other lanes of this wave; LDS accesses of a wave complete in order
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1489,7 +1505,7 @@ __device__ __attribute__((noinline)) uint64_t flush_many(uint32_t nb, int bits, 
 // entries so that the key's visiting order (b1's slots, b2's, then the walk) meets them in
 // ascending order: each entry finds its rank among its key's entries and the slot of that rank
 // in the visiting order, and after a barrier stores its rid there.  Keys stay where they are.
-template <bool HASHED, bool MARKED>
+template <bool HASHED, bool MARKED, int B>
 __device__ void canonicalize(const Table& t, int bits, const Unit& un, const Chunk<true>& c,
                              const uint32_t (&pos)[kBuildItems], uint32_t* rids)
 {
@@ -1497,7 +1513,7 @@ __device__ void canonicalize(const Table& t, int bits, const Unit& un, const Chu
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
         target[i] = ~0u;
-        const uint32_t e = (uint32_t)(i * kJoinBlock + threadIdx.x);
+        const uint32_t e = (uint32_t)(i * B + threadIdx.x);
         if (e < un.rN) {
             const int32_t mine = (int32_t)c.r[i];
             uint32_t m = 0, rank = 0;
@@ -1636,10 +1652,11 @@ __device__ __forceinline__ uint32_t sched_after(const Sched& s, bool need, uint3
 #ifndef JL_HASH_COUNT_BATCH
 #define JL_HASH_COUNT_BATCH 2
 #endif
-// The count kernel's keys-only table lets two 1024-thread workgroups share a CU, so it is
-// compiled for 8 waves per SIMD (64 VGPRs); the write kernel runs one workgroup per CU.
-#define JL_COUNT_ATTR __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(8)))
-#define JL_WRITE_ATTR __launch_bounds__(kJoinBlock)
+// The count kernel's keys-only table lets two 1024-thread workgroups (four of a batch's 512)
+// share a CU, so it is compiled for 8 waves per SIMD (64 VGPRs); the write kernel for 4 (128
+// VGPRs): one 1024-thread workgroup per CU, or two of a batch's.
+#define JL_COUNT_ATTR(B) __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8)))
+#define JL_WRITE_ATTR(B) __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4)))
 constexpr int kCountBatch = JL_HASH_COUNT_BATCH;  // S keys in flight per thread in the count pass
 static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a time");
 #ifndef JL_HASH_WRITE_PROBE
@@ -1652,11 +1669,11 @@ constexpr int kWriteBatch = JL_HASH_WRITE_PROBE;  // S tuples per thread per rou
 constexpr int kWriteLoad = JL_HASH_WRITE_LOAD;    // S tuples per thread in flight in the write pass
 static_assert(kWriteLoad % kWriteBatch == 0, "write loads are probed kWriteBatch tuples at a time");
 
-template <bool AOS>
+template <bool AOS, int B>
 __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
                                             uint32_t (&x)[kWriteLoad], int32_t (&r)[kWriteLoad])
 {
-    const bool full = e0 + (uint32_t)(kWriteLoad * kJoinBlock) <= un.sN;  // uniform
+    const bool full = e0 + (uint32_t)(kWriteLoad * B) <= un.sN;  // uniform
     if (un.sN == 0) {  // no tuple to stand in for the out-of-range lanes
 #pragma unroll
         for (int i = 0; i < kWriteLoad; ++i) x[i] = 0u, r[i] = 0;
@@ -1664,7 +1681,7 @@ __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, u
     }
 #pragma unroll
     for (int i = 0; i < kWriteLoad; ++i) {
-        const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+        const uint32_t e = e0 + i * B + threadIdx.x;
         const bool ok = full || e < un.sN;
         uint32_t idx = un.sBeg + (ok ? e : 0u);
         // computed where the load is issued: hoisted out of the probe loop, the addresses of the
@@ -1685,14 +1702,14 @@ __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, u
 
 // A batch of S keys of a unit with un.sN > 0.  Out-of-range lanes read the unit's first tuple and
 // drop it (the probe masks them), so the loads carry no branch.
-template <bool AOS>
+template <bool AOS, int B>
 __device__ __forceinline__ void load_keys_of(const JoinGeom& g, const Unit& un, uint32_t e0,
                                              uint32_t (&xs)[kCountBatch])
 {
-    const bool full = e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN;  // uniform
+    const bool full = e0 + (uint32_t)(kCountBatch * B) <= un.sN;  // uniform
 #pragma unroll
     for (int i = 0; i < kCountBatch; ++i) {
-        const uint32_t e = e0 + i * kJoinBlock + threadIdx.x;
+        const uint32_t e = e0 + i * B + threadIdx.x;
         const bool ok = full || e < un.sN;
         const uint32_t idx = un.sBeg + (ok ? e : 0u);
         // no select on the loaded value: the probe masks the out-of-range lanes
@@ -1702,7 +1719,7 @@ __device__ __forceinline__ void load_keys_of(const JoinGeom& g, const Unit& un, 
 }
 
 // The same for any unit: a unit without probes loads nothing.
-template <bool AOS>
+template <bool AOS, int B>
 __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uint32_t e0,
                                           uint32_t (&xs)[kCountBatch])
 {
@@ -1711,7 +1728,7 @@ __device__ __forceinline__ void load_keys(const JoinGeom& g, const Unit& un, uin
         for (int i = 0; i < kCountBatch; ++i) xs[i] = 0u;
         return;
     }
-    load_keys_of<AOS>(g, un, e0, xs);
+    load_keys_of<AOS, B>(g, un, e0, xs);
 }
 
 // Count pass.  A workgroup walks the units of its sequence (Sched).  The S keys come in
@@ -1739,11 +1756,12 @@ __device__ __forceinline__ uint32_t semi_slot(uint32_t sBeg, uint32_t k, int wv)
     return sBeg + (k / kWave) * kJoinBlock + (uint32_t)wv * kWave + (k % kWave);
 }
 
-template <bool AOS, bool MARKED, bool FULL, bool SEMI>
+template <bool AOS, bool MARKED, bool FULL, bool SEMI, int B>
 __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& un, uint32_t e0,
                                                    const uint32_t (&xs)[kCountBatch], bool& multi,
                                                    uint32_t& many, Semi& sm)
 {
+    static_assert(!SEMI || B == kJoinBlock, "the semi-join record is laid out for 1024 threads");
     uint32_t cnt = 0;
 #pragma unroll
     for (int h = 0; h < kCountBatch; h += kProbe) {
@@ -1752,7 +1770,7 @@ __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& u
 #pragma unroll
         for (int i = 0; i < kProbe; ++i) {
             x[i] = xs[h + i];
-            ok[i] = e0 + (h + i) * kJoinBlock + threadIdx.x < un.sN;
+            ok[i] = e0 + (h + i) * B + threadIdx.x < un.sN;
         }
         cnt += probe_count<kProbe, AOS, MARKED, FULL>(t, un.bits, x, ok, multi, many, hv);
         if (SEMI && sm.rows) {  // uniform
@@ -1761,7 +1779,7 @@ __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& u
             for (int i = 0; i < kProbe; ++i) {
                 const bool hit = hv[i] > 0;  // zero for rows past the unit
                 const uint64_t bm = ballot(hit);
-                if (hit) sm.rows[semi_slot(sm.sBeg, sm.k + mask_rank(bm), wv)] = un.sBeg + e0 + (h + i) * kJoinBlock + threadIdx.x;
+                if (hit) sm.rows[semi_slot(sm.sBeg, sm.k + mask_rank(bm), wv)] = un.sBeg + e0 + (h + i) * B + threadIdx.x;
                 sm.k += (uint32_t)__builtin_popcountll(bm);
             }
         }
@@ -1770,14 +1788,14 @@ __device__ __forceinline__ uint32_t count_batch_of(const Table& t, const Unit& u
 }
 
 // A batch wholly inside the unit (the common case) probes without per-key range checks.
-template <bool AOS, bool MARKED, bool SEMI>
+template <bool AOS, bool MARKED, bool SEMI, int B>
 __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, uint32_t e0,
                                                 const uint32_t (&xs)[kCountBatch], bool& multi,
                                                 uint32_t& many, Semi& sm)
 {
-    if (e0 + (uint32_t)(kCountBatch * kJoinBlock) <= un.sN)  // uniform
-        return count_batch_of<AOS, MARKED, true, SEMI>(t, un, e0, xs, multi, many, sm);
-    return count_batch_of<AOS, MARKED, false, SEMI>(t, un, e0, xs, multi, many, sm);
+    if (e0 + (uint32_t)(kCountBatch * B) <= un.sN)  // uniform
+        return count_batch_of<AOS, MARKED, true, SEMI, B>(t, un, e0, xs, multi, many, sm);
+    return count_batch_of<AOS, MARKED, false, SEMI, B>(t, un, e0, xs, multi, many, sm);
 }
 
 // Each wave of the count and write passes takes the same probe tuples of a unit: those at
@@ -1791,9 +1809,13 @@ __device__ __forceinline__ uint32_t count_batch(const Table& t, const Unit& un, 
 // where that second block starts inside the wave's range.
 constexpr int kJoinWaves = kJoinBlock / kWave;
 constexpr int kWaveRec = 2 * kJoinWaves;  // uint64 entries per unit in the wave record
+constexpr int kWaveHalf = kJoinWaves;     // its second half (a 512-thread workgroup uses 8 + 8)
 // the write pass's queues of probes with many matches, beside its dynamic table
 constexpr size_t kWriteStaticLds = (size_t)kJoinWaves * kManyQ * 16;
+constexpr size_t kBatchStaticLds = (size_t)(kBatchBlock / kWave) * kManyQ * 16;
 static_assert(table_lds(kMaxCap, true) + kWriteStaticLds <= 160 * 1024, "write pass LDS");
+static_assert(2 * (table_lds(kBatchCap, true) + kBatchStaticLds + 256) <= 160 * 1024,
+              "two batch write workgroups per CU");
 
 // End of a unit in the count pass: lane totals -> wave totals -> the unit's total in counts[u],
 // the waves' starts in wave_off[u][1..kJoinWaves) and, in wave_off[u][kJoinWaves + w], each
@@ -1801,6 +1823,7 @@ static_assert(table_lds(kMaxCap, true) + kWriteStaticLds <= 160 * 1024, "write p
 // probe row of the wave) and its count of probe rows with matches when the semi-join is recorded
 // (high 32 bits, else 0); sh: kJoinWaves + 1 words of LDS.  rec_word (partitioned joins): the
 // second word of the unit's record, which receives the canonical-order flag as well.
+template <int B>
 __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi,
                                             uint32_t semi_rows, uint32_t u, uint64_t* __restrict__ counts,
                                             uint64_t* __restrict__ wave_off, uint64_t* sh, uint32_t* rec_word)
@@ -1811,13 +1834,13 @@ __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_m
     const int wv = threadIdx.x / kWave;
     if (lane_id() == 0) {
         sh[wv] = wt | (wm ? (1ull << 63) : 0ull);
-        wave_off[(size_t)u * kWaveRec + kJoinWaves + wv] = (wt - wmany) | ((uint64_t)semi_rows << 32);
+        wave_off[(size_t)u * kWaveRec + kWaveHalf + wv] = (wt - wmany) | ((uint64_t)semi_rows << 32);
     }
     __syncthreads();
-    if (threadIdx.x < kJoinWaves) {
+    if (threadIdx.x < (B / kWave)) {
         uint64_t before = 0, sum = 0, any = 0;
 #pragma unroll
-        for (int w = 0; w < kJoinWaves; ++w) {
+        for (int w = 0; w < (B / kWave); ++w) {
             const uint64_t v = sh[w];
             const uint64_t c = v & ~(1ull << 63);
             before += w < (int)threadIdx.x ? c : 0ull;
@@ -1841,6 +1864,7 @@ constexpr int64_t kFuseScanMax = (int64_t)kJoinBlock * kFuseScanPer;
 // Exclusive scan of counts[0, U) in place by one workgroup, kFuseScanPer consecutive counts per
 // thread; entries U..Umax-1 are set to the sum, and *total receives it.  wsum: kJoinBlock / 64
 // words of LDS.
+template <int B>
 __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, uint64_t* total,
                                   uint64_t* pub, uint64_t* wsum)
 {
@@ -1858,7 +1882,7 @@ __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, ui
     __syncthreads();
     uint64_t run = inc - s, sum = 0;
 #pragma unroll
-    for (int w = 0; w < kJoinBlock / kWave; ++w) {
+    for (int w = 0; w < B / kWave; ++w) {
         const uint64_t t = wsum[w];
         run += w < wv ? t : 0;
         sum += t;
@@ -1877,15 +1901,15 @@ __device__ void scan_counts_block(uint64_t* counts, uint32_t U, int64_t Umax, ui
 // done: NULL, or a zeroed arrival counter; then the last workgroup to arrive scans the counts
 // (Umax <= kFuseScanMax) and writes the sum to *total and, when pub is not NULL, to that pinned
 // host slot.
-template <bool AOS, bool SEMI>
-__global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
+template <bool AOS, bool SEMI, int B>
+__global__ JL_COUNT_ATTR(B) void join_count_k(JoinGeom g, uint64_t* __restrict__ counts,
                                            uint64_t* __restrict__ wave_off,
                                            uint32_t* __restrict__ done, uint64_t* __restrict__ total,
                                            uint64_t* pub)
 {
     extern __shared__ uint4 tab[];
-    __shared__ uint64_t wsum[kJoinWaves + 1];
-    constexpr uint32_t kB = kJoinBlock * kCountBatch;  // keys per batch
+    __shared__ uint64_t wsum[B / kWave + 1];
+    constexpr uint32_t kB = B * kCountBatch;  // keys per batch
     const uint32_t U = unit_total(g);
     if (g.stamp_at && blockIdx.x == 0 && threadIdx.x == 0) *g.stamp_at = g.stamp;  // for the write pass
     __shared__ uint32_t slot[2];
@@ -1896,16 +1920,16 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
     Unit un{};
     if (u < U) {
         un = decode_unit<AOS>(g, u);
-        load_keys<AOS>(g, un, 0, xa);
+        load_keys<AOS, B>(g, un, 0, xa);
     }
     while (u < U) {
         const bool need = sched_need(sc, nxi);
         uint32_t tk = 0;
         if (need && threadIdx.x == 0) tk = atomicAdd(sc.ticket, 1u);
         Chunk<false> ch;
-        load_chunk<AOS, false>(g, un, ch);
+        load_chunk<AOS, false, B>(g, un, ch);
         uint32_t pos[kBuildItems];
-        const Table t = insert_chunk<false, AOS>(g, un, ch, tab, pos);
+        const Table t = insert_chunk<false, AOS, B>(g, un, ch, tab, pos);
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
         const bool more = nxi < U;
         const Unit nx = more ? decode_unit<AOS>(g, nxi) : Unit{};
@@ -1917,22 +1941,22 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
             for (uint32_t e0 = 0; e0 < un.sN; e0 += 2 * kB) {
                 const uint32_t e1 = e0 + kB, e2 = e1 + kB;
                 uint32_t ma = 0, mb = 0;
-                load_keys_of<AOS>(g, un, e1 < un.sN ? e1 : e0, xb);
-                cnt += count_batch<AOS, M, SEMI>(t, un, e0, xa, multi, ma, sm);
+                load_keys_of<AOS, B>(g, un, e1 < un.sN ? e1 : e0, xb);
+                cnt += count_batch<AOS, M, SEMI, B>(t, un, e0, xa, multi, ma, sm);
                 const bool here = e2 < un.sN, there = !here && more && nx.sN > 0;
-                load_keys_of<AOS>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
-                cnt += count_batch<AOS, M, SEMI>(t, un, e1, xb, multi, mb, sm);  // every lane masked past the unit
+                load_keys_of<AOS, B>(g, there ? nx : un, here ? e2 : (there ? 0u : e0), xa);
+                cnt += count_batch<AOS, M, SEMI, B>(t, un, e1, xb, multi, mb, sm);  // every lane masked past the unit
                 many += (uint64_t)ma + mb;
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
-        if (un.sN == 0 && more) load_keys<AOS>(g, nx, 0, xa);
+        if (un.sN == 0 && more) load_keys<AOS, B>(g, nx, 0, xa);
         sched_put(sc, need, tk, slot);
         // a partitioned join's record is read only by this workgroup in this pass (it decoded it
         // before), so the flag can go into it
         uint32_t* rec_word = AOS ? const_cast<uint32_t*>(&g.urec[u].y) : nullptr;
-        unit_totals(cnt, many, multi, sm.k, u, counts, wave_off, wsum, rec_word);  // ends with a barrier
+        unit_totals<B>(cnt, many, multi, sm.k, u, counts, wave_off, wsum, rec_word);  // ends with a barrier
         const uint32_t nn = sched_after(sc, need, nxi, slot);
         u = nxi;
         nxi = nn;
@@ -1951,13 +1975,13 @@ __global__ JL_COUNT_ATTR void join_count_k(JoinGeom g, uint64_t* __restrict__ co
         __syncthreads();
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            scan_counts_block(counts, U, g.Umax, total, pub, wsum);
+            scan_counts_block<B>(counts, U, g.Umax, total, pub, wsum);
         }
         return;
     }
     // units past the device-side total must read as zero for the scan over Umax entries
-    for (int64_t i = (int64_t)U + (int64_t)blockIdx.x * kJoinBlock + threadIdx.x; i < g.Umax;
-         i += (int64_t)gridDim.x * kJoinBlock)
+    for (int64_t i = (int64_t)U + (int64_t)blockIdx.x * B + threadIdx.x; i < g.Umax;
+         i += (int64_t)gridDim.x * B)
         counts[i] = 0;
 }
 
@@ -1991,8 +2015,8 @@ __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint6
 // tuples from the start the count pass recorded for it, in (batch, tuple, lane) order, with one
 // wave-wide scan per round and no shared cursor: the output depends on the input and the plan
 // only, not on which workgroup takes a unit.
-template <bool AOS, bool SEMI>
-__global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restrict__ offsets,
+template <bool AOS, bool SEMI, int B>
+__global__ JL_WRITE_ATTR(B) void join_write_k(JoinGeom g, const uint64_t* __restrict__ offsets,
                                            const uint64_t* __restrict__ wave_off,
                                            const uint64_t* __restrict__ total,
                                            int2* __restrict__ out, uint64_t cap)
@@ -2004,7 +2028,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     const uint32_t U = unit_total(g);
     const bool contig = g.contig != 0;  // uniform
     const int wv = uniform((int32_t)(threadIdx.x / kWave));
-    uint4* q = write_manyq + wv * kManyQ;  // this wave's queue of probes with many matches
+    uint4* q = manyq<B>() + wv * kManyQ;  // this wave's queue of probes with many matches
     uint32_t qn = 0;                 // uniform: its length
     __shared__ uint32_t slot[2];
     Sched sc = make_sched(U, contig, g.sched ? g.sched + 1 : nullptr);
@@ -2022,8 +2046,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
     int32_t nr[kWriteLoad];
     if (u < U) {
         un = decode_unit<AOS>(g, u);
-        load_chunk<AOS, true>(g, un, ch);
-        if constexpr (!SEMI) load_tuples<AOS>(g, un, 0, nx, nr);
+        load_chunk<AOS, true, B>(g, un, ch);
+        if constexpr (!SEMI) load_tuples<AOS, B>(g, un, 0, nx, nr);
     }
     Unit tu{};  // the unit whose chunk is in the table (rN == 0: none yet)
     const cptr<uint64_t> offs = as_const(offsets);
@@ -2037,17 +2061,17 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
         const bool next_in_run = contig && sc.pos + 1 < sc.head;  // uniform
         if (!in_run || tu.rN == 0 || !same_chunk(un, tu)) {  // uniform: a new chunk (loaded in ch)
             const bool order = chunk_needs_order<AOS>(g, wave_off, u, in_run ? run_end : 0u, un);
-            const Table tb = insert_chunk<true, AOS>(g, un, ch, tab, pos);
+            const Table tb = insert_chunk<true, AOS, B>(g, un, ch, tab, pos);
             if (order) {
                 uint32_t* rids = reinterpret_cast<uint32_t*>(tab + tb.nb);
-                if (AOS && tb.marked) canonicalize<AOS, true>(tb, un.bits, un, ch, pos, rids);
-                else canonicalize<AOS, false>(tb, un.bits, un, ch, pos, rids);
+                if (AOS && tb.marked) canonicalize<AOS, true, B>(tb, un.bits, un, ch, pos, rids);
+                else canonicalize<AOS, false, B>(tb, un.bits, un, ch, pos, rids);
             }
             tu = un;
         }
         // this wave's first output slot in unit u, and the start of its block of many-match pairs
         uint64_t cursor = uniform(offs[u]) + (wv ? uniform(wo[(size_t)u * kWaveRec + wv]) : 0ull);
-        const uint64_t wrec = uniform(wo[(size_t)u * kWaveRec + kJoinWaves + wv]);
+        const uint64_t wrec = uniform(wo[(size_t)u * kWaveRec + kWaveHalf + wv]);
         uint64_t cmany = cursor + (uint32_t)wrec;
         const uint32_t semi_rows = (uint32_t)(wrec >> 32);  // the semi-join's rows of this wave
 #if JL_DEBUG
@@ -2055,7 +2079,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
 #endif
         const Table t = table_of<true, AOS>(un, tab);
         const Unit nxt = more ? decode_unit<AOS>(g, nxi) : Unit{};
-        if (more && (!next_in_run || !same_chunk(nxt, un))) load_chunk<AOS, true>(g, nxt, ch);
+        if (more && (!next_in_run || !same_chunk(nxt, un))) load_chunk<AOS, true, B>(g, nxt, ch);
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(t.rids);
         auto batches = [&](auto marked) {
             constexpr bool M = decltype(marked)::value;
@@ -2100,7 +2124,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                         if (bm) {  // uniform
                             const uint32_t c = (uint32_t)__builtin_popcountll(bm);
                             if (qn + c > (uint32_t)kManyQ) {
-                                cmany = flush_many<AOS, M>(t.nb, un.bits, wv, qn, cmany, out, cap);
+                                cmany = flush_many<AOS, M, B>(t.nb, un.bits, wv, qn, cmany, out, cap);
                                 qn = 0;
                             }
                             if (many) q[qn + mask_rank(bm)] = make_uint4(x[i], (uint32_t)srid[i], m[i], 0u);
@@ -2126,8 +2150,8 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                     round(cx, cr, [&](int j) { return k0 + j * kWave + lane_id() < semi_rows; });
                 }
             } else {
-                if (SEMI) load_tuples<AOS>(g, un, 0, nx, nr);  // not loaded ahead in this mode
-                for (uint32_t e0 = 0; e0 < un.sN; e0 += kJoinBlock * kWriteLoad) {
+                if (SEMI) load_tuples<AOS, B>(g, un, 0, nx, nr);  // not loaded ahead in this mode
+                for (uint32_t e0 = 0; e0 < un.sN; e0 += B * kWriteLoad) {
                     uint32_t cx[kWriteLoad];
                     int32_t cr[kWriteLoad];
 #pragma unroll
@@ -2135,19 +2159,19 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
                         cx[i] = nx[i];
                         cr[i] = nr[i];
                     }
-                    if (e0 + kJoinBlock * kWriteLoad < un.sN)
-                        load_tuples<AOS>(g, un, e0 + kJoinBlock * kWriteLoad, nx, nr);
+                    if (e0 + B * kWriteLoad < un.sN)
+                        load_tuples<AOS, B>(g, un, e0 + B * kWriteLoad, nx, nr);
                     else if (more)
-                        load_tuples<AOS>(g, nxt, 0, nx, nr);
-                    round(cx, cr, [&](int j) { return e0 + j * kJoinBlock + threadIdx.x < un.sN; });
+                        load_tuples<AOS, B>(g, nxt, 0, nx, nr);
+                    round(cx, cr, [&](int j) { return e0 + j * B + threadIdx.x < un.sN; });
                 }
             }
         };
         if (AOS && t.marked) batches(std::true_type{});
         else batches(std::false_type{});
         if (qn) {  // uniform: the queue must be empty before the table changes
-            if (AOS && t.marked) cmany = flush_many<AOS, true>(t.nb, un.bits, wv, qn, cmany, out, cap);
-            else cmany = flush_many<AOS, false>(t.nb, un.bits, wv, qn, cmany, out, cap);
+            if (AOS && t.marked) cmany = flush_many<AOS, true, B>(t.nb, un.bits, wv, qn, cmany, out, cap);
+            else cmany = flush_many<AOS, false, B>(t.nb, un.bits, wv, qn, cmany, out, cap);
             qn = 0;
         }
 #if JL_DEBUG
@@ -2156,7 +2180,7 @@ __global__ JL_WRITE_ATTR void join_write_k(JoinGeom g, const uint64_t* __restric
             atomicAdd(reinterpret_cast<unsigned long long*>(&g.dbg[u]), (unsigned long long)wrote);
 #endif
         if constexpr (!SEMI)
-            if (un.sN == 0 && more) load_tuples<AOS>(g, nxt, 0, nx, nr);
+            if (un.sN == 0 && more) load_tuples<AOS, B>(g, nxt, 0, nx, nr);
         sched_put(sc, need, tk, slot);
         __syncthreads();
         const uint32_t nn = sched_after(sc, need, nxi, slot);
@@ -2329,19 +2353,25 @@ static hipError_t set_attrs()
     if (g_attr_done) return hipSuccess;
     const int big = 160 * 1024 - 4096;
     const int write_max = (int)(160 * 1024 - kWriteStaticLds - 256);  // beside its static queue
+    const int write_max_b = (int)(160 * 1024 - kBatchStaticLds - 256);
     const void* fns[] = {
         (const void*)scatter_k<true, false>, (const void*)scatter_k<false, false>,
         (const void*)scatter_k<true, true>, (const void*)scatter_k<false, true>, (const void*)hist_k,
-        (const void*)join_count_k<true, false>, (const void*)join_count_k<false, false>,
-        (const void*)join_count_k<true, true>,
+        (const void*)join_count_k<true, false, kJoinBlock>, (const void*)join_count_k<false, false, kJoinBlock>,
+        (const void*)join_count_k<true, true, kJoinBlock>, (const void*)join_count_k<true, false, kBatchBlock>,
     };
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
         if (e != hipSuccess) return e;
     }
-    for (const void* f : {(const void*)join_write_k<true, false>, (const void*)join_write_k<false, false>,
-                          (const void*)join_write_k<true, true>}) {
+    for (const void* f : {(const void*)join_write_k<true, false, kJoinBlock>, (const void*)join_write_k<false, false, kJoinBlock>,
+                          (const void*)join_write_k<true, true, kJoinBlock>}) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, write_max);
+        if (e != hipSuccess) return e;
+    }
+    {
+        const hipError_t e = hipFuncSetAttribute((const void*)join_write_k<true, false, kBatchBlock>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, write_max_b);
         if (e != hipSuccess) return e;
     }
     g_attr_done = true;
@@ -2640,9 +2670,9 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
                              ? reinterpret_cast<uint32_t*>(ws + pl.off_done) : nullptr;
         uint64_t* wave_off = reinterpret_cast<uint64_t*>(ws + pl.off_wave);
         prof::Scope pc(st, "hash.count");
-        if (pl.single) join_count_k<false, false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, nullptr, total, nullptr);
-        else if (pl.semi) join_count_k<true, true><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
-        else join_count_k<true, false><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
+        if (pl.single) join_count_k<false, false, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, nullptr, total, nullptr);
+        else if (pl.semi) join_count_k<true, true, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
+        else join_count_k<true, false, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, counts, wave_off, done, total, pub);
         e = hipGetLastError();
         if (e != hipSuccess || done) return e;
     }
@@ -2664,9 +2694,9 @@ hipError_t hash_write(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
     const size_t lds = table_lds((uint32_t)pl.cap, true);
     int2* out = reinterpret_cast<int2*>(pairs);
     prof::Scope pw(st, "hash.write");
-    if (pl.single) join_write_k<false, false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
-    else if (pl.semi) join_write_k<true, true><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
-    else join_write_k<true, false><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    if (pl.single) join_write_k<false, false, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    else if (pl.semi) join_write_k<true, true, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
+    else join_write_k<true, false, kJoinBlock><<<grid, kJoinBlock, lds, st>>>(g, offsets, wave_off, total, out, cap);
     return hipGetLastError();
 }
 
@@ -2773,7 +2803,7 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
 {
     BatchPlan bp{};
     bp.njobs = njobs;
-    bp.cap = env_cap();
+    bp.cap = env_cap() < kBatchCap ? env_cap() : kBatchCap;  // the batch kernels' tables
     bp.slice = (int)tune_get(TUNE_HASH_SLICE, 32768);
     if (bp.slice < 1024) bp.slice = 1024;
     bp.ordered = ordered_knob();
@@ -2823,10 +2853,13 @@ int hash_batch_plan(int njobs, const join_job_t* jobs, int num_cus, BatchPlan* o
     temp = temp > t1 ? temp : t1;
     bp.off_temp = take(off, temp + 8);
     bp.bytes = off;
+    // 512-thread workgroups: four count workgroups (64 VGPRs) or two write workgroups (128
+    // VGPRs, and their static queues) fit a CU when their tables do
     auto grid_for = [&](bool rids) {
-        int per_cu = (int)((160 * 1024) / (table_lds((uint32_t)bp.cap, rids) + 128));
+        const size_t lds = table_lds((uint32_t)bp.cap, rids) + (rids ? kBatchStaticLds : 0) + 256;
+        int per_cu = (int)((160 * 1024) / lds);
         if (per_cu < 1) per_cu = 1;
-        if (per_cu > 2) per_cu = 2;
+        if (per_cu > (rids ? 2 : 4)) per_cu = rids ? 2 : 4;
         return num_cus * per_cu;
     };
     bp.gridCount = grid_for(false);
@@ -2979,7 +3012,7 @@ hipError_t hash_batch_count(const BatchPlan& bp, char* ws, uint64_t* offsets, hi
     if (bp.Umax > 0) {
         const JoinGeom g = batch_geom(bp, ws);
         prof::Scope pc(st, "hash.count");
-        join_count_k<true, false><<<(unsigned)bp.gridCount, kJoinBlock, table_lds((uint32_t)bp.cap, false), st>>>(
+        join_count_k<true, false, kBatchBlock><<<(unsigned)bp.gridCount, kBatchBlock, table_lds((uint32_t)bp.cap, false), st>>>(
             g, counts, reinterpret_cast<uint64_t*>(ws + bp.off_wave), nullptr, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -3001,7 +3034,7 @@ hipError_t hash_batch_write(const BatchPlan& bp, char* ws, int32_t* pairs, uint6
     if (e != hipSuccess) return e;
     const JoinGeom g = batch_geom(bp, ws);
     prof::Scope pw(st, "hash.write");
-    join_write_k<true, false><<<(unsigned)bp.gridWrite, kJoinBlock, table_lds((uint32_t)bp.cap, true), st>>>(
+    join_write_k<true, false, kBatchBlock><<<(unsigned)bp.gridWrite, kBatchBlock, table_lds((uint32_t)bp.cap, true), st>>>(
         g, reinterpret_cast<const uint64_t*>(ws + bp.off_counts),
         reinterpret_cast<const uint64_t*>(ws + bp.off_wave), reinterpret_cast<const uint64_t*>(ws),
         reinterpret_cast<int2*>(pairs), cap);

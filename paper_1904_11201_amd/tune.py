@@ -5,7 +5,7 @@ The paper picks its cut of the work, the reducer count alpha, by measurement (Se
 partition fan-out (per build size; used for every join of a batch) and the theta join's S tile
 (per relation size).  Only speed depends on these choices; every candidate gives the same result.
 
-    python -m paper_1904_11201_amd.tune [--quick] [--out PATH]
+    python -m paper_1904_11201_amd.tune [--quick] [--out PATH] [--only hash|theta]
 
 writes a JSON cache (default: tune_cache.json next to this file) that Batch / hash_join_batch and
 theta_join(tuned=True) read through `load()`.
@@ -55,7 +55,7 @@ def _nearest(table: dict, n: int):
     return table[str(below[-1] if below else keys[0])]
 
 
-HASH_CAP = 9216     # the library's default R chunk capacity (entries of one LDS table)
+HASH_CAP = 4608     # entries of one LDS table of a batched join (the library's batch capacity)
 HASH_MAX_BITS = 11  # the library's largest fan-out
 
 
@@ -69,7 +69,8 @@ def hash_min_bits(nR: int, cap: int = HASH_CAP) -> int:
 
 
 def hash_bits_for(nR: int, cache: dict | None = None, cap: int = HASH_CAP) -> int:
-    """Tuned fan-out (log2) for a build side of nR rows, or -1 (library default).  The table is
+    """Tuned fan-out (log2) for a build side of nR rows of a batched join, or -1 (library
+    default).  The table is
     tuned at powers of two and looked up by the largest bucket <= log2(nR); a size up to twice its
     bucket's would overflow the partitions at the bucket's fan-out, so the result is at least
     hash_min_bits(nR)."""
@@ -130,7 +131,7 @@ def tune_hash(buckets, reps: int = 3, log=print) -> dict:
     import torch
     from . import _native
     from .join import Batch, Job, Relation
-    cap = _native.tune_get("hash.cap", 9216)
+    cap = min(_native.tune_get("hash.cap", 9216), HASH_CAP)  # the batch kernels' table
     out = {}
     g = torch.Generator(device="cuda")
     for b in buckets:
@@ -200,6 +201,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="fewer buckets and repetitions")
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--only", choices=("hash", "theta"),
+                    help="measure one table and keep the other from the existing cache")
     args = ap.parse_args(argv)
     import torch
     reps = 2 if args.quick else 3
@@ -207,10 +210,11 @@ def main(argv=None):
     tb = [12, 16] if args.quick else [12, 14, 16, 18]
     t0 = time.time()
     log = lambda m: print(m, flush=True)  # noqa: E731
+    old = load(args.out) if args.only else {}
     cache = {
         "device": torch.cuda.get_device_name(0),
-        "hash_bits": tune_hash(hb, reps, log),
-        "theta_ts": tune_theta(tb, reps, log),
+        "hash_bits": tune_hash(hb, reps, log) if args.only != "theta" else old.get("hash_bits", {}),
+        "theta_ts": tune_theta(tb, reps, log) if args.only != "hash" else old.get("theta_ts", {}),
     }
     with open(args.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

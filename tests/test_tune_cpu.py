@@ -13,10 +13,11 @@ CACHE = {"hash_bits": {"10": 0, "14": 1, "18": 6, "22": 10}, "theta_ts": {"12": 
 
 def test_nearest_bucket_at_or_below():
     assert tune.hash_bits_for(1 << 18, CACHE) == 6
-    # bucket 20 -> tuned 18's 6 bits, raised to the 7 that 2^20 rows need (16K-row partitions
-    # would not fit one table)
-    assert tune.hash_bits_for((1 << 20) + 5, CACHE) == 7
-    assert tune.hash_bits_for(1 << 23, CACHE) == 10
+    # bucket 20 -> tuned 18's 6 bits, raised to the 8 that 2^20 rows need with 4608-entry tables
+    # (16K-row partitions would take four tables, each probing the partition's S slice)
+    assert tune.hash_bits_for((1 << 20) + 5, CACHE) == 8
+    assert tune.hash_bits_for((1 << 20) + 5, CACHE, cap=9216) == 7
+    assert tune.hash_bits_for(1 << 23, CACHE) == 11
     assert tune.hash_bits_for(100, CACHE) == 0                # below every bucket: the smallest
     assert tune.hash_bits_for(1 << 18, {}) == -1              # nothing tuned: library default
 
@@ -28,7 +29,8 @@ def test_fan_out_keeps_partitions_inside_one_table():
     cap = tune.HASH_CAP
     assert tune.hash_min_bits(int(0.9 * cap), cap) == 0
     assert tune.hash_min_bits(int(0.9 * cap) + 1, cap) == 1
-    assert tune.hash_min_bits(3_000_000, cap) == 9          # 3M / 2^9 = 5859 <= 8294 < 11719
+    assert tune.hash_min_bits(3_000_000, cap) == 10         # 3M / 2^10 = 2930 <= 4147 < 5859
+    assert tune.hash_min_bits(3_000_000, 9216) == 9         # 3M / 2^9 = 5859 <= 8294 < 11719
     assert tune.hash_min_bits(1 << 40, cap) == tune.HASH_MAX_BITS
     sizes = np.unique(np.logspace(10, 22, 200, base=2).astype(np.int64))
     got = tune.hash_bits_for_sizes(sizes, CACHE)
@@ -45,7 +47,7 @@ def test_theta_tile_clamped_to_probe_side():
 def test_apply_bits_keeps_explicit_choices():
     jobs = [_J(1 << 14), _J(1 << 22, bits=3)]
     tune.apply_bits(jobs, CACHE)
-    assert [j.bits for j in jobs] == [1, 3]
+    assert [j.bits for j in jobs] == [2, 3]  # 2^14 rows: tuned 1 bit, raised to fit 4608 entries
 
 
 def test_bits_for_sizes_matches_the_per_size_lookup():
