@@ -1139,10 +1139,11 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
     uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
     const bool marked = HASHED && un.bits >= 2;
     if (marked) {
-        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed);
-        // every thread's first chunk entry is a hash of the partition (lanes past the chunk hold
-        // its last one)
-        const uint32_t m = (c.k[0] ^ 0x80000000u) & 0xC0000000u;
+        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed).
+        // The write pass loaded its chunk a unit ahead, and every thread's first entry is a hash
+        // of the partition (lanes past the chunk hold its last one); the count pass loads the
+        // chunk now, so one scalar load lets the table be cleared while the chunk is in flight.
+        const uint32_t m = ((RIDS ? c.k[0] : (uint32_t)g.rt[un.rBeg].x) ^ 0x80000000u) & 0xC0000000u;
         for (uint32_t b = tid; b < nb; b += B) {
             cnt[b] = 0;
             lds[b] = make_uint4(m, m, m, m);
@@ -1560,13 +1561,13 @@ __device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u
 }
 
 // The sequence of units a workgroup of the count or write pass takes.  A fixed share per
-// workgroup leaves CUs idle at the end of a pass: units differ in size (batches), CUs in speed,
-// and of two count workgroups on one CU the older one runs ahead.  With a ticket counter (two
-// words of the workspace, zero before the pass), each workgroup takes a static head, half of
-// its even share (a contiguous run for the write pass of one join, whose consecutive units of
-// one R chunk keep the table, else round robin), and then units handed out one at a time after
-// all static heads, so that faster workgroups take more.  Without one, the whole share is static
-// as before.  The unit two places ahead is fixed while a unit runs (its ticket taken at the
+// workgroup leaves CUs idle at the end of a batch's passes: its units differ widely in size, and
+// of the count workgroups sharing a CU the older ones run ahead.  With a ticket counter (words
+// of the workspace, zero before the pass; batches), each workgroup takes a static head, half of
+// its even share in round-robin order, and then units handed out one at a time after all static
+// heads, so that faster workgroups take more.  Without one (one join, whose units are even), the
+// whole share is static: round robin, or for the write pass a contiguous run, whose consecutive
+// units of one R chunk keep the table.  The unit two places ahead is fixed while a unit runs (its ticket taken at the
 // unit's start, read back after the unit's last barrier), so the loads the passes issue ahead
 // for the next unit never wait for a ticket.
 constexpr uint32_t kTicketed = 0xFFFFFFFFu;
@@ -2288,10 +2289,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool 
         pl.off_tot = off;
         pl.off_grpS = off + (size_t)2 * pl.P * 4;
         pl.off_grpR = pl.off_grpS + (size_t)kGroups * pl.P * 4;
-        // the count kernel's arrival counter and the passes' unit tickets (Sched): cleared with
-        // the sizes and shares
-        pl.off_done = pl.off_grpR + (size_t)kGroups * pl.P * 4;
-        off = align_up(pl.off_done + 16);
+        pl.off_done = pl.off_grpR + (size_t)kGroups * pl.P * 4;  // cleared with the sizes and shares
+        off = align_up(pl.off_done + 4);
         pl.off_baseR = off;
         off = align_up(off + (size_t)(pl.P + 1) * 4);
         pl.off_baseS = off;
@@ -2588,7 +2587,9 @@ static JoinGeom make_geom(const HashPlan& pl, const join_rel_t& R, const join_re
         g.urec = reinterpret_cast<const uint4*>(ws + pl.off_umap);
         g.Uptr = reinterpret_cast<const uint32_t*>(ws + 8);
         g.P = pl.P;
-        g.sched = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 1;
+        // one join's units are even and its write pass keeps a table across consecutive units of
+        // one R chunk: static shares (tickets measured slower on 16M x 64M and 1M x 64M)
+        g.sched = nullptr;
     }
     return g;
 }
@@ -2614,7 +2615,7 @@ hipError_t hash_count(const HashPlan& pl, const join_rel_t& R, const join_rel_t&
             // a prebuilt R keeps its sizes: only the S sizes and shares are cleared
             prof::Scope pz(st, "hash.plan");
             uint32_t* z = pre ? totS : totR;
-            const int64_t nz = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 4 - z;
+            const int64_t nz = reinterpret_cast<uint32_t*>(ws + pl.off_done) + 1 - z;
             zero_u32_k<<<(unsigned)ceil_div(nz, 256), 256, 0, st>>>(z, nz);
         }
         e = hipGetLastError();
