@@ -17,6 +17,8 @@
  *
  * Knobs (name, environment variable, meaning):
  *   "hash.cap"               JOIN_HASH_CAP                R entries per LDS table, 64..9728
+ *                                                         (batches: at most 4608, the table of
+ *                                                         their 512-thread workgroups)
  *   "hash.slice"             JOIN_HASH_SLICE              S rows per work unit, >= 1024
  *   "hash.bits"              JOIN_HASH_BITS               single-join fan-out log2, -1 automatic
  *   "hash.single_max_chunks" JOIN_HASH_SINGLE_MAX_CHUNKS  R up to this many tables: no partitioning
