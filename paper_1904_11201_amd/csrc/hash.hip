@@ -2232,6 +2232,16 @@ static int env_cap()
     return (int)cap;
 }
 
+// Persistent grid of one join's count (rids false) or write kernel: as many 1024-thread
+// workgroups per CU as the LDS table allows, at most 2.
+static int join_grid(int num_cus, int cap, bool rids)
+{
+    int per_cu = (int)((160 * 1024) / (table_lds((uint32_t)cap, rids) + 128));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 2) per_cu = 2;
+    return num_cus * per_cu;
+}
+
 HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool semi)
 {
     HashPlan pl{};
@@ -2246,6 +2256,15 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool 
     pl.ordered = ordered_knob();
     const int forced_bits = pl.prebuilt ? prebuilt_bits : (int)tune_get(TUNE_HASH_BITS, -1);
     pl.single = !pl.prebuilt && (forced_bits == 0 || (forced_bits < 0 && nR <= single_max));
+    if (semi && !pl.single) {
+        // The semi-join's write pass visits about the matching probe rows only, so its units pay
+        // their fixed costs (table build, per-unit loads) for few rows: S slices up to one unit
+        // per count workgroup, at most 128K rows (1M x 64M, 1% matching: write 56 -> 32 us, the
+        // count pass unchanged).
+        int64_t sl = nS / join_grid(num_cus, cap, false) / 1024 * 1024;
+        if (sl > 131072) sl = 131072;
+        if (sl > pl.slice) pl.slice = (int)sl;
+    }
     size_t off = 256;  // header: [0] uint64 total, [8] uint32 units
     if (pl.single) {
         pl.bits = 0;
@@ -2330,15 +2349,8 @@ HashPlan hash_plan(int64_t nR, int64_t nS, int num_cus, int prebuilt_bits, bool 
     pl.off_dbg = off;  // last: the checking build's per-unit written counts
     off = align_up(off + (JL_DEBUG ? (size_t)(pl.Umax > 0 ? pl.Umax : 1) * 8 : 0));
     pl.bytes = off;
-    // persistent grids of the join kernels: as many workgroups per CU as the LDS table allows
-    auto grid_for = [&](bool rids) {
-        int per_cu = (int)((160 * 1024) / (table_lds((uint32_t)cap, rids) + 128));
-        if (per_cu < 1) per_cu = 1;
-        if (per_cu > 2) per_cu = 2;  // 1024-thread workgroups: at most 2 per CU
-        return num_cus * per_cu;
-    };
-    pl.gridCount = grid_for(false);
-    pl.gridWrite = grid_for(true);
+    pl.gridCount = join_grid(num_cus, cap, false);
+    pl.gridWrite = join_grid(num_cus, cap, true);
     pl.stamp = plan_stamp({JOIN_KIND_HASH, pl.nR, pl.nS, pl.single, pl.prebuilt, pl.ordered, pl.semi, pl.bits, pl.P, pl.cap,
                            pl.slice, pl.nSs, pl.chR, pl.chS, pl.Umax, pl.gridCount, pl.gridWrite,
                            (int64_t)pl.bytes});
