@@ -58,7 +58,13 @@ static_assert(kBatchCap <= kBatchBlock * kBuildItems, "a batch chunk fits its wo
 #define JL_NT_PAIRS 1
 #endif
 __device__ __forceinline__ void put(int2* p, int2 v) { *p = v; }
-__device__ __forceinline__ void put_pair(int2* p, int2 v)
+// A pair pointer in the global address space.  A function that is not inlined receives its
+// pointer arguments as generic (flat) pointers, and a flat store also counts against the LDS
+// wait counter, so every LDS wait after it would wait for the store to reach memory.
+typedef __attribute__((address_space(1))) int2 global_int2;
+
+template <typename P>
+__device__ __forceinline__ void put_pair(P* p, int2 v)
 {
 #if JL_NT_PAIRS
     __builtin_nontemporal_store(v.x, &p->x);
@@ -1388,10 +1394,10 @@ __device__ __forceinline__ void sort8(uint32_t (&v)[8])
 //    values are the matches in order either way.
 //  * A walk with up to kEmitSort matches (rare): gathered in registers, each written at its rank.
 //  * More: the table was put in canonical order, so the visiting order is ascending.
-template <bool HASHED, bool MARKED>
+template <bool HASHED, bool MARKED, typename P>
 __device__ __forceinline__ void emit_many(const Table& t, int bits, uint32_t x, int32_t srid,
                                           uint64_t slot, const uint32_t* rw,
-                                          int2* __restrict__ out, uint64_t cap)
+                                          P* __restrict__ out, uint64_t cap)
 {
     uint32_t b1, b2;
     choices(HASHED ? x : hmix(x), bits, t.nb, b1, b2);
@@ -1490,7 +1496,7 @@ __device__ __attribute__((noinline)) uint64_t flush_many(uint32_t nb, int bits, 
     const uint64_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
     if (mine)
         emit_many<HASHED, MARKED>(t, bits, e.x, (int32_t)e.y, at + (inc - e.z),
-                                  reinterpret_cast<const uint32_t*>(t.rids), out, cap);
+                                  reinterpret_cast<const uint32_t*>(t.rids), (global_int2*)out, cap);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
