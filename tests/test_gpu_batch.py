@@ -136,6 +136,32 @@ def test_count_pass_in_a_replayed_graph():
     _check_batch(jobs, out, [int(v) for v in b.offsets.cpu().tolist()])
 
 
+@gpu
+def test_write_pass_runs_again_from_one_count():
+    """One count, then three write passes from the same workspace: into a buffer one slot too
+    small (writes nothing), then twice into full buffers.  The write pass takes units past a
+    static head from a ticket counter that its last workgroup resets, so each run covers every
+    unit; output positions depend on the plan only, so the two outputs are equal bit for bit."""
+    need_gpu()
+    from paper_1904_11201_amd.join import Batch
+    jobs = _mixed_jobs(66, 20, 400_000)  # units well past twice the write grid
+    b = Batch(_to_jobs(jobs))
+    offs = b.count()
+    total = int(offs[-1].item())
+    log(f"batch of {len(jobs)} joins, {total} pairs, written three times")
+    small = torch.full((max(total - 1, 0), 2), -7, dtype=torch.int32, device="cuda")
+    b.materialize(small)
+    outs = []
+    for _ in range(2):
+        out = torch.full((total, 2), -7, dtype=torch.int32, device="cuda")
+        b.materialize(out)
+        outs.append(out)
+    torch.cuda.synchronize()
+    assert bool((small == -7).all())
+    assert torch.equal(outs[0], outs[1])
+    _check_batch(jobs, outs[1], [int(v) for v in offs.cpu().tolist()])
+
+
 def _side_jobs(seed: int):
     """Joins that exercise the choice of the hashed table and probes with many matches: S smaller
     than R (S hashed: pairs must still leave as (rid_R, rid_S)), with S keys from a handful of
