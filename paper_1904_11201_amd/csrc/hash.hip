@@ -1134,7 +1134,33 @@ __device__ __forceinline__ Table table_of(const Unit& un, uint4* lds)
 // Insert a loaded chunk into the LDS table (two barriers: cleared counters, finished table).
 // HASHED: the chunk holds hmix(key) values (partitioned tuples), else raw keys.  pos[i]
 // receives the LDS word position of item i's slot.
+// Clears the table of unit un's chunk: claim counters to zero and, for a marked table, every key
+// to the marker (top bit flipped, bit 30 as the partition's, so it never reads as overflowed);
+// h: any hash of the partition (read only for a marked table).
 template <bool RIDS, bool HASHED, int B>
+__device__ __forceinline__ void clear_table(const Unit& un, uint32_t h, uint4* lds)
+{
+    const uint32_t nb = table_buckets(un.rN);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
+    if (HASHED && un.bits >= 2) {
+        const uint32_t m = (h ^ 0x80000000u) & 0xC0000000u;
+        for (uint32_t b = threadIdx.x; b < nb; b += B) {
+            cnt[b] = 0;
+            lds[b] = make_uint4(m, m, m, m);
+        }
+    } else {
+        for (uint32_t b = threadIdx.x; b < nb; b += B) cnt[b] = 0;
+    }
+}
+
+// A hash of unit un's partition for its table's marker (a scalar load; only for marked tables).
+template <bool HASHED>
+__device__ __forceinline__ uint32_t marker_hash(const JoinGeom& g, const Unit& un)
+{
+    return HASHED && un.bits >= 2 ? (uint32_t)g.rt[un.rBeg].x : 0u;
+}
+
+template <bool RIDS, bool HASHED, int B, bool CLEARED = false>
 __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un, const Chunk<RIDS>& c,
                                               uint4* lds, uint32_t (&pos)[kBuildItems])
 {
@@ -1144,20 +1170,12 @@ __device__ __forceinline__ Table insert_chunk(const JoinGeom& g, const Unit& un,
     uint32_t* rids = reinterpret_cast<uint32_t*>(lds + nb);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + (RIDS ? 2 : 1) * nb);
     const bool marked = HASHED && un.bits >= 2;
-    if (marked) {
-        // marker: top bit flipped, bit 30 as the partition's (so it never reads as overflowed).
+    if constexpr (!CLEARED) {  // else the caller cleared the table and passed a barrier since
         // The write pass loaded its chunk a unit ahead, and every thread's first entry is a hash
-        // of the partition (lanes past the chunk hold its last one); the count pass loads the
-        // chunk now, so one scalar load lets the table be cleared while the chunk is in flight.
-        const uint32_t m = ((RIDS ? c.k[0] : (uint32_t)g.rt[un.rBeg].x) ^ 0x80000000u) & 0xC0000000u;
-        for (uint32_t b = tid; b < nb; b += B) {
-            cnt[b] = 0;
-            lds[b] = make_uint4(m, m, m, m);
-        }
-    } else {
-        for (uint32_t b = tid; b < nb; b += B) cnt[b] = 0;
+        // of the partition (lanes past the chunk hold its last one).
+        clear_table<RIDS, HASHED, B>(un, RIDS ? c.k[0] : marker_hash<HASHED>(g, un), lds);
+        __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < kBuildItems; ++i) {
         const uint32_t e = (uint32_t)(i * B + tid);
@@ -1829,11 +1847,13 @@ static_assert(2 * (table_lds(kBatchCap, true) + kBatchStaticLds + 256) <= 160 * 
 // wave's count of pairs before its block of many-match pairs (low 32 bits: at most two pairs per
 // probe row of the wave) and its count of probe rows with matches when the semi-join is recorded
 // (high 32 bits, else 0); sh: kJoinWaves + 1 words of LDS.  rec_word (partitioned joins): the
-// second word of the unit's record, which receives the canonical-order flag as well.
-template <int B>
+// second word of the unit's record, which receives the canonical-order flag as well.  between:
+// run by every thread after all waves have finished the unit, before the closing barrier.
+template <int B, typename Between>
 __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_many, bool multi,
                                             uint32_t semi_rows, uint32_t u, uint64_t* __restrict__ counts,
-                                            uint64_t* __restrict__ wave_off, uint64_t* sh, uint32_t* rec_word)
+                                            uint64_t* __restrict__ wave_off, uint64_t* sh, uint32_t* rec_word,
+                                            Between between)
 {
     const uint64_t wt = wave_sum64(lane_total);
     const uint64_t wmany = wave_sum64(lane_many);
@@ -1860,6 +1880,7 @@ __device__ __forceinline__ void unit_totals(uint64_t lane_total, uint64_t lane_m
             if (any && rec_word) atomicOr(rec_word, 1u << kRecOrder);
         }
     }
+    between();  // every wave has finished the unit's probes
     __syncthreads();
 }
 
@@ -1928,6 +1949,9 @@ __global__ JL_COUNT_ATTR(B) void join_count_k(JoinGeom g, uint64_t* __restrict__
     if (u < U) {
         un = decode_unit<AOS>(g, u);
         load_keys<AOS, B>(g, un, 0, xa);
+        // each unit's table is cleared in the previous unit's closing step; the first one here
+        clear_table<false, AOS, B>(un, marker_hash<AOS>(g, un), tab);
+        __syncthreads();
     }
     while (u < U) {
         const bool need = sched_need(sc, nxi);
@@ -1936,7 +1960,7 @@ __global__ JL_COUNT_ATTR(B) void join_count_k(JoinGeom g, uint64_t* __restrict__
         Chunk<false> ch;
         load_chunk<AOS, false, B>(g, un, ch);
         uint32_t pos[kBuildItems];
-        const Table t = insert_chunk<false, AOS, B>(g, un, ch, tab, pos);
+        const Table t = insert_chunk<false, AOS, B, true>(g, un, ch, tab, pos);
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight enters the batch loop
         const bool more = nxi < U;
         const Unit nx = more ? decode_unit<AOS>(g, nxi) : Unit{};
@@ -1963,7 +1987,13 @@ __global__ JL_COUNT_ATTR(B) void join_count_k(JoinGeom g, uint64_t* __restrict__
         // a partitioned join's record is read only by this workgroup in this pass (it decoded it
         // before), so the flag can go into it
         uint32_t* rec_word = AOS ? const_cast<uint32_t*>(&g.urec[u].y) : nullptr;
-        unit_totals<B>(cnt, many, multi, sm.k, u, counts, wave_off, wsum, rec_word);  // ends with a barrier
+        // The next unit's table is cleared once every wave is done with this one.  Its marker
+        // comes from the next unit's first probe keys, loaded during the last batch: every hash
+        // of a partition has the partition's top bits (a unit without probe keys never reads
+        // its table, so its marker does not matter).
+        unit_totals<B>(cnt, many, multi, sm.k, u, counts, wave_off, wsum, rec_word, [&] {
+            if (more) clear_table<false, AOS, B>(nx, xa[0], tab);
+        });  // ends with a barrier
         const uint32_t nn = sched_after(sc, need, nxi, slot);
         u = nxi;
         nxi = nn;
