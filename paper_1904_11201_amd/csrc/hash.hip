@@ -1591,9 +1591,9 @@ __device__ __forceinline__ void unit_range(uint32_t U, uint32_t& u0, uint32_t& u
 // its even share in round-robin order, and then units handed out one at a time after all static
 // heads, so that faster workgroups take more.  Without one (one join, whose units are even), the
 // whole share is static: round robin, or for the write pass a contiguous run, whose consecutive
-// units of one R chunk keep the table.  The unit two places ahead is fixed while a unit runs (its ticket taken at the
-// unit's start, read back after the unit's last barrier), so the loads the passes issue ahead
-// for the next unit never wait for a ticket.
+// units of one R chunk keep the table.  The unit two places ahead is fixed while a unit runs
+// (its ticket taken at the unit's start, read back after the unit's last barrier), so the loads
+// the passes issue ahead for the next unit never wait for a ticket.
 constexpr uint32_t kTicketed = 0xFFFFFFFFu;
 
 struct Sched {
@@ -2047,8 +2047,8 @@ __device__ __forceinline__ bool chunk_needs_order(const JoinGeom& g, const uint6
     return any;
 }
 
-// Write pass.  Units are walked in a Sched sequence (its static head a contiguous run per
-// workgroup for one join, round robin for batches); each wave writes the pairs of its probe
+// Write pass.  Units are walked in a Sched sequence (for one join a contiguous run per
+// workgroup, for batches a round-robin head, then tickets); each wave writes the pairs of its probe
 // tuples from the start the count pass recorded for it, in (batch, tuple, lane) order, with one
 // wave-wide scan per round and no shared cursor: the output depends on the input and the plan
 // only, not on which workgroup takes a unit.
