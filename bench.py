@@ -554,6 +554,7 @@ def main():
     R_pf = J.Relation(torch.arange(0, 100 * M, 100, device=dev, dtype=torch.int32))
     S_pf = J.Relation(torch.randint(0, 100 * M, (nS,), device=dev, dtype=torch.int32, generator=g_pf))
     pf = {}
+    canon = {}
     for name, kind in (("plain_ms", J.JOIN_KIND_HASH), ("prefilter_ms", J.JOIN_KIND_HASH_PREFILTER)):
         ws_pf = J.workspace(kind, R_pf.n, nS)
         ts = []
@@ -569,7 +570,14 @@ def main():
                 ts.append(a.elapsed_time(b))
         pf[name] = round(statistics.median(ts), 4)
         pf["pairs"] = n_pf
+        # the pairs in canonical order (R rid, then S rid), compared below: the pre-filtered join
+        # must give the plain join's pairs
+        canon[name] = torch.sort(out[:, 0].to(torch.int64) * (1 << 32) + out[:, 1].to(torch.int64)).values
         del ws_pf, out
+    if not torch.equal(canon["plain_ms"], canon["prefilter_ms"]):
+        raise SystemExit("bench: the pre-filtered 1M x 64M join's pairs differ from the plain join's")
+    del canon
+    pf["same_pairs_as_plain"] = True
     pf["speedup"] = round(pf["plain_ms"] / pf["prefilter_ms"], 3)
     pf["workload"] = ("hash equi-join 1M x 64M, R keys the multiples of 100 below 100M, S keys "
                       "uniform in [0, 100M): one probe in a hundred matches")

@@ -61,6 +61,17 @@ def test_duplicates_and_extreme_keys():
 
 
 @gpu
+def test_semi_join_with_longer_probe_slices():
+    """A probe side past 32K rows per count workgroup (1M x 20M, 1% matching): the semi-join plan
+    cuts it into longer slices; the oracle's pairs and the plain join's."""
+    need_gpu()
+    g = datagen.rng_for(85)
+    R = datagen.Rel(key=np.arange(0, 100_000_000, 100, dtype=np.int32), rid=None)
+    S = datagen.Rel(key=datagen.uniform_keys(g, 20_000_000, 0, 100_000_000), rid=None)
+    _check(R, S, "semi-join, 1M x 20M, longer slices")
+
+
+@gpu
 def test_full_stages_semi_join_and_the_ordered_compaction(monkeypatch):
     """Every build row passes S's filter (more passing rows per workgroup than its LDS stage
     holds, so waves write straight out); a probe side too large for a filter (the count pass
