@@ -1691,21 +1691,26 @@ static_assert(kCountBatch % kProbe == 0, "count batch is probed kProbe keys at a
 #define JL_HASH_WRITE_LOAD 4
 #endif
 constexpr int kWriteBatch = JL_HASH_WRITE_PROBE;  // S tuples per thread per round of the write pass
-constexpr int kWriteLoad = JL_HASH_WRITE_LOAD;    // S tuples per thread in flight in the write pass
-static_assert(kWriteLoad % kWriteBatch == 0, "write loads are probed kWriteBatch tuples at a time");
+// S tuples per thread in flight in the write pass: 4 for one join's 1024-thread workgroups, 2 for
+// a batch's 512-thread ones (two share a CU; with 4, a batch's units of about 3K probe rows
+// left their second round mostly empty: batch write 22.5 -> 21.7 ms with 2).
+template <int B>
+constexpr int kWriteLoadOf = B == kBatchBlock ? 2 : JL_HASH_WRITE_LOAD;
+static_assert(kWriteLoadOf<kJoinBlock> % kWriteBatch == 0 && kWriteLoadOf<kBatchBlock> % kWriteBatch == 0,
+              "write loads are probed kWriteBatch tuples at a time");
 
 template <bool AOS, int B>
 __device__ __forceinline__ void load_tuples(const JoinGeom& g, const Unit& un, uint32_t e0,
-                                            uint32_t (&x)[kWriteLoad], int32_t (&r)[kWriteLoad])
+                                            uint32_t (&x)[kWriteLoadOf<B>], int32_t (&r)[kWriteLoadOf<B>])
 {
-    const bool full = e0 + (uint32_t)(kWriteLoad * B) <= un.sN;  // uniform
+    const bool full = e0 + (uint32_t)(kWriteLoadOf<B> * B) <= un.sN;  // uniform
     if (un.sN == 0) {  // no tuple to stand in for the out-of-range lanes
 #pragma unroll
-        for (int i = 0; i < kWriteLoad; ++i) x[i] = 0u, r[i] = 0;
+        for (int i = 0; i < kWriteLoadOf<B>; ++i) x[i] = 0u, r[i] = 0;
         return;
     }
 #pragma unroll
-    for (int i = 0; i < kWriteLoad; ++i) {
+    for (int i = 0; i < kWriteLoadOf<B>; ++i) {
         const uint32_t e = e0 + i * B + threadIdx.x;
         const bool ok = full || e < un.sN;
         uint32_t idx = un.sBeg + (ok ? e : 0u);
@@ -2079,6 +2084,7 @@ __global__ JL_WRITE_ATTR(B) void join_write_k(JoinGeom g, const uint64_t* __rest
     Unit un{};
     Chunk<true> ch;
     uint32_t pos[kBuildItems];
+    constexpr int kWriteLoad = kWriteLoadOf<B>;
     uint32_t nx[kWriteLoad];
     int32_t nr[kWriteLoad];
     if (u < U) {
